@@ -1,0 +1,123 @@
+"""Seeded synthetic workloads shared by the CPU oracle and the GPU path.
+
+This module holds problem parameters and random draws only: no step of the
+method's arithmetic lives here, so that the oracle and the HIP path can both
+take their inputs from it without sharing any computation.
+
+The problem class is the linear parametric diffusion equation
+    u' = -A(xi) u + f,  u(0) = u0 = 0,
+with A(xi) the finite-difference discretisation of -div(a(x, xi) grad u) on
+the unit interval or square with zero Dirichlet data, and log a a truncated
+Karhunen-Loeve expansion of a Gaussian field with exponential covariance
+(xi_k i.i.d. standard normal).  The parareal method with diagonalised coarse
+grid correction (Section 3.2 of the paper) is applied to it, started from a
+KL/gPC initial guess (Algorithm 3).
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import Optional
+
+import numpy as np
+
+__all__ = ["Workload", "CONFIGS", "draw_xi", "get", "small_1d", "small_2d"]
+
+
+@dataclasses.dataclass(frozen=True)
+class Workload:
+    name: str
+    dim: int                 # 1 or 2
+    n: int                   # interior nodes per dimension, h = 1/(n+1)
+    T: float                 # horizon
+    N: int                   # coarse slices (power of two)
+    J: int                   # fine backward-Euler steps per slice
+    alpha: float             # twist parameter of the coarse model, in (0, 1)
+    forcing: float           # constant source f
+    d: int                   # retained KL terms of the input field
+    corr_len: float          # correlation length of the exponential covariance
+    sigma: float             # standard deviation of log a
+    M: int                   # samples solved in one batch
+    precision: str           # "f64" or "f32_refined" (fine path)
+    tol: float               # parareal stopping tolerance on the increment
+    max_iter: int
+    gpc_degree: int          # total degree p of the Hermite gPC surrogate
+    n_train: int             # training-set size n_t
+    eps_kl: float            # KL truncation tolerance
+    seed_train: int
+    seed_eval: int
+
+    @property
+    def Nx(self) -> int:
+        return self.n ** self.dim
+
+    @property
+    def n_faces(self) -> int:
+        return self.n + 1 if self.dim == 1 else 2 * self.n * (self.n + 1)
+
+    def replace(self, **kw) -> "Workload":
+        return dataclasses.replace(self, **kw)
+
+
+CONFIGS = {
+    # 1D, 127 interior nodes, KL d=4 (corr 0.5, sigma 0.5), N=16, J=32, alpha=1e-2,
+    # Hermite gPC degree 3 on 50 training samples, 8 evaluation samples, FP64.
+    "c1_1d_n127": Workload("c1_1d_n127", 1, 127, 1.0, 16, 32, 1e-2, 1.0, 4, 0.5, 0.5,
+                           8, "f64", 1e-8, 60, 3, 50, 1e-10, 1001, 2001),
+    # 2D 128x128, KL d=10 (corr 0.3, sigma 1), N=64, J=64, alpha=1e-4, M=256,
+    # FP32 PCG fine path refined to FP64, FP64 coarse correction.
+    "c2_2d_n128": Workload("c2_2d_n128", 2, 128, 1.0, 64, 64, 1e-4, 1.0, 10, 0.3, 1.0,
+                           256, "f32_refined", 1e-8, 60, 3, 512, 1e-10, 1002, 2002),
+    # 2D 512x512, KL d=20 (corr 0.2, sigma 1), N=256, J=128, M=64.
+    "c5_2d_n512": Workload("c5_2d_n512", 2, 512, 1.0, 256, 128, 1e-4, 1.0, 20, 0.2, 1.0,
+                           64, "f32_refined", 1e-8, 60, 2, 256, 1e-10, 1005, 2005),
+}
+
+
+def get(name: str) -> Workload:
+    return CONFIGS[name]
+
+
+def small_1d(**kw) -> Workload:
+    """A small 1D case that the oracle finishes in well under a second."""
+    base = Workload("small_1d", 1, 31, 1.0, 8, 8, 1e-2, 1.0, 4, 0.5, 0.5,
+                    4, "f64", 1e-8, 60, 2, 30, 1e-10, 11, 21)
+    return base.replace(**kw)
+
+
+def small_2d(**kw) -> Workload:
+    """A small 2D case (several tiles plus a ragged tail in every direction)."""
+    base = Workload("small_2d", 2, 20, 1.0, 8, 8, 1e-2, 1.0, 6, 0.3, 1.0,
+                    3, "f64", 1e-8, 60, 2, 40, 1e-10, 12, 22)
+    return base.replace(**kw)
+
+
+def draw_xi(M: int, d: int, seed: int) -> np.ndarray:
+    """xi ~ N(0, I_d), M rows, from a seeded PCG64 generator (FP64)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.standard_normal((M, d))
+
+
+def draw_uniform(shape, seed: int) -> np.ndarray:
+    """i.i.d. U(0,1) entries (used for the RANDOM initial guess)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.random(shape)
+
+
+def draw_ragged(M: int, seed: int, grids=(64, 128, 256), slices=(32, 64, 128)):
+    """Uneven batch: per-sample grid size and slice count, uniform categorical."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    g = rng.integers(0, len(grids), size=M)
+    s = rng.integers(0, len(slices), size=M)
+    return np.asarray(grids)[g], np.asarray(slices)[s]
+
+
+def draw_normal(shape, seed: int, scale: float = 1.0) -> np.ndarray:
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return scale * rng.standard_normal(shape)
+
+
+def describe(w: Workload, M: Optional[int] = None) -> dict:
+    d = dataclasses.asdict(w)
+    if M is not None:
+        d["M"] = M
+    return d
