@@ -1,0 +1,197 @@
+/*
+ * klecgc.h -- C ABI of the MI355X (gfx950) KLE-CGC library.
+ *
+ * KLE-CGC (arXiv 2510.26180) solves the parametric linear diffusion problem
+ *     u' = -A(xi) u + f,  u(0) = u0,  t in [0, T]                  (Section 2, eq. psys;
+ *                                                                    Section 4.1, eq. ODE)
+ * for many samples xi by parareal with a diagonalised coarse grid correction
+ * (Section 3.2, Algorithm 2) started from a KL/gPC initial guess (Algorithm 3).
+ *
+ * Conventions
+ *  - Every `*_dev` pointer is caller-owned device memory on the context's device,
+ *    contiguous, row-major, with the layout stated at each argument.  The library
+ *    never frees, keeps or reads caller pointers after a call returns (work is
+ *    enqueued on the context's stream; a call that writes host memory
+ *    synchronises that stream before returning).
+ *  - States are [M][N][Nx] float64 with x fastest; in 2D the unknown of node
+ *    (i, j) (0-based, x = (i+1)h, y = (j+1)h, h = 1/(n+1)) is j*n + i.
+ *  - Face coefficients a are [M][Fc] float64:
+ *      1D: Fc = n+1, face f between nodes f-1 and f (nodes -1 and n are the
+ *          zero-Dirichlet boundary), at x = (f + 1/2) h;
+ *      2D: Fc = 2n(n+1); x-faces first, index j*(n+1)+f between nodes (f-1, j)
+ *          and (f, j); then y-faces, index n(n+1) + f*n + i between (i, f-1) and
+ *          (i, f).
+ *    The operator is (A u)_p = sum over the faces of p of a_f (u_p - u_q) / h^2
+ *    with u_q = 0 outside the grid.
+ *  - Library-owned handles are created by kle_build / gpc_fit and released
+ *    with klecgc_kle_free / klecgc_gpc_free.
+ *  - Errors: every entry point returns KC_OK or a negative code; no exception
+ *    or abort crosses the ABI.  klecgc_last_error(ctx) returns a message for
+ *    the last failing call on that context (valid until the next call).
+ *  - One context per host thread.
+ */
+#ifndef KLECGC_H
+#define KLECGC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  KC_OK = 0,
+  KC_EINVAL = -1,        /* invalid argument (null pointer, bad size or parameter) */
+  KC_ENOMEM = -2,        /* device or host allocation failed */
+  KC_EHIP = -3,          /* a HIP runtime call failed */
+  KC_ERANK = -4,         /* least-squares design matrix rank-deficient or n_t < P */
+  KC_ENOCONV = -5,       /* an iterative solve hit its iteration cap */
+  KC_ENONFINITE = -6,    /* NaN or Inf met in a sample */
+  KC_EUNSUPPORTED = -7   /* parameter combination not implemented */
+};
+
+enum { KC_PREC_F64 = 0, KC_PREC_F32_REFINED = 1 };
+enum { KC_KLE_FIELD_EXP = 0, KC_KLE_SNAPSHOT = 1 };
+enum { KC_INIT_GIVEN = 0, KC_INIT_ZERO = 1, KC_INIT_COARSE = 2, KC_INIT_GPC = 3 };
+/* per-sample status written by parareal_solve */
+enum { KC_SAMPLE_CONVERGED = 0, KC_SAMPLE_MAXITER = 1, KC_SAMPLE_NONFINITE = 2 };
+
+typedef struct klecgc_ctx klecgc_ctx;
+typedef struct klecgc_kle klecgc_kle;
+typedef struct klecgc_gpc klecgc_gpc;
+
+/* One problem family (uniform batch).  Section 3.1: N coarse slices of length
+ * dT = T/N, J fine steps of dt = dT/J per slice, backward Euler for F and G;
+ * Section 3.2: alpha in (0,1) couples u(0) = alpha u(T) in the coarse model. */
+typedef struct {
+  int32_t dim;            /* 1 or 2 */
+  int32_t n;              /* interior nodes per dimension (Nx = n^dim), n >= 1 */
+  double  T;              /* horizon, > 0 */
+  int32_t N;              /* coarse slices, power of two, 2 <= N <= 256 */
+  int32_t J;              /* fine steps per slice, >= 1 */
+  double  alpha;          /* twist parameter, 0 < alpha < 1 */
+  double  forcing;        /* constant source f */
+  int32_t precision;      /* KC_PREC_F64 or KC_PREC_F32_REFINED (2D fine path only) */
+  double  tol;            /* parareal stop: max|U^{k+1}-U^k| / max|U^{k+1}| <= tol (> 0) */
+  int32_t max_iter;       /* parareal iteration cap, >= 1 */
+  double  inner_rtol;     /* 2D fine solves: FP64 residual <= inner_rtol * (|w|_inf + dt|f|)
+                             + 8 eps max_p(diag_p) |w|_inf (the FP64 rounding floor of the
+                             residual itself); 0 selects 1e-14 */
+  int32_t inner_max_iter; /* 2D fine solves: Krylov iteration cap per solve; 0 selects 4000 */
+  double  cgc_rtol;       /* 2D shifted solves of step (b): relative residual; 0 selects 1e-13 */
+  int32_t cgc_max_iter;   /* 2D shifted solves: iteration cap; 0 selects 20000 */
+} klecgc_problem;
+
+/* KL descriptor.
+ * FIELD_EXP (input field; Section 2, separated representation): Gaussian field
+ *   with covariance sigma^2 exp(-|x-y|/corr_len) on [0,1] (separable product in
+ *   2D), closed-form eigenpairs, the d largest modes evaluated at the faces.
+ * SNAPSHOT (solution snapshots; Section 2.1, Algorithm 3 steps 1-2, 4): rows of
+ *   S are n_t flattened states of length L = N*Nx; modes kept by the smallest
+ *   M_Q with eigenvalue fraction >= 1 - eps_kl, capped at numerical rank. */
+typedef struct {
+  int32_t kind;           /* KC_KLE_FIELD_EXP or KC_KLE_SNAPSHOT */
+  int32_t dim, n, d;      /* FIELD_EXP */
+  double  corr_len, sigma;/* FIELD_EXP */
+  int64_t L;              /* SNAPSHOT: row length */
+  double  eps_kl;         /* SNAPSHOT: truncation tolerance (e.g. 1e-10) */
+} klecgc_kle_desc;
+
+/* ---- lifecycle ---------------------------------------------------------- */
+/* Create a context on `device` that enqueues on `hip_stream` (a hipStream_t;
+ * NULL = the null stream).  The stream is borrowed, not owned. */
+int klecgc_create(klecgc_ctx** out, int device, void* hip_stream);
+void klecgc_destroy(klecgc_ctx* ctx);
+int klecgc_set_stream(klecgc_ctx* ctx, void* hip_stream);
+const char* klecgc_last_error(const klecgc_ctx* ctx);
+void klecgc_kle_free(klecgc_kle* h);
+void klecgc_gpc_free(klecgc_gpc* h);
+/* Counters of the last call on ctx (instrumentation): out8[0..3] = fine implicit solves:
+ * total Krylov iterations, total float64 refinement passes, number of implicit steps, max
+ * iterations of one solve; out8[4..7] = the same for the shifted solves of step (b)
+ * (2D only; passes unused).  Zeros where a path has no iterative solver. */
+int klecgc_last_stats(const klecgc_ctx* ctx, int64_t* out8);
+/* Library version string (static storage). */
+const char* klecgc_version(void);
+
+/* ---- KL ----------------------------------------------------------------- */
+/* kle_build: FIELD_EXP ignores S_dev/n_t; SNAPSHOT reads S_dev [n_t][L] float64
+ * (Section 2.1: mean, centred Gram matrix C = S~ S~^T / n_t on the device, its
+ * eigenpairs on the host, basis g_k = (lam_k n_t)^{-1/2} S~^T e_k on the device).
+ * *n_modes receives d (FIELD_EXP) or M_Q (SNAPSHOT). */
+int kle_build(klecgc_ctx* ctx, const klecgc_kle_desc* desc, const double* S_dev, int64_t n_t,
+              klecgc_kle** out, int32_t* n_modes);
+/* kle_synthesize: a[m][f] = exp(sum_k sqrt(lam_k) phi_k(face f) xi[m][k]) for a
+ * FIELD_EXP handle.  xi_dev [M][d] float64, a_dev [M][Fc] float64. */
+int kle_synthesize(klecgc_ctx* ctx, const klecgc_kle* field, const double* xi_dev, int64_t M,
+                   double* a_dev);
+/* Copy a SNAPSHOT handle's mean [L] and scaled basis W = diag(sqrt(lam)) G
+ * [M_Q][L] (row k = sqrt(lam_k) g_k) and eigenvalues [M_Q] to caller device memory
+ * (any pointer may be NULL). */
+int kle_export(klecgc_ctx* ctx, const klecgc_kle* snap, double* mean_dev, double* W_dev,
+               double* lam_dev);
+
+/* ---- gPC (Section 2.2; Algorithm 3 steps 3, 5, 6) ------------------------- */
+/* gpc_fit: orthonormal probabilists' Hermite tensor basis of total degree <= p
+ * in d variables (P = C(p+d, p) terms, degree-graded lexicographic order),
+ * B[j][i] = psi_i(xi_j), D = zeta(xi_j) of the training snapshots of `snap`,
+ * h = argmin |B h - D|_2 by Householder QR on the host.  xi_train_dev [n_t][d]
+ * float64 must be the parameters of the rows of S given to kle_build.
+ * Returns KC_ERANK if n_t < P or B is rank-deficient.  *P receives P. */
+int gpc_fit(klecgc_ctx* ctx, const klecgc_kle* snap, const double* xi_train_dev, int64_t n_t,
+            int32_t d, int32_t p, klecgc_gpc** out, int32_t* P);
+/* gpc_predict: U0[m] = u_bar + sum_i sqrt(lam_i) (sum_j h_{j,i} psi_j(xi_m)) g_i
+ * (Algorithm 3 step 6).  xi_dev [M][d], U0_dev [M][L] float64. */
+int gpc_predict(klecgc_ctx* ctx, const klecgc_gpc* gpc, const double* xi_dev, int64_t M,
+                double* U0_dev);
+
+/* ---- parareal building blocks ------------------------------------------- */
+/* fine_propagate (Algorithm 2 step 1, eq. PGC_step1): for every sample m and
+ * slice s, J backward-Euler steps of size dt = T/(N J) from start[m][s]:
+ *     (I + dt A_m) w_{j+1} = w_j + dt f,   end[m][s] = w_J.
+ * a_dev [M][Fc], start_dev and end_dev [M][N][Nx] float64 (may not alias).
+ * 1D: direct tridiagonal (Thomas) solves in float64.
+ * 2D: precision F64 -> float64 Jacobi-PCG to inner_rtol; F32_REFINED ->
+ * float32 Jacobi-PCG corrections with float64 residuals and coefficients
+ * until the float64 residual meets inner_rtol.  Returns KC_ENOCONV if a
+ * solve hits inner_max_iter (results are still written). */
+int fine_propagate(klecgc_ctx* ctx, const klecgc_problem* prob, const double* a_dev,
+                   const double* start_dev, int64_t M, double* end_dev);
+/* cgc_diag_solve (Section 3.2, eq. matrix_NT and eq. three-steps): solves
+ *     (C_alpha (x) I + dT I (x) A_m) u_m = r_m   for every sample m,
+ * C_alpha the alpha-circulant time matrix, by (a) p = F_N^* Lambda r (real FFT
+ * over slices, float64), (b) (lambda_k I + dT A) q_k = p_k for k = 0..N/2
+ * (conjugate symmetry; complex Thomas in 1D, Jacobi-COCG in complex128 in 2D),
+ * (c) u = Lambda^{-1} F_N q (float64).  Lambda = diag(alpha^{s/N}).
+ * r_dev, u_dev [M][N][Nx] float64 (may alias). */
+int cgc_diag_solve(klecgc_ctx* ctx, const klecgc_problem* prob, const double* a_dev,
+                   const double* r_dev, int64_t M, double* u_dev);
+/* coarse_propagate (Section 3.1, G): U[m][s] = G(U[m][s-1]) sequentially over
+ * slices from u0 (NULL = 0): one backward-Euler step of dT per slice. */
+int coarse_propagate(klecgc_ctx* ctx, const klecgc_problem* prob, const double* a_dev,
+                     const double* u0_dev, int64_t M, double* U_dev);
+
+/* ---- driver (Algorithms 2 and 3) ----------------------------------------- */
+/* parareal_solve: parareal with diagonalised CGC for M samples.
+ *   u0_dev [M][Nx] or NULL (zero initial condition);
+ *   init: KC_INIT_GIVEN (init_dev [M][N][Nx]), KC_INIT_ZERO, KC_INIT_COARSE
+ *         (one sequential G sweep), KC_INIT_GPC (gpc + xi_dev [M][d]);
+ *   U_dev [M][N][Nx] receives U^k at each sample's stop;
+ *   iters_host [M], status_host [M] (KC_SAMPLE_*) host arrays;
+ *   delta_hist_host [M][max_iter] (nullable) receives the increments
+ *   (unused entries set to 0).
+ * Each iteration: fine sweep over all active (sample, slice) pairs (the first
+ * slice's F(u0) is computed once), defect d_s = (I + dT A)(F_s - U_s), one
+ * cgc_diag_solve, U += correction; a sample stops when its increment
+ * max|U^{k+1}-U^k| / max|U^{k+1}| <= tol.  In exact arithmetic the iterates
+ * equal those of Algorithm 2 (the correction form solves the same
+ * all-at-once system for U^{k+1} - U^k). */
+int parareal_solve(klecgc_ctx* ctx, const klecgc_problem* prob, const double* a_dev,
+                   const double* u0_dev, int64_t M, int32_t init, const double* init_dev,
+                   const klecgc_gpc* gpc, const double* xi_dev, double* U_dev,
+                   int32_t* iters_host, int32_t* status_host, double* delta_hist_host);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KLECGC_H */

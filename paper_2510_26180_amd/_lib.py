@@ -1,0 +1,84 @@
+"""ctypes declarations of the C ABI in include/klecgc.h (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libklecgc.so")
+
+KC_OK = 0
+ERRORS = {
+    -1: "KC_EINVAL", -2: "KC_ENOMEM", -3: "KC_EHIP", -4: "KC_ERANK",
+    -5: "KC_ENOCONV", -6: "KC_ENONFINITE", -7: "KC_EUNSUPPORTED",
+}
+KC_PREC_F64, KC_PREC_F32_REFINED = 0, 1
+KC_KLE_FIELD_EXP, KC_KLE_SNAPSHOT = 0, 1
+KC_INIT_GIVEN, KC_INIT_ZERO, KC_INIT_COARSE, KC_INIT_GPC = 0, 1, 2, 3
+KC_SAMPLE_CONVERGED, KC_SAMPLE_MAXITER, KC_SAMPLE_NONFINITE = 0, 1, 2
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int32), ("n", ctypes.c_int32),
+        ("T", ctypes.c_double), ("N", ctypes.c_int32), ("J", ctypes.c_int32),
+        ("alpha", ctypes.c_double), ("forcing", ctypes.c_double),
+        ("precision", ctypes.c_int32),
+        ("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
+        ("inner_rtol", ctypes.c_double), ("inner_max_iter", ctypes.c_int32),
+        ("cgc_rtol", ctypes.c_double), ("cgc_max_iter", ctypes.c_int32),
+    ]
+
+
+class KleDesc(ctypes.Structure):
+    _fields_ = [
+        ("kind", ctypes.c_int32), ("dim", ctypes.c_int32), ("n", ctypes.c_int32), ("d", ctypes.c_int32),
+        ("corr_len", ctypes.c_double), ("sigma", ctypes.c_double),
+        ("L", ctypes.c_int64), ("eps_kl", ctypes.c_double),
+    ]
+
+
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_i32 = ctypes.c_int32
+_P = ctypes.POINTER
+
+SIGNATURES = {
+    "klecgc_create": (ctypes.c_int, [_P(_vp), ctypes.c_int, _vp]),
+    "klecgc_destroy": (None, [_vp]),
+    "klecgc_set_stream": (ctypes.c_int, [_vp, _vp]),
+    "klecgc_last_error": (ctypes.c_char_p, [_vp]),
+    "klecgc_kle_free": (None, [_vp]),
+    "klecgc_gpc_free": (None, [_vp]),
+    "klecgc_version": (ctypes.c_char_p, []),
+    "klecgc_last_stats": (ctypes.c_int, [_vp, _P(ctypes.c_int64)]),
+    "kle_build": (ctypes.c_int, [_vp, _P(KleDesc), _vp, _i64, _P(_vp), _P(_i32)]),
+    "kle_synthesize": (ctypes.c_int, [_vp, _vp, _vp, _i64, _vp]),
+    "kle_export": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
+    "gpc_fit": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, _i32, _P(_vp), _P(_i32)]),
+    "gpc_predict": (ctypes.c_int, [_vp, _vp, _vp, _i64, _vp]),
+    "fine_propagate": (ctypes.c_int, [_vp, _P(Problem), _vp, _vp, _i64, _vp]),
+    "cgc_diag_solve": (ctypes.c_int, [_vp, _P(Problem), _vp, _vp, _i64, _vp]),
+    "coarse_propagate": (ctypes.c_int, [_vp, _P(Problem), _vp, _vp, _i64, _vp]),
+    "parareal_solve": (ctypes.c_int, [_vp, _P(Problem), _vp, _vp, _i64, _i32, _vp, _vp, _vp, _vp,
+                                      _P(_i32), _P(_i32), _P(ctypes.c_double)]),
+}
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libklecgc.so; raises if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_2510_26180_amd.build` "
+                          "(the HIP library is required; there is no CPU fallback)")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib

@@ -1,0 +1,197 @@
+"""Thin Python binding over the C ABI (include/klecgc.h).
+
+Device memory and streams come from PyTorch (tensors on the context's GPU,
+float64, contiguous); every step of the computation runs in the HIP library.
+The functions keep the ABI's names and argument order.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+from . import _lib as L
+
+
+class KlecgcError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{L.ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("expected a torch tensor")
+    if not t.is_cuda:
+        raise ValueError("tensor must live on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return t.data_ptr()
+
+
+@dataclass
+class ProblemSpec:
+    dim: int
+    n: int
+    T: float
+    N: int
+    J: int
+    alpha: float
+    forcing: float = 1.0
+    precision: int = L.KC_PREC_F64
+    tol: float = 1e-8
+    max_iter: int = 60
+    inner_rtol: float = 0.0
+    inner_max_iter: int = 0
+    cgc_rtol: float = 0.0
+    cgc_max_iter: int = 0
+
+    @property
+    def Nx(self) -> int:
+        return self.n ** self.dim
+
+    @property
+    def n_faces(self) -> int:
+        return self.n + 1 if self.dim == 1 else 2 * self.n * (self.n + 1)
+
+    def c(self) -> L.Problem:
+        return L.Problem(self.dim, self.n, self.T, self.N, self.J, self.alpha, self.forcing,
+                         self.precision, self.tol, self.max_iter, self.inner_rtol, self.inner_max_iter,
+                         self.cgc_rtol, self.cgc_max_iter)
+
+    @staticmethod
+    def from_workload(w, **kw) -> "ProblemSpec":
+        prec = L.KC_PREC_F64 if w.precision == "f64" else L.KC_PREC_F32_REFINED
+        args = dict(dim=w.dim, n=w.n, T=w.T, N=w.N, J=w.J, alpha=w.alpha, forcing=w.forcing,
+                    precision=prec, tol=w.tol, max_iter=w.max_iter)
+        args.update(kw)
+        return ProblemSpec(**args)
+
+
+class Handle:
+    def __init__(self, ptr: int, free, **meta):
+        self.ptr = ptr
+        self._free = free
+        self.__dict__.update(meta)
+
+    def close(self):
+        if self.ptr:
+            self._free(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Context:
+    """klecgc_ctx bound to one device and a borrowed HIP stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        self.lib = L.load()
+        torch = _torch()
+        if stream is None:
+            stream = torch.cuda.current_stream(device).cuda_stream
+        h = ctypes.c_void_p()
+        rc = self.lib.klecgc_create(ctypes.byref(h), device, ctypes.c_void_p(stream))
+        if rc != 0:
+            raise KlecgcError(rc, "klecgc_create failed")
+        self.h = h
+        self.device = device
+
+    def _check(self, rc: int, allow=()):
+        if rc != 0 and rc not in allow:
+            raise KlecgcError(rc, self.lib.klecgc_last_error(self.h).decode())
+        return rc
+
+    def last_stats(self) -> dict:
+        out = (ctypes.c_int64 * 8)()
+        self._check(self.lib.klecgc_last_stats(self.h, out))
+        v = list(out)
+        return {"fine_krylov_its": v[0], "fine_passes": v[1], "fine_solves": v[2], "fine_max_its": v[3],
+                "cgc_krylov_its": v[4], "cgc_solves": v[6], "cgc_max_its": v[7]}
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.klecgc_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- KL / gPC
+    def kle_build_field(self, dim: int, n: int, d: int, corr_len: float, sigma: float) -> Handle:
+        desc = L.KleDesc(L.KC_KLE_FIELD_EXP, dim, n, d, corr_len, sigma, 0, 0.0)
+        out = ctypes.c_void_p()
+        nm = ctypes.c_int32()
+        self._check(self.lib.kle_build(self.h, ctypes.byref(desc), None, 0, ctypes.byref(out), ctypes.byref(nm)))
+        return Handle(out.value, self.lib.klecgc_kle_free, d=nm.value, dim=dim, n=n)
+
+    def kle_build(self, S, eps_kl: float) -> Handle:
+        n_t, Lrow = S.shape
+        desc = L.KleDesc(L.KC_KLE_SNAPSHOT, 0, 0, 0, 0.0, 0.0, Lrow, eps_kl)
+        out = ctypes.c_void_p()
+        nm = ctypes.c_int32()
+        self._check(self.lib.kle_build(self.h, ctypes.byref(desc), _ptr(S), n_t, ctypes.byref(out), ctypes.byref(nm)))
+        return Handle(out.value, self.lib.klecgc_kle_free, n_modes=nm.value, L=Lrow, n_t=n_t)
+
+    def kle_synthesize(self, field: Handle, xi, a):
+        self._check(self.lib.kle_synthesize(self.h, field.ptr, _ptr(xi), xi.shape[0], _ptr(a)))
+        return a
+
+    def kle_export(self, snap: Handle, mean=None, W=None, lam=None):
+        self._check(self.lib.kle_export(self.h, snap.ptr, _ptr(mean), _ptr(W), _ptr(lam)))
+
+    def gpc_fit(self, snap: Handle, xi_train, p: int) -> Handle:
+        n_t, d = xi_train.shape
+        out = ctypes.c_void_p()
+        P = ctypes.c_int32()
+        self._check(self.lib.gpc_fit(self.h, snap.ptr, _ptr(xi_train), n_t, d, p, ctypes.byref(out), ctypes.byref(P)))
+        return Handle(out.value, self.lib.klecgc_gpc_free, P=P.value, d=d, p=p, snap=snap)
+
+    def gpc_predict(self, gpc: Handle, xi, U0):
+        self._check(self.lib.gpc_predict(self.h, gpc.ptr, _ptr(xi), xi.shape[0], _ptr(U0)))
+        return U0
+
+    # ---- parareal pieces
+    def fine_propagate(self, prob: ProblemSpec, a, start, end, allow_noconv=False) -> int:
+        pc = prob.c()
+        return self._check(self.lib.fine_propagate(self.h, ctypes.byref(pc), _ptr(a), _ptr(start), start.shape[0], _ptr(end)),
+                           allow=(-5,) if allow_noconv else ())
+
+    def cgc_diag_solve(self, prob: ProblemSpec, a, r, u, allow_noconv=False) -> int:
+        pc = prob.c()
+        return self._check(self.lib.cgc_diag_solve(self.h, ctypes.byref(pc), _ptr(a), _ptr(r), r.shape[0], _ptr(u)),
+                           allow=(-5,) if allow_noconv else ())
+
+    def coarse_propagate(self, prob: ProblemSpec, a, u0, U) -> int:
+        pc = prob.c()
+        return self._check(self.lib.coarse_propagate(self.h, ctypes.byref(pc), _ptr(a), _ptr(u0), U.shape[0], _ptr(U)))
+
+    def parareal_solve(self, prob: ProblemSpec, a, U, u0=None, init: int = L.KC_INIT_ZERO, init_U=None,
+                       gpc: Optional[Handle] = None, xi=None, allow_noconv=False):
+        M = U.shape[0]
+        iters = (ctypes.c_int32 * M)()
+        status = (ctypes.c_int32 * M)()
+        hist = (ctypes.c_double * (M * prob.max_iter))()
+        pc = prob.c()
+        rc = self.lib.parareal_solve(self.h, ctypes.byref(pc), _ptr(a), _ptr(u0), M, init, _ptr(init_U),
+                                     gpc.ptr if gpc is not None else None, _ptr(xi), _ptr(U), iters, status, hist)
+        self._check(rc, allow=(-5,) if allow_noconv else ())
+        return (np.frombuffer(iters, dtype=np.int32).copy(), np.frombuffer(status, dtype=np.int32).copy(),
+                np.frombuffer(hist, dtype=np.float64).reshape(M, prob.max_iter).copy(), rc)

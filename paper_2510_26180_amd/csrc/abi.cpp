@@ -1,0 +1,533 @@
+// C ABI entry points: argument validation, stream/device binding, error capture, and
+// the host-side orchestration of the KL / gPC stages and of the parareal iteration.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <functional>
+#include <vector>
+
+#include "common.h"
+
+namespace kc {
+
+void field_kl_host(int dim, int n, int d, double corr_len, double sigma, std::vector<double>& lam,
+                   std::vector<double>& phi);
+int propagate_impl(klecgc_ctx* ctx, const klecgc_problem& p, const FineArgs& fa, double tau, int J,
+                   int N);
+void launch_dgemm_nt(hipStream_t s, int64_t Mr, int64_t Nc, int64_t K, const double* A,
+                     int64_t lda, const double* B, int64_t ldb, double* C, int64_t ldc,
+                     double alpha);
+
+void* Workspace::get(int slot, size_t bytes) {
+  if ((int)ptr.size() < WS_COUNT) {
+    ptr.resize(WS_COUNT, nullptr);
+    cap.resize(WS_COUNT, 0);
+  }
+  if (bytes == 0) bytes = 1;
+  if (cap[slot] < bytes) {
+    if (ptr[slot]) {
+      KC_TRY_HIP(hipDeviceSynchronize());
+      KC_TRY_HIP(hipFree(ptr[slot]));
+      ptr[slot] = nullptr;
+      cap[slot] = 0;
+    }
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      throw Error{KC_ENOMEM, "device workspace allocation of " + std::to_string(bytes) + " bytes failed"};
+    }
+    ptr[slot] = p;
+    cap[slot] = bytes;
+  }
+  return ptr[slot];
+}
+
+void Workspace::release() {
+  for (auto& p : ptr)
+    if (p) {
+      (void)hipFree(p);
+      p = nullptr;
+    }
+  std::fill(cap.begin(), cap.end(), 0);
+}
+
+DevStatus status_block(klecgc_ctx* ctx) {
+  char* b = (char*)ctx->ws.get(WS_STATUS, kStatusBytes);
+  return DevStatus{(int*)b, (unsigned long long*)(b + 8)};
+}
+
+void status_reset(klecgc_ctx* ctx, const DevStatus& st) {
+  KC_TRY_HIP(hipMemsetAsync(st.flag, 0, kStatusBytes, ctx->stream));
+}
+
+int status_collect(klecgc_ctx* ctx, const DevStatus& st, int base) {
+  unsigned char h[kStatusBytes];
+  KC_TRY_HIP(hipMemcpyAsync(h, st.flag, kStatusBytes, hipMemcpyDeviceToHost, ctx->stream));
+  KC_TRY_HIP(hipStreamSynchronize(ctx->stream));
+  int flag;
+  unsigned long long c[4];
+  std::memcpy(&flag, h, sizeof(int));
+  std::memcpy(c, h + 8, sizeof(c));
+  ctx->stats[base + 0] += (int64_t)c[0];
+  ctx->stats[base + 1] += (int64_t)c[1];
+  ctx->stats[base + 2] += (int64_t)c[2];
+  ctx->stats[base + 3] = std::max<int64_t>(ctx->stats[base + 3], (int64_t)c[3]);
+  return flag;
+}
+
+void validate_problem(const klecgc_problem& p) {
+  KC_REQUIRE(p.dim == 1 || p.dim == 2, KC_EINVAL, "dim must be 1 or 2");
+  KC_REQUIRE(p.n >= 1, KC_EINVAL, "n must be >= 1");
+  KC_REQUIRE(p.T > 0 && std::isfinite(p.T), KC_EINVAL, "T must be positive");
+  KC_REQUIRE(p.N >= 2 && p.N <= 256 && (p.N & (p.N - 1)) == 0, KC_EINVAL,
+             "N must be a power of two in [2, 256]");
+  KC_REQUIRE(p.J >= 1, KC_EINVAL, "J must be >= 1");
+  KC_REQUIRE(p.alpha > 0 && p.alpha < 1, KC_EINVAL, "alpha must lie in (0, 1)");
+  KC_REQUIRE(std::isfinite(p.forcing), KC_EINVAL, "forcing must be finite");
+  KC_REQUIRE(p.precision == KC_PREC_F64 || p.precision == KC_PREC_F32_REFINED, KC_EINVAL,
+             "unknown precision");
+  KC_REQUIRE(p.tol > 0, KC_EINVAL, "tol must be positive");
+  KC_REQUIRE(p.max_iter >= 1, KC_EINVAL, "max_iter must be >= 1");
+  KC_REQUIRE(p.inner_rtol >= 0 && p.cgc_rtol >= 0, KC_EINVAL, "tolerances must be >= 0");
+  KC_REQUIRE(p.inner_max_iter >= 0 && p.cgc_max_iter >= 0, KC_EINVAL, "iteration caps must be >= 0");
+  if (p.dim == 1)
+    KC_REQUIRE(p.precision == KC_PREC_F64, KC_EUNSUPPORTED, "1D supports only KC_PREC_F64");
+  if (p.dim == 2) KC_REQUIRE(p.n <= 4096, KC_EUNSUPPORTED, "2D grids above 4096^2 unsupported");
+}
+
+static std::vector<std::vector<int>> index_set(int d, int p) {
+  // total-order multi-indices, degree ascending then lexicographic ascending
+  std::vector<std::vector<int>> out;
+  std::vector<int> cur(d, 0);
+  for (int deg = 0; deg <= p; ++deg) {
+    // enumerate compositions of deg into d parts in lexicographic order
+    std::function<void(int, int)> rec = [&](int pos, int left) {
+      if (pos == d - 1) {
+        cur[pos] = left;
+        out.push_back(cur);
+        return;
+      }
+      for (int v = 0; v <= left; ++v) {
+        cur[pos] = v;
+        rec(pos + 1, left - v);
+      }
+    };
+    rec(0, deg);
+  }
+  return out;
+}
+
+int gpc_predict_impl(klecgc_ctx* ctx, const klecgc_gpc* g, const double* xi, int64_t M, double* U0) {
+  hipStream_t st = ctx->stream;
+  double* Psi = (double*)ctx->ws.get(WS_GEMM_A, sizeof(double) * M * g->P);
+  double* Z = (double*)ctx->ws.get(WS_GEMM_B, sizeof(double) * M * g->n_modes);
+  launch_hermite(st, xi, M, g->d, g->idx, g->P, g->p, Psi);
+  launch_dgemm(st, M, g->n_modes, g->P, Psi, g->P, g->H, g->n_modes, Z, g->n_modes, nullptr, 1.0);
+  launch_dgemm(st, M, g->L, g->n_modes, Z, g->n_modes, g->W, g->L, U0, g->L, g->mean, 1.0);
+  return KC_OK;
+}
+
+static int parareal_impl(klecgc_ctx* ctx, const klecgc_problem& p, const double* a, const double* u0,
+                         int64_t M, int32_t init, const double* init_dev, const klecgc_gpc* gpc,
+                         const double* xi, double* U, int32_t* iters, int32_t* status, double* hist) {
+  hipStream_t st = ctx->stream;
+  const int64_t Nx = n_unknowns(p);
+  const int N = p.N, K = N / 2 + 1;
+  const int64_t S = (int64_t)N * Nx;
+  int rc = KC_OK;
+  switch (init) {
+    case KC_INIT_GIVEN:
+      KC_REQUIRE(init_dev, KC_EINVAL, "init_dev required for KC_INIT_GIVEN");
+      KC_TRY_HIP(hipMemcpyAsync(U, init_dev, sizeof(double) * M * S, hipMemcpyDeviceToDevice, st));
+      break;
+    case KC_INIT_ZERO:
+      KC_TRY_HIP(hipMemsetAsync(U, 0, sizeof(double) * M * S, st));
+      break;
+    case KC_INIT_COARSE: {
+      int r = coarse_sweep_impl(ctx, p, a, u0, M, U);
+      if (r != KC_OK) rc = r;
+      break;
+    }
+    case KC_INIT_GPC:
+      KC_REQUIRE(gpc && xi, KC_EINVAL, "gpc handle and xi_dev required for KC_INIT_GPC");
+      KC_REQUIRE(gpc->L == S, KC_EINVAL, "gpc surrogate state length differs from N*Nx");
+      gpc_predict_impl(ctx, gpc, xi, M, U);
+      break;
+    default:
+      throw Error{KC_EINVAL, "unknown init mode"};
+  }
+  double* Fv = (double*)ctx->ws.get(WS_FINE, sizeof(double) * M * S);
+  double* D = (double*)ctx->ws.get(WS_DEFECT, sizeof(double) * M * S);
+  double* spec = (double*)ctx->ws.get(WS_SPEC, sizeof(double) * 2 * M * K * Nx);
+  size_t small_bytes = 256 + (size_t)M * (1 + 16);
+  uint8_t* small = (uint8_t*)ctx->ws.get(WS_SMALL, small_bytes);
+  unsigned long long* maxima = (unsigned long long*)small;          // [M][2]
+  uint8_t* active = small + 16 * M;                                 // [M]
+  std::vector<uint8_t> act(M, 1);
+  std::vector<unsigned long long> hmax(2 * M);
+  for (int64_t m = 0; m < M; ++m) {
+    iters[m] = 0;
+    status[m] = KC_SAMPLE_MAXITER;
+  }
+  if (hist) std::fill(hist, hist + M * p.max_iter, 0.0);
+  KC_TRY_HIP(hipMemcpyAsync(active, act.data(), M, hipMemcpyHostToDevice, st));
+  int64_t n_active = M;
+  for (int k = 0; k < p.max_iter && n_active > 0; ++k) {
+    FineArgs fa{a, U, u0, true, k > 0 ? 1 : 0, active, Fv, M};
+    int r = fine_propagate_impl(ctx, p, fa);
+    if (r != KC_OK) rc = r;
+    launch_defect(st, p, a, Fv, U, active, M, D);
+    launch_fft_forward(st, p, D, active, M, spec);
+    r = shifted_solve_impl(ctx, p, a, active, M, spec);
+    if (r != KC_OK) rc = r;
+    KC_TRY_HIP(hipMemsetAsync(maxima, 0, sizeof(unsigned long long) * 2 * M, st));
+    launch_fft_inverse(st, p, spec, active, M, U, true, maxima);
+    KC_TRY_HIP(hipMemcpyAsync(hmax.data(), maxima, sizeof(unsigned long long) * 2 * M,
+                              hipMemcpyDeviceToHost, st));
+    KC_TRY_HIP(hipStreamSynchronize(st));
+    for (int64_t m = 0; m < M; ++m) {
+      if (!act[m]) continue;
+      double cmax, umax;
+      std::memcpy(&cmax, &hmax[2 * m], 8);
+      std::memcpy(&umax, &hmax[2 * m + 1], 8);
+      double delta = cmax / (umax > 0 ? umax : 1.0);
+      iters[m] = k + 1;
+      if (hist) hist[m * p.max_iter + k] = delta;
+      if (!std::isfinite(delta)) {
+        status[m] = KC_SAMPLE_NONFINITE;
+        act[m] = 0;
+        --n_active;
+      } else if (delta <= p.tol) {
+        status[m] = KC_SAMPLE_CONVERGED;
+        act[m] = 0;
+        --n_active;
+      }
+    }
+    KC_TRY_HIP(hipMemcpyAsync(active, act.data(), M, hipMemcpyHostToDevice, st));
+  }
+  KC_TRY_HIP(hipStreamSynchronize(st));
+  return rc;
+}
+
+}  // namespace kc
+
+using namespace kc;
+
+namespace {
+
+template <class F>
+int guarded(klecgc_ctx* ctx, F&& f) {
+  if (!ctx) return KC_EINVAL;
+  ctx->err.clear();
+  for (auto& v : ctx->stats) v = 0;
+  try {
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) throw Error{KC_EHIP, std::string("hipSetDevice: ") + hipGetErrorString(e)};
+    return f();
+  } catch (const Error& e) {
+    ctx->err = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    ctx->err = "host allocation failed";
+    return KC_ENOMEM;
+  } catch (const std::exception& e) {
+    ctx->err = e.what();
+    return KC_EINVAL;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* klecgc_version(void) { return "klecgc 0.1 (gfx950)"; }
+
+int klecgc_create(klecgc_ctx** out, int device, void* hip_stream) {
+  if (!out) return KC_EINVAL;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return KC_EHIP;
+  if (hipSetDevice(device) != hipSuccess) return KC_EHIP;
+  auto* c = new (std::nothrow) klecgc_ctx;
+  if (!c) return KC_ENOMEM;
+  c->device = device;
+  c->stream = (hipStream_t)hip_stream;
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
+    c->num_cus = cus;
+  *out = c;
+  return KC_OK;
+}
+
+void klecgc_destroy(klecgc_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  ctx->ws.release();
+  delete ctx;
+}
+
+int klecgc_set_stream(klecgc_ctx* ctx, void* s) {
+  return guarded(ctx, [&] {
+    ctx->stream = (hipStream_t)s;
+    return KC_OK;
+  });
+}
+
+const char* klecgc_last_error(const klecgc_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int klecgc_last_stats(const klecgc_ctx* ctx, int64_t* out8) {
+  if (!ctx || !out8) return KC_EINVAL;
+  for (int i = 0; i < 8; ++i) out8[i] = ctx->stats[i];
+  return KC_OK;
+}
+
+void klecgc_kle_free(klecgc_kle* h) {
+  if (!h) return;
+  (void)hipFree(h->phi);
+  (void)hipFree(h->sqrt_lam);
+  (void)hipFree(h->mean);
+  (void)hipFree(h->W);
+  (void)hipFree(h->lam);
+  delete h;
+}
+
+void klecgc_gpc_free(klecgc_gpc* h) {
+  if (!h) return;
+  (void)hipFree(h->idx);
+  (void)hipFree(h->H);
+  delete h;
+}
+
+int kle_build(klecgc_ctx* ctx, const klecgc_kle_desc* desc, const double* S_dev, int64_t n_t,
+              klecgc_kle** out, int32_t* n_modes) {
+  return guarded(ctx, [&] {
+    KC_REQUIRE(desc && out, KC_EINVAL, "null argument");
+    *out = nullptr;
+    hipStream_t st = ctx->stream;
+    auto* h = new klecgc_kle;
+    h->kind = desc->kind;
+    try {
+      if (desc->kind == KC_KLE_FIELD_EXP) {
+        KC_REQUIRE(desc->dim == 1 || desc->dim == 2, KC_EINVAL, "dim must be 1 or 2");
+        KC_REQUIRE(desc->n >= 1 && desc->d >= 1 && desc->d <= 256, KC_EINVAL, "bad n or d");
+        KC_REQUIRE(desc->corr_len > 0 && desc->sigma >= 0, KC_EINVAL, "bad corr_len or sigma");
+        h->dim = desc->dim;
+        h->n = desc->n;
+        h->d = desc->d;
+        h->nfaces = n_faces(desc->dim, desc->n);
+        std::vector<double> lam, phi;
+        field_kl_host(desc->dim, desc->n, desc->d, desc->corr_len, desc->sigma, lam, phi);
+        std::vector<double> sl(desc->d);
+        for (int k = 0; k < desc->d; ++k) sl[k] = std::sqrt(lam[k]);
+        h->lam_host = lam;
+        KC_TRY_HIP(hipMalloc(&h->phi, sizeof(double) * phi.size()));
+        KC_TRY_HIP(hipMalloc(&h->sqrt_lam, sizeof(double) * sl.size()));
+        KC_TRY_HIP(hipMemcpyAsync(h->phi, phi.data(), sizeof(double) * phi.size(), hipMemcpyHostToDevice, st));
+        KC_TRY_HIP(hipMemcpyAsync(h->sqrt_lam, sl.data(), sizeof(double) * sl.size(), hipMemcpyHostToDevice, st));
+        KC_TRY_HIP(hipStreamSynchronize(st));
+        if (n_modes) *n_modes = desc->d;
+      } else if (desc->kind == KC_KLE_SNAPSHOT) {
+        KC_REQUIRE(S_dev, KC_EINVAL, "S_dev required");
+        KC_REQUIRE(n_t >= 2 && desc->L >= 1, KC_EINVAL, "need n_t >= 2 and L >= 1");
+        KC_REQUIRE(desc->eps_kl >= 0 && desc->eps_kl < 1, KC_EINVAL, "eps_kl must lie in [0, 1)");
+        const int64_t L = desc->L;
+        h->L = L;
+        h->n_t = n_t;
+        double* Sc = nullptr;
+        double* Cd = nullptr;
+        KC_TRY_HIP(hipMalloc(&h->mean, sizeof(double) * L));
+        KC_TRY_HIP(hipMalloc(&Sc, sizeof(double) * L * n_t));
+        KC_TRY_HIP(hipMalloc(&Cd, sizeof(double) * n_t * n_t));
+        launch_col_mean_center(st, S_dev, n_t, L, h->mean, Sc);
+        launch_dgemm_nt(st, n_t, n_t, L, Sc, L, Sc, L, Cd, n_t, 1.0 / (double)n_t);
+        std::vector<double> C((size_t)n_t * n_t), w;
+        KC_TRY_HIP(hipMemcpyAsync(C.data(), Cd, sizeof(double) * C.size(), hipMemcpyDeviceToHost, st));
+        KC_TRY_HIP(hipStreamSynchronize(st));
+        // symmetrise the Gram matrix against summation-order asymmetry
+        for (int64_t i = 0; i < n_t; ++i)
+          for (int64_t j = 0; j < i; ++j) {
+            double v = 0.5 * (C[i * n_t + j] + C[j * n_t + i]);
+            C[i * n_t + j] = C[j * n_t + i] = v;
+          }
+        sym_eig((int)n_t, C, w);
+        for (auto& x : w) x = std::max(x, 0.0);
+        double total = 0.0;
+        for (double x : w) total += x;
+        KC_REQUIRE(total > 0, KC_ERANK, "snapshots have zero variance");
+        int MQ = 0;
+        double cum = 0.0;
+        for (int64_t i = 0; i < n_t; ++i) {
+          cum += w[i];
+          MQ = (int)i + 1;
+          if (cum / total >= 1.0 - desc->eps_kl) break;
+        }
+        int rank = 0;
+        for (int64_t i = 0; i < n_t; ++i)
+          if (w[i] > (double)n_t * 2.220446049250313e-16 * w[0]) ++rank;
+        MQ = std::max(1, std::min(MQ, rank));
+        h->n_modes = MQ;
+        // E [n_t][MQ]; W = E^T S~ / sqrt(n_t)  (= diag(sqrt(lam)) g)
+        std::vector<double> E((size_t)n_t * MQ);
+        h->zeta_train.resize((size_t)n_t * MQ);
+        for (int64_t r = 0; r < n_t; ++r)
+          for (int c = 0; c < MQ; ++c) {
+            E[r * MQ + c] = C[r * n_t + c];
+            h->zeta_train[r * MQ + c] = std::sqrt((double)n_t) * C[r * n_t + c];
+          }
+        double* Ed = nullptr;
+        KC_TRY_HIP(hipMalloc(&Ed, sizeof(double) * E.size()));
+        KC_TRY_HIP(hipMalloc(&h->W, sizeof(double) * MQ * L));
+        KC_TRY_HIP(hipMalloc(&h->lam, sizeof(double) * MQ));
+        KC_TRY_HIP(hipMemcpyAsync(Ed, E.data(), sizeof(double) * E.size(), hipMemcpyHostToDevice, st));
+        KC_TRY_HIP(hipMemcpyAsync(h->lam, w.data(), sizeof(double) * MQ, hipMemcpyHostToDevice, st));
+        launch_dgemm_tn(st, MQ, L, n_t, Ed, MQ, Sc, L, h->W, L, 1.0 / std::sqrt((double)n_t));
+        KC_TRY_HIP(hipStreamSynchronize(st));
+        (void)hipFree(Ed);
+        (void)hipFree(Sc);
+        (void)hipFree(Cd);
+        h->lam_host.assign(w.begin(), w.begin() + MQ);
+        if (n_modes) *n_modes = MQ;
+      } else {
+        throw Error{KC_EINVAL, "unknown KL kind"};
+      }
+    } catch (...) {
+      klecgc_kle_free(h);
+      throw;
+    }
+    *out = h;
+    return KC_OK;
+  });
+}
+
+int kle_synthesize(klecgc_ctx* ctx, const klecgc_kle* f, const double* xi_dev, int64_t M, double* a_dev) {
+  return guarded(ctx, [&] {
+    KC_REQUIRE(f && xi_dev && a_dev, KC_EINVAL, "null argument");
+    KC_REQUIRE(f->kind == KC_KLE_FIELD_EXP, KC_EINVAL, "handle is not a FIELD_EXP KL");
+    KC_REQUIRE(M >= 1, KC_EINVAL, "M must be >= 1");
+    launch_field_synth(ctx->stream, f->phi, f->sqrt_lam, f->d, f->nfaces, xi_dev, M, a_dev);
+    return KC_OK;
+  });
+}
+
+int kle_export(klecgc_ctx* ctx, const klecgc_kle* h, double* mean_dev, double* W_dev, double* lam_dev) {
+  return guarded(ctx, [&] {
+    KC_REQUIRE(h && h->kind == KC_KLE_SNAPSHOT, KC_EINVAL, "handle is not a SNAPSHOT KL");
+    hipStream_t st = ctx->stream;
+    if (mean_dev) KC_TRY_HIP(hipMemcpyAsync(mean_dev, h->mean, sizeof(double) * h->L, hipMemcpyDeviceToDevice, st));
+    if (W_dev)
+      KC_TRY_HIP(hipMemcpyAsync(W_dev, h->W, sizeof(double) * h->L * h->n_modes, hipMemcpyDeviceToDevice, st));
+    if (lam_dev) KC_TRY_HIP(hipMemcpyAsync(lam_dev, h->lam, sizeof(double) * h->n_modes, hipMemcpyDeviceToDevice, st));
+    return KC_OK;
+  });
+}
+
+int gpc_fit(klecgc_ctx* ctx, const klecgc_kle* snap, const double* xi_train_dev, int64_t n_t,
+            int32_t d, int32_t p, klecgc_gpc** out, int32_t* P) {
+  return guarded(ctx, [&] {
+    KC_REQUIRE(snap && xi_train_dev && out, KC_EINVAL, "null argument");
+    KC_REQUIRE(snap->kind == KC_KLE_SNAPSHOT, KC_EINVAL, "handle is not a SNAPSHOT KL");
+    KC_REQUIRE(n_t == snap->n_t, KC_EINVAL, "n_t differs from the snapshot count");
+    KC_REQUIRE(d >= 1 && p >= 0 && p <= 16, KC_EINVAL, "bad d or p");
+    *out = nullptr;
+    hipStream_t st = ctx->stream;
+    auto idx = index_set(d, p);
+    const int Pn = (int)idx.size();
+    if (P) *P = Pn;
+    KC_REQUIRE(n_t >= Pn, KC_ERANK, "n_t < P: least-squares problem under-determined");
+    auto* g = new klecgc_gpc;
+    try {
+      g->d = d;
+      g->p = p;
+      g->P = Pn;
+      g->n_modes = snap->n_modes;
+      g->L = snap->L;
+      g->kl = snap;
+      g->mean = snap->mean;
+      g->W = snap->W;
+      std::vector<int32_t> flat((size_t)Pn * d);
+      for (int i = 0; i < Pn; ++i)
+        for (int l = 0; l < d; ++l) flat[(size_t)i * d + l] = idx[i][l];
+      KC_TRY_HIP(hipMalloc(&g->idx, sizeof(int32_t) * flat.size()));
+      KC_TRY_HIP(hipMemcpyAsync(g->idx, flat.data(), sizeof(int32_t) * flat.size(), hipMemcpyHostToDevice, st));
+      double* Bd = (double*)ctx->ws.get(WS_GEMM_A, sizeof(double) * n_t * Pn);
+      launch_hermite(st, xi_train_dev, n_t, d, g->idx, Pn, p, Bd);
+      std::vector<double> B((size_t)n_t * Pn);
+      KC_TRY_HIP(hipMemcpyAsync(B.data(), Bd, sizeof(double) * B.size(), hipMemcpyDeviceToHost, st));
+      KC_TRY_HIP(hipStreamSynchronize(st));
+      std::vector<double> Dm = snap->zeta_train, X;
+      int r = householder_lstsq((int)n_t, Pn, snap->n_modes, B, Dm, X);
+      KC_REQUIRE(r == KC_OK, KC_ERANK, "gPC design matrix is rank-deficient");
+      KC_TRY_HIP(hipMalloc(&g->H, sizeof(double) * X.size()));
+      KC_TRY_HIP(hipMemcpyAsync(g->H, X.data(), sizeof(double) * X.size(), hipMemcpyHostToDevice, st));
+      KC_TRY_HIP(hipStreamSynchronize(st));
+    } catch (...) {
+      klecgc_gpc_free(g);
+      throw;
+    }
+    *out = g;
+    return KC_OK;
+  });
+}
+
+int gpc_predict(klecgc_ctx* ctx, const klecgc_gpc* g, const double* xi_dev, int64_t M, double* U0_dev) {
+  return guarded(ctx, [&] {
+    KC_REQUIRE(g && xi_dev && U0_dev, KC_EINVAL, "null argument");
+    KC_REQUIRE(M >= 1, KC_EINVAL, "M must be >= 1");
+    return gpc_predict_impl(ctx, g, xi_dev, M, U0_dev);
+  });
+}
+
+int fine_propagate(klecgc_ctx* ctx, const klecgc_problem* prob, const double* a_dev,
+                   const double* start_dev, int64_t M, double* end_dev) {
+  return guarded(ctx, [&] {
+    KC_REQUIRE(prob && a_dev && start_dev && end_dev, KC_EINVAL, "null argument");
+    KC_REQUIRE(M >= 1, KC_EINVAL, "M must be >= 1");
+    validate_problem(*prob);
+    KC_REQUIRE(start_dev != end_dev, KC_EINVAL, "start_dev and end_dev may not alias");
+    FineArgs fa{a_dev, start_dev, nullptr, false, 0, nullptr, end_dev, M};
+    return fine_propagate_impl(ctx, *prob, fa);
+  });
+}
+
+int cgc_diag_solve(klecgc_ctx* ctx, const klecgc_problem* prob, const double* a_dev, const double* r_dev,
+                   int64_t M, double* u_dev) {
+  return guarded(ctx, [&] {
+    KC_REQUIRE(prob && a_dev && r_dev && u_dev, KC_EINVAL, "null argument");
+    KC_REQUIRE(M >= 1, KC_EINVAL, "M must be >= 1");
+    validate_problem(*prob);
+    const int64_t Nx = n_unknowns(*prob);
+    const int K = prob->N / 2 + 1;
+    double* spec = (double*)ctx->ws.get(WS_SPEC, sizeof(double) * 2 * M * K * Nx);
+    launch_fft_forward(ctx->stream, *prob, r_dev, nullptr, M, spec);
+    int rc = shifted_solve_impl(ctx, *prob, a_dev, nullptr, M, spec);
+    launch_fft_inverse(ctx->stream, *prob, spec, nullptr, M, u_dev, false, nullptr);
+    return rc;
+  });
+}
+
+int coarse_propagate(klecgc_ctx* ctx, const klecgc_problem* prob, const double* a_dev, const double* u0_dev,
+                     int64_t M, double* U_dev) {
+  return guarded(ctx, [&] {
+    KC_REQUIRE(prob && a_dev && U_dev, KC_EINVAL, "null argument");
+    KC_REQUIRE(M >= 1, KC_EINVAL, "M must be >= 1");
+    validate_problem(*prob);
+    return coarse_sweep_impl(ctx, *prob, a_dev, u0_dev, M, U_dev);
+  });
+}
+
+int parareal_solve(klecgc_ctx* ctx, const klecgc_problem* prob, const double* a_dev, const double* u0_dev,
+                   int64_t M, int32_t init, const double* init_dev, const klecgc_gpc* gpc,
+                   const double* xi_dev, double* U_dev, int32_t* iters_host, int32_t* status_host,
+                   double* delta_hist_host) {
+  return guarded(ctx, [&] {
+    KC_REQUIRE(prob && a_dev && U_dev && iters_host && status_host, KC_EINVAL, "null argument");
+    KC_REQUIRE(M >= 1, KC_EINVAL, "M must be >= 1");
+    validate_problem(*prob);
+    return parareal_impl(ctx, *prob, a_dev, u0_dev, M, init, init_dev, gpc, xi_dev, U_dev, iters_host,
+                         status_host, delta_hist_host);
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,169 @@
+// Internal definitions shared by the KLE-CGC library sources (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "klecgc.h"
+
+namespace kc {
+
+// ---- error plumbing ---------------------------------------------------------
+struct Error {
+  int code;
+  std::string msg;
+};
+
+#define KC_TRY_HIP(expr)                                                                  \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      throw ::kc::Error{KC_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)};      \
+  } while (0)
+
+#define KC_REQUIRE(cond, code, text)                                                      \
+  do {                                                                                    \
+    if (!(cond)) throw ::kc::Error{(code), std::string(text)};                            \
+  } while (0)
+
+#define KC_LAUNCH_CHECK() KC_TRY_HIP(hipGetLastError())
+
+// ---- device workspace ---------------------------------------------------------
+// Grow-only device buffers keyed by slot; freed when the context is destroyed.
+struct Workspace {
+  std::vector<void*> ptr;
+  std::vector<size_t> cap;
+  void* get(int slot, size_t bytes);
+  void release();
+};
+
+enum WsSlot {
+  WS_FACTORS = 0,   // per-sample solver tables
+  WS_FSCALED,       // float32 Jacobi-scaled coefficients
+  WS_DINV,          // float64 D^{-1/2}
+  WS_KRYLOV,        // streaming Krylov vectors
+  WS_FINE,          // parareal: F(U) buffer
+  WS_DEFECT,        // parareal: defect buffer
+  WS_SPEC,          // spectral (complex) buffer
+  WS_SMALL,         // small per-sample arrays (flags, maxima)
+  WS_START,         // start buffer for the coarse sweep
+  WS_GEMM_A,
+  WS_GEMM_B,
+  WS_STATUS,
+  WS_COUNT
+};
+
+}  // namespace kc
+
+struct klecgc_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  kc::Workspace ws;
+  int num_cus = 256;
+  // counters of the last call: [0..3] fine solves (Krylov iterations, refinement passes,
+  // implicit steps, max iterations of one solve), [4..7] the same for the shifted solves
+  int64_t stats[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+};
+
+struct klecgc_kle {
+  int32_t kind = 0;
+  // FIELD_EXP
+  int32_t dim = 0, n = 0, d = 0;
+  int64_t nfaces = 0;
+  double* phi = nullptr;      // [d][Fc] device
+  double* sqrt_lam = nullptr; // [d] device
+  std::vector<double> lam_host;
+  // SNAPSHOT
+  int64_t L = 0, n_t = 0;
+  int32_t n_modes = 0;
+  double* mean = nullptr;     // [L]
+  double* W = nullptr;        // [M_Q][L]  rows sqrt(lam_k) g_k
+  double* lam = nullptr;      // [M_Q]
+  std::vector<double> zeta_train;  // [n_t][M_Q] host (training coefficients)
+};
+
+struct klecgc_gpc {
+  int32_t d = 0, p = 0, P = 0, n_modes = 0;
+  int64_t L = 0;
+  int32_t* idx = nullptr;     // [P][d] device multi-indices
+  double* H = nullptr;        // [P][M_Q] device
+  const klecgc_kle* kl = nullptr;
+  double* mean = nullptr;     // [L] device (copy of the KL mean)
+  double* W = nullptr;        // [M_Q][L] device (copy of sqrt(lam) g rows)
+};
+
+namespace kc {
+
+// Device status block: int flag at byte 0, unsigned long long counters from byte 8.
+constexpr size_t kStatusBytes = 256;
+struct DevStatus {
+  int* flag;
+  unsigned long long* cnt;
+};
+DevStatus status_block(klecgc_ctx* ctx);
+void status_reset(klecgc_ctx* ctx, const DevStatus& st);
+// copies the block to the host, adds the counters into ctx->stats[base..base+3]; returns flag
+int status_collect(klecgc_ctx* ctx, const DevStatus& st, int base);
+
+inline int64_t n_unknowns(const klecgc_problem& p) { return p.dim == 1 ? p.n : (int64_t)p.n * p.n; }
+inline int64_t n_faces(int dim, int n) { return dim == 1 ? n + 1 : 2LL * n * (n + 1); }
+
+void validate_problem(const klecgc_problem& p);
+
+// ---- kernels' host launchers -------------------------------------------------
+// field
+void launch_field_synth(hipStream_t s, const double* phi, const double* sqrt_lam, int d,
+                        int64_t nfaces, const double* xi, int64_t M, double* a);
+// fine propagator
+// start rows: if start_shift, the start of (m, s) is u0[m] (or 0) for s == 0 and
+// U[m][s-1] otherwise (the parareal layout); else start[m][s].
+struct FineArgs {
+  const double* a;
+  const double* start;
+  const double* u0;       // used with start_shift (nullable = zero)
+  bool start_shift;
+  int skip_first;         // skip slice 0 (iteration-invariant F(u0))
+  const uint8_t* active;  // [M] nullable
+  double* out;
+  int64_t M;
+};
+int fine_propagate_impl(klecgc_ctx* ctx, const klecgc_problem& p, const FineArgs& fa);
+
+// coarse grid correction pieces
+void launch_defect(hipStream_t s, const klecgc_problem& p, const double* a, const double* Fv,
+                   const double* U, const uint8_t* active, int64_t M, double* D);
+void launch_fft_forward(hipStream_t s, const klecgc_problem& p, const double* r,
+                        const uint8_t* active, int64_t M, double* spec);
+void launch_fft_inverse(hipStream_t s, const klecgc_problem& p, const double* spec,
+                        const uint8_t* active, int64_t M, double* u, bool accumulate,
+                        unsigned long long* maxima);
+int shifted_solve_impl(klecgc_ctx* ctx, const klecgc_problem& p, const double* a,
+                       const uint8_t* active, int64_t M, double* spec);
+int coarse_sweep_impl(klecgc_ctx* ctx, const klecgc_problem& p, const double* a,
+                      const double* u0, int64_t M, double* U);
+
+// dense float64 GEMM: C[m][n] = beta_bias[n] + sum_k A[m][k] B[k][n]  (row-major,
+// lda/ldb/ldc leading dimensions); bias nullable.
+void launch_dgemm(hipStream_t s, int64_t Mr, int64_t Nc, int64_t K, const double* A, int64_t lda,
+                  const double* B, int64_t ldb, double* C, int64_t ldc, const double* bias,
+                  double alpha);
+// C = alpha * A^T-style products used by the snapshot KL
+void launch_dgemm_tn(hipStream_t s, int64_t Mr, int64_t Nc, int64_t K, const double* A,
+                     int64_t lda, const double* B, int64_t ldb, double* C, int64_t ldc,
+                     double alpha);
+void launch_hermite(hipStream_t s, const double* xi, int64_t M, int d, const int32_t* idx, int P,
+                    int pmax, double* Psi);
+void launch_col_mean_center(hipStream_t s, const double* S, int64_t n_t, int64_t L, double* mean,
+                            double* Sc);
+
+// host linear algebra
+void sym_eig(int n, std::vector<double>& A, std::vector<double>& w);   // A -> eigenvectors (cols)
+int householder_lstsq(int m, int n, int nrhs, std::vector<double>& B, std::vector<double>& D,
+                      std::vector<double>& X);
+
+}  // namespace kc

@@ -1,0 +1,641 @@
+// Fine propagator F (Algorithm 2 step 1): J backward-Euler steps per (sample, slice).
+//
+// One step of size tau solves (I + tau A) w_new = w + tau f (Section 3.1; Section 5 uses
+// backward Euler for F and G).  Three implementations:
+//  * 1D: direct tridiagonal (Thomas) solves in float64, one thread per system, the
+//    factorisation tables built once per sample (the matrix is the same for every slice).
+//  * 2D, float64: Jacobi-PCG, one work-group per system streaming its vectors.
+//  * 2D, float32-refined: one work-group of 8 waves per system keeps the whole system
+//    on the CU.  The float32 Jacobi-PCG state (x, r, p, q) and the float32 scaled
+//    stencil coefficients live in registers; neighbours cross lanes with shuffles and
+//    cross waves through LDS halo rows.  Each step is refined in float64: the residual
+//    of the step equation is formed in float64 with float64 coefficients, float32 PCG
+//    solves for a correction, the correction is added in float64 and the float64
+//    residual is updated, until it meets inner_rtol * (|w|_inf + tau |f|).
+#include <cmath>
+
+#include "common.h"
+#include "reduce.h"
+
+namespace kc {
+
+namespace {
+
+constexpr int kStreamThreads = 256;
+constexpr int kMaxRefinePasses = 12;
+#ifndef KC_RES128_NW
+#define KC_RES128_NW 8
+#endif
+
+struct StartRef {
+  const double* start;
+  const double* u0;
+  bool shift;
+  __device__ __forceinline__ const double* row(int64_t m, int s, int N, int64_t Nx) const {
+    if (!shift) return start + ((int64_t)m * N + s) * Nx;
+    if (s == 0) return u0 ? u0 + m * Nx : nullptr;
+    return start + ((int64_t)m * N + (s - 1)) * Nx;
+  }
+};
+
+// ------------------------------------------------------------------------- 1D
+__global__ void tri_factor_kernel(const double* __restrict__ a, int n, double c, int64_t M,
+                                  double* __restrict__ tab) {
+  int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= M) return;
+  const double* af = a + m * (n + 1);
+  double* sub = tab + m * 3 * n;
+  double* cp = sub + n;
+  double* inv = cp + n;
+  double prev = 0.0;
+  for (int i = 0; i < n; ++i) {
+    double aw = af[i], ae = af[i + 1];
+    double diag = 1.0 + c * (aw + ae);
+    double lo = (i > 0) ? -c * aw : 0.0;
+    double up = (i < n - 1) ? -c * ae : 0.0;
+    double iv = 1.0 / (diag - lo * prev);
+    sub[i] = lo;
+    inv[i] = iv;
+    cp[i] = up * iv;
+    prev = cp[i];
+  }
+}
+
+__global__ void fine1d_kernel(const double* __restrict__ tab, int n, int J, double tauf,
+                              StartRef sr, double* __restrict__ out, int64_t M, int N,
+                              int skip_first, const uint8_t* __restrict__ active) {
+  int64_t sys = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t m = sys / N;
+  int s = (int)(sys % N);
+  if (m >= M) return;
+  if (active && !active[m]) return;
+  if (skip_first && s == 0) return;
+  const double* src = sr.row(m, s, N, n);
+  double* w = out + sys * n;
+  for (int i = 0; i < n; ++i) w[i] = src ? src[i] : 0.0;
+  const double* sub = tab + m * 3 * n;
+  const double* cp = sub + n;
+  const double* inv = cp + n;
+  for (int j = 0; j < J; ++j) {
+    double prev = 0.0;
+    for (int i = 0; i < n; ++i) {
+      double d = (w[i] + tauf - sub[i] * prev) * inv[i];
+      w[i] = d;
+      prev = d;
+    }
+    for (int i = n - 2; i >= 0; --i) w[i] -= cp[i] * w[i + 1];
+  }
+}
+
+// --------------------------------------------------------------- 2D helpers
+struct Grid2 {
+  int n;
+  int64_t nx;   // number of x-faces, n(n+1)
+  __device__ __forceinline__ int64_t fW(int i, int j) const { return (int64_t)j * (n + 1) + i; }
+  __device__ __forceinline__ int64_t fE(int i, int j) const { return (int64_t)j * (n + 1) + i + 1; }
+  __device__ __forceinline__ int64_t fS(int i, int j) const { return nx + (int64_t)j * n + i; }
+  __device__ __forceinline__ int64_t fN(int i, int j) const { return nx + (int64_t)(j + 1) * n + i; }
+};
+
+// D^{-1/2} of M = I + c h^2 A (c = tau / h^2): d_p = 1 + c * (sum of the face coefficients of p)
+__global__ void dinv_kernel(const double* __restrict__ a, int n, double c, int64_t M,
+                            double* __restrict__ dinv) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t m = blockIdx.y;
+  int64_t Nx = (int64_t)n * n;
+  if (p >= Nx || m >= M) return;
+  Grid2 g{n, (int64_t)n * (n + 1)};
+  int i = (int)(p % n), j = (int)(p / n);
+  const double* af = a + m * 2 * g.nx;
+  double d = 1.0 + c * (af[g.fW(i, j)] + af[g.fE(i, j)] + af[g.fS(i, j)] + af[g.fN(i, j)]);
+  dinv[m * Nx + p] = 1.0 / sqrt(d);
+}
+
+// float32 coefficients of the symmetrically Jacobi-scaled operator D^{-1/2} M D^{-1/2}:
+// s_f = c a_f / sqrt(d_L d_R) on interior faces, 0 on boundary faces.
+__global__ void scaled_faces_kernel(const double* __restrict__ a, const double* __restrict__ dinv,
+                                    int n, double c, int64_t M, float* __restrict__ sf) {
+  int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t m = blockIdx.y;
+  int64_t nx = (int64_t)n * (n + 1);
+  int64_t Fc = 2 * nx;
+  if (f >= Fc || m >= M) return;
+  int64_t Nx = (int64_t)n * n;
+  const double* dv = dinv + m * Nx;
+  float out = 0.f;
+  if (f < nx) {
+    int j = (int)(f / (n + 1)), fi = (int)(f % (n + 1));
+    if (fi >= 1 && fi <= n - 1)
+      out = (float)(c * a[m * Fc + f] * dv[(int64_t)j * n + fi - 1] * dv[(int64_t)j * n + fi]);
+  } else {
+    int64_t g = f - nx;
+    int fj = (int)(g / n), i = (int)(g % n);
+    if (fj >= 1 && fj <= n - 1)
+      out = (float)(c * a[m * Fc + f] * dv[(int64_t)(fj - 1) * n + i] * dv[(int64_t)fj * n + i]);
+  }
+  sf[m * Fc + f] = out;
+}
+
+// Stopping target for the float64 residual of one implicit step: tol relative to the
+// state size, but never below the rounding floor of forming that residual in float64,
+// about eps * max_p d_p * |w|_inf (d_p the diagonal of I + tau A).
+__device__ __forceinline__ double residual_target(double tol, double wmax, double tauf, double dmax) {
+  return tol * (wmax + fabs(tauf)) + 8.0 * 2.220446049250313e-16 * dmax * wmax;
+}
+
+// (M v)_p - v_p = c * sum_faces a_f (v_p - v_q), float64, v read from global memory.
+__device__ __forceinline__ double stencil64(const double* __restrict__ af, const double* __restrict__ v,
+                                            const Grid2& g, int i, int j) {
+  const int n = g.n;
+  int64_t p = (int64_t)j * n + i;
+  double vp = v[p];
+  double vw = i > 0 ? v[p - 1] : 0.0;
+  double ve = i < n - 1 ? v[p + 1] : 0.0;
+  double vs = j > 0 ? v[p - n] : 0.0;
+  double vn = j < n - 1 ? v[p + n] : 0.0;
+  return af[g.fW(i, j)] * (vp - vw) + af[g.fE(i, j)] * (vp - ve) + af[g.fS(i, j)] * (vp - vs) +
+         af[g.fN(i, j)] * (vp - vn);
+}
+
+// --------------------------------------------------- 2D streaming float64 PCG
+// One work-group per (sample, slice) system; x is the state row of `out`, r/p/q live
+// in per-system scratch.  Jacobi preconditioner z = d^{-1} r (d^{-1} = dinv^2).
+__global__ __launch_bounds__(kStreamThreads) void fine2d_pcg64_kernel(
+    const double* __restrict__ a, const double* __restrict__ dinv, int n, double c, double tauf,
+    int J, double tol, int maxit, StartRef sr, double* __restrict__ out, double* __restrict__ scr,
+    int64_t M, int N, int skip_first, const uint8_t* __restrict__ active, int* __restrict__ flag,
+    unsigned long long* __restrict__ cnt) {
+  __shared__ double slots[3 * (kStreamThreads / 64)];
+  unsigned long long tot_it = 0, max_it = 0;
+  const int64_t sys = blockIdx.x;
+  const int64_t m = sys / N;
+  const int s = (int)(sys % N);
+  if (active && !active[m]) return;
+  if (skip_first && s == 0) return;
+  const int64_t Nx = (int64_t)n * n;
+  Grid2 g{n, (int64_t)n * (n + 1)};
+  const double* af = a + m * 2 * g.nx;
+  const double* dv = dinv + m * Nx;
+  double* x = out + sys * Nx;
+  double* R = scr + sys * 3 * Nx;
+  double* P = R + Nx;
+  double* Q = P + Nx;
+  const double* src = sr.row(m, s, N, Nx);
+  double dmx[1] = {0.0};
+  const bool mxd[1] = {true};
+  for (int64_t p = threadIdx.x; p < Nx; p += blockDim.x) {
+    x[p] = src ? src[p] : 0.0;
+    dmx[0] = nanmax(dmx[0], 1.0 / (dv[p] * dv[p]));
+  }
+  block_reduce<1>(dmx, mxd, slots);
+  const double dmax = dmx[0];
+  for (int step = 0; step < J; ++step) {
+    // r = (x + tau f) - M x, initial guess x (the previous state)
+    double acc[3] = {0.0, 0.0, 0.0};
+    const bool mx3[3] = {false, true, true};
+    for (int64_t p = threadIdx.x; p < Nx; p += blockDim.x) {
+      int i = (int)(p % n), j = (int)(p / n);
+      double r = tauf - c * stencil64(af, x, g, i, j);
+      double z = r * dv[p] * dv[p];
+      R[p] = r;
+      P[p] = z;
+      acc[0] += r * z;
+      acc[1] = nanmax(acc[1], fabs(r));
+      acc[2] = nanmax(acc[2], fabs(x[p]));
+    }
+    block_reduce<3>(acc, mx3, slots);
+    double rz = acc[0], rmax = acc[1];
+    const double target = residual_target(tol, acc[2], tauf, dmax);
+    int it = 0;
+    while (rmax > target && it < maxit) {
+      double pq[1] = {0.0};
+      const bool mx1[1] = {false};
+      for (int64_t p = threadIdx.x; p < Nx; p += blockDim.x) {
+        int i = (int)(p % n), j = (int)(p / n);
+        double q = P[p] + c * stencil64(af, P, g, i, j);
+        Q[p] = q;
+        pq[0] += P[p] * q;
+      }
+      block_reduce<1>(pq, mx1, slots);
+      const double alpha = rz / pq[0];
+      double acc2[2] = {0.0, 0.0};
+      const bool mx2[2] = {false, true};
+      for (int64_t p = threadIdx.x; p < Nx; p += blockDim.x) {
+        x[p] += alpha * P[p];
+        double r = R[p] - alpha * Q[p];
+        R[p] = r;
+        acc2[0] += r * r * dv[p] * dv[p];
+        acc2[1] = nanmax(acc2[1], fabs(r));
+      }
+      block_reduce<2>(acc2, mx2, slots);
+      const double beta = acc2[0] / rz;
+      rz = acc2[0];
+      rmax = acc2[1];
+      for (int64_t p = threadIdx.x; p < Nx; p += blockDim.x) P[p] = R[p] * dv[p] * dv[p] + beta * P[p];
+      __syncthreads();
+      ++it;
+    }
+    if (rmax > target && threadIdx.x == 0) atomicOr(flag, 1);
+    tot_it += it;
+    max_it = it > (int)max_it ? it : max_it;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    atomicAdd(&cnt[0], tot_it);
+    atomicAdd(&cnt[1], (unsigned long long)J);
+    atomicAdd(&cnt[2], (unsigned long long)J);
+    atomicMax(&cnt[3], max_it);
+  }
+}
+
+// ---------------------------------------------- 2D resident float32-refined PCG
+// Tile ownership: wave w of NW owns grid rows [w*RPW, (w+1)*RPW); lane l owns columns
+// [l*CPL, (l+1)*CPL).  Padded unknowns (outside the n x n grid) carry zero
+// coefficients and stay zero.
+template <int NW, int CPL, int RPW>
+struct Resident {
+  static constexpr int ROWW = 64 * CPL;   // halo row width per wave
+
+  // Q = P - sum_f s_f P_nbr (scaled operator with unit diagonal); returns the lane's P.Q.
+  // EW[s][t] is the coefficient of the face west of column t, NS[s][t] that of the face
+  // south of row s.  The faces east of the lane's last column and north of the wave's
+  // last row belong to the neighbouring lane / wave, which supplies the products
+  // coefficient * value: across lanes by a shuffle, across waves in the `top` halo.
+  static __device__ __forceinline__ float matvec(const float (&P)[RPW][CPL], float (&Q)[RPW][CPL],
+                                                 const float (&EW)[RPW][CPL],
+                                                 const float (&NS)[RPW][CPL],
+                                                 const float* top, const float* bot, int lane,
+                                                 int wave) {
+    float pq = 0.f;
+#pragma unroll
+    for (int s = 0; s < RPW; ++s) {
+      float wv = __shfl_up(P[s][CPL - 1], 1, 64);
+      float ep = __shfl_down(EW[s][0] * P[s][0], 1, 64);
+      if (lane == 0) wv = 0.f;
+      if (lane == 63) ep = 0.f;
+#pragma unroll
+      for (int t = 0; t < CPL; ++t) {
+        float left = (t == 0) ? wv : P[s][t - 1];
+        float q = P[s][t];
+        q = fmaf(-EW[s][t], left, q);
+        if (t == CPL - 1)
+          q -= ep;
+        else
+          q = fmaf(-EW[s][t + 1], P[s][t + 1], q);
+        float down;
+        if (s == 0)
+          down = (wave > 0) ? bot[(wave - 1) * ROWW + lane * CPL + t] : 0.f;
+        else
+          down = P[s - 1][t];
+        q = fmaf(-NS[s][t], down, q);
+        if (s == RPW - 1)
+          q -= (wave < NW - 1) ? top[(wave + 1) * ROWW + lane * CPL + t] : 0.f;
+        else
+          q = fmaf(-NS[s + 1][t], P[s + 1][t], q);
+        Q[s][t] = q;
+        pq = fmaf(P[s][t], q, pq);
+      }
+    }
+    return pq;
+  }
+
+  // top: coefficient of the face south of row 0 times the row-0 value (the wave above
+  // needs it as its northern term); bot: the last row's values.
+  static __device__ __forceinline__ void store_halo(const float (&V)[RPW][CPL],
+                                                    const float (&NS)[RPW][CPL], float* top,
+                                                    float* bot, int lane, int wave) {
+#pragma unroll
+    for (int t = 0; t < CPL; ++t) {
+      top[wave * ROWW + lane * CPL + t] = NS[0][t] * V[0][t];
+      bot[wave * ROWW + lane * CPL + t] = V[RPW - 1][t];
+    }
+  }
+};
+
+__device__ __forceinline__ float block_sum_f(float v, float* slots, int lane, int wave, int nw) {
+  v = wave_sum(v);
+  if (lane == 0) slots[wave] = v;
+  __syncthreads();
+  float acc = slots[0];
+  for (int w = 1; w < nw; ++w) acc += slots[w];
+  return acc;
+}
+
+// LDS: xs[n*n] float32 staging tile of the whole system, halo rows, reduction slots.
+template <int NW, int CPL, int RPW>
+__global__ __launch_bounds__(64 * NW) void fine2d_resident_kernel(
+    const double* __restrict__ a, const float* __restrict__ sf, const double* __restrict__ dinv,
+    int n, double c, double tauf, int J, double tol, float pcg_rtol, int maxit, StartRef sr,
+    double* __restrict__ out, double* __restrict__ resbuf, int64_t M, int N, int skip_first,
+    const uint8_t* __restrict__ active, int* __restrict__ flag, unsigned long long* __restrict__ cnt) {
+  using RS = Resident<NW, CPL, RPW>;
+  unsigned long long tot_it = 0, tot_pass = 0, max_it = 0;
+  extern __shared__ float xs[];                       // [n*n]
+  __shared__ float top[NW * RS::ROWW];
+  __shared__ float bot[NW * RS::ROWW];
+  __shared__ float fslots[2][NW];
+  __shared__ double dslots[4 * NW];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t sys = blockIdx.x;
+  const int64_t m = sys / N;
+  const int s = (int)(sys % N);
+  if (active && !active[m]) return;
+  if (skip_first && s == 0) return;
+  const int64_t Nx = (int64_t)n * n;
+  Grid2 g{n, (int64_t)n * (n + 1)};
+  const int64_t Fc = 2 * g.nx;
+  const double* af = a + m * Fc;
+  const float* sfm = sf + m * Fc;
+  const double* dv = dinv + m * Nx;
+  double* w = out + sys * Nx;
+  double* res = resbuf + sys * Nx;
+  const int j0 = wave * RPW;
+  const int i0 = lane * CPL;
+
+  // scaled coefficients into registers (0 on boundary faces and outside the grid)
+  float EW[RPW][CPL];
+  float NS[RPW][CPL];
+#pragma unroll
+  for (int r = 0; r < RPW; ++r) {
+    int j = j0 + r;
+#pragma unroll
+    for (int t = 0; t < CPL; ++t) {
+      int col = i0 + t;
+      EW[r][t] = (j < n && col >= 1 && col <= n - 1) ? sfm[(int64_t)j * (n + 1) + col] : 0.f;
+      NS[r][t] = (col < n && j >= 1 && j <= n - 1) ? sfm[g.nx + (int64_t)j * n + col] : 0.f;
+    }
+  }
+
+  const double* src = sr.row(m, s, N, Nx);
+  double dmx[1] = {0.0};
+  const bool mxd[1] = {true};
+  for (int64_t p = threadIdx.x; p < Nx; p += blockDim.x) {
+    w[p] = src ? src[p] : 0.0;
+    dmx[0] = nanmax(dmx[0], 1.0 / (dv[p] * dv[p]));
+  }
+  block_reduce<1>(dmx, mxd, dslots);   // also orders the copy before the first stencil
+  const double dmax = dmx[0];
+
+  float X[RPW][CPL], R[RPW][CPL], P[RPW][CPL], Q[RPW][CPL];
+  bool fail = false;
+
+  for (int step = 0; step < J; ++step) {
+    // float64 residual of the increment equation: M e = tau f - tau A w
+    double acc[2] = {0.0, 0.0};
+    const bool mx[2] = {true, true};
+#pragma unroll 1
+    for (int r = 0; r < RPW; ++r) {
+      int j = j0 + r;
+      if (j >= n) break;
+#pragma unroll 1
+      for (int t = 0; t < CPL; ++t) {
+        int i = i0 + t;
+        if (i < n) {
+          int64_t p = (int64_t)j * n + i;
+          double rv = tauf - c * stencil64(af, w, g, i, j);
+          res[p] = rv;
+          acc[0] = nanmax(acc[0], fabs(rv));
+          acc[1] = nanmax(acc[1], fabs(w[p]));
+        }
+      }
+    }
+    block_reduce<2>(acc, mx, dslots);
+    double rmax = acc[0];
+    const double target = residual_target(tol, acc[1], tauf, dmax);
+    int pass = 0;
+    while (rmax > target && pass < kMaxRefinePasses) {
+      // scaled right-hand side D^{-1/2} res, staged through LDS
+#pragma unroll 1
+      for (int r = 0; r < RPW; ++r) {
+        int j = j0 + r;
+        if (j >= n) break;
+#pragma unroll 1
+        for (int t = 0; t < CPL; ++t) {
+          int i = i0 + t;
+          if (i < n) {
+            int64_t p = (int64_t)j * n + i;
+            xs[p] = (float)(dv[p] * res[p]);
+          }
+        }
+      }
+      __syncthreads();
+      float rr = 0.f;
+#pragma unroll
+      for (int r = 0; r < RPW; ++r) {
+        int j = j0 + r;
+#pragma unroll
+        for (int t = 0; t < CPL; ++t) {
+          int i = i0 + t;
+          float v = (j < n && i < n) ? xs[j * n + i] : 0.f;
+          R[r][t] = v;
+          P[r][t] = v;
+          X[r][t] = 0.f;
+          rr = fmaf(v, v, rr);
+        }
+      }
+      rr = block_sum_f(rr, fslots[0], lane, wave, NW);
+      const float stop = pcg_rtol * pcg_rtol * rr;
+      int it = 0;
+      while (rr > stop && it < maxit) {
+        RS::store_halo(P, NS, top, bot, lane, wave);
+        __syncthreads();
+        float pq = RS::matvec(P, Q, EW, NS, top, bot, lane, wave);
+        pq = block_sum_f(pq, fslots[0], lane, wave, NW);
+        const float alpha = rr / pq;
+        float rn = 0.f;
+#pragma unroll
+        for (int r = 0; r < RPW; ++r)
+#pragma unroll
+          for (int t = 0; t < CPL; ++t) {
+            X[r][t] = fmaf(alpha, P[r][t], X[r][t]);
+            R[r][t] = fmaf(-alpha, Q[r][t], R[r][t]);
+            rn = fmaf(R[r][t], R[r][t], rn);
+          }
+        rn = block_sum_f(rn, fslots[1], lane, wave, NW);
+        const float beta = rn / rr;
+        rr = rn;
+#pragma unroll
+        for (int r = 0; r < RPW; ++r)
+#pragma unroll
+          for (int t = 0; t < CPL; ++t) P[r][t] = fmaf(beta, P[r][t], R[r][t]);
+        ++it;
+      }
+      if (it >= maxit && rr > stop) fail = true;
+      tot_it += it;
+      max_it = it > (int)max_it ? it : max_it;
+      // float64 update with the correction e = D^{-1/2} X:  res -= M e,  w += e
+      __syncthreads();   // every wave is done reading xs as the right-hand side
+#pragma unroll
+      for (int r = 0; r < RPW; ++r) {
+        int j = j0 + r;
+#pragma unroll
+        for (int t = 0; t < CPL; ++t) {
+          int i = i0 + t;
+          if (j < n && i < n) xs[j * n + i] = X[r][t];
+        }
+      }
+      __syncthreads();
+      double emax[1] = {0.0};
+      const bool mx1[1] = {true};
+#pragma unroll 1
+      for (int r = 0; r < RPW; ++r) {
+        int j = j0 + r;
+        if (j >= n) break;
+#pragma unroll 1
+        for (int t = 0; t < CPL; ++t) {
+          int i = i0 + t;
+          if (i < n) {
+            int64_t p = (int64_t)j * n + i;
+            double ep = dv[p] * (double)xs[p];
+            double ew = i > 0 ? dv[p - 1] * (double)xs[p - 1] : 0.0;
+            double ee = i < n - 1 ? dv[p + 1] * (double)xs[p + 1] : 0.0;
+            double es = j > 0 ? dv[p - n] * (double)xs[p - n] : 0.0;
+            double en = j < n - 1 ? dv[p + n] * (double)xs[p + n] : 0.0;
+            double Me = ep + c * (af[g.fW(i, j)] * (ep - ew) + af[g.fE(i, j)] * (ep - ee) +
+                                  af[g.fS(i, j)] * (ep - es) + af[g.fN(i, j)] * (ep - en));
+            double rv = res[p] - Me;
+            res[p] = rv;
+            w[p] += ep;
+            emax[0] = nanmax(emax[0], fabs(rv));
+          }
+        }
+      }
+      block_reduce<1>(emax, mx1, dslots);
+      rmax = emax[0];
+      ++pass;
+    }
+    tot_pass += pass;
+    if (rmax > target) fail = true;
+  }
+  if (threadIdx.x == 0) {
+    if (fail) atomicOr(flag, 1);
+    atomicAdd(&cnt[0], tot_it);
+    atomicAdd(&cnt[1], tot_pass);
+    atomicAdd(&cnt[2], (unsigned long long)J);
+    atomicMax(&cnt[3], max_it);
+  }
+}
+
+template <int NW, int CPL, int RPW>
+void launch_resident(hipStream_t st, int64_t nsys, const double* a, const float* sf,
+                     const double* dinv, int n, double c, double tauf, int J, double tol,
+                     float pcg_rtol, int maxit, StartRef sr, double* out, double* resbuf,
+                     int64_t M, int N, int skip_first, const uint8_t* active, int* flag,
+                     unsigned long long* cnt) {
+  size_t lds = sizeof(float) * (size_t)n * n;
+  fine2d_resident_kernel<NW, CPL, RPW><<<dim3((unsigned)nsys), dim3(64 * NW), lds, st>>>(
+      a, sf, dinv, n, c, tauf, J, tol, pcg_rtol, maxit, sr, out, resbuf, M, N, skip_first, active,
+      flag, cnt);
+  KC_LAUNCH_CHECK();
+}
+
+}  // namespace
+
+// 2D system tables (float64 D^{-1/2} and float32 scaled coefficients) for tau.
+void build_tables_2d(hipStream_t st, const double* a, int n, double c, int64_t M, double* dinv,
+                     float* sf) {
+  int64_t Nx = (int64_t)n * n;
+  dim3 b(256);
+  dinv_kernel<<<dim3((unsigned)((Nx + 255) / 256), (unsigned)M), b, 0, st>>>(a, n, c, M, dinv);
+  KC_LAUNCH_CHECK();
+  if (sf) {
+    int64_t Fc = 2LL * n * (n + 1);
+    scaled_faces_kernel<<<dim3((unsigned)((Fc + 255) / 256), (unsigned)M), b, 0, st>>>(a, dinv, n, c,
+                                                                                        M, sf);
+    KC_LAUNCH_CHECK();
+  }
+}
+
+// Generic driver: J steps of size tau on every (m, s) of an [M][N] batch.
+int propagate_impl(klecgc_ctx* ctx, const klecgc_problem& p, const FineArgs& fa, double tau, int J,
+                   int N) {
+  hipStream_t st = ctx->stream;
+  const int n = p.n;
+  const double h = 1.0 / (n + 1);
+  const double c = tau / (h * h);
+  const double tauf = tau * p.forcing;
+  const int64_t M = fa.M;
+  const int64_t nsys = M * N;
+  StartRef sr{fa.start, fa.u0, fa.start_shift};
+  DevStatus ds = status_block(ctx);
+  status_reset(ctx, ds);
+  int* flag = ds.flag;
+  unsigned long long* cnt = ds.cnt;
+  if (p.dim == 1) {
+    double* tab = (double*)ctx->ws.get(WS_FACTORS, sizeof(double) * 3 * n * M);
+    tri_factor_kernel<<<dim3((unsigned)((M + 63) / 64)), dim3(64), 0, st>>>(fa.a, n, c, M, tab);
+    KC_LAUNCH_CHECK();
+    fine1d_kernel<<<dim3((unsigned)((nsys + 63) / 64)), dim3(64), 0, st>>>(
+        tab, n, J, tauf, sr, fa.out, M, N, fa.skip_first, fa.active);
+    KC_LAUNCH_CHECK();
+    return KC_OK;
+  }
+  const int64_t Nx = (int64_t)n * n;
+  const int64_t Fc = 2LL * n * (n + 1);
+  const double tol = p.inner_rtol > 0 ? p.inner_rtol : 1e-14;
+  const int maxit = p.inner_max_iter > 0 ? p.inner_max_iter : 4000;
+  double* dinv = (double*)ctx->ws.get(WS_DINV, sizeof(double) * Nx * M);
+  bool resident = (p.precision == KC_PREC_F32_REFINED) && n <= 128;
+  float* sf = resident ? (float*)ctx->ws.get(WS_FSCALED, sizeof(float) * Fc * M) : nullptr;
+  build_tables_2d(st, fa.a, n, c, M, dinv, sf);
+  if (resident) {
+    double* resbuf = (double*)ctx->ws.get(WS_KRYLOV, sizeof(double) * Nx * nsys);
+    const float pcg_rtol = 1e-6f;
+    if (n <= 16)
+      launch_resident<8, 1, 2>(st, nsys, fa.a, sf, dinv, n, c, tauf, J, tol, pcg_rtol, maxit, sr,
+                               fa.out, resbuf, M, N, fa.skip_first, fa.active, flag, cnt);
+    else if (n <= 32)
+      launch_resident<8, 1, 4>(st, nsys, fa.a, sf, dinv, n, c, tauf, J, tol, pcg_rtol, maxit, sr,
+                               fa.out, resbuf, M, N, fa.skip_first, fa.active, flag, cnt);
+    else if (n <= 64)
+      launch_resident<8, 1, 8>(st, nsys, fa.a, sf, dinv, n, c, tauf, J, tol, pcg_rtol, maxit, sr,
+                               fa.out, resbuf, M, N, fa.skip_first, fa.active, flag, cnt);
+    else
+      launch_resident<KC_RES128_NW, 2, 128 / KC_RES128_NW>(st, nsys, fa.a, sf, dinv, n, c, tauf, J, tol,
+                                                           pcg_rtol, maxit, sr, fa.out, resbuf, M, N,
+                                                           fa.skip_first, fa.active, flag, cnt);
+  } else {
+    double* scr = (double*)ctx->ws.get(WS_KRYLOV, sizeof(double) * 3 * Nx * nsys);
+    fine2d_pcg64_kernel<<<dim3((unsigned)nsys), dim3(kStreamThreads), 0, st>>>(
+        fa.a, dinv, n, c, tauf, J, tol, maxit, sr, fa.out, scr, M, N, fa.skip_first, fa.active, flag, cnt);
+    KC_LAUNCH_CHECK();
+  }
+  return status_collect(ctx, ds, 0) ? KC_ENOCONV : KC_OK;
+}
+
+int fine_propagate_impl(klecgc_ctx* ctx, const klecgc_problem& p, const FineArgs& fa) {
+  return propagate_impl(ctx, p, fa, p.T / p.N / p.J, p.J, p.N);
+}
+
+int coarse_sweep_impl(klecgc_ctx* ctx, const klecgc_problem& p, const double* a, const double* u0,
+                      int64_t M, double* U) {
+  // U[m][s] = G(U[m][s-1]), sequential over slices; each launch is one BE step of dT
+  // for all samples (the N = 1 batch view of slice s).
+  const int64_t Nx = n_unknowns(p);
+  const double dT = p.T / p.N;
+  int rc = KC_OK;
+  for (int s = 0; s < p.N; ++s) {
+    // batch of M systems, each reading row s-1 (or u0) and writing row s, stride N*Nx
+    // handled by staging through a contiguous [M][Nx] start buffer
+    double* stage = (double*)ctx->ws.get(WS_START, sizeof(double) * Nx * M);
+    double* outb = (double*)ctx->ws.get(WS_GEMM_A, sizeof(double) * Nx * M);
+    if (s == 0) {
+      if (u0)
+        KC_TRY_HIP(hipMemcpyAsync(stage, u0, sizeof(double) * Nx * M, hipMemcpyDeviceToDevice, ctx->stream));
+      else
+        KC_TRY_HIP(hipMemsetAsync(stage, 0, sizeof(double) * Nx * M, ctx->stream));
+    } else {
+      KC_TRY_HIP(hipMemcpy2DAsync(stage, sizeof(double) * Nx, U + (s - 1) * Nx, sizeof(double) * Nx * p.N,
+                                  sizeof(double) * Nx, M, hipMemcpyDeviceToDevice, ctx->stream));
+    }
+    FineArgs fa{a, stage, nullptr, false, 0, nullptr, outb, M};
+    int r = propagate_impl(ctx, p, fa, dT, 1, 1);
+    if (r != KC_OK) rc = r;
+    KC_TRY_HIP(hipMemcpy2DAsync(U + s * Nx, sizeof(double) * Nx * p.N, outb, sizeof(double) * Nx,
+                                sizeof(double) * Nx, M, hipMemcpyDeviceToDevice, ctx->stream));
+  }
+  return rc;
+}
+
+}  // namespace kc
