@@ -1,0 +1,201 @@
+#!/usr/bin/env python3
+"""Benchmark: KLE-CGC parareal solves/s at 1e-8 vs the serial fine solution on one MI355X.
+
+Workload (2D diffusion with a log-normal KL coefficient): 128x128 interior grid, KL
+d = 10 (corr 0.3, sigma 1), f = 1, T = 1, N = 64 slices, J = 64 fine backward-Euler
+steps, alpha = 1e-4, M = 256 samples, float32-refined fine path, float64 coarse
+correction, Hermite gPC degree-3 initial guess.  One step = one parareal_solve of the
+whole batch (gPC prediction + all parareal iterations to tol 1e-8), inputs resident
+in HBM.  The offline stage (training solutions, snapshot KL, gPC fit) runs before the
+timed region and is reported separately.
+
+Usage: python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+PEAK_FP32_TFLOPS = 157.3
+# algorithmic work per unit
+FLOPS_PER_PCG_UNKNOWN_IT = 18.0        # 5-point scaled matvec 8, two dots 4, three axpys 6
+BYTES_PER_COCG_UNKNOWN_IT = 128.0      # complex128 vectors streamed per COCG iteration
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(w, xi_row, iters_mean):
+    """The oracle, single-threaded: one parareal iteration on one sample, scaled."""
+    os.environ.setdefault("OMP_NUM_THREADS", "1")
+    import numpy as np
+    from oracle import field, parareal as opar, prop
+    lam, Phi = field.kl_modes(w.dim, w.n, w.d, w.corr_len, w.sigma)
+    a = field.synthesize(lam, Phi, xi_row[None, :])[0]
+    t0 = time.perf_counter()
+    P = prop.Propagators(w.dim, w.n, a, w.T, w.N, w.J, w.forcing)
+    opar.parareal_diag(P, w.alpha, np.zeros(w.Nx), np.zeros((w.N, w.Nx)), w.tol, 1, fixed_iters=1)
+    t_iter = time.perf_counter() - t0
+    t_solve = t_iter * iters_mean
+    return {"value": 1.0 / t_solve, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": f"1 sample x 1 parareal iteration ({w.N} slices x {w.J} BE steps + diagonalised CGC)"
+                      f" = {t_iter:.1f} s, scaled by the measured mean iteration count {iters_mean:.2f}"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="c2_2d_n128")
+    ap.add_argument("--M", type=int, default=0, help="override the batch size (0 = config)")
+    ap.add_argument("--n-train", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-oracle-check", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU sharding is "
+                                   "described in DESIGN.md but not built"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2510_26180_amd as K
+    import workloads as W
+
+    w = W.get(args.config)
+    if args.M:
+        w = w.replace(M=args.M)
+    if args.n_train:
+        w = w.replace(n_train=args.n_train)
+    dev = torch.device("cuda:0")
+    ctx = K.Context(0)
+    prob = K.ProblemSpec.from_workload(w)
+    log(f"workload {w.name}: dim={w.dim} n={w.n} N={w.N} J={w.J} M={w.M} alpha={w.alpha} n_train={w.n_train}")
+
+    # ---- inputs resident in HBM
+    field_h = ctx.kle_build_field(w.dim, w.n, w.d, w.corr_len, w.sigma)
+    xi_eval_np = W.draw_xi(w.M, w.d, w.seed_eval)
+    xi_train_np = W.draw_xi(w.n_train, w.d, w.seed_train)
+    xi_eval = torch.as_tensor(xi_eval_np).to(dev)
+    xi_train = torch.as_tensor(xi_train_np).to(dev)
+    a_eval = torch.empty((w.M, w.n_faces), dtype=torch.float64, device=dev)
+    a_train = torch.empty((w.n_train, w.n_faces), dtype=torch.float64, device=dev)
+    ctx.kle_synthesize(field_h, xi_eval, a_eval)
+    ctx.kle_synthesize(field_h, xi_train, a_train)
+
+    # ---- offline stage (untimed): training solutions, snapshot KL, gPC fit
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    S = torch.empty((w.n_train, w.N * w.Nx), dtype=torch.float64, device=dev)
+    ctx.serial_fine_propagate(prob, a_train, None, S.view(w.n_train, w.N, w.Nx))
+    torch.cuda.synchronize()
+    t_snap = time.perf_counter() - t0
+    kl = ctx.kle_build(S, w.eps_kl)
+    gpc = ctx.gpc_fit(kl, xi_train, w.gpc_degree)
+    torch.cuda.synchronize()
+    t_offline = time.perf_counter() - t0
+    del S
+    log(f"offline: {w.n_train} training solutions {t_snap:.1f} s, KL modes {kl.n_modes}, gPC P={gpc.P}, "
+        f"total {t_offline:.1f} s")
+
+    U = torch.empty((w.M, w.N, w.Nx), dtype=torch.float64, device=dev)
+
+    def step():
+        return ctx.parareal_solve(prob, a_eval, U, init=K.KC_INIT_GPC, gpc=gpc, xi=xi_eval, allow_noconv=True)
+
+    for i in range(args.warmup):
+        its, st, _, _ = step()
+        log(f"warmup {i}: iterations mean {its.mean():.2f} max {its.max()}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        its, status, hist, rc = step()
+        log(f"step {i}: iterations mean {its.mean():.2f} max {its.max()} rc={rc}")
+    torch.cuda.synchronize()
+    t_steps = time.perf_counter() - t0
+    ms_per_step = 1e3 * t_steps / args.steps
+    ktimes = ctx.last_times()
+    stats = ctx.last_stats()
+
+    # ---- accuracy: batched GPU serial fine reference for every sample
+    ref = torch.empty_like(U)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.serial_fine_propagate(prob, a_eval, None, ref)
+    torch.cuda.synchronize()
+    t_serial = time.perf_counter() - t0
+    err = ((U - ref).abs().amax(dim=(1, 2)) / ref.abs().amax(dim=(1, 2))).cpu().numpy()
+    n_ok = int((err <= 1e-8).sum())
+    value = n_ok / (ms_per_step / 1e3)
+    oracle_check = None
+    if not args.no_oracle_check:
+        from oracle import field, prop
+        lam, Phi = field.kl_modes(w.dim, w.n, w.d, w.corr_len, w.sigma)
+        a0 = field.synthesize(lam, Phi, xi_eval_np[:1])[0]
+        P = prop.Propagators(w.dim, w.n, a0, w.T, w.N, w.J, w.forcing)
+        ref_o = prop.serial_fine(P, np.zeros(w.Nx), w.N)
+        U0 = U[0].cpu().numpy()
+        R0 = ref[0].cpu().numpy()
+        oracle_check = {"sample": 0,
+                        "parareal_vs_oracle_serial_fine": float(np.abs(U0 - ref_o).max() / np.abs(ref_o).max()),
+                        "gpu_serial_fine_vs_oracle": float(np.abs(R0 - ref_o).max() / np.abs(ref_o).max())}
+        log(f"oracle check: {oracle_check}")
+
+    # ---- roofline of the dominant kernel (HIP-event time of the last timed step)
+    dom = max(ktimes, key=lambda k: ktimes[k][0])
+    dom_ms, dom_n = ktimes[dom]
+    if dom == "fine":
+        flops = FLOPS_PER_PCG_UNKNOWN_IT * w.Nx * stats["fine_krylov_its"]
+        achieved = flops / (dom_ms / 1e3) / 1e12
+        roof = {"kernel": "fine2d_resident_kernel", "bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
+                "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                "launches": dom_n, "ms_per_launch": dom_ms / max(dom_n, 1)}
+    elif dom == "shifted":
+        byts = BYTES_PER_COCG_UNKNOWN_IT * w.Nx * stats["cgc_krylov_its"]
+        achieved = byts / (dom_ms / 1e3) / 1e9
+        roof = {"kernel": "cocg_kernel", "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS,
+                "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+                "launches": dom_n, "ms_per_launch": dom_ms / max(dom_n, 1)}
+    else:
+        roof = {"kernel": dom, "bound": "hbm", "achieved": None, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": None, "traffic": None}
+
+    line = {
+        "metric": "parareal solves/s at 1e-8 vs serial fine",
+        "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64+f32", "data": "synthetic",
+        "config": {"workload": f"{w.name}: 2D diffusion {w.n}x{w.n}, KL d={w.d}, N={w.N}, J={w.J}, "
+                               f"alpha={w.alpha}, M={w.M}, gPC p={w.gpc_degree} (n_t={w.n_train})",
+                   "samples": w.M, "grid": w.n, "slices": w.N, "fine_steps": w.J},
+        "iters": {"mean": float(its.mean()), "max": int(its.max()), "min": int(its.min()),
+                  "hist": {int(k): int(v) for k, v in zip(*np.unique(its, return_counts=True))}},
+        "accuracy": {"n_within_1e-8": n_ok, "max_rel_err_vs_serial_fine": float(err.max()),
+                     "median_rel_err": float(np.median(err)), "oracle_check": oracle_check},
+        "serial_fine_gpu": {"solves_per_s": w.M / t_serial, "ms": 1e3 * t_serial},
+        "offline_s": t_offline,
+        "kernel_ms": {k: v[0] for k, v in ktimes.items()},
+        "solver_stats": stats,
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a bounded sample")
+        line["cpu_baseline"] = cpu_baseline(w, xi_eval_np[0], float(its.mean()))
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

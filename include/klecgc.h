@@ -76,9 +76,11 @@ typedef struct {
   int32_t max_iter;       /* parareal iteration cap, >= 1 */
   double  inner_rtol;     /* 2D fine solves: FP64 residual <= inner_rtol * (|w|_inf + dt|f|)
                              + 8 eps max_p(diag_p) |w|_inf (the FP64 rounding floor of the
-                             residual itself); 0 selects 1e-14 */
+                             residual itself); 0 selects 1e-13 */
   int32_t inner_max_iter; /* 2D fine solves: Krylov iteration cap per solve; 0 selects 4000 */
-  double  cgc_rtol;       /* 2D shifted solves of step (b): relative residual; 0 selects 1e-13 */
+  double  cgc_rtol;       /* 2D shifted solves of step (b): relative residual; 0 selects 1e-13
+                             in cgc_diag_solve and 1e-7 inside parareal_solve (which solves
+                             for the correction, see parareal_solve) */
   int32_t cgc_max_iter;   /* 2D shifted solves: iteration cap; 0 selects 20000 */
 } klecgc_problem;
 
@@ -106,11 +108,17 @@ int klecgc_set_stream(klecgc_ctx* ctx, void* hip_stream);
 const char* klecgc_last_error(const klecgc_ctx* ctx);
 void klecgc_kle_free(klecgc_kle* h);
 void klecgc_gpc_free(klecgc_gpc* h);
-/* Counters of the last call on ctx (instrumentation): out8[0..3] = fine implicit solves:
- * total Krylov iterations, total float64 refinement passes, number of implicit steps, max
- * iterations of one solve; out8[4..7] = the same for the shifted solves of step (b)
- * (2D only; passes unused).  Zeros where a path has no iterative solver. */
-int klecgc_last_stats(const klecgc_ctx* ctx, int64_t* out8);
+/* Counters of the last call on ctx (instrumentation), out16[16]: [0..3] fine implicit
+ * solves: total Krylov iterations, total float64 refinement passes, number of implicit
+ * steps, max iterations of one solve; [4..7] the same for the shifted solves of step (b)
+ * (2D only; passes unused); [8] shader-clock cycles of the 2D resident fine kernel summed
+ * over work-groups, [9] of which inside its float32 Krylov loops; [10..15] reserved (0). */
+int klecgc_last_stats(const klecgc_ctx* ctx, int64_t* out16);
+/* Device time of the last call on ctx, measured with HIP events on the context stream
+ * around each kernel launch (instrumentation): ms8[c] milliseconds and count8[c] launches
+ * (count8 nullable) for the kernel classes c = 0 fine propagator, 1 shifted solves of
+ * step (b), 2 forward slice FFT, 3 inverse slice FFT, 4 defect stencil, 5 prediction GEMM. */
+int klecgc_last_times(const klecgc_ctx* ctx, double* ms8, int64_t* count8);
 /* Library version string (static storage). */
 const char* klecgc_version(void);
 
@@ -170,6 +178,13 @@ int cgc_diag_solve(klecgc_ctx* ctx, const klecgc_problem* prob, const double* a_
  * slices from u0 (NULL = 0): one backward-Euler step of dT per slice. */
 int coarse_propagate(klecgc_ctx* ctx, const klecgc_problem* prob, const double* a_dev,
                      const double* u0_dev, int64_t M, double* U_dev);
+
+/* serial_fine_propagate (the reference solution of Section 2 and Section 5):
+ * U[m][s] = F(U[m][s-1]) sequentially over the slices from u0 (NULL = 0), F as in
+ * fine_propagate.  The batched serial sweep, used as the accuracy reference and as
+ * the time-serial baseline. */
+int serial_fine_propagate(klecgc_ctx* ctx, const klecgc_problem* prob, const double* a_dev,
+                          const double* u0_dev, int64_t M, double* U_dev);
 
 /* ---- driver (Algorithms 2 and 3) ----------------------------------------- */
 /* parareal_solve: parareal with diagonalised CGC for M samples.

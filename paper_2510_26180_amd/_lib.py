@@ -52,6 +52,8 @@ SIGNATURES = {
     "klecgc_gpc_free": (None, [_vp]),
     "klecgc_version": (ctypes.c_char_p, []),
     "klecgc_last_stats": (ctypes.c_int, [_vp, _P(ctypes.c_int64)]),
+    "klecgc_last_times": (ctypes.c_int, [_vp, _P(ctypes.c_double), _P(ctypes.c_int64)]),
+    "serial_fine_propagate": (ctypes.c_int, [_vp, _P(Problem), _vp, _vp, _i64, _vp]),
     "kle_build": (ctypes.c_int, [_vp, _P(KleDesc), _vp, _i64, _P(_vp), _P(_i32)]),
     "kle_synthesize": (ctypes.c_int, [_vp, _vp, _vp, _i64, _vp]),
     "kle_export": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),

@@ -117,11 +117,20 @@ class Context:
         return rc
 
     def last_stats(self) -> dict:
-        out = (ctypes.c_int64 * 8)()
+        out = (ctypes.c_int64 * 16)()
         self._check(self.lib.klecgc_last_stats(self.h, out))
         v = list(out)
         return {"fine_krylov_its": v[0], "fine_passes": v[1], "fine_solves": v[2], "fine_max_its": v[3],
-                "cgc_krylov_its": v[4], "cgc_solves": v[6], "cgc_max_its": v[7]}
+                "cgc_krylov_its": v[4], "cgc_solves": v[6], "cgc_max_its": v[7],
+                "fine_cycles": v[8], "fine_krylov_cycles": v[9]}
+
+    KCLASSES = ("fine", "shifted", "fft_fwd", "fft_inv", "defect", "gemm")
+
+    def last_times(self) -> dict:
+        ms = (ctypes.c_double * 8)()
+        cnt = (ctypes.c_int64 * 8)()
+        self._check(self.lib.klecgc_last_times(self.h, ms, cnt))
+        return {k: (ms[i], cnt[i]) for i, k in enumerate(self.KCLASSES)}
 
     def close(self):
         if getattr(self, "h", None):
@@ -177,6 +186,11 @@ class Context:
     def cgc_diag_solve(self, prob: ProblemSpec, a, r, u, allow_noconv=False) -> int:
         pc = prob.c()
         return self._check(self.lib.cgc_diag_solve(self.h, ctypes.byref(pc), _ptr(a), _ptr(r), r.shape[0], _ptr(u)),
+                           allow=(-5,) if allow_noconv else ())
+
+    def serial_fine_propagate(self, prob: ProblemSpec, a, u0, U, allow_noconv=False) -> int:
+        pc = prob.c()
+        return self._check(self.lib.serial_fine_propagate(self.h, ctypes.byref(pc), _ptr(a), _ptr(u0), U.shape[0], _ptr(U)),
                            allow=(-5,) if allow_noconv else ())
 
     def coarse_propagate(self, prob: ProblemSpec, a, u0, U) -> int:

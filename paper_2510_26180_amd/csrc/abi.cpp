@@ -66,9 +66,13 @@ int status_collect(klecgc_ctx* ctx, const DevStatus& st, int base) {
   KC_TRY_HIP(hipMemcpyAsync(h, st.flag, kStatusBytes, hipMemcpyDeviceToHost, ctx->stream));
   KC_TRY_HIP(hipStreamSynchronize(ctx->stream));
   int flag;
-  unsigned long long c[4];
+  unsigned long long c[10];
   std::memcpy(&flag, h, sizeof(int));
   std::memcpy(c, h + 8, sizeof(c));
+  if (base == 0) {
+    ctx->stats[8] += (int64_t)c[8];
+    ctx->stats[9] += (int64_t)c[9];
+  }
   ctx->stats[base + 0] += (int64_t)c[0];
   ctx->stats[base + 1] += (int64_t)c[1];
   ctx->stats[base + 2] += (int64_t)c[2];
@@ -124,7 +128,7 @@ int gpc_predict_impl(klecgc_ctx* ctx, const klecgc_gpc* g, const double* xi, int
   double* Z = (double*)ctx->ws.get(WS_GEMM_B, sizeof(double) * M * g->n_modes);
   launch_hermite(st, xi, M, g->d, g->idx, g->P, g->p, Psi);
   launch_dgemm(st, M, g->n_modes, g->P, Psi, g->P, g->H, g->n_modes, Z, g->n_modes, nullptr, 1.0);
-  launch_dgemm(st, M, g->L, g->n_modes, Z, g->n_modes, g->W, g->L, U0, g->L, g->mean, 1.0);
+  timed(ctx, KT_GEMM, [&] { launch_dgemm(st, M, g->L, g->n_modes, Z, g->n_modes, g->W, g->L, U0, g->L, g->mean, 1.0); });
   return KC_OK;
 }
 
@@ -173,16 +177,22 @@ static int parareal_impl(klecgc_ctx* ctx, const klecgc_problem& p, const double*
   if (hist) std::fill(hist, hist + M * p.max_iter, 0.0);
   KC_TRY_HIP(hipMemcpyAsync(active, act.data(), M, hipMemcpyHostToDevice, st));
   int64_t n_active = M;
+  // The driver solves the coarse system for the correction U^{k+1} - U^k, whose
+  // right-hand side is the defect; errors of the shifted solves then only perturb the
+  // contraction (by ~ cgc_rtol / alpha), not the fixed point, so a relative 1e-7
+  // suffices by default.
+  klecgc_problem pb = p;
+  if (pb.cgc_rtol <= 0) pb.cgc_rtol = 1e-7;
   for (int k = 0; k < p.max_iter && n_active > 0; ++k) {
     FineArgs fa{a, U, u0, true, k > 0 ? 1 : 0, active, Fv, M};
     int r = fine_propagate_impl(ctx, p, fa);
     if (r != KC_OK) rc = r;
-    launch_defect(st, p, a, Fv, U, active, M, D);
-    launch_fft_forward(st, p, D, active, M, spec);
-    r = shifted_solve_impl(ctx, p, a, active, M, spec);
+    timed(ctx, KT_DEFECT, [&] { launch_defect(st, p, a, Fv, U, active, M, D); });
+    timed(ctx, KT_FFT_FWD, [&] { launch_fft_forward(st, p, D, active, M, spec); });
+    r = shifted_solve_impl(ctx, pb, a, active, M, spec);
     if (r != KC_OK) rc = r;
     KC_TRY_HIP(hipMemsetAsync(maxima, 0, sizeof(unsigned long long) * 2 * M, st));
-    launch_fft_inverse(st, p, spec, active, M, U, true, maxima);
+    timed(ctx, KT_FFT_INV, [&] { launch_fft_inverse(st, p, spec, active, M, U, true, maxima); });
     KC_TRY_HIP(hipMemcpyAsync(hmax.data(), maxima, sizeof(unsigned long long) * 2 * M,
                               hipMemcpyDeviceToHost, st));
     KC_TRY_HIP(hipStreamSynchronize(st));
@@ -221,6 +231,8 @@ int guarded(klecgc_ctx* ctx, F&& f) {
   if (!ctx) return KC_EINVAL;
   ctx->err.clear();
   for (auto& v : ctx->stats) v = 0;
+  for (auto& v : ctx->ktime) v = 0;
+  for (auto& v : ctx->kcount) v = 0;
   try {
     hipError_t e = hipSetDevice(ctx->device);
     if (e != hipSuccess) throw Error{KC_EHIP, std::string("hipSetDevice: ") + hipGetErrorString(e)};
@@ -256,6 +268,10 @@ int klecgc_create(klecgc_ctx** out, int device, void* hip_stream) {
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
     c->num_cus = cus;
+  if (hipEventCreate(&c->ev[0]) != hipSuccess || hipEventCreate(&c->ev[1]) != hipSuccess) {
+    delete c;
+    return KC_EHIP;
+  }
   *out = c;
   return KC_OK;
 }
@@ -265,6 +281,8 @@ void klecgc_destroy(klecgc_ctx* ctx) {
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
   ctx->ws.release();
+  for (auto& e : ctx->ev)
+    if (e) (void)hipEventDestroy(e);
   delete ctx;
 }
 
@@ -277,9 +295,18 @@ int klecgc_set_stream(klecgc_ctx* ctx, void* s) {
 
 const char* klecgc_last_error(const klecgc_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 
-int klecgc_last_stats(const klecgc_ctx* ctx, int64_t* out8) {
-  if (!ctx || !out8) return KC_EINVAL;
-  for (int i = 0; i < 8; ++i) out8[i] = ctx->stats[i];
+int klecgc_last_times(const klecgc_ctx* ctx, double* ms8, int64_t* count8) {
+  if (!ctx || !ms8) return KC_EINVAL;
+  for (int i = 0; i < 8; ++i) {
+    ms8[i] = ctx->ktime[i];
+    if (count8) count8[i] = ctx->kcount[i];
+  }
+  return KC_OK;
+}
+
+int klecgc_last_stats(const klecgc_ctx* ctx, int64_t* out16) {
+  if (!ctx || !out16) return KC_EINVAL;
+  for (int i = 0; i < 16; ++i) out16[i] = ctx->stats[i];
   return KC_OK;
 }
 
@@ -500,9 +527,9 @@ int cgc_diag_solve(klecgc_ctx* ctx, const klecgc_problem* prob, const double* a_
     const int64_t Nx = n_unknowns(*prob);
     const int K = prob->N / 2 + 1;
     double* spec = (double*)ctx->ws.get(WS_SPEC, sizeof(double) * 2 * M * K * Nx);
-    launch_fft_forward(ctx->stream, *prob, r_dev, nullptr, M, spec);
+    timed(ctx, KT_FFT_FWD, [&] { launch_fft_forward(ctx->stream, *prob, r_dev, nullptr, M, spec); });
     int rc = shifted_solve_impl(ctx, *prob, a_dev, nullptr, M, spec);
-    launch_fft_inverse(ctx->stream, *prob, spec, nullptr, M, u_dev, false, nullptr);
+    timed(ctx, KT_FFT_INV, [&] { launch_fft_inverse(ctx->stream, *prob, spec, nullptr, M, u_dev, false, nullptr); });
     return rc;
   });
 }
@@ -514,6 +541,16 @@ int coarse_propagate(klecgc_ctx* ctx, const klecgc_problem* prob, const double* 
     KC_REQUIRE(M >= 1, KC_EINVAL, "M must be >= 1");
     validate_problem(*prob);
     return coarse_sweep_impl(ctx, *prob, a_dev, u0_dev, M, U_dev);
+  });
+}
+
+int serial_fine_propagate(klecgc_ctx* ctx, const klecgc_problem* prob, const double* a_dev,
+                          const double* u0_dev, int64_t M, double* U_dev) {
+  return guarded(ctx, [&] {
+    KC_REQUIRE(prob && a_dev && U_dev, KC_EINVAL, "null argument");
+    KC_REQUIRE(M >= 1, KC_EINVAL, "M must be >= 1");
+    validate_problem(*prob);
+    return serial_fine_impl(ctx, *prob, a_dev, u0_dev, M, U_dev);
   });
 }
 

@@ -346,6 +346,360 @@ __global__ __launch_bounds__(kCocgThreads) void cocg_kernel(const double* __rest
   }
 }
 
+// ------------------------------------------------ step (b), 2D, CU-resident
+// For grids up to 64x64 (the whole system's Krylov state fits one CU's registers; a
+// 128x128 complex system does not), the same shifted systems solved on one CU each: float32 complex COCG on the
+// real-Jacobi-scaled matrix  D^{-1/2} (lambda I + dT A) D^{-1/2} = diag(1 + i theta) - S,
+// D = Re(lambda) + dT diag(A), theta_p = Im(lambda) / D_p, S the scaled (real) face
+// couplings, refined in float64: the complex128 residual p - (lambda I + dT A) q is kept
+// in global memory, each pass solves for a correction in float32 (Krylov state in
+// registers, the correction accumulated in an LDS tile), adds it to q in float64 and
+// updates the residual, until |res|_2 <= rtol |p|_2.
+
+__global__ void shift_dinv_kernel(const double* __restrict__ a, int n, double cT, int N, double alpha,
+                                  int64_t M, double* __restrict__ dr) {
+  const int K = N / 2 + 1;
+  const int64_t Nx = (int64_t)n * n;
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t mk = blockIdx.y;
+  if (p >= Nx || mk >= M * K) return;
+  int64_t m = mk / K;
+  int k = (int)(mk % K);
+  double sv, cv;
+  sincospi(-2.0 * k / N, &sv, &cv);
+  const double lre = 1.0 - exp(log(alpha) / N) * cv;
+  const int64_t nx = (int64_t)n * (n + 1);
+  const double* af = a + m * 2 * nx;
+  int i = (int)(p % n), j = (int)(p / n);
+  double sa = af[(int64_t)j * (n + 1) + i] + af[(int64_t)j * (n + 1) + i + 1] + af[nx + (int64_t)j * n + i] +
+              af[nx + (int64_t)(j + 1) * n + i];
+  dr[mk * Nx + p] = 1.0 / sqrt(lre + cT * sa);
+}
+
+template <int CTRL>
+__device__ __forceinline__ float dppf_c(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xf, 0xf, true));
+}
+__device__ __forceinline__ float wsum_dpp(float v) {
+  v += dppf_c<0xB1>(v);
+  v += dppf_c<0x4E>(v);
+  v += dppf_c<0x141>(v);
+  v += dppf_c<0x140>(v);
+  const int iv = __builtin_bit_cast(int, v);
+  return (__builtin_bit_cast(float, __builtin_amdgcn_readlane(iv, 0)) +
+          __builtin_bit_cast(float, __builtin_amdgcn_readlane(iv, 16))) +
+         (__builtin_bit_cast(float, __builtin_amdgcn_readlane(iv, 32)) +
+          __builtin_bit_cast(float, __builtin_amdgcn_readlane(iv, 48)));
+}
+template <int NW, int K>
+__device__ __forceinline__ void block_sum_fk(float (&v)[K], float* slots, int lane, int wave) {
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = wsum_dpp(v[k]);
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) slots[k * NW + wave] = v[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    float acc = slots[k * NW];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) acc += slots[k * NW + w];
+    v[k] = acc;
+  }
+}
+
+struct cf {
+  float x, y;
+};
+__device__ __forceinline__ cf cf_div(cf a, cf b) {
+  float den = b.x * b.x + b.y * b.y;
+  return {(a.x * b.x + a.y * b.y) / den, (a.y * b.x - a.x * b.y) / den};
+}
+
+template <int NW, int CPL, int RPW>
+__global__ __launch_bounds__(64 * NW) void cocg_resident_kernel(
+    const double* __restrict__ a, const double* __restrict__ dinvr, int n, double cT, int N, double alpha,
+    double rtol, float inner_rtol, int maxit, const uint8_t* __restrict__ active, double* __restrict__ spec,
+    double* __restrict__ resbuf, int* __restrict__ flag, unsigned long long* __restrict__ cnt) {
+  constexpr int ROWW = 64 * CPL;
+  extern __shared__ float2 xs[];                 // [n*n] complex64 correction / staging
+  __shared__ float2 htop[(NW - 1) * ROWW];       // boundary b: NS(row 0 of wave b+1) * P
+  __shared__ float2 hbot[(NW - 1) * ROWW];       // boundary b: last row of wave b
+  __shared__ float fsl[2][3 * NW];
+  __shared__ double dsl[4 * NW];
+  const int K = N / 2 + 1;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t sys = blockIdx.x;
+  const int64_t m = sys / K;
+  const int k = (int)(sys % K);
+  if (active && !active[m]) return;
+  const int64_t Nx = (int64_t)n * n;
+  const int64_t nx = (int64_t)n * (n + 1);
+  const double* af = a + m * 2 * nx;
+  const double* dr = dinvr + sys * Nx;
+  double2* q = (double2*)spec + sys * Nx;
+  double2* res = (double2*)resbuf + sys * Nx;
+  double sv, cv;
+  sincospi(-2.0 * k / N, &sv, &cv);
+  const double an = exp(log(alpha) / N);
+  const double lre = 1.0 - an * cv, lim = -an * sv;
+  const int j0 = wave * RPW, i0 = lane * CPL;
+
+  float EW[RPW][CPL], NS[RPW][CPL], TH[RPW][CPL];
+#pragma unroll
+  for (int r = 0; r < RPW; ++r) {
+    const int j = j0 + r;
+#pragma unroll
+    for (int t = 0; t < CPL; ++t) {
+      const int i = i0 + t;
+      const bool in = (j < n && i < n);
+      const int64_t p = (int64_t)j * n + i;
+      EW[r][t] = (in && i >= 1) ? (float)(cT * af[(int64_t)j * (n + 1) + i] * dr[p - 1] * dr[p]) : 0.f;
+      NS[r][t] = (in && j >= 1) ? (float)(cT * af[nx + (int64_t)j * n + i] * dr[p - n] * dr[p]) : 0.f;
+      TH[r][t] = in ? (float)(lim * dr[p] * dr[p]) : 0.f;
+    }
+  }
+  // res = p, q = 0, |p|_2^2 and the scale of the next float32 right-hand side
+  double bn[2] = {0.0, 0.0};
+  const bool sm[2] = {false, true};
+  for (int64_t p = threadIdx.x; p < Nx; p += blockDim.x) {
+    double2 v = q[p];
+    res[p] = v;
+    q[p] = make_double2(0.0, 0.0);
+    bn[0] += v.x * v.x + v.y * v.y;
+    bn[1] = nanmax(bn[1], dr[p] * fmax(fabs(v.x), fabs(v.y)));
+  }
+  block_reduce<2>(bn, sm, dsl);
+  const double stop2 = rtol * rtol * bn[0];
+  double rn2 = bn[0];
+  // float32 right-hand sides are normalised by their max so that tiny late-pass
+  // residuals do not underflow
+  double sig = bn[1];
+  unsigned long long tot_it = 0, max_it = 0;
+  int pass = 0;
+  float2 R[RPW][CPL], P[RPW][CPL];
+  while (rn2 > stop2 && sig > 0.0 && pass < 12) {
+    const double isig = 1.0 / sig;
+    // stage D^{-1/2} res / sig as complex64 through LDS
+#pragma unroll 1
+    for (int kk = 0; kk < RPW * CPL; ++kk) {
+      const int j = j0 + kk / CPL, i = i0 + kk % CPL;
+      if (j < n && i < n) {
+        const int64_t p = (int64_t)j * n + i;
+        const double2 v = res[p];
+        xs[p] = make_float2((float)(isig * dr[p] * v.x), (float)(isig * dr[p] * v.y));
+      }
+    }
+    __syncthreads();
+    float acc3[3] = {0.f, 0.f, 0.f};   // r.r (re, im), |r|^2
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) {
+      const int j = j0 + r;
+#pragma unroll
+      for (int t = 0; t < CPL; ++t) {
+        const int i = i0 + t;
+        float2 v = (j < n && i < n) ? xs[j * n + i] : make_float2(0.f, 0.f);
+        R[r][t] = v;
+        P[r][t] = v;
+        acc3[0] += v.x * v.x - v.y * v.y;
+        acc3[1] += 2.f * v.x * v.y;
+        acc3[2] += v.x * v.x + v.y * v.y;
+      }
+    }
+    __syncthreads();   // everyone has read the staged right-hand side
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) {
+      const int j = j0 + r;
+#pragma unroll
+      for (int t = 0; t < CPL; ++t) {
+        const int i = i0 + t;
+        if (j < n && i < n) xs[j * n + i] = make_float2(0.f, 0.f);
+      }
+    }
+    block_sum_fk<NW, 3>(acc3, fsl[1], lane, wave);
+    cf rz = {acc3[0], acc3[1]};
+    float rr = acc3[2];
+    const float stop_in = inner_rtol * inner_rtol * rr;
+    int it = 0;
+    while (rr > stop_in && it < maxit) {
+      // halos of P
+#pragma unroll
+      for (int t = 0; t < CPL; ++t) {
+        if (wave < NW - 1) hbot[wave * ROWW + lane * CPL + t] = P[RPW - 1][t];
+        if (wave > 0)
+          htop[(wave - 1) * ROWW + lane * CPL + t] = make_float2(NS[0][t] * P[0][t].x, NS[0][t] * P[0][t].y);
+      }
+      __syncthreads();
+      // pass 1: pq = sum p (M p) (unconjugated)
+      float pq2[2] = {0.f, 0.f};
+#pragma unroll
+      for (int pass_mv = 0; pass_mv < 2; ++pass_mv) {
+        cf alph = {0.f, 0.f};
+        if (pass_mv == 1) {
+          block_sum_fk<NW, 2>(pq2, fsl[0], lane, wave);
+          alph = cf_div(rz, cf{pq2[0], pq2[1]});
+        }
+        float racc[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+        for (int r = 0; r < RPW; ++r) {
+          const float wvx = dppf_c<0x138>(P[r][CPL - 1].x), wvy = dppf_c<0x138>(P[r][CPL - 1].y);
+          const float epx = dppf_c<0x130>(EW[r][0] * P[r][0].x), epy = dppf_c<0x130>(EW[r][0] * P[r][0].y);
+#pragma unroll
+          for (int t = 0; t < CPL; ++t) {
+            const float2 pv = P[r][t];
+            float qx = pv.x - TH[r][t] * pv.y, qy = pv.y + TH[r][t] * pv.x;
+            const float lx = (t == 0) ? wvx : P[r][t - 1].x, ly = (t == 0) ? wvy : P[r][t - 1].y;
+            qx = fmaf(-EW[r][t], lx, qx);
+            qy = fmaf(-EW[r][t], ly, qy);
+            if (t == CPL - 1) {
+              qx -= epx;
+              qy -= epy;
+            } else {
+              qx = fmaf(-EW[r][t + 1], P[r][t + 1].x, qx);
+              qy = fmaf(-EW[r][t + 1], P[r][t + 1].y, qy);
+            }
+            float2 dn, up;
+            if (r == 0)
+              dn = (wave > 0) ? hbot[(wave - 1) * ROWW + lane * CPL + t] : make_float2(0.f, 0.f);
+            else
+              dn = P[r - 1][t];
+            qx = fmaf(-NS[r][t], dn.x, qx);
+            qy = fmaf(-NS[r][t], dn.y, qy);
+            if (r == RPW - 1) {
+              up = (wave < NW - 1) ? htop[wave * ROWW + lane * CPL + t] : make_float2(0.f, 0.f);
+              qx -= up.x;
+              qy -= up.y;
+            } else {
+              qx = fmaf(-NS[r + 1][t], P[r + 1][t].x, qx);
+              qy = fmaf(-NS[r + 1][t], P[r + 1][t].y, qy);
+            }
+            if (pass_mv == 0) {
+              pq2[0] += pv.x * qx - pv.y * qy;
+              pq2[1] += pv.x * qy + pv.y * qx;
+            } else {
+              float2 rv = R[r][t];
+              rv.x -= alph.x * qx - alph.y * qy;
+              rv.y -= alph.x * qy + alph.y * qx;
+              R[r][t] = rv;
+            }
+          }
+        }
+        if (pass_mv == 1) {
+          // correction tile X += alpha P, and the new residual's dot products
+#pragma unroll
+          for (int r = 0; r < RPW; ++r) {
+            const int j = j0 + r;
+#pragma unroll
+            for (int t = 0; t < CPL; ++t) {
+              const int i = i0 + t;
+              const float2 pv = P[r][t], rv = R[r][t];
+              if (j < n && i < n) {
+                float2 xv = xs[j * n + i];
+                xv.x += alph.x * pv.x - alph.y * pv.y;
+                xv.y += alph.x * pv.y + alph.y * pv.x;
+                xs[j * n + i] = xv;
+              }
+              racc[0] += rv.x * rv.x - rv.y * rv.y;
+              racc[1] += 2.f * rv.x * rv.y;
+              racc[2] += rv.x * rv.x + rv.y * rv.y;
+            }
+          }
+        }
+        if (pass_mv == 1) {
+          block_sum_fk<NW, 3>(racc, fsl[1], lane, wave);
+          const cf rzn = {racc[0], racc[1]};
+          const cf beta = cf_div(rzn, rz);
+          rz = rzn;
+          rr = racc[2];
+#pragma unroll
+          for (int r = 0; r < RPW; ++r)
+#pragma unroll
+            for (int t = 0; t < CPL; ++t) {
+              const float2 pv = P[r][t], rv = R[r][t];
+              P[r][t] = make_float2(rv.x + beta.x * pv.x - beta.y * pv.y, rv.y + beta.x * pv.y + beta.y * pv.x);
+            }
+        }
+      }
+      ++it;
+    }
+    tot_it += it;
+    max_it = it > (int)max_it ? it : max_it;
+    if (it >= maxit && rr > stop_in) atomicOr(flag, 1);
+    __syncthreads();   // correction tile complete
+    // float64: e = sig D^{-1/2} X; res -= (lambda I + dT A) e; q += e
+    double acc[2] = {0.0, 0.0};
+#pragma unroll 1
+    for (int kk = 0; kk < RPW * CPL; ++kk) {
+      const int j = j0 + kk / CPL, i = i0 + kk % CPL;
+      if (j < n && i < n) {
+        const int64_t p = (int64_t)j * n + i;
+        const float2 xp = xs[p];
+        const double ex = sig * dr[p] * xp.x, ey = sig * dr[p] * xp.y;
+        double sx = 0.0, sy = 0.0;
+        const double aW = af[(int64_t)j * (n + 1) + i], aE = af[(int64_t)j * (n + 1) + i + 1];
+        const double aS = af[nx + (int64_t)j * n + i], aN = af[nx + (int64_t)(j + 1) * n + i];
+        {
+          double nxv = 0.0, nyv = 0.0;
+          if (i > 0) { const float2 v = xs[p - 1]; nxv = sig * dr[p - 1] * v.x; nyv = sig * dr[p - 1] * v.y; }
+          sx += aW * (ex - nxv); sy += aW * (ey - nyv);
+        }
+        {
+          double nxv = 0.0, nyv = 0.0;
+          if (i < n - 1) { const float2 v = xs[p + 1]; nxv = sig * dr[p + 1] * v.x; nyv = sig * dr[p + 1] * v.y; }
+          sx += aE * (ex - nxv); sy += aE * (ey - nyv);
+        }
+        {
+          double nxv = 0.0, nyv = 0.0;
+          if (j > 0) { const float2 v = xs[p - n]; nxv = sig * dr[p - n] * v.x; nyv = sig * dr[p - n] * v.y; }
+          sx += aS * (ex - nxv); sy += aS * (ey - nyv);
+        }
+        {
+          double nxv = 0.0, nyv = 0.0;
+          if (j < n - 1) { const float2 v = xs[p + n]; nxv = sig * dr[p + n] * v.x; nyv = sig * dr[p + n] * v.y; }
+          sx += aN * (ex - nxv); sy += aN * (ey - nyv);
+        }
+        const double mex = lre * ex - lim * ey + cT * sx;
+        const double mey = lre * ey + lim * ex + cT * sy;
+        double2 rv = res[p];
+        rv.x -= mex;
+        rv.y -= mey;
+        res[p] = rv;
+        double2 qv = q[p];
+        qv.x += ex;
+        qv.y += ey;
+        q[p] = qv;
+        acc[0] += rv.x * rv.x + rv.y * rv.y;
+        acc[1] = nanmax(acc[1], dr[p] * fmax(fabs(rv.x), fabs(rv.y)));
+      }
+    }
+    block_reduce<2>(acc, sm, dsl);
+    rn2 = acc[0];
+    sig = acc[1];
+    ++pass;
+  }
+  if (threadIdx.x == 0) {
+    if (rn2 > stop2) atomicOr(flag, 1);
+    atomicAdd(&cnt[0], tot_it);
+    atomicAdd(&cnt[1], (unsigned long long)pass);
+    atomicAdd(&cnt[2], 1ull);
+    atomicMax(&cnt[3], max_it);
+  }
+}
+
+template <int NW, int CPL, int RPW>
+void launch_cocg_resident(hipStream_t st, int64_t nsys, const double* a, const double* dr, int n, double cT,
+                          int N, double alpha, double rtol, float inner_rtol, int maxit, const uint8_t* active,
+                          double* spec, double* resbuf, int* flag, unsigned long long* cnt) {
+  const size_t lds = sizeof(float2) * (size_t)n * n;
+  KC_TRY_HIP(hipFuncSetAttribute((const void*)cocg_resident_kernel<NW, CPL, RPW>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  cocg_resident_kernel<NW, CPL, RPW><<<dim3((unsigned)nsys), dim3(64 * NW), lds, st>>>(
+      a, dr, n, cT, N, alpha, rtol, inner_rtol, maxit, active, spec, resbuf, flag, cnt);
+  KC_LAUNCH_CHECK();
+}
+
 template <int COLS>
 size_t fft_lds(int N) {
   return sizeof(cd) * ((size_t)N * COLS + N / 2);
@@ -414,19 +768,44 @@ int shifted_solve_impl(klecgc_ctx* ctx, const klecgc_problem& p, const double* a
   const int64_t nsys = M * K;
   if (p.dim == 1) {
     double* scr = (double*)ctx->ws.get(WS_FACTORS, sizeof(double) * 2 * Nx * nsys);
-    shifted_tri_kernel<<<dim3((unsigned)((nsys + 63) / 64)), dim3(64), 0, st>>>(
-        a, p.n, cT, p.N, p.alpha, active, M, spec, scr);
-    KC_LAUNCH_CHECK();
+    timed(ctx, KT_SHIFTED, [&] {
+      shifted_tri_kernel<<<dim3((unsigned)((nsys + 63) / 64)), dim3(64), 0, st>>>(
+          a, p.n, cT, p.N, p.alpha, active, M, spec, scr);
+      KC_LAUNCH_CHECK();
+    });
     return KC_OK;
   }
-  double* scr = (double*)ctx->ws.get(WS_KRYLOV, sizeof(double) * 6 * Nx * nsys);
   DevStatus ds = status_block(ctx);
   status_reset(ctx, ds);
   const double rtol = p.cgc_rtol > 0 ? p.cgc_rtol : 1e-13;
   const int maxit = p.cgc_max_iter > 0 ? p.cgc_max_iter : 20000;
-  cocg_kernel<<<dim3((unsigned)nsys), dim3(kCocgThreads), 0, st>>>(a, p.n, cT, p.N, p.alpha, rtol,
-                                                                   maxit, active, spec, scr, ds.flag, ds.cnt);
-  KC_LAUNCH_CHECK();
+  if (p.precision == KC_PREC_F32_REFINED && p.n <= 64) {
+    double* dr = (double*)ctx->ws.get(WS_DINV, sizeof(double) * Nx * nsys);
+    double* resb = (double*)ctx->ws.get(WS_KRYLOV, sizeof(double) * 2 * Nx * nsys);
+    shift_dinv_kernel<<<dim3((unsigned)((Nx + 255) / 256), (unsigned)nsys), dim3(256), 0, st>>>(
+        a, p.n, cT, p.N, p.alpha, M, dr);
+    KC_LAUNCH_CHECK();
+    const float inner = 1e-5f;
+    timed(ctx, KT_SHIFTED, [&] {
+      // 8 waves; one grid row block of RPW rows per wave, one column per lane
+      if (p.n <= 16)
+        launch_cocg_resident<8, 1, 2>(st, nsys, a, dr, p.n, cT, p.N, p.alpha, rtol, inner, maxit, active, spec,
+                                      resb, ds.flag, ds.cnt);
+      else if (p.n <= 32)
+        launch_cocg_resident<8, 1, 4>(st, nsys, a, dr, p.n, cT, p.N, p.alpha, rtol, inner, maxit, active, spec,
+                                      resb, ds.flag, ds.cnt);
+      else
+        launch_cocg_resident<8, 1, 8>(st, nsys, a, dr, p.n, cT, p.N, p.alpha, rtol, inner, maxit, active, spec,
+                                      resb, ds.flag, ds.cnt);
+    });
+    return status_collect(ctx, ds, 4) ? KC_ENOCONV : KC_OK;
+  }
+  double* scr = (double*)ctx->ws.get(WS_KRYLOV, sizeof(double) * 6 * Nx * nsys);
+  timed(ctx, KT_SHIFTED, [&] {
+    cocg_kernel<<<dim3((unsigned)nsys), dim3(kCocgThreads), 0, st>>>(a, p.n, cT, p.N, p.alpha, rtol,
+                                                                     maxit, active, spec, scr, ds.flag, ds.cnt);
+    KC_LAUNCH_CHECK();
+  });
   return status_collect(ctx, ds, 4) ? KC_ENOCONV : KC_OK;
 }
 

@@ -67,7 +67,13 @@ struct klecgc_ctx {
   int num_cus = 256;
   // counters of the last call: [0..3] fine solves (Krylov iterations, refinement passes,
   // implicit steps, max iterations of one solve), [4..7] the same for the shifted solves
-  int64_t stats[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  // [8] shader-clock cycles of the fine kernel summed over work-groups, [9] of which in
+  // the float32 Krylov loops
+  int64_t stats[16] = {0};
+  // HIP-event time (ms) and launch count per kernel class of the last call
+  double ktime[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int64_t kcount[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  hipEvent_t ev[2] = {nullptr, nullptr};
 };
 
 struct klecgc_kle {
@@ -107,8 +113,25 @@ struct DevStatus {
 };
 DevStatus status_block(klecgc_ctx* ctx);
 void status_reset(klecgc_ctx* ctx, const DevStatus& st);
-// copies the block to the host, adds the counters into ctx->stats[base..base+3]; returns flag
+// copies the block to the host, adds the counters into ctx->stats[base..base+3] (and
+// the cycle counters 8, 9 for base 0); returns flag
 int status_collect(klecgc_ctx* ctx, const DevStatus& st, int base);
+
+// Kernel classes timed with HIP events on the context stream.
+enum KClass { KT_FINE = 0, KT_SHIFTED = 1, KT_FFT_FWD = 2, KT_FFT_INV = 3, KT_DEFECT = 4, KT_GEMM = 5, KT_COUNT = 8 };
+// Records an event pair around `launch` and adds the elapsed time to ctx->ktime[cls]
+// (synchronises the stream).
+template <class F>
+void timed(klecgc_ctx* ctx, int cls, F&& launch) {
+  KC_TRY_HIP(hipEventRecord(ctx->ev[0], ctx->stream));
+  launch();
+  KC_TRY_HIP(hipEventRecord(ctx->ev[1], ctx->stream));
+  KC_TRY_HIP(hipEventSynchronize(ctx->ev[1]));
+  float ms = 0.f;
+  KC_TRY_HIP(hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]));
+  ctx->ktime[cls] += ms;
+  ctx->kcount[cls] += 1;
+}
 
 inline int64_t n_unknowns(const klecgc_problem& p) { return p.dim == 1 ? p.n : (int64_t)p.n * p.n; }
 inline int64_t n_faces(int dim, int n) { return dim == 1 ? n + 1 : 2LL * n * (n + 1); }
@@ -146,6 +169,8 @@ int shifted_solve_impl(klecgc_ctx* ctx, const klecgc_problem& p, const double* a
                        const uint8_t* active, int64_t M, double* spec);
 int coarse_sweep_impl(klecgc_ctx* ctx, const klecgc_problem& p, const double* a,
                       const double* u0, int64_t M, double* U);
+int serial_fine_impl(klecgc_ctx* ctx, const klecgc_problem& p, const double* a,
+                     const double* u0, int64_t M, double* U);
 
 // dense float64 GEMM: C[m][n] = beta_bias[n] + sum_k A[m][k] B[k][n]  (row-major,
 // lda/ldb/ldc leading dimensions); bias nullable.

@@ -252,6 +252,41 @@ __global__ __launch_bounds__(kStreamThreads) void fine2d_pcg64_kernel(
 // Tile ownership: wave w of NW owns grid rows [w*RPW, (w+1)*RPW); lane l owns columns
 // [l*CPL, (l+1)*CPL).  Padded unknowns (outside the n x n grid) carry zero
 // coefficients and stay zero.
+
+// DPP helpers (gfx9 wavefront shifts; bound_ctrl fills the shifted-in lane with 0)
+template <int CTRL>
+__device__ __forceinline__ float dppf(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xf, 0xf, true));
+}
+__device__ __forceinline__ float from_west(float v) { return dppf<0x138>(v); }   // wave_shr:1
+__device__ __forceinline__ float from_east(float v) { return dppf<0x130>(v); }   // wave_shl:1
+
+// Sum over the 64 lanes, uniform result: butterflies within 16-lane rows by DPP, then
+// the four row sums read into scalar registers.
+__device__ __forceinline__ float wave_sum_dpp(float v) {
+  v += dppf<0xB1>(v);    // quad_perm [1,0,3,2]
+  v += dppf<0x4E>(v);    // quad_perm [2,3,0,1]
+  v += dppf<0x141>(v);   // row_half_mirror
+  v += dppf<0x140>(v);   // row_mirror
+  const int iv = __builtin_bit_cast(int, v);
+  const float s0 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(iv, 0));
+  const float s1 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(iv, 16));
+  const float s2 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(iv, 32));
+  const float s3 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(iv, 48));
+  return (s0 + s1) + (s2 + s3);
+}
+
+template <int NW>
+__device__ __forceinline__ float block_sum_f(float v, float* slots, int lane, int wave) {
+  v = wave_sum_dpp(v);
+  if (lane == 0) slots[wave] = v;
+  __syncthreads();
+  float acc = slots[0];
+#pragma unroll
+  for (int w = 1; w < NW; ++w) acc += slots[w];
+  return acc;
+}
+
 template <int NW, int CPL, int RPW>
 struct Resident {
   static constexpr int ROWW = 64 * CPL;   // halo row width per wave
@@ -260,22 +295,23 @@ struct Resident {
   // EW[s][t] is the coefficient of the face west of column t, NS[s][t] that of the face
   // south of row s.  The faces east of the lane's last column and north of the wave's
   // last row belong to the neighbouring lane / wave, which supplies the products
-  // coefficient * value: across lanes by a shuffle, across waves in the `top` halo.
+  // coefficient * value: across lanes by a DPP shift, across waves through LDS halos.
+  // The halos hold the previous iteration's r and p rows; the current p row is
+  // r + beta p, formed here (the halo exchange rides on the reduction barrier).
   static __device__ __forceinline__ float matvec(const float (&P)[RPW][CPL], float (&Q)[RPW][CPL],
                                                  const float (&EW)[RPW][CPL],
                                                  const float (&NS)[RPW][CPL],
-                                                 const float* top, const float* bot, int lane,
-                                                 int wave) {
+                                                 const float* hr_top, const float* hp_top,
+                                                 const float* hr_bot, const float* hp_bot,
+                                                 float beta, int lane, int wave) {
     float pq = 0.f;
 #pragma unroll
     for (int s = 0; s < RPW; ++s) {
-      float wv = __shfl_up(P[s][CPL - 1], 1, 64);
-      float ep = __shfl_down(EW[s][0] * P[s][0], 1, 64);
-      if (lane == 0) wv = 0.f;
-      if (lane == 63) ep = 0.f;
+      const float wv = from_west(P[s][CPL - 1]);
+      const float ep = from_east(EW[s][0] * P[s][0]);
 #pragma unroll
       for (int t = 0; t < CPL; ++t) {
-        float left = (t == 0) ? wv : P[s][t - 1];
+        const float left = (t == 0) ? wv : P[s][t - 1];
         float q = P[s][t];
         q = fmaf(-EW[s][t], left, q);
         if (t == CPL - 1)
@@ -283,15 +319,19 @@ struct Resident {
         else
           q = fmaf(-EW[s][t + 1], P[s][t + 1], q);
         float down;
-        if (s == 0)
-          down = (wave > 0) ? bot[(wave - 1) * ROWW + lane * CPL + t] : 0.f;
-        else
+        if (s == 0) {
+          const int h = (wave - 1) * ROWW + lane * CPL + t;
+          down = (wave > 0) ? fmaf(beta, hp_bot[h], hr_bot[h]) : 0.f;
+        } else {
           down = P[s - 1][t];
+        }
         q = fmaf(-NS[s][t], down, q);
-        if (s == RPW - 1)
-          q -= (wave < NW - 1) ? top[(wave + 1) * ROWW + lane * CPL + t] : 0.f;
-        else
+        if (s == RPW - 1) {
+          const int h = (wave + 1) * ROWW + lane * CPL + t;
+          q -= (wave < NW - 1) ? fmaf(beta, hp_top[h], hr_top[h]) : 0.f;
+        } else {
           q = fmaf(-NS[s + 1][t], P[s + 1][t], q);
+        }
         Q[s][t] = q;
         pq = fmaf(P[s][t], q, pq);
       }
@@ -299,27 +339,22 @@ struct Resident {
     return pq;
   }
 
-  // top: coefficient of the face south of row 0 times the row-0 value (the wave above
+  // top: south-face coefficient times the row-0 value (the wave below the boundary
   // needs it as its northern term); bot: the last row's values.
-  static __device__ __forceinline__ void store_halo(const float (&V)[RPW][CPL],
-                                                    const float (&NS)[RPW][CPL], float* top,
-                                                    float* bot, int lane, int wave) {
+  static __device__ __forceinline__ void store_halo(const float (&Rv)[RPW][CPL], const float (&Pv)[RPW][CPL],
+                                                    const float (&NS)[RPW][CPL], float* hr_top,
+                                                    float* hp_top, float* hr_bot, float* hp_bot,
+                                                    int lane, int wave) {
 #pragma unroll
     for (int t = 0; t < CPL; ++t) {
-      top[wave * ROWW + lane * CPL + t] = NS[0][t] * V[0][t];
-      bot[wave * ROWW + lane * CPL + t] = V[RPW - 1][t];
+      const int h = wave * ROWW + lane * CPL + t;
+      hr_top[h] = NS[0][t] * Rv[0][t];
+      hp_top[h] = NS[0][t] * Pv[0][t];
+      hr_bot[h] = Rv[RPW - 1][t];
+      hp_bot[h] = Pv[RPW - 1][t];
     }
   }
 };
-
-__device__ __forceinline__ float block_sum_f(float v, float* slots, int lane, int wave, int nw) {
-  v = wave_sum(v);
-  if (lane == 0) slots[wave] = v;
-  __syncthreads();
-  float acc = slots[0];
-  for (int w = 1; w < nw; ++w) acc += slots[w];
-  return acc;
-}
 
 // LDS: xs[n*n] float32 staging tile of the whole system, halo rows, reduction slots.
 template <int NW, int CPL, int RPW>
@@ -329,12 +364,14 @@ __global__ __launch_bounds__(64 * NW) void fine2d_resident_kernel(
     double* __restrict__ out, double* __restrict__ resbuf, int64_t M, int N, int skip_first,
     const uint8_t* __restrict__ active, int* __restrict__ flag, unsigned long long* __restrict__ cnt) {
   using RS = Resident<NW, CPL, RPW>;
-  unsigned long long tot_it = 0, tot_pass = 0, max_it = 0;
+  const long long t_start = clock64();
+  long long t_cg = 0;
   extern __shared__ float xs[];                       // [n*n]
-  __shared__ float top[NW * RS::ROWW];
-  __shared__ float bot[NW * RS::ROWW];
+  __shared__ float hr_top[NW * RS::ROWW], hp_top[NW * RS::ROWW];
+  __shared__ float hr_bot[NW * RS::ROWW], hp_bot[NW * RS::ROWW];
   __shared__ float fslots[2][NW];
   __shared__ double dslots[4 * NW];
+  unsigned long long tot_it = 0, tot_pass = 0, max_it = 0;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int64_t sys = blockIdx.x;
@@ -382,41 +419,35 @@ __global__ __launch_bounds__(64 * NW) void fine2d_resident_kernel(
 
   for (int step = 0; step < J; ++step) {
     // float64 residual of the increment equation: M e = tau f - tau A w
-    double acc[2] = {0.0, 0.0};
-    const bool mx[2] = {true, true};
+    double acc[3] = {0.0, 0.0, 0.0};
+    const bool mx[3] = {true, true, true};
 #pragma unroll 1
-    for (int r = 0; r < RPW; ++r) {
-      int j = j0 + r;
-      if (j >= n) break;
-#pragma unroll 1
-      for (int t = 0; t < CPL; ++t) {
-        int i = i0 + t;
-        if (i < n) {
-          int64_t p = (int64_t)j * n + i;
-          double rv = tauf - c * stencil64(af, w, g, i, j);
-          res[p] = rv;
-          acc[0] = nanmax(acc[0], fabs(rv));
-          acc[1] = nanmax(acc[1], fabs(w[p]));
-        }
+    for (int k = 0; k < RPW * CPL; ++k) {
+      const int j = j0 + k / CPL, i = i0 + k % CPL;
+      if (j < n && i < n) {
+        int64_t p = (int64_t)j * n + i;
+        double rv = tauf - c * stencil64(af, w, g, i, j);
+        res[p] = rv;
+        acc[0] = nanmax(acc[0], fabs(rv));
+        acc[1] = nanmax(acc[1], fabs(w[p]));
+        acc[2] = nanmax(acc[2], dv[p] * fabs(rv));
       }
     }
-    block_reduce<2>(acc, mx, dslots);
+    block_reduce<3>(acc, mx, dslots);
     double rmax = acc[0];
+    // float32 right-hand sides are normalised by their max (no underflow late in the passes)
+    double sig = acc[2];
     const double target = residual_target(tol, acc[1], tauf, dmax);
     int pass = 0;
-    while (rmax > target && pass < kMaxRefinePasses) {
-      // scaled right-hand side D^{-1/2} res, staged through LDS
+    while (rmax > target && sig > 0.0 && pass < kMaxRefinePasses) {
+      const double isig = 1.0 / sig;
+      // scaled right-hand side D^{-1/2} res / sig, staged through LDS
 #pragma unroll 1
-      for (int r = 0; r < RPW; ++r) {
-        int j = j0 + r;
-        if (j >= n) break;
-#pragma unroll 1
-        for (int t = 0; t < CPL; ++t) {
-          int i = i0 + t;
-          if (i < n) {
-            int64_t p = (int64_t)j * n + i;
-            xs[p] = (float)(dv[p] * res[p]);
-          }
+      for (int k = 0; k < RPW * CPL; ++k) {
+        const int j = j0 + k / CPL, i = i0 + k % CPL;
+        if (j < n && i < n) {
+          int64_t p = (int64_t)j * n + i;
+          xs[p] = (float)(isig * dv[p] * res[p]);
         }
       }
       __syncthreads();
@@ -434,14 +465,15 @@ __global__ __launch_bounds__(64 * NW) void fine2d_resident_kernel(
           rr = fmaf(v, v, rr);
         }
       }
-      rr = block_sum_f(rr, fslots[0], lane, wave, NW);
+      RS::store_halo(R, P, NS, hr_top, hp_top, hr_bot, hp_bot, lane, wave);
+      rr = block_sum_f<NW>(rr, fslots[1], lane, wave);
       const float stop = pcg_rtol * pcg_rtol * rr;
+      float beta = 0.f;
       int it = 0;
+      const long long t0 = clock64();
       while (rr > stop && it < maxit) {
-        RS::store_halo(P, NS, top, bot, lane, wave);
-        __syncthreads();
-        float pq = RS::matvec(P, Q, EW, NS, top, bot, lane, wave);
-        pq = block_sum_f(pq, fslots[0], lane, wave, NW);
+        float pq = RS::matvec(P, Q, EW, NS, hr_top, hp_top, hr_bot, hp_bot, beta, lane, wave);
+        pq = block_sum_f<NW>(pq, fslots[0], lane, wave);
         const float alpha = rr / pq;
         float rn = 0.f;
 #pragma unroll
@@ -452,8 +484,9 @@ __global__ __launch_bounds__(64 * NW) void fine2d_resident_kernel(
             R[r][t] = fmaf(-alpha, Q[r][t], R[r][t]);
             rn = fmaf(R[r][t], R[r][t], rn);
           }
-        rn = block_sum_f(rn, fslots[1], lane, wave, NW);
-        const float beta = rn / rr;
+        RS::store_halo(R, P, NS, hr_top, hp_top, hr_bot, hp_bot, lane, wave);
+        rn = block_sum_f<NW>(rn, fslots[1], lane, wave);
+        beta = rn / rr;
         rr = rn;
 #pragma unroll
         for (int r = 0; r < RPW; ++r)
@@ -461,6 +494,7 @@ __global__ __launch_bounds__(64 * NW) void fine2d_resident_kernel(
           for (int t = 0; t < CPL; ++t) P[r][t] = fmaf(beta, P[r][t], R[r][t]);
         ++it;
       }
+      t_cg += clock64() - t0;
       if (it >= maxit && rr > stop) fail = true;
       tot_it += it;
       max_it = it > (int)max_it ? it : max_it;
@@ -476,33 +510,31 @@ __global__ __launch_bounds__(64 * NW) void fine2d_resident_kernel(
         }
       }
       __syncthreads();
-      double emax[1] = {0.0};
-      const bool mx1[1] = {true};
+      double emax[2] = {0.0, 0.0};
+      const bool mx1[2] = {true, true};
+      const double sdv = sig;
 #pragma unroll 1
-      for (int r = 0; r < RPW; ++r) {
-        int j = j0 + r;
-        if (j >= n) break;
-#pragma unroll 1
-        for (int t = 0; t < CPL; ++t) {
-          int i = i0 + t;
-          if (i < n) {
-            int64_t p = (int64_t)j * n + i;
-            double ep = dv[p] * (double)xs[p];
-            double ew = i > 0 ? dv[p - 1] * (double)xs[p - 1] : 0.0;
-            double ee = i < n - 1 ? dv[p + 1] * (double)xs[p + 1] : 0.0;
-            double es = j > 0 ? dv[p - n] * (double)xs[p - n] : 0.0;
-            double en = j < n - 1 ? dv[p + n] * (double)xs[p + n] : 0.0;
-            double Me = ep + c * (af[g.fW(i, j)] * (ep - ew) + af[g.fE(i, j)] * (ep - ee) +
-                                  af[g.fS(i, j)] * (ep - es) + af[g.fN(i, j)] * (ep - en));
-            double rv = res[p] - Me;
-            res[p] = rv;
-            w[p] += ep;
-            emax[0] = nanmax(emax[0], fabs(rv));
-          }
+      for (int k = 0; k < RPW * CPL; ++k) {
+        const int j = j0 + k / CPL, i = i0 + k % CPL;
+        if (j < n && i < n) {
+          int64_t p = (int64_t)j * n + i;
+          double ep = sdv * dv[p] * (double)xs[p];
+          double ew = i > 0 ? sdv * dv[p - 1] * (double)xs[p - 1] : 0.0;
+          double ee = i < n - 1 ? sdv * dv[p + 1] * (double)xs[p + 1] : 0.0;
+          double es = j > 0 ? sdv * dv[p - n] * (double)xs[p - n] : 0.0;
+          double en = j < n - 1 ? sdv * dv[p + n] * (double)xs[p + n] : 0.0;
+          double Me = ep + c * (af[g.fW(i, j)] * (ep - ew) + af[g.fE(i, j)] * (ep - ee) +
+                                af[g.fS(i, j)] * (ep - es) + af[g.fN(i, j)] * (ep - en));
+          double rv = res[p] - Me;
+          res[p] = rv;
+          w[p] += ep;
+          emax[0] = nanmax(emax[0], fabs(rv));
+          emax[1] = nanmax(emax[1], dv[p] * fabs(rv));
         }
       }
-      block_reduce<1>(emax, mx1, dslots);
+      block_reduce<2>(emax, mx1, dslots);
       rmax = emax[0];
+      sig = emax[1];
       ++pass;
     }
     tot_pass += pass;
@@ -514,6 +546,8 @@ __global__ __launch_bounds__(64 * NW) void fine2d_resident_kernel(
     atomicAdd(&cnt[1], tot_pass);
     atomicAdd(&cnt[2], (unsigned long long)J);
     atomicMax(&cnt[3], max_it);
+    atomicAdd(&cnt[8], (unsigned long long)(clock64() - t_start));
+    atomicAdd(&cnt[9], (unsigned long long)t_cg);
   }
 }
 
@@ -566,22 +600,26 @@ int propagate_impl(klecgc_ctx* ctx, const klecgc_problem& p, const FineArgs& fa,
     double* tab = (double*)ctx->ws.get(WS_FACTORS, sizeof(double) * 3 * n * M);
     tri_factor_kernel<<<dim3((unsigned)((M + 63) / 64)), dim3(64), 0, st>>>(fa.a, n, c, M, tab);
     KC_LAUNCH_CHECK();
-    fine1d_kernel<<<dim3((unsigned)((nsys + 63) / 64)), dim3(64), 0, st>>>(
-        tab, n, J, tauf, sr, fa.out, M, N, fa.skip_first, fa.active);
-    KC_LAUNCH_CHECK();
+    timed(ctx, KT_FINE, [&] {
+      fine1d_kernel<<<dim3((unsigned)((nsys + 63) / 64)), dim3(64), 0, st>>>(
+          tab, n, J, tauf, sr, fa.out, M, N, fa.skip_first, fa.active);
+      KC_LAUNCH_CHECK();
+    });
     return KC_OK;
   }
   const int64_t Nx = (int64_t)n * n;
   const int64_t Fc = 2LL * n * (n + 1);
-  const double tol = p.inner_rtol > 0 ? p.inner_rtol : 1e-14;
+  const double tol = p.inner_rtol > 0 ? p.inner_rtol : 1e-13;
   const int maxit = p.inner_max_iter > 0 ? p.inner_max_iter : 4000;
   double* dinv = (double*)ctx->ws.get(WS_DINV, sizeof(double) * Nx * M);
   bool resident = (p.precision == KC_PREC_F32_REFINED) && n <= 128;
   float* sf = resident ? (float*)ctx->ws.get(WS_FSCALED, sizeof(float) * Fc * M) : nullptr;
   build_tables_2d(st, fa.a, n, c, M, dinv, sf);
+  double* resbuf = resident ? (double*)ctx->ws.get(WS_KRYLOV, sizeof(double) * Nx * nsys) : nullptr;
+  double* scr = resident ? nullptr : (double*)ctx->ws.get(WS_KRYLOV, sizeof(double) * 3 * Nx * nsys);
+  const float pcg_rtol = 1e-6f;
+  timed(ctx, KT_FINE, [&] {
   if (resident) {
-    double* resbuf = (double*)ctx->ws.get(WS_KRYLOV, sizeof(double) * Nx * nsys);
-    const float pcg_rtol = 1e-6f;
     if (n <= 16)
       launch_resident<8, 1, 2>(st, nsys, fa.a, sf, dinv, n, c, tauf, J, tol, pcg_rtol, maxit, sr,
                                fa.out, resbuf, M, N, fa.skip_first, fa.active, flag, cnt);
@@ -596,11 +634,11 @@ int propagate_impl(klecgc_ctx* ctx, const klecgc_problem& p, const FineArgs& fa,
                                                            pcg_rtol, maxit, sr, fa.out, resbuf, M, N,
                                                            fa.skip_first, fa.active, flag, cnt);
   } else {
-    double* scr = (double*)ctx->ws.get(WS_KRYLOV, sizeof(double) * 3 * Nx * nsys);
     fine2d_pcg64_kernel<<<dim3((unsigned)nsys), dim3(kStreamThreads), 0, st>>>(
         fa.a, dinv, n, c, tauf, J, tol, maxit, sr, fa.out, scr, M, N, fa.skip_first, fa.active, flag, cnt);
     KC_LAUNCH_CHECK();
   }
+  });
   return status_collect(ctx, ds, 0) ? KC_ENOCONV : KC_OK;
 }
 
@@ -608,18 +646,15 @@ int fine_propagate_impl(klecgc_ctx* ctx, const klecgc_problem& p, const FineArgs
   return propagate_impl(ctx, p, fa, p.T / p.N / p.J, p.J, p.N);
 }
 
-int coarse_sweep_impl(klecgc_ctx* ctx, const klecgc_problem& p, const double* a, const double* u0,
-                      int64_t M, double* U) {
-  // U[m][s] = G(U[m][s-1]), sequential over slices; each launch is one BE step of dT
-  // for all samples (the N = 1 batch view of slice s).
+// Sequential sweep over the slices: U[m][s] = P(U[m][s-1]) with P = J steps of tau,
+// each launch advancing all samples by one slice (an [M][1] batch).
+static int sweep_impl(klecgc_ctx* ctx, const klecgc_problem& p, const double* a, const double* u0,
+                      int64_t M, double* U, double tau, int J) {
   const int64_t Nx = n_unknowns(p);
-  const double dT = p.T / p.N;
   int rc = KC_OK;
+  double* stage = (double*)ctx->ws.get(WS_START, sizeof(double) * Nx * M);
+  double* outb = (double*)ctx->ws.get(WS_GEMM_A, sizeof(double) * Nx * M);
   for (int s = 0; s < p.N; ++s) {
-    // batch of M systems, each reading row s-1 (or u0) and writing row s, stride N*Nx
-    // handled by staging through a contiguous [M][Nx] start buffer
-    double* stage = (double*)ctx->ws.get(WS_START, sizeof(double) * Nx * M);
-    double* outb = (double*)ctx->ws.get(WS_GEMM_A, sizeof(double) * Nx * M);
     if (s == 0) {
       if (u0)
         KC_TRY_HIP(hipMemcpyAsync(stage, u0, sizeof(double) * Nx * M, hipMemcpyDeviceToDevice, ctx->stream));
@@ -630,12 +665,22 @@ int coarse_sweep_impl(klecgc_ctx* ctx, const klecgc_problem& p, const double* a,
                                   sizeof(double) * Nx, M, hipMemcpyDeviceToDevice, ctx->stream));
     }
     FineArgs fa{a, stage, nullptr, false, 0, nullptr, outb, M};
-    int r = propagate_impl(ctx, p, fa, dT, 1, 1);
+    int r = propagate_impl(ctx, p, fa, tau, J, 1);
     if (r != KC_OK) rc = r;
     KC_TRY_HIP(hipMemcpy2DAsync(U + s * Nx, sizeof(double) * Nx * p.N, outb, sizeof(double) * Nx,
                                 sizeof(double) * Nx, M, hipMemcpyDeviceToDevice, ctx->stream));
   }
   return rc;
+}
+
+int coarse_sweep_impl(klecgc_ctx* ctx, const klecgc_problem& p, const double* a, const double* u0,
+                      int64_t M, double* U) {
+  return sweep_impl(ctx, p, a, u0, M, U, p.T / p.N, 1);
+}
+
+int serial_fine_impl(klecgc_ctx* ctx, const klecgc_problem& p, const double* a, const double* u0,
+                     int64_t M, double* U) {
+  return sweep_impl(ctx, p, a, u0, M, U, p.T / p.N / p.J, p.J);
 }
 
 }  // namespace kc

@@ -100,6 +100,25 @@ def test_cgc_diag_solve(ctx, dim, n, N, alpha):
         assert rel(got[m], want) < max(1e-10, 1e-13 * amp)
 
 
+@pytest.mark.parametrize("n,N,alpha", [(12, 8, 1e-2), (20, 16, 1e-4), (33, 8, 1e-4), (64, 16, 1e-4), (1, 4, 0.3)])
+def test_cgc_diag_solve_resident(ctx, n, N, alpha):
+    # float32 complex COCG with float64 residual refinement (CU-resident, n <= 64)
+    log(f"cgc resident n={n} N={N} alpha={alpha}")
+    w = W.small_2d(n=n, N=N, alpha=alpha)
+    M = 2
+    xi = W.draw_xi(M, w.d, 19)
+    a = oracle_faces(w, xi)
+    r = W.draw_normal((M, N, w.Nx), 20)
+    prob = spec_of(w, precision=1, cgc_rtol=1e-14)
+    u = torch.empty_like(dev(r))
+    ctx.cgc_diag_solve(prob, dev(a), dev(r), u, allow_noconv=True)
+    got = host(u)
+    amp = alpha ** (-(N - 1) / N)
+    for m in range(M):
+        want = cgc.diag_solve(2, n, a[m], w.T / N, alpha, r[m])
+        assert rel(got[m], want) < max(1e-10, 1e-13 * amp)
+
+
 @pytest.mark.parametrize("dim,n", [(1, 31), (2, 12)])
 def test_coarse_propagate(ctx, dim, n):
     log(f"coarse sweep dim={dim} n={n}")
