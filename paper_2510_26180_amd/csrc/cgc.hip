@@ -523,7 +523,11 @@ __global__ __launch_bounds__(64 * NW) void cocg_resident_kernel(
     float rr = acc3[2];
     const float stop_in = inner_rtol * inner_rtol * rr;
     int it = 0;
-    while (rr > stop_in && it < maxit) {
+    // a pass restarts from the true float64 residual after a few times n iterations
+    // (COCG can stagnate near a breakdown of its unconjugated form)
+    const int cap = maxit < 4 * n + 200 ? maxit : 4 * n + 200;
+    bool bad = false;
+    while (rr > stop_in && it < cap) {
       // halos of P
 #pragma unroll
       for (int t = 0; t < CPL; ++t) {
@@ -613,6 +617,7 @@ __global__ __launch_bounds__(64 * NW) void cocg_resident_kernel(
           const cf beta = cf_div(rzn, rz);
           rz = rzn;
           rr = racc[2];
+          if (!(rr < 3.0e38f) || !(fabsf(rz.x) + fabsf(rz.y) < 3.0e38f)) bad = true;
 #pragma unroll
           for (int r = 0; r < RPW; ++r)
 #pragma unroll
@@ -623,10 +628,14 @@ __global__ __launch_bounds__(64 * NW) void cocg_resident_kernel(
         }
       }
       ++it;
+      if (bad) break;
     }
     tot_it += it;
     max_it = it > (int)max_it ? it : max_it;
-    if (it >= maxit && rr > stop_in) atomicOr(flag, 1);
+    if (bad) {   // keep the last good q and report
+      if (threadIdx.x == 0) atomicOr(flag, 1);
+      break;
+    }
     __syncthreads();   // correction tile complete
     // float64: e = sig D^{-1/2} X; res -= (lambda I + dT A) e; q += e
     double acc[2] = {0.0, 0.0};
@@ -673,6 +682,189 @@ __global__ __launch_bounds__(64 * NW) void cocg_resident_kernel(
         acc[0] += rv.x * rv.x + rv.y * rv.y;
         acc[1] = nanmax(acc[1], dr[p] * fmax(fabs(rv.x), fabs(rv.y)));
       }
+    }
+    block_reduce<2>(acc, sm, dsl);
+    rn2 = acc[0];
+    sig = acc[1];
+    ++pass;
+  }
+  if (threadIdx.x == 0) {
+    if (rn2 > stop2) atomicOr(flag, 1);
+    atomicAdd(&cnt[0], tot_it);
+    atomicAdd(&cnt[1], (unsigned long long)pass);
+    atomicAdd(&cnt[2], 1ull);
+    atomicMax(&cnt[3], max_it);
+  }
+}
+
+// Streaming variant for grids too large for one CU's registers: one work-group per
+// (m, k) system, complex64 Krylov vectors and float32 scaled couplings in per-system
+// global scratch, with the same float64 residual refinement as above.
+struct Cocg32Scratch {
+  float2 *X, *R, *P, *Q;   // [Nx] each
+  float *cw, *cs, *th;     // west / south coupling, imaginary diagonal
+};
+
+__global__ __launch_bounds__(512) void cocg32_stream_kernel(
+    const double* __restrict__ a, const double* __restrict__ dinvr, int n, double cT, int N, double alpha,
+    double rtol, float inner_rtol, int maxit, const uint8_t* __restrict__ active, double* __restrict__ spec,
+    double* __restrict__ resbuf, float* __restrict__ scr, int* __restrict__ flag,
+    unsigned long long* __restrict__ cnt) {
+  constexpr int NW = 8;
+  __shared__ float fsl[2][3 * NW];
+  __shared__ double dsl[4 * NW];
+  const int K = N / 2 + 1;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t sys = blockIdx.x;
+  const int64_t m = sys / K;
+  const int k = (int)(sys % K);
+  if (active && !active[m]) return;
+  const int64_t Nx = (int64_t)n * n;
+  const int64_t nx = (int64_t)n * (n + 1);
+  const double* af = a + m * 2 * nx;
+  const double* dr = dinvr + sys * Nx;
+  double2* q = (double2*)spec + sys * Nx;
+  double2* res = (double2*)resbuf + sys * Nx;
+  float* base = scr + sys * 11 * Nx;
+  float2* X = (float2*)base;
+  float2* R = X + Nx;
+  float2* P = R + Nx;
+  float2* Q = P + Nx;
+  float* cw = (float*)(Q + Nx);
+  float* cs = cw + Nx;
+  float* th = cs + Nx;
+  double sv, cv;
+  sincospi(-2.0 * k / N, &sv, &cv);
+  const double an = exp(log(alpha) / N);
+  const double lre = 1.0 - an * cv, lim = -an * sv;
+
+  double bn[2] = {0.0, 0.0};
+  const bool sm[2] = {false, true};
+  for (int64_t p = threadIdx.x; p < Nx; p += blockDim.x) {
+    const int i = (int)(p % n), j = (int)(p / n);
+    cw[p] = i >= 1 ? (float)(cT * af[(int64_t)j * (n + 1) + i] * dr[p - 1] * dr[p]) : 0.f;
+    cs[p] = j >= 1 ? (float)(cT * af[nx + (int64_t)j * n + i] * dr[p - n] * dr[p]) : 0.f;
+    th[p] = (float)(lim * dr[p] * dr[p]);
+    const double2 v = q[p];
+    res[p] = v;
+    q[p] = make_double2(0.0, 0.0);
+    bn[0] += v.x * v.x + v.y * v.y;
+    bn[1] = nanmax(bn[1], dr[p] * fmax(fabs(v.x), fabs(v.y)));
+  }
+  block_reduce<2>(bn, sm, dsl);
+  const double stop2 = rtol * rtol * bn[0];
+  double rn2 = bn[0];
+  double sig = bn[1];
+  unsigned long long tot_it = 0, max_it = 0;
+  int pass = 0;
+  while (rn2 > stop2 && sig > 0.0 && pass < 12) {
+    const double isig = 1.0 / sig;
+    float acc3[3] = {0.f, 0.f, 0.f};
+    for (int64_t p = threadIdx.x; p < Nx; p += blockDim.x) {
+      const double2 rv = res[p];
+      const float2 v = make_float2((float)(isig * dr[p] * rv.x), (float)(isig * dr[p] * rv.y));
+      R[p] = v;
+      P[p] = v;
+      X[p] = make_float2(0.f, 0.f);
+      acc3[0] += v.x * v.x - v.y * v.y;
+      acc3[1] += 2.f * v.x * v.y;
+      acc3[2] += v.x * v.x + v.y * v.y;
+    }
+    block_sum_fk<NW, 3>(acc3, fsl[1], lane, wave);   // its barrier also publishes P
+    cf rz = {acc3[0], acc3[1]};
+    float rr = acc3[2];
+    const float stop_in = inner_rtol * inner_rtol * rr;
+    int it = 0;
+    // a pass restarts from the true float64 residual after a few times n iterations
+    // (COCG can stagnate near a breakdown of its unconjugated form)
+    const int cap = maxit < 4 * n + 200 ? maxit : 4 * n + 200;
+    bool bad = false;
+    while (rr > stop_in && it < cap) {
+      float pq2[2] = {0.f, 0.f};
+      for (int64_t p = threadIdx.x; p < Nx; p += blockDim.x) {
+        const int i = (int)(p % n), j = (int)(p / n);
+        const float2 pv = P[p];
+        const float2 zero = make_float2(0.f, 0.f);
+        const float2 lw = i > 0 ? P[p - 1] : zero, le = i < n - 1 ? P[p + 1] : zero;
+        const float2 ls = j > 0 ? P[p - n] : zero, ln = j < n - 1 ? P[p + n] : zero;
+        const float ce = i < n - 1 ? cw[p + 1] : 0.f, cn = j < n - 1 ? cs[p + n] : 0.f;
+        const float c0 = cw[p], c1 = cs[p], t0 = th[p];
+        float qx = pv.x - t0 * pv.y - c0 * lw.x - ce * le.x - c1 * ls.x - cn * ln.x;
+        float qy = pv.y + t0 * pv.x - c0 * lw.y - ce * le.y - c1 * ls.y - cn * ln.y;
+        Q[p] = make_float2(qx, qy);
+        pq2[0] += pv.x * qx - pv.y * qy;
+        pq2[1] += pv.x * qy + pv.y * qx;
+      }
+      block_sum_fk<NW, 2>(pq2, fsl[0], lane, wave);
+      const cf al = cf_div(rz, cf{pq2[0], pq2[1]});
+      float racc[3] = {0.f, 0.f, 0.f};
+      for (int64_t p = threadIdx.x; p < Nx; p += blockDim.x) {
+        const float2 pv = P[p], qv = Q[p];
+        float2 xv = X[p], rv = R[p];
+        xv.x += al.x * pv.x - al.y * pv.y;
+        xv.y += al.x * pv.y + al.y * pv.x;
+        rv.x -= al.x * qv.x - al.y * qv.y;
+        rv.y -= al.x * qv.y + al.y * qv.x;
+        X[p] = xv;
+        R[p] = rv;
+        racc[0] += rv.x * rv.x - rv.y * rv.y;
+        racc[1] += 2.f * rv.x * rv.y;
+        racc[2] += rv.x * rv.x + rv.y * rv.y;
+      }
+      block_sum_fk<NW, 3>(racc, fsl[1], lane, wave);
+      const cf rzn = {racc[0], racc[1]};
+      const cf be = cf_div(rzn, rz);
+      rz = rzn;
+      rr = racc[2];
+      if (!(rr < 3.0e38f) || !(fabsf(rz.x) + fabsf(rz.y) < 3.0e38f)) bad = true;
+      for (int64_t p = threadIdx.x; p < Nx; p += blockDim.x) {
+        const float2 pv = P[p], rv = R[p];
+        P[p] = make_float2(rv.x + be.x * pv.x - be.y * pv.y, rv.y + be.x * pv.y + be.y * pv.x);
+      }
+      __syncthreads();
+      ++it;
+      if (bad) break;
+    }
+    tot_it += it;
+    max_it = it > (int)max_it ? it : max_it;
+    if (bad) {   // keep the last good q and report
+      if (threadIdx.x == 0) atomicOr(flag, 1);
+      break;
+    }
+    double acc[2] = {0.0, 0.0};
+    for (int64_t p = threadIdx.x; p < Nx; p += blockDim.x) {
+      const int i = (int)(p % n), j = (int)(p / n);
+      const float2 xp = X[p];
+      const double ex = sig * dr[p] * xp.x, ey = sig * dr[p] * xp.y;
+      double sx = 0.0, sy = 0.0;
+      const double aW = af[(int64_t)j * (n + 1) + i], aE = af[(int64_t)j * (n + 1) + i + 1];
+      const double aS = af[nx + (int64_t)j * n + i], aN = af[nx + (int64_t)(j + 1) * n + i];
+      double nxv, nyv;
+      nxv = nyv = 0.0;
+      if (i > 0) { const float2 v = X[p - 1]; nxv = sig * dr[p - 1] * v.x; nyv = sig * dr[p - 1] * v.y; }
+      sx += aW * (ex - nxv); sy += aW * (ey - nyv);
+      nxv = nyv = 0.0;
+      if (i < n - 1) { const float2 v = X[p + 1]; nxv = sig * dr[p + 1] * v.x; nyv = sig * dr[p + 1] * v.y; }
+      sx += aE * (ex - nxv); sy += aE * (ey - nyv);
+      nxv = nyv = 0.0;
+      if (j > 0) { const float2 v = X[p - n]; nxv = sig * dr[p - n] * v.x; nyv = sig * dr[p - n] * v.y; }
+      sx += aS * (ex - nxv); sy += aS * (ey - nyv);
+      nxv = nyv = 0.0;
+      if (j < n - 1) { const float2 v = X[p + n]; nxv = sig * dr[p + n] * v.x; nyv = sig * dr[p + n] * v.y; }
+      sx += aN * (ex - nxv); sy += aN * (ey - nyv);
+      const double mex = lre * ex - lim * ey + cT * sx;
+      const double mey = lre * ey + lim * ex + cT * sy;
+      double2 rv = res[p];
+      rv.x -= mex;
+      rv.y -= mey;
+      res[p] = rv;
+      double2 qv = q[p];
+      qv.x += ex;
+      qv.y += ey;
+      q[p] = qv;
+      acc[0] += rv.x * rv.x + rv.y * rv.y;
+      acc[1] = nanmax(acc[1], dr[p] * fmax(fabs(rv.x), fabs(rv.y)));
     }
     block_reduce<2>(acc, sm, dsl);
     rn2 = acc[0];
@@ -779,6 +971,20 @@ int shifted_solve_impl(klecgc_ctx* ctx, const klecgc_problem& p, const double* a
   status_reset(ctx, ds);
   const double rtol = p.cgc_rtol > 0 ? p.cgc_rtol : 1e-13;
   const int maxit = p.cgc_max_iter > 0 ? p.cgc_max_iter : 20000;
+  if (p.precision == KC_PREC_F32_REFINED && p.n > 64) {
+    double* dr = (double*)ctx->ws.get(WS_DINV, sizeof(double) * Nx * nsys);
+    double* resb = (double*)ctx->ws.get(WS_KRYLOV, sizeof(double) * 2 * Nx * nsys);
+    float* scr = (float*)ctx->ws.get(WS_FINE_AUX, sizeof(float) * 11 * Nx * nsys);
+    shift_dinv_kernel<<<dim3((unsigned)((Nx + 255) / 256), (unsigned)nsys), dim3(256), 0, st>>>(
+        a, p.n, cT, p.N, p.alpha, M, dr);
+    KC_LAUNCH_CHECK();
+    timed(ctx, KT_SHIFTED, [&] {
+      cocg32_stream_kernel<<<dim3((unsigned)nsys), dim3(512), 0, st>>>(
+          a, dr, p.n, cT, p.N, p.alpha, rtol, 1e-5f, maxit, active, spec, resb, scr, ds.flag, ds.cnt);
+      KC_LAUNCH_CHECK();
+    });
+    return status_collect(ctx, ds, 4) ? KC_ENOCONV : KC_OK;
+  }
   if (p.precision == KC_PREC_F32_REFINED && p.n <= 64) {
     double* dr = (double*)ctx->ws.get(WS_DINV, sizeof(double) * Nx * nsys);
     double* resb = (double*)ctx->ws.get(WS_KRYLOV, sizeof(double) * 2 * Nx * nsys);

@@ -54,6 +54,7 @@ enum WsSlot {
   WS_GEMM_A,
   WS_GEMM_B,
   WS_STATUS,
+  WS_FINE_AUX,      // float32 correction tiles of the shifted solves
   WS_COUNT
 };
 

@@ -100,7 +100,8 @@ def test_cgc_diag_solve(ctx, dim, n, N, alpha):
         assert rel(got[m], want) < max(1e-10, 1e-13 * amp)
 
 
-@pytest.mark.parametrize("n,N,alpha", [(12, 8, 1e-2), (20, 16, 1e-4), (33, 8, 1e-4), (64, 16, 1e-4), (1, 4, 0.3)])
+@pytest.mark.parametrize("n,N,alpha", [(12, 8, 1e-2), (20, 16, 1e-4), (33, 8, 1e-4), (64, 16, 1e-4), (1, 4, 0.3),
+                                     (65, 4, 1e-2), (100, 8, 1e-4)])
 def test_cgc_diag_solve_resident(ctx, n, N, alpha):
     # float32 complex COCG with float64 residual refinement (CU-resident, n <= 64)
     log(f"cgc resident n={n} N={N} alpha={alpha}")
