@@ -31,6 +31,20 @@ FLOPS_PER_PCG_UNKNOWN_IT = 18.0        # 5-point scaled matvec 8, two dots 4, th
 BYTES_PER_COCG_UNKNOWN_IT = 128.0      # complex128 vectors streamed per COCG iteration
 
 
+def profiled_traffic(kernel_src: str, profile_json: str):
+    """HBM bytes per launch from the committed rocprofv3 counter passes, or None if the
+    kernel source has changed since the counters were taken."""
+    import hashlib
+    try:
+        prof = json.load(open(os.path.join(ROOT, "profiles", profile_json)))
+        sha = hashlib.sha256(open(os.path.join(ROOT, "paper_2510_26180_amd", "csrc", kernel_src), "rb").read()).hexdigest()
+    except OSError:
+        return None
+    if prof.get("fine_hip_sha256") != sha:
+        return None
+    return (prof["fetch_bytes_per_launch"] + prof["write_bytes_per_launch"]) / 1e9
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -160,7 +174,10 @@ def main():
         flops = FLOPS_PER_PCG_UNKNOWN_IT * w.Nx * stats["fine_krylov_its"]
         achieved = flops / (dom_ms / 1e3) / 1e12
         roof = {"kernel": "fine2d_resident_kernel", "bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
-                "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
+                "traffic": profiled_traffic("fine.hip", "fine2d_resident_c2_traffic.json"),
+                "traffic_unit": "GB/launch (HBM FETCH+WRITE, copy-calibrated)",
+                "algorithmic_tflop_per_launch": flops / 1e12 / max(dom_n, 1),
                 "launches": dom_n, "ms_per_launch": dom_ms / max(dom_n, 1)}
     elif dom == "shifted":
         byts = BYTES_PER_COCG_UNKNOWN_IT * w.Nx * stats["cgc_krylov_its"]
