@@ -59,6 +59,7 @@ enum { KC_SAMPLE_CONVERGED = 0, KC_SAMPLE_MAXITER = 1, KC_SAMPLE_NONFINITE = 2 }
 typedef struct klecgc_ctx klecgc_ctx;
 typedef struct klecgc_kle klecgc_kle;
 typedef struct klecgc_gpc klecgc_gpc;
+typedef struct klecgc_mlp klecgc_mlp;
 
 /* One problem family (uniform batch).  Section 3.1: N coarse slices of length
  * dT = T/N, J fine steps of dt = dT/J per slice, backward Euler for F and G;
@@ -108,6 +109,7 @@ int klecgc_set_stream(klecgc_ctx* ctx, void* hip_stream);
 const char* klecgc_last_error(const klecgc_ctx* ctx);
 void klecgc_kle_free(klecgc_kle* h);
 void klecgc_gpc_free(klecgc_gpc* h);
+void klecgc_mlp_free(klecgc_mlp* h);
 /* Counters of the last call on ctx (instrumentation), out16[16]: [0..3] fine implicit
  * solves: total Krylov iterations, total float64 refinement passes, number of implicit
  * steps, max iterations of one solve; [4..7] the same for the shifted solves of step (b)
@@ -117,7 +119,8 @@ int klecgc_last_stats(const klecgc_ctx* ctx, int64_t* out16);
 /* Device time of the last call on ctx, measured with HIP events on the context stream
  * around each kernel launch (instrumentation): ms8[c] milliseconds and count8[c] launches
  * (count8 nullable) for the kernel classes c = 0 fine propagator, 1 shifted solves of
- * step (b), 2 forward slice FFT, 3 inverse slice FFT, 4 defect stencil, 5 prediction GEMM. */
+ * step (b), 2 forward slice FFT, 3 inverse slice FFT, 4 defect stencil, 5 prediction GEMM,
+ * 6 MLP forward/backward/Adam. */
 int klecgc_last_times(const klecgc_ctx* ctx, double* ms8, int64_t* count8);
 /* Library version string (static storage). */
 const char* klecgc_version(void);
@@ -205,6 +208,60 @@ int parareal_solve(klecgc_ctx* ctx, const klecgc_problem* prob, const double* a_
                    const double* u0_dev, int64_t M, int32_t init, const double* init_dev,
                    const klecgc_gpc* gpc, const double* xi_dev, double* U_dev,
                    int32_t* iters_host, int32_t* status_host, double* delta_hist_host);
+
+/* ---- learned initial guess (replaces the gPC map of Algorithm 3 step 6) ------
+ * A multilayer perceptron maps xi [d] to the states of all N slices restricted to an
+ * nc x nc grid (n_out = N nc^2), trained on solutions the method produced:
+ *     pre1 = X W1 + b1, h1 = GELU(pre1); pre2 = h1 W2 + b2, h2 = GELU(pre2);
+ *     Y = h2 W3 + b3;  loss = mean((Y - T)^2) on per-output z-scored targets.
+ * GELU is x Phi(x) (exact erf).  GEMMs run on BF16 MFMA with FP32 accumulation;
+ * the operands X, W1..W3, h1, h2 and the backward products dY, dpre2, dpre1 are
+ * rounded to bfloat16 (nearest even).  Adam (beta1 0.9, beta2 0.999, eps 1e-8,
+ * bias-corrected) updates FP32 master weights.
+ * Flat parameter layout (FP32): W1 [n_in][H], b1 [H], W2 [H][H], b2 [H],
+ * W3 [H][n_out], b3 [n_out]; n_params = n_in H + H + H H + H + H n_out + n_out.
+ * Grid transfer (2D): bilinear interpolation with zero boundary values between the
+ * n x n grid (h = 1/(n+1)) and the nc x nc grid (H = 1/(nc+1)), evaluated at the
+ * nodes of the target grid; both x fastest. */
+/* Allocate a network (weights zero, normalisation identity).  1 <= n_in <= 4096,
+ * 1 <= hidden <= 16384, hidden * n_out < 2^31.  *n_params (nullable) receives the
+ * flat parameter count. */
+int mlp_create(klecgc_ctx* ctx, int32_t n_in, int32_t hidden, int64_t n_out, klecgc_mlp** out,
+               int64_t* n_params);
+/* Load FP32 parameters params_dev [n_params] (e.g. a seeded initialisation drawn by
+ * the caller) and reset the Adam state. */
+int mlp_set_params(klecgc_ctx* ctx, klecgc_mlp* h, const float* params_dev);
+/* Copy the FP32 parameters [n_params] and the target mean / std [n_out] to device
+ * memory (each pointer nullable). */
+int mlp_get_params(klecgc_ctx* ctx, const klecgc_mlp* h, float* params_dev, float* mean_dev,
+                   float* std_dev);
+/* Y_dev [n][n_out] FP32: store the per-output mean and population standard deviation
+ * over the n rows in the handle (std 0 is replaced by 1) and z-score Y in place. */
+int mlp_normalize_targets(klecgc_ctx* ctx, klecgc_mlp* h, float* Y_dev, int64_t n);
+/* Adam training: `epochs` passes over the n rows, mini-batches of `batch` consecutive
+ * rows of the order perm_dev [epochs][n] int32 (nullable = identity; each row a
+ * permutation of 0..n-1), one Adam step per mini-batch, learning rate lr.
+ * xi_dev [n][n_in] float64, Y_dev [n][n_out] z-scored FP32 targets.
+ * loss_host [epochs] (nullable) receives the mean of the per-batch losses weighted by
+ * batch size (evaluated before each step). */
+int mlp_train(klecgc_ctx* ctx, klecgc_mlp* h, const double* xi_dev, const float* Y_dev, int64_t n,
+              int32_t epochs, int32_t batch, float lr, const int32_t* perm_dev, float* loss_host);
+/* Y_dev [M][n_out] FP32 = network output (normalised units) for xi_dev [M][n_in]. */
+int mlp_predict(klecgc_ctx* ctx, klecgc_mlp* h, const double* xi_dev, int64_t M, float* Y_dev);
+/* Gradient of the loss of one batch (all n rows, n <= 65535) at the current
+ * parameters into grads_dev [n_params] FP32 (flat layout); *loss_host (nullable)
+ * receives the loss.  Parameters and Adam state are unchanged. */
+int mlp_grad(klecgc_ctx* ctx, klecgc_mlp* h, const double* xi_dev, const float* Y_dev, int64_t n,
+             float* grads_dev, double* loss_host);
+/* Restriction: Yc[r] = the bilinear interpolant of U[r] (n x n) at the nc x nc nodes,
+ * for r < R.  U_dev [R][n*n] float64, Yc_dev [R][nc*nc] FP32. */
+int grid_restrict(klecgc_ctx* ctx, int32_t n, int32_t nc, const double* U_dev, int64_t R,
+                  float* Yc_dev);
+/* Learned initial guess for parareal_solve (KC_INIT_GIVEN): U0[m][s] = bilinear
+ * prolongation to n x n of mean + std * Y[m][s] (Y = mlp_predict(xi)[m] read as
+ * [N][nc*nc]).  Requires n_out = N nc^2.  xi_dev [M][n_in], U0_dev [M][N][n*n]. */
+int mlp_initial_guess(klecgc_ctx* ctx, klecgc_mlp* h, int32_t n, int32_t nc, int32_t N,
+                      const double* xi_dev, int64_t M, double* U0_dev);
 
 #ifdef __cplusplus
 }

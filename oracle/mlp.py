@@ -117,6 +117,16 @@ def adam_step(p: Params, g: dict, m: dict, v: dict, t: int, lr: float, b1=0.9, b
         setattr(p, k, getattr(p, k) - lr * mh / (np.sqrt(vh) + eps))
 
 
+def zscore(Y: np.ndarray):
+    """Per-output mean and population standard deviation over the rows (a zero
+    deviation is replaced by 1) and the z-scored targets."""
+    Y = np.asarray(Y, dtype=np.float64)
+    mu = Y.mean(0)
+    sd = np.sqrt(((Y - mu) ** 2).mean(0))
+    sd = np.where(sd > 0, sd, 1.0)
+    return mu, sd, (Y - mu) / sd
+
+
 # ---------------------------------------------------------------- grid transfer
 def _interp_matrix_1d(n_from: int, n_to: int) -> np.ndarray:
     """Linear interpolation (zero end values) from n_from interior nodes on (0,1) to the

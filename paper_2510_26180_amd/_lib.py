@@ -50,6 +50,7 @@ SIGNATURES = {
     "klecgc_last_error": (ctypes.c_char_p, [_vp]),
     "klecgc_kle_free": (None, [_vp]),
     "klecgc_gpc_free": (None, [_vp]),
+    "klecgc_mlp_free": (None, [_vp]),
     "klecgc_version": (ctypes.c_char_p, []),
     "klecgc_last_stats": (ctypes.c_int, [_vp, _P(ctypes.c_int64)]),
     "klecgc_last_times": (ctypes.c_int, [_vp, _P(ctypes.c_double), _P(ctypes.c_int64)]),
@@ -64,6 +65,16 @@ SIGNATURES = {
     "coarse_propagate": (ctypes.c_int, [_vp, _P(Problem), _vp, _vp, _i64, _vp]),
     "parareal_solve": (ctypes.c_int, [_vp, _P(Problem), _vp, _vp, _i64, _i32, _vp, _vp, _vp, _vp,
                                       _P(_i32), _P(_i32), _P(ctypes.c_double)]),
+    "mlp_create": (ctypes.c_int, [_vp, _i32, _i32, _i64, _P(_vp), _P(_i64)]),
+    "mlp_set_params": (ctypes.c_int, [_vp, _vp, _vp]),
+    "mlp_get_params": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
+    "mlp_normalize_targets": (ctypes.c_int, [_vp, _vp, _vp, _i64]),
+    "mlp_train": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i64, _i32, _i32, ctypes.c_float, _vp,
+                                 _P(ctypes.c_float)]),
+    "mlp_predict": (ctypes.c_int, [_vp, _vp, _vp, _i64, _vp]),
+    "mlp_grad": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i64, _vp, _P(ctypes.c_double)]),
+    "grid_restrict": (ctypes.c_int, [_vp, _i32, _i32, _vp, _i64, _vp]),
+    "mlp_initial_guess": (ctypes.c_int, [_vp, _vp, _i32, _i32, _i32, _vp, _i64, _vp]),
 }
 
 _lib = None

@@ -124,7 +124,7 @@ class Context:
                 "cgc_krylov_its": v[4], "cgc_solves": v[6], "cgc_max_its": v[7],
                 "fine_cycles": v[8], "fine_krylov_cycles": v[9]}
 
-    KCLASSES = ("fine", "shifted", "fft_fwd", "fft_inv", "defect", "gemm")
+    KCLASSES = ("fine", "shifted", "fft_fwd", "fft_inv", "defect", "gemm", "mlp")
 
     def last_times(self) -> dict:
         ms = (ctypes.c_double * 8)()
@@ -209,3 +209,47 @@ class Context:
         self._check(rc, allow=(-5,) if allow_noconv else ())
         return (np.frombuffer(iters, dtype=np.int32).copy(), np.frombuffer(status, dtype=np.int32).copy(),
                 np.frombuffer(hist, dtype=np.float64).reshape(M, prob.max_iter).copy(), rc)
+
+    # ---- learned initial guess
+    def mlp_create(self, n_in: int, hidden: int, n_out: int, params=None) -> Handle:
+        out = ctypes.c_void_p()
+        npar = ctypes.c_int64()
+        self._check(self.lib.mlp_create(self.h, n_in, hidden, n_out, ctypes.byref(out), ctypes.byref(npar)))
+        h = Handle(out.value, self.lib.klecgc_mlp_free, n_in=n_in, hidden=hidden, n_out=n_out, n_params=npar.value)
+        if params is not None:
+            self.mlp_set_params(h, params)
+        return h
+
+    def mlp_set_params(self, h: Handle, params):
+        self._check(self.lib.mlp_set_params(self.h, h.ptr, _ptr(params)))
+
+    def mlp_get_params(self, h: Handle, params=None, mean=None, std=None):
+        self._check(self.lib.mlp_get_params(self.h, h.ptr, _ptr(params), _ptr(mean), _ptr(std)))
+
+    def mlp_normalize_targets(self, h: Handle, Y):
+        self._check(self.lib.mlp_normalize_targets(self.h, h.ptr, _ptr(Y), Y.shape[0]))
+        return Y
+
+    def mlp_train(self, h: Handle, xi, Y, epochs: int, batch: int, lr: float, perm=None) -> np.ndarray:
+        loss = (ctypes.c_float * max(epochs, 1))()
+        self._check(self.lib.mlp_train(self.h, h.ptr, _ptr(xi), _ptr(Y), xi.shape[0], epochs, batch, lr,
+                                       _ptr(perm), loss))
+        return np.frombuffer(loss, dtype=np.float32)[:epochs].copy()
+
+    def mlp_predict(self, h: Handle, xi, Y):
+        self._check(self.lib.mlp_predict(self.h, h.ptr, _ptr(xi), xi.shape[0], _ptr(Y)))
+        return Y
+
+    def mlp_grad(self, h: Handle, xi, Y, grads) -> float:
+        loss = ctypes.c_double()
+        self._check(self.lib.mlp_grad(self.h, h.ptr, _ptr(xi), _ptr(Y), xi.shape[0], _ptr(grads), ctypes.byref(loss)))
+        return loss.value
+
+    def grid_restrict(self, n: int, nc: int, U, Yc):
+        R = U.numel() // (n * n)
+        self._check(self.lib.grid_restrict(self.h, n, nc, _ptr(U), R, _ptr(Yc)))
+        return Yc
+
+    def mlp_initial_guess(self, h: Handle, n: int, nc: int, N: int, xi, U0):
+        self._check(self.lib.mlp_initial_guess(self.h, h.ptr, n, nc, N, _ptr(xi), xi.shape[0], _ptr(U0)))
+        return U0

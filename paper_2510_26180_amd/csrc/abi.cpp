@@ -143,7 +143,8 @@ static int parareal_impl(klecgc_ctx* ctx, const klecgc_problem& p, const double*
   switch (init) {
     case KC_INIT_GIVEN:
       KC_REQUIRE(init_dev, KC_EINVAL, "init_dev required for KC_INIT_GIVEN");
-      KC_TRY_HIP(hipMemcpyAsync(U, init_dev, sizeof(double) * M * S, hipMemcpyDeviceToDevice, st));
+      if (init_dev != U)
+        KC_TRY_HIP(hipMemcpyAsync(U, init_dev, sizeof(double) * M * S, hipMemcpyDeviceToDevice, st));
       break;
     case KC_INIT_ZERO:
       KC_TRY_HIP(hipMemsetAsync(U, 0, sizeof(double) * M * S, st));
@@ -564,6 +565,82 @@ int parareal_solve(klecgc_ctx* ctx, const klecgc_problem* prob, const double* a_
     validate_problem(*prob);
     return parareal_impl(ctx, *prob, a_dev, u0_dev, M, init, init_dev, gpc, xi_dev, U_dev, iters_host,
                          status_host, delta_hist_host);
+  });
+}
+
+int mlp_create(klecgc_ctx* ctx, int32_t n_in, int32_t hidden, int64_t n_out, klecgc_mlp** out, int64_t* n_params) {
+  return guarded(ctx, [&] {
+    KC_REQUIRE(out, KC_EINVAL, "null argument");
+    *out = nullptr;
+    int rc = mlp_create_impl(ctx, n_in, hidden, n_out, out);
+    if (n_params) *n_params = mlp_param_count(*out);
+    return rc;
+  });
+}
+
+int mlp_set_params(klecgc_ctx* ctx, klecgc_mlp* h, const float* params_dev) {
+  return guarded(ctx, [&] {
+    KC_REQUIRE(h && params_dev, KC_EINVAL, "null argument");
+    return mlp_set_params_impl(ctx, h, params_dev);
+  });
+}
+
+int mlp_get_params(klecgc_ctx* ctx, const klecgc_mlp* h, float* params_dev, float* mean_dev, float* std_dev) {
+  return guarded(ctx, [&] {
+    KC_REQUIRE(h, KC_EINVAL, "null argument");
+    int rc = mlp_get_params_impl(ctx, h, params_dev, mean_dev, std_dev);
+    KC_TRY_HIP(hipStreamSynchronize(ctx->stream));
+    return rc;
+  });
+}
+
+int mlp_normalize_targets(klecgc_ctx* ctx, klecgc_mlp* h, float* Y_dev, int64_t n) {
+  return guarded(ctx, [&] {
+    KC_REQUIRE(h && Y_dev, KC_EINVAL, "null argument");
+    KC_REQUIRE(n >= 1, KC_EINVAL, "n must be >= 1");
+    return mlp_normalize_impl(ctx, h, Y_dev, n);
+  });
+}
+
+int mlp_train(klecgc_ctx* ctx, klecgc_mlp* h, const double* xi_dev, const float* Y_dev, int64_t n, int32_t epochs,
+              int32_t batch, float lr, const int32_t* perm_dev, float* loss_host) {
+  return guarded(ctx, [&] {
+    KC_REQUIRE(h && xi_dev && Y_dev, KC_EINVAL, "null argument");
+    KC_REQUIRE(n >= 1, KC_EINVAL, "n must be >= 1");
+    return mlp_train_impl(ctx, h, xi_dev, Y_dev, n, epochs, batch, lr, perm_dev, loss_host);
+  });
+}
+
+int mlp_predict(klecgc_ctx* ctx, klecgc_mlp* h, const double* xi_dev, int64_t M, float* Y_dev) {
+  return guarded(ctx, [&] {
+    KC_REQUIRE(h && xi_dev && Y_dev, KC_EINVAL, "null argument");
+    KC_REQUIRE(M >= 1, KC_EINVAL, "M must be >= 1");
+    return mlp_predict_impl(ctx, h, xi_dev, M, Y_dev);
+  });
+}
+
+int mlp_grad(klecgc_ctx* ctx, klecgc_mlp* h, const double* xi_dev, const float* Y_dev, int64_t n, float* grads_dev,
+             double* loss_host) {
+  return guarded(ctx, [&] {
+    KC_REQUIRE(h && xi_dev && Y_dev, KC_EINVAL, "null argument");
+    return mlp_grad_impl(ctx, h, xi_dev, Y_dev, n, grads_dev, loss_host);
+  });
+}
+
+int grid_restrict(klecgc_ctx* ctx, int32_t n, int32_t nc, const double* U_dev, int64_t R, float* Yc_dev) {
+  return guarded(ctx, [&] {
+    KC_REQUIRE(U_dev && Yc_dev, KC_EINVAL, "null argument");
+    KC_REQUIRE(n >= 1 && nc >= 1 && R >= 1, KC_EINVAL, "n, nc and R must be >= 1");
+    return grid_restrict_impl(ctx, n, nc, U_dev, R, Yc_dev);
+  });
+}
+
+int mlp_initial_guess(klecgc_ctx* ctx, klecgc_mlp* h, int32_t n, int32_t nc, int32_t N, const double* xi_dev,
+                      int64_t M, double* U0_dev) {
+  return guarded(ctx, [&] {
+    KC_REQUIRE(h && xi_dev && U0_dev, KC_EINVAL, "null argument");
+    KC_REQUIRE(n >= 1 && nc >= 1 && N >= 1 && M >= 1, KC_EINVAL, "n, nc, N and M must be >= 1");
+    return mlp_initial_guess_impl(ctx, h, n, nc, N, xi_dev, M, U0_dev);
   });
 }
 

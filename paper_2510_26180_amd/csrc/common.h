@@ -55,6 +55,7 @@ enum WsSlot {
   WS_GEMM_B,
   WS_STATUS,
   WS_FINE_AUX,      // float32 correction tiles of the shifted solves
+  WS_MLP,           // MLP predictions before prolongation
   WS_COUNT
 };
 
@@ -119,7 +120,7 @@ void status_reset(klecgc_ctx* ctx, const DevStatus& st);
 int status_collect(klecgc_ctx* ctx, const DevStatus& st, int base);
 
 // Kernel classes timed with HIP events on the context stream.
-enum KClass { KT_FINE = 0, KT_SHIFTED = 1, KT_FFT_FWD = 2, KT_FFT_INV = 3, KT_DEFECT = 4, KT_GEMM = 5, KT_COUNT = 8 };
+enum KClass { KT_FINE = 0, KT_SHIFTED = 1, KT_FFT_FWD = 2, KT_FFT_INV = 3, KT_DEFECT = 4, KT_GEMM = 5, KT_MLP = 6, KT_COUNT = 8 };
 // Records an event pair around `launch` and adds the elapsed time to ctx->ktime[cls]
 // (synchronises the stream).
 template <class F>
@@ -186,6 +187,23 @@ void launch_hermite(hipStream_t s, const double* xi, int64_t M, int d, const int
                     int pmax, double* Psi);
 void launch_col_mean_center(hipStream_t s, const double* S, int64_t n_t, int64_t L, double* mean,
                             double* Sc);
+
+// MLP initial guess (BF16 MFMA)
+int64_t mlp_param_count(const klecgc_mlp* h);
+int64_t mlp_out_count(const klecgc_mlp* h);
+int mlp_in_count(const klecgc_mlp* h);
+int mlp_create_impl(klecgc_ctx* ctx, int n_in, int hidden, int64_t n_out, klecgc_mlp** out);
+int mlp_set_params_impl(klecgc_ctx* ctx, klecgc_mlp* h, const float* params);
+int mlp_get_params_impl(klecgc_ctx* ctx, const klecgc_mlp* h, float* params, float* mean, float* stdv);
+int mlp_normalize_impl(klecgc_ctx* ctx, klecgc_mlp* h, float* Y, int64_t n);
+int mlp_predict_impl(klecgc_ctx* ctx, klecgc_mlp* h, const double* xi, int64_t M, float* Y);
+int mlp_grad_impl(klecgc_ctx* ctx, klecgc_mlp* h, const double* xi, const float* Y, int64_t n, float* grads,
+                  double* loss);
+int mlp_train_impl(klecgc_ctx* ctx, klecgc_mlp* h, const double* xi, const float* Y, int64_t n, int epochs, int batch,
+                   float lr, const int32_t* perm, float* loss_host);
+int grid_restrict_impl(klecgc_ctx* ctx, int n, int nc, const double* U, int64_t R, float* Yc);
+int mlp_initial_guess_impl(klecgc_ctx* ctx, klecgc_mlp* h, int n, int nc, int N, const double* xi, int64_t M,
+                           double* U0);
 
 // host linear algebra
 void sym_eig(int n, std::vector<double>& A, std::vector<double>& w);   // A -> eigenvectors (cols)

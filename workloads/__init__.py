@@ -20,7 +20,8 @@ from typing import Optional
 
 import numpy as np
 
-__all__ = ["Workload", "CONFIGS", "draw_xi", "get", "small_1d", "small_2d"]
+__all__ = ["Workload", "CONFIGS", "MlpSpec", "MLP_C4", "draw_xi", "draw_mlp_init", "draw_perms", "get",
+           "small_1d", "small_2d"]
 
 
 @dataclasses.dataclass(frozen=True)
@@ -67,10 +68,29 @@ CONFIGS = {
     # FP32 PCG fine path refined to FP64, FP64 coarse correction.
     "c2_2d_n128": Workload("c2_2d_n128", 2, 128, 1.0, 64, 64, 1e-4, 1.0, 10, 0.3, 1.0,
                            256, "f32_refined", 1e-8, 60, 3, 512, 1e-10, 1002, 2002),
+    # The c2 problem with the learned initial guess: 4096 training solutions,
+    # 512 fresh evaluation samples (gPC degree 3 on the same training set for comparison).
+    "c4_2d_n128_mlp": Workload("c4_2d_n128_mlp", 2, 128, 1.0, 64, 64, 1e-4, 1.0, 10, 0.3, 1.0,
+                               512, "f32_refined", 1e-8, 60, 3, 4096, 1e-10, 1004, 2004),
     # 2D 512x512, KL d=20 (corr 0.2, sigma 1), N=256, J=128, M=64.
     "c5_2d_n512": Workload("c5_2d_n512", 2, 512, 1.0, 256, 128, 1e-4, 1.0, 20, 0.2, 1.0,
                            64, "f32_refined", 1e-8, 60, 2, 256, 1e-10, 1005, 2005),
 }
+
+
+@dataclasses.dataclass(frozen=True)
+class MlpSpec:
+    """Learned initial guess: xi [d] -> GELU(hidden) -> GELU(hidden) -> N nc^2 outputs."""
+    hidden: int
+    nc: int                  # coarse grid (nc x nc interior nodes, H = 1/(nc+1))
+    epochs: int
+    batch: int
+    lr: float
+    seed_init: int
+    seed_perm: int
+
+
+MLP_C4 = MlpSpec(hidden=256, nc=32, epochs=200, batch=256, lr=1e-3, seed_init=3004, seed_perm=4004)
 
 
 def get(name: str) -> Workload:
@@ -114,6 +134,25 @@ def draw_ragged(M: int, seed: int, grids=(64, 128, 256), slices=(32, 64, 128)):
 def draw_normal(shape, seed: int, scale: float = 1.0) -> np.ndarray:
     rng = np.random.Generator(np.random.PCG64(seed))
     return scale * rng.standard_normal(shape)
+
+
+def draw_mlp_init(n_in: int, hidden: int, n_out: int, seed: int) -> np.ndarray:
+    """Flat FP32 MLP parameters [W1 b1 W2 b2 W3 b3] (W [in][out] row-major): weights
+    i.i.d. U(-1/sqrt(fan_in), 1/sqrt(fan_in)), biases zero."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    parts = []
+    for fi, fo in ((n_in, hidden), (hidden, hidden), (hidden, n_out)):
+        b = 1.0 / np.sqrt(fi)
+        parts.append(rng.uniform(-b, b, size=fi * fo))
+        parts.append(np.zeros(fo))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def draw_perms(epochs: int, n: int, seed: int) -> np.ndarray:
+    """One random permutation of 0..n-1 per epoch, int32 [epochs][n]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return np.stack([rng.permutation(n) for _ in range(epochs)]).astype(np.int32) if epochs else \
+        np.zeros((0, n), np.int32)
 
 
 def describe(w: Workload, M: Optional[int] = None) -> dict:
