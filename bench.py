@@ -9,7 +9,12 @@ whole batch (gPC prediction + all parareal iterations to tol 1e-8), inputs resid
 in HBM.  The offline stage (training solutions, snapshot KL, gPC fit) runs before the
 timed region and is reported separately.
 
-Usage: python bench.py [--steps K] [--warmup W] [--gpus 1]
+With --config c4_2d_n128_mlp the same problem is solved on 512 fresh samples from the
+learned initial guess (an MLP trained on 4096 serial-fine solutions restricted to a
+32x32 grid, BF16 MFMA) and, for comparison, from the gPC guess fitted to the same
+training set; `value` is then the MLP-initialised rate.
+
+Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--config NAME] [--init gpc|mlp|both]
 """
 from __future__ import annotations
 
@@ -26,6 +31,7 @@ if ROOT not in sys.path:
 
 PEAK_HBM_GBS = 8000.0
 PEAK_FP32_TFLOPS = 157.3
+PEAK_BF16_TFLOPS = 2500.0
 # algorithmic work per unit
 FLOPS_PER_PCG_UNKNOWN_IT = 18.0        # 5-point scaled matvec 8, two dots 4, three axpys 6
 BYTES_PER_COCG_UNKNOWN_IT = 128.0      # complex128 vectors streamed per COCG iteration
@@ -74,6 +80,9 @@ def main():
     ap.add_argument("--config", default="c2_2d_n128")
     ap.add_argument("--M", type=int, default=0, help="override the batch size (0 = config)")
     ap.add_argument("--n-train", type=int, default=0)
+    ap.add_argument("--init", choices=["gpc", "mlp", "both"], default=None,
+                    help="initial guess (default: gpc; both for the MLP workload)")
+    ap.add_argument("--epochs", type=int, default=0, help="override the MLP epochs (0 = spec)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-oracle-check", action="store_true")
     args = ap.parse_args()
@@ -109,48 +118,101 @@ def main():
     ctx.kle_synthesize(field_h, xi_eval, a_eval)
     ctx.kle_synthesize(field_h, xi_train, a_train)
 
-    # ---- offline stage (untimed): training solutions, snapshot KL, gPC fit
+    init = args.init or ("both" if "mlp" in w.name else "gpc")
+    inits = {"gpc": ["gpc"], "mlp": ["mlp"], "both": ["mlp", "gpc"]}[init]
+    spec = W.MLP_C4
+    if args.epochs:
+        spec = W.MlpSpec(**{**spec.__dict__, "epochs": args.epochs})
+
+    # ---- offline stage (untimed): training solutions, snapshot KL + gPC fit, MLP training
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     S = torch.empty((w.n_train, w.N * w.Nx), dtype=torch.float64, device=dev)
     ctx.serial_fine_propagate(prob, a_train, None, S.view(w.n_train, w.N, w.Nx))
     torch.cuda.synchronize()
     t_snap = time.perf_counter() - t0
-    kl = ctx.kle_build(S, w.eps_kl)
-    gpc = ctx.gpc_fit(kl, xi_train, w.gpc_degree)
-    torch.cuda.synchronize()
-    t_offline = time.perf_counter() - t0
+    log(f"offline: {w.n_train} training solutions {t_snap:.1f} s")
+    offline = {"training_solutions_s": t_snap}
+    gpc = mlp = None
+    learned = None
+    if "mlp" in inits:
+        t1 = time.perf_counter()
+        nc = spec.nc
+        O = w.N * nc * nc
+        Yc = torch.empty((w.n_train, O), dtype=torch.float32, device=dev)
+        ctx.grid_restrict(w.n, nc, S, Yc)
+        mlp = ctx.mlp_create(w.d, spec.hidden, O, params=torch.as_tensor(
+            W.draw_mlp_init(w.d, spec.hidden, O, spec.seed_init)).to(dev))
+        ctx.mlp_normalize_targets(mlp, Yc)
+        perm = torch.as_tensor(W.draw_perms(spec.epochs, w.n_train, spec.seed_perm)).to(dev)
+        losses = ctx.mlp_train(mlp, xi_train, Yc, epochs=spec.epochs, batch=spec.batch, lr=spec.lr, perm=perm,
+                               lr_final=spec.lr_final)
+        torch.cuda.synchronize()
+        t_train = time.perf_counter() - t1
+        ms_train = ctx.last_times()["mlp"][0]
+        H, B, n_in_pad = spec.hidden, spec.batch, (w.d + 15) // 16 * 16
+        n_steps = spec.epochs * ((w.n_train + B - 1) // B)
+        flops_step = 2.0 * B * (n_in_pad * H + H * H + H * O) + 2.0 * B * (2 * H * O + 2 * H * H + w.d * H)
+        tflops = flops_step * n_steps / (ms_train / 1e3) / 1e12
+        learned = {"hidden": H, "nc": nc, "outputs": O, "params": mlp.n_params, "epochs": spec.epochs,
+                   "batch": B, "lr": spec.lr, "lr_final": spec.lr_final, "adam_steps": n_steps, "loss_first": float(losses[0]),
+                   "loss_last": float(losses[-1]), "train_s": t_train, "train_kernel_ms": ms_train,
+                   "train_tflops": tflops, "train_frac_bf16_peak": tflops / PEAK_BF16_TFLOPS}
+        log(f"offline: MLP {mlp.n_params} params, {spec.epochs} epochs in {t_train:.1f} s "
+            f"({tflops:.1f} TFLOP/s), loss {losses[0]:.3e} -> {losses[-1]:.3e}")
+        offline["mlp_train_s"] = t_train
+        del Yc
+    if "gpc" in inits:
+        t1 = time.perf_counter()
+        kl = ctx.kle_build(S, w.eps_kl)
+        gpc = ctx.gpc_fit(kl, xi_train, w.gpc_degree)
+        torch.cuda.synchronize()
+        offline["kl_gpc_s"] = time.perf_counter() - t1
+        log(f"offline: KL modes {kl.n_modes}, gPC P={gpc.P}, {offline['kl_gpc_s']:.1f} s")
     del S
-    log(f"offline: {w.n_train} training solutions {t_snap:.1f} s, KL modes {kl.n_modes}, gPC P={gpc.P}, "
-        f"total {t_offline:.1f} s")
+    t_offline = sum(offline.values())
 
     U = torch.empty((w.M, w.N, w.Nx), dtype=torch.float64, device=dev)
 
-    def step():
+    def step(kind):
+        if kind == "mlp":
+            ctx.mlp_initial_guess(mlp, w.n, spec.nc, w.N, xi_eval, U)
+            return ctx.parareal_solve(prob, a_eval, U, init=K.KC_INIT_GIVEN, init_U=U, allow_noconv=True)
         return ctx.parareal_solve(prob, a_eval, U, init=K.KC_INIT_GPC, gpc=gpc, xi=xi_eval, allow_noconv=True)
 
-    for i in range(args.warmup):
-        its, st, _, _ = step()
-        log(f"warmup {i}: iterations mean {its.mean():.2f} max {its.max()}")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        its, status, hist, rc = step()
-        log(f"step {i}: iterations mean {its.mean():.2f} max {its.max()} rc={rc}")
-    torch.cuda.synchronize()
-    t_steps = time.perf_counter() - t0
-    ms_per_step = 1e3 * t_steps / args.steps
-    ktimes = ctx.last_times()
-    stats = ctx.last_stats()
-
-    # ---- accuracy: batched GPU serial fine reference for every sample
+    # accuracy reference: batched GPU serial fine for every evaluation sample
     ref = torch.empty_like(U)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ctx.serial_fine_propagate(prob, a_eval, None, ref)
     torch.cuda.synchronize()
     t_serial = time.perf_counter() - t0
-    err = ((U - ref).abs().amax(dim=(1, 2)) / ref.abs().amax(dim=(1, 2))).cpu().numpy()
+    refmax = ref.abs().amax(dim=(1, 2))
+    results = {}
+    for kind in inits:
+        # quality of the initial guess itself (untimed)
+        if kind == "mlp":
+            ctx.mlp_initial_guess(mlp, w.n, spec.nc, w.N, xi_eval, U)
+        else:
+            ctx.gpc_predict(gpc, xi_eval, U.view(w.M, -1))
+        e0 = ((U - ref).abs().amax(dim=(1, 2)) / refmax).cpu().numpy()
+        for i in range(args.warmup):
+            its, st, _, _ = step(kind)
+            log(f"[{kind}] warmup {i}: iterations mean {its.mean():.2f} max {its.max()}")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            its, status, hist, rc = step(kind)
+            log(f"[{kind}] step {i}: iterations mean {its.mean():.2f} max {its.max()} rc={rc}")
+        torch.cuda.synchronize()
+        t_steps = time.perf_counter() - t0
+        ktimes = ctx.last_times()
+        stats = ctx.last_stats()
+        err = ((U - ref).abs().amax(dim=(1, 2)) / refmax).cpu().numpy()
+        results[kind] = dict(ms_per_step=1e3 * t_steps / args.steps, its=its, err=err, ktimes=ktimes, e0=e0,
+                             stats=stats, U0=U[0].cpu().numpy() if kind == inits[0] else None)
+    primary = results[inits[0]]
+    ms_per_step, its, err, ktimes, stats = (primary[k] for k in ("ms_per_step", "its", "err", "ktimes", "stats"))
     n_ok = int((err <= 1e-8).sum())
     value = n_ok / (ms_per_step / 1e3)
     oracle_check = None
@@ -160,7 +222,7 @@ def main():
         a0 = field.synthesize(lam, Phi, xi_eval_np[:1])[0]
         P = prop.Propagators(w.dim, w.n, a0, w.T, w.N, w.J, w.forcing)
         ref_o = prop.serial_fine(P, np.zeros(w.Nx), w.N)
-        U0 = U[0].cpu().numpy()
+        U0 = primary["U0"]
         R0 = ref[0].cpu().numpy()
         oracle_check = {"sample": 0,
                         "parareal_vs_oracle_serial_fine": float(np.abs(U0 - ref_o).max() / np.abs(ref_o).max()),
@@ -203,10 +265,23 @@ def main():
                      "median_rel_err": float(np.median(err)), "oracle_check": oracle_check},
         "serial_fine_gpu": {"solves_per_s": w.M / t_serial, "ms": 1e3 * t_serial},
         "offline_s": t_offline,
+        "offline": offline,
         "kernel_ms": {k: v[0] for k, v in ktimes.items()},
         "solver_stats": stats,
         "roofline": roof,
     }
+    line["init"] = inits[0]
+    if learned is not None:
+        line["learned"] = learned
+    if len(inits) > 1:
+        line["compare"] = {k: {"solves_per_s": int((r["err"] <= 1e-8).sum()) / (r["ms_per_step"] / 1e3),
+                               "ms_per_step": r["ms_per_step"], "iters_mean": float(r["its"].mean()),
+                               "iters_max": int(r["its"].max()),
+                               "hist": {int(a): int(b) for a, b in zip(*np.unique(r["its"], return_counts=True))},
+                               "n_within_1e-8": int((r["err"] <= 1e-8).sum()),
+                               "max_rel_err": float(r["err"].max()),
+                               "init_err_median": float(np.median(r["e0"])), "init_err_max": float(r["e0"].max())}
+                           for k, r in results.items()}
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
         line["cpu_baseline"] = cpu_baseline(w, xi_eval_np[0], float(its.mean()))

@@ -240,12 +240,15 @@ int mlp_get_params(klecgc_ctx* ctx, const klecgc_mlp* h, float* params_dev, floa
 int mlp_normalize_targets(klecgc_ctx* ctx, klecgc_mlp* h, float* Y_dev, int64_t n);
 /* Adam training: `epochs` passes over the n rows, mini-batches of `batch` consecutive
  * rows of the order perm_dev [epochs][n] int32 (nullable = identity; each row a
- * permutation of 0..n-1), one Adam step per mini-batch, learning rate lr.
+ * permutation of 0..n-1), one Adam step per mini-batch.  Learning rate of epoch e:
+ * lr (lr_final/lr)^(e/(epochs-1)) (geometric decay; lr_final <= 0 keeps lr).
+ * KC_EINVAL if a perm entry lies outside [0, n).
  * xi_dev [n][n_in] float64, Y_dev [n][n_out] z-scored FP32 targets.
  * loss_host [epochs] (nullable) receives the mean of the per-batch losses weighted by
  * batch size (evaluated before each step). */
 int mlp_train(klecgc_ctx* ctx, klecgc_mlp* h, const double* xi_dev, const float* Y_dev, int64_t n,
-              int32_t epochs, int32_t batch, float lr, const int32_t* perm_dev, float* loss_host);
+              int32_t epochs, int32_t batch, float lr, float lr_final, const int32_t* perm_dev,
+              float* loss_host);
 /* Y_dev [M][n_out] FP32 = network output (normalised units) for xi_dev [M][n_in]. */
 int mlp_predict(klecgc_ctx* ctx, klecgc_mlp* h, const double* xi_dev, int64_t M, float* Y_dev);
 /* Gradient of the loss of one batch (all n rows, n <= 65535) at the current

@@ -69,7 +69,7 @@ SIGNATURES = {
     "mlp_set_params": (ctypes.c_int, [_vp, _vp, _vp]),
     "mlp_get_params": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "mlp_normalize_targets": (ctypes.c_int, [_vp, _vp, _vp, _i64]),
-    "mlp_train": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i64, _i32, _i32, ctypes.c_float, _vp,
+    "mlp_train": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i64, _i32, _i32, ctypes.c_float, ctypes.c_float, _vp,
                                  _P(ctypes.c_float)]),
     "mlp_predict": (ctypes.c_int, [_vp, _vp, _vp, _i64, _vp]),
     "mlp_grad": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i64, _vp, _P(ctypes.c_double)]),

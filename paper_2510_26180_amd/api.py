@@ -230,9 +230,10 @@ class Context:
         self._check(self.lib.mlp_normalize_targets(self.h, h.ptr, _ptr(Y), Y.shape[0]))
         return Y
 
-    def mlp_train(self, h: Handle, xi, Y, epochs: int, batch: int, lr: float, perm=None) -> np.ndarray:
+    def mlp_train(self, h: Handle, xi, Y, epochs: int, batch: int, lr: float, perm=None,
+                  lr_final: float = 0.0) -> np.ndarray:
         loss = (ctypes.c_float * max(epochs, 1))()
-        self._check(self.lib.mlp_train(self.h, h.ptr, _ptr(xi), _ptr(Y), xi.shape[0], epochs, batch, lr,
+        self._check(self.lib.mlp_train(self.h, h.ptr, _ptr(xi), _ptr(Y), xi.shape[0], epochs, batch, lr, lr_final,
                                        _ptr(perm), loss))
         return np.frombuffer(loss, dtype=np.float32)[:epochs].copy()
 

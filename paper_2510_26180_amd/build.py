@@ -26,7 +26,8 @@ def sources():
 
 def build(verbose: bool = False, extra=()) -> str:
     cmd = [HIPCC, *FLAGS, *extra, "-I" + os.path.join(ROOT, "include"), "-I" + os.path.join(HERE, "csrc"),
-           *sources(), "-o", LIB + ".tmp"]
+           *sources(), "-L/opt/rocm/lib", "-Wl,-rpath,/opt/rocm/lib", "-lrocsolver", "-lrocblas",
+           "-o", LIB + ".tmp"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

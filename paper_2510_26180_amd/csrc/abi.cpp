@@ -227,6 +227,17 @@ using namespace kc;
 
 namespace {
 
+// device allocation released when the scope ends (also on an error)
+struct DevBuf {
+  void* p = nullptr;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+};
+
 template <class F>
 int guarded(klecgc_ctx* ctx, F&& f) {
   if (!ctx) return KC_EINVAL;
@@ -281,6 +292,7 @@ void klecgc_destroy(klecgc_ctx* ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
+  kc::release_blas(ctx);
   ctx->ws.release();
   for (auto& e : ctx->ev)
     if (e) (void)hipEventDestroy(e);
@@ -363,23 +375,16 @@ int kle_build(klecgc_ctx* ctx, const klecgc_kle_desc* desc, const double* S_dev,
         const int64_t L = desc->L;
         h->L = L;
         h->n_t = n_t;
-        double* Sc = nullptr;
-        double* Cd = nullptr;
+        DevBuf sc_buf, cd_buf, e_buf;
         KC_TRY_HIP(hipMalloc(&h->mean, sizeof(double) * L));
-        KC_TRY_HIP(hipMalloc(&Sc, sizeof(double) * L * n_t));
-        KC_TRY_HIP(hipMalloc(&Cd, sizeof(double) * n_t * n_t));
+        KC_TRY_HIP(hipMalloc(&sc_buf.p, sizeof(double) * L * n_t));
+        KC_TRY_HIP(hipMalloc(&cd_buf.p, sizeof(double) * n_t * n_t));
+        double* Sc = (double*)sc_buf.p;
+        double* Cd = (double*)cd_buf.p;
         launch_col_mean_center(st, S_dev, n_t, L, h->mean, Sc);
         launch_dgemm_nt(st, n_t, n_t, L, Sc, L, Sc, L, Cd, n_t, 1.0 / (double)n_t);
-        std::vector<double> C((size_t)n_t * n_t), w;
-        KC_TRY_HIP(hipMemcpyAsync(C.data(), Cd, sizeof(double) * C.size(), hipMemcpyDeviceToHost, st));
-        KC_TRY_HIP(hipStreamSynchronize(st));
-        // symmetrise the Gram matrix against summation-order asymmetry
-        for (int64_t i = 0; i < n_t; ++i)
-          for (int64_t j = 0; j < i; ++j) {
-            double v = 0.5 * (C[i * n_t + j] + C[j * n_t + i]);
-            C[i * n_t + j] = C[j * n_t + i] = v;
-          }
-        sym_eig((int)n_t, C, w);
+        std::vector<double> C, w;
+        gram_eig(ctx, (int)n_t, Cd, C, w);
         for (auto& x : w) x = std::max(x, 0.0);
         double total = 0.0;
         for (double x : w) total += x;
@@ -404,17 +409,14 @@ int kle_build(klecgc_ctx* ctx, const klecgc_kle_desc* desc, const double* S_dev,
             E[r * MQ + c] = C[r * n_t + c];
             h->zeta_train[r * MQ + c] = std::sqrt((double)n_t) * C[r * n_t + c];
           }
-        double* Ed = nullptr;
-        KC_TRY_HIP(hipMalloc(&Ed, sizeof(double) * E.size()));
+        KC_TRY_HIP(hipMalloc(&e_buf.p, sizeof(double) * E.size()));
+        double* Ed = (double*)e_buf.p;
         KC_TRY_HIP(hipMalloc(&h->W, sizeof(double) * MQ * L));
         KC_TRY_HIP(hipMalloc(&h->lam, sizeof(double) * MQ));
         KC_TRY_HIP(hipMemcpyAsync(Ed, E.data(), sizeof(double) * E.size(), hipMemcpyHostToDevice, st));
         KC_TRY_HIP(hipMemcpyAsync(h->lam, w.data(), sizeof(double) * MQ, hipMemcpyHostToDevice, st));
         launch_dgemm_tn(st, MQ, L, n_t, Ed, MQ, Sc, L, h->W, L, 1.0 / std::sqrt((double)n_t));
         KC_TRY_HIP(hipStreamSynchronize(st));
-        (void)hipFree(Ed);
-        (void)hipFree(Sc);
-        (void)hipFree(Cd);
         h->lam_host.assign(w.begin(), w.begin() + MQ);
         if (n_modes) *n_modes = MQ;
       } else {
@@ -603,11 +605,11 @@ int mlp_normalize_targets(klecgc_ctx* ctx, klecgc_mlp* h, float* Y_dev, int64_t 
 }
 
 int mlp_train(klecgc_ctx* ctx, klecgc_mlp* h, const double* xi_dev, const float* Y_dev, int64_t n, int32_t epochs,
-              int32_t batch, float lr, const int32_t* perm_dev, float* loss_host) {
+              int32_t batch, float lr, float lr_final, const int32_t* perm_dev, float* loss_host) {
   return guarded(ctx, [&] {
     KC_REQUIRE(h && xi_dev && Y_dev, KC_EINVAL, "null argument");
     KC_REQUIRE(n >= 1, KC_EINVAL, "n must be >= 1");
-    return mlp_train_impl(ctx, h, xi_dev, Y_dev, n, epochs, batch, lr, perm_dev, loss_host);
+    return mlp_train_impl(ctx, h, xi_dev, Y_dev, n, epochs, batch, lr, lr_final, perm_dev, loss_host);
   });
 }
 

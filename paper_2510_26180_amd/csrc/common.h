@@ -76,6 +76,7 @@ struct klecgc_ctx {
   double ktime[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   int64_t kcount[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   hipEvent_t ev[2] = {nullptr, nullptr};
+  void* blas = nullptr;   // rocblas handle of the offline eigen-solver (created on first use)
 };
 
 struct klecgc_kle {
@@ -200,13 +201,16 @@ int mlp_predict_impl(klecgc_ctx* ctx, klecgc_mlp* h, const double* xi, int64_t M
 int mlp_grad_impl(klecgc_ctx* ctx, klecgc_mlp* h, const double* xi, const float* Y, int64_t n, float* grads,
                   double* loss);
 int mlp_train_impl(klecgc_ctx* ctx, klecgc_mlp* h, const double* xi, const float* Y, int64_t n, int epochs, int batch,
-                   float lr, const int32_t* perm, float* loss_host);
+                   float lr, float lr_final, const int32_t* perm, float* loss_host);
 int grid_restrict_impl(klecgc_ctx* ctx, int n, int nc, const double* U, int64_t R, float* Yc);
 int mlp_initial_guess_impl(klecgc_ctx* ctx, klecgc_mlp* h, int n, int nc, int N, const double* xi, int64_t M,
                            double* U0);
 
 // host linear algebra
-void sym_eig(int n, std::vector<double>& A, std::vector<double>& w);   // A -> eigenvectors (cols)
+// Gram eigen-decomposition on the device (eig.cpp): Cd [n][n] symmetric (overwritten) ->
+// V (host, row-major, eigenvectors as columns) and w, descending
+void gram_eig(klecgc_ctx* ctx, int n, double* Cd, std::vector<double>& V, std::vector<double>& w);
+void release_blas(klecgc_ctx* ctx);
 int householder_lstsq(int m, int n, int nrhs, std::vector<double>& B, std::vector<double>& D,
                       std::vector<double>& X);
 

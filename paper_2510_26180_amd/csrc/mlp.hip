@@ -609,11 +609,12 @@ int mlp_grad_impl(klecgc_ctx* ctx, klecgc_mlp* h, const double* xi, const float*
 }
 
 int mlp_train_impl(klecgc_ctx* ctx, klecgc_mlp* h, const double* xi, const float* Y, int64_t n, int epochs, int batch,
-                   float lr, const int32_t* perm, float* loss_host) {
+                   float lr, float lr_final, const int32_t* perm, float* loss_host) {
   hipStream_t s = ctx->stream;
   KC_REQUIRE(batch >= 1 && batch <= 65535, KC_EINVAL, "batch must be in [1, 65535]");
   KC_REQUIRE(epochs >= 0, KC_EINVAL, "epochs must be >= 0");
   KC_REQUIRE(lr > 0.f && std::isfinite(lr), KC_EINVAL, "lr must be positive and finite");
+  KC_REQUIRE(std::isfinite(lr_final), KC_EINVAL, "lr_final must be finite");
   const Layout L = layout_of(h);
   const AdamSeg sg{L.oW2, L.ob2, L.oW3, L.ob3, L.bW2, L.bW3};
   const int64_t nbatch = (n + batch - 1) / batch;
@@ -632,6 +633,9 @@ int mlp_train_impl(klecgc_ctx* ctx, klecgc_mlp* h, const double* xi, const float
   for (int ep = 0; ep < epochs; ++ep) {
     KC_TRY_HIP(hipMemsetAsync(w.loss, 0, sizeof(double), s));
     const int32_t* pe = perm ? perm + (int64_t)ep * n : nullptr;
+    const float lr_ep = (lr_final > 0.f && epochs > 1)
+                            ? (float)(lr * std::pow((double)lr_final / lr, (double)ep / (epochs - 1)))
+                            : lr;
     timed(ctx, KT_MLP, [&] {
       for (int64_t bi = 0; bi < nbatch; ++bi) {
         const int64_t off = bi * batch;
@@ -642,7 +646,7 @@ int mlp_train_impl(klecgc_ctx* ctx, klecgc_mlp* h, const double* xi, const float
         h->t += 1;
         const float c1 = (float)(1.0 - std::pow(0.9, (double)h->t));
         const float c2 = (float)(1.0 - std::pow(0.999, (double)h->t));
-        adam_kernel<<<grid1d(h->n_params), 256, 0, s>>>(h->w, h->g, h->m, h->v, h->n_params, lr, 0.9f, 0.999f, 1e-8f,
+        adam_kernel<<<grid1d(h->n_params), 256, 0, s>>>(h->w, h->g, h->m, h->v, h->n_params, lr_ep, 0.9f, 0.999f, 1e-8f,
                                                         c1, c2, L.ob1, sg, h->wb);
         KC_LAUNCH_CHECK();
       }

@@ -118,22 +118,23 @@ def test_mlp_training_tracks_oracle_and_decreases(ctx):
     ctx.mlp_normalize_targets(h, Tdev)
     mu, sd, Tz = omlp.zscore(Traw.astype(np.float64))
     assert rel(host(Tdev), Tz) <= 1e-6
-    epochs, batch, lr = 3, 64, 3e-3
+    epochs, batch, lr, lr_final = 3, 64, 3e-3, 1e-3
     perm = W.draw_perms(epochs, n, 14)
-    losses = ctx.mlp_train(h, dev(X), Tdev, epochs=epochs, batch=batch, lr=lr, perm=dev(perm))
+    losses = ctx.mlp_train(h, dev(X), Tdev, epochs=epochs, batch=batch, lr=lr, perm=dev(perm), lr_final=lr_final)
     # oracle: same permutations, same mini-batches (the last one ragged), FP64 masters
     m = {k: 0.0 for k in ("W1", "b1", "W2", "b2", "W3", "b3")}
     v = dict(m)
     t = 0
     want = []
     for ep in range(epochs):
+        lr_ep = lr * (lr_final / lr) ** (ep / (epochs - 1))      # geometric decay per epoch
         tot = 0.0
         for off in range(0, n, batch):
             rows = perm[ep, off:off + batch]
             l, g = omlp.loss_and_grad(p, X[rows], Tz[rows], mirror_bf16=True)
             tot += l * len(rows)
             t += 1
-            omlp.adam_step(p, g, m, v, t, lr)
+            omlp.adam_step(p, g, m, v, t, lr_ep)
         want.append(tot / n)
     log(f"  losses gpu {losses} oracle {np.array(want)}")
     assert np.allclose(losses, want, rtol=2e-3)
@@ -214,3 +215,49 @@ def test_mlp_rejects_bad_arguments(ctx):
     with pytest.raises(K.KlecgcError) as e:
         ctx.mlp_train(h, dev(np.zeros((2, 3))), dev(np.zeros((2, 40), np.float32)), 1, 0, 1e-3)
     assert e.value.code == -1
+
+
+def test_trained_network_gains_over_no_guess(ctx):
+    """Train the MLP on serial-fine solutions of a small 2D problem, then solve fresh
+    samples from (a) the zero guess, (b) the gPC guess, (c) the MLP guess.  The network
+    must cut the iteration count against (a) and every run must reach the oracle's
+    serial fine solution to 1e-8; the comparison with (b) is reported."""
+    import paper_2510_26180_amd as K
+    from oracle import prop
+    from tests.gpu_helpers import oracle_faces
+    w = W.small_2d(n=20, N=8, J=8, alpha=1e-2, d=6, M=32)
+    prob = K.ProblemSpec.from_workload(w)
+    n_t, nc, H = 512, 9, 64
+    fh = ctx.kle_build_field(w.dim, w.n, w.d, w.corr_len, w.sigma)
+    xi_t = dev(W.draw_xi(n_t, w.d, 31))
+    xi_e_np = W.draw_xi(w.M, w.d, 32)
+    xi_e = dev(xi_e_np)
+    a_t = torch.empty((n_t, w.n_faces), dtype=torch.float64, device="cuda")
+    a_e = torch.empty((w.M, w.n_faces), dtype=torch.float64, device="cuda")
+    ctx.kle_synthesize(fh, xi_t, a_t)
+    ctx.kle_synthesize(fh, xi_e, a_e)
+    S = torch.empty((n_t, w.N, w.Nx), dtype=torch.float64, device="cuda")
+    ctx.serial_fine_propagate(prob, a_t, None, S)
+    O = w.N * nc * nc
+    Yc = torch.empty((n_t, O), dtype=torch.float32, device="cuda")
+    ctx.grid_restrict(w.n, nc, S, Yc)
+    h = ctx.mlp_create(w.d, H, O, params=dev(W.draw_mlp_init(w.d, H, O, 33)))
+    ctx.mlp_normalize_targets(h, Yc)
+    epochs = 300
+    losses = ctx.mlp_train(h, xi_t, Yc, epochs=epochs, batch=64, lr=1e-3, lr_final=1e-5,
+                           perm=dev(W.draw_perms(epochs, n_t, 34)))
+    kl = ctx.kle_build(S.view(n_t, -1), w.eps_kl)
+    gpc = ctx.gpc_fit(kl, xi_t, 2)
+    U = torch.empty((w.M, w.N, w.Nx), dtype=torch.float64, device="cuda")
+    its = {}
+    its["zero"], st0, _, _ = ctx.parareal_solve(prob, a_e, U, init=K.KC_INIT_ZERO)
+    its["gpc"], st1, _, _ = ctx.parareal_solve(prob, a_e, U, init=K.KC_INIT_GPC, gpc=gpc, xi=xi_e)
+    ctx.mlp_initial_guess(h, w.n, nc, w.N, xi_e, U)
+    its["mlp"], st2, _, _ = ctx.parareal_solve(prob, a_e, U, init=K.KC_INIT_GIVEN, init_U=U)
+    log(f"  loss {losses[0]:.3e} -> {losses[-1]:.3e}; mean iterations " +
+        ", ".join(f"{k} {v.mean():.2f}" for k, v in its.items()))
+    assert all((s == K.KC_SAMPLE_CONVERGED).all() for s in (st0, st1, st2))
+    assert its["mlp"].mean() < its["zero"].mean() - 1.0
+    a0 = oracle_faces(w, xi_e_np[:1])[0]
+    ref = prop.serial_fine(prop.Propagators(w.dim, w.n, a0, w.T, w.N, w.J, w.forcing), np.zeros(w.Nx), w.N)
+    assert rel(host(U)[0], ref) <= 1e-8

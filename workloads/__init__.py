@@ -86,11 +86,12 @@ class MlpSpec:
     epochs: int
     batch: int
     lr: float
+    lr_final: float          # geometric per-epoch decay from lr to lr_final
     seed_init: int
     seed_perm: int
 
 
-MLP_C4 = MlpSpec(hidden=256, nc=32, epochs=200, batch=256, lr=1e-3, seed_init=3004, seed_perm=4004)
+MLP_C4 = MlpSpec(hidden=256, nc=32, epochs=1000, batch=64, lr=1e-3, lr_final=1e-5, seed_init=3004, seed_perm=4004)
 
 
 def get(name: str) -> Workload:
