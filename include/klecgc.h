@@ -209,6 +209,34 @@ int parareal_solve(klecgc_ctx* ctx, const klecgc_problem* prob, const double* a_
                    const klecgc_gpc* gpc, const double* xi_dev, double* U_dev,
                    int32_t* iters_host, int32_t* status_host, double* delta_hist_host);
 
+/* ---- ragged batches ------------------------------------------------------------
+ * Samples of one problem family that differ in grid size n and slice count N, solved
+ * together by the iteration of parareal_solve (Algorithm 2 with the diagonalised CGC of
+ * Section 3.2).  Sample m has n = tasks[m].n and N = tasks[m].N; its faces a [Fc(n)]
+ * start at element tasks[m].face_off of a_dev, its states U [N][n^dim] at element
+ * tasks[m].state_off of U_dev (float64).  Regions of different samples must not
+ * overlap.  The other parameters come from *base (its n and N are ignored); u0 = 0.
+ * Samples of equal (n, N) form a class; classes run concurrently, each on its own
+ * stream.  With KC_BATCH_GRAPH, the first iteration runs eagerly and one iteration of
+ * all classes is then captured into a HIP graph and replayed until every sample has
+ * stopped (convergence is tested on the device).
+ *   init: KC_INIT_ZERO, KC_INIT_COARSE, or KC_INIT_GIVEN (U_dev holds the guess);
+ *   iters_host [M], status_host [M] (KC_SAMPLE_*) as in parareal_solve;
+ *   latency_ms_host [M] (nullable): time from the start of the call to the iteration
+ *   at which the sample stopped (device clock); total_ms_host (nullable): wall time of
+ *   the call on the context stream. */
+typedef struct {
+  int32_t n;          /* interior nodes per dimension */
+  int32_t N;          /* coarse slices (power of two, 2..256) */
+  int64_t face_off;   /* element offset of the sample's faces in a_dev */
+  int64_t state_off;  /* element offset of the sample's N * n^dim states in U_dev */
+} klecgc_task;
+enum { KC_BATCH_GRAPH = 1 };
+int parareal_solve_batch(klecgc_ctx* ctx, const klecgc_problem* base, const klecgc_task* tasks,
+                         int64_t M, const double* a_dev, int32_t init, double* U_dev, int32_t flags,
+                         int32_t* iters_host, int32_t* status_host, double* latency_ms_host,
+                         double* total_ms_host);
+
 /* ---- learned initial guess (replaces the gPC map of Algorithm 3 step 6) ------
  * A multilayer perceptron maps xi [d] to the states of all N slices restricted to an
  * nc x nc grid (n_out = N nc^2), trained on solutions the method produced:

@@ -38,6 +38,13 @@ class KleDesc(ctypes.Structure):
     ]
 
 
+class Task(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("N", ctypes.c_int32), ("face_off", ctypes.c_int64),
+                ("state_off", ctypes.c_int64)]
+
+
+KC_BATCH_GRAPH = 1
+
 _vp = ctypes.c_void_p
 _i64 = ctypes.c_int64
 _i32 = ctypes.c_int32
@@ -65,6 +72,8 @@ SIGNATURES = {
     "coarse_propagate": (ctypes.c_int, [_vp, _P(Problem), _vp, _vp, _i64, _vp]),
     "parareal_solve": (ctypes.c_int, [_vp, _P(Problem), _vp, _vp, _i64, _i32, _vp, _vp, _vp, _vp,
                                       _P(_i32), _P(_i32), _P(ctypes.c_double)]),
+    "parareal_solve_batch": (ctypes.c_int, [_vp, _P(Problem), _P(Task), _i64, _vp, _i32, _vp, _i32,
+                                            _P(_i32), _P(_i32), _P(ctypes.c_double), _P(ctypes.c_double)]),
     "mlp_create": (ctypes.c_int, [_vp, _i32, _i32, _i64, _P(_vp), _P(_i64)]),
     "mlp_set_params": (ctypes.c_int, [_vp, _vp, _vp]),
     "mlp_get_params": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),

@@ -210,6 +210,23 @@ class Context:
         return (np.frombuffer(iters, dtype=np.int32).copy(), np.frombuffer(status, dtype=np.int32).copy(),
                 np.frombuffer(hist, dtype=np.float64).reshape(M, prob.max_iter).copy(), rc)
 
+    def parareal_solve_batch(self, base: ProblemSpec, tasks, a, U, init: int = L.KC_INIT_ZERO, graph: bool = True,
+                             allow_noconv=False):
+        """tasks: sequence of (n, N, face_off, state_off); a, U: flat float64 device buffers."""
+        M = len(tasks)
+        arr = (L.Task * M)(*[L.Task(int(n), int(N), int(fo), int(so)) for n, N, fo, so in tasks])
+        iters = (ctypes.c_int32 * M)()
+        status = (ctypes.c_int32 * M)()
+        lat = (ctypes.c_double * M)()
+        total = ctypes.c_double()
+        pc = base.c()
+        rc = self.lib.parareal_solve_batch(self.h, ctypes.byref(pc), arr, M, _ptr(a), init, _ptr(U),
+                                           L.KC_BATCH_GRAPH if graph else 0, iters, status, lat,
+                                           ctypes.byref(total))
+        self._check(rc, allow=(-5,) if allow_noconv else ())
+        return (np.frombuffer(iters, dtype=np.int32).copy(), np.frombuffer(status, dtype=np.int32).copy(),
+                np.frombuffer(lat, dtype=np.float64).copy(), total.value, rc)
+
     # ---- learned initial guess
     def mlp_create(self, n_in: int, hidden: int, n_out: int, params=None) -> Handle:
         out = ctypes.c_void_p()

@@ -52,16 +52,18 @@ void Workspace::release() {
   std::fill(cap.begin(), cap.end(), 0);
 }
 
-DevStatus status_block(klecgc_ctx* ctx) {
-  char* b = (char*)ctx->ws.get(WS_STATUS, kStatusBytes);
+DevStatus status_block(klecgc_ctx* ctx, int slot) {
+  char* b = (char*)ctx->ws.get(slot, kStatusBytes);
   return DevStatus{(int*)b, (unsigned long long*)(b + 8)};
 }
 
 void status_reset(klecgc_ctx* ctx, const DevStatus& st) {
+  if (ctx->capturing) return;
   KC_TRY_HIP(hipMemsetAsync(st.flag, 0, kStatusBytes, ctx->stream));
 }
 
 int status_collect(klecgc_ctx* ctx, const DevStatus& st, int base) {
+  if (ctx->capturing) return 0;
   unsigned char h[kStatusBytes];
   KC_TRY_HIP(hipMemcpyAsync(h, st.flag, kStatusBytes, hipMemcpyDeviceToHost, ctx->stream));
   KC_TRY_HIP(hipStreamSynchronize(ctx->stream));
@@ -130,95 +132,6 @@ int gpc_predict_impl(klecgc_ctx* ctx, const klecgc_gpc* g, const double* xi, int
   launch_dgemm(st, M, g->n_modes, g->P, Psi, g->P, g->H, g->n_modes, Z, g->n_modes, nullptr, 1.0);
   timed(ctx, KT_GEMM, [&] { launch_dgemm(st, M, g->L, g->n_modes, Z, g->n_modes, g->W, g->L, U0, g->L, g->mean, 1.0); });
   return KC_OK;
-}
-
-static int parareal_impl(klecgc_ctx* ctx, const klecgc_problem& p, const double* a, const double* u0,
-                         int64_t M, int32_t init, const double* init_dev, const klecgc_gpc* gpc,
-                         const double* xi, double* U, int32_t* iters, int32_t* status, double* hist) {
-  hipStream_t st = ctx->stream;
-  const int64_t Nx = n_unknowns(p);
-  const int N = p.N, K = N / 2 + 1;
-  const int64_t S = (int64_t)N * Nx;
-  int rc = KC_OK;
-  switch (init) {
-    case KC_INIT_GIVEN:
-      KC_REQUIRE(init_dev, KC_EINVAL, "init_dev required for KC_INIT_GIVEN");
-      if (init_dev != U)
-        KC_TRY_HIP(hipMemcpyAsync(U, init_dev, sizeof(double) * M * S, hipMemcpyDeviceToDevice, st));
-      break;
-    case KC_INIT_ZERO:
-      KC_TRY_HIP(hipMemsetAsync(U, 0, sizeof(double) * M * S, st));
-      break;
-    case KC_INIT_COARSE: {
-      int r = coarse_sweep_impl(ctx, p, a, u0, M, U);
-      if (r != KC_OK) rc = r;
-      break;
-    }
-    case KC_INIT_GPC:
-      KC_REQUIRE(gpc && xi, KC_EINVAL, "gpc handle and xi_dev required for KC_INIT_GPC");
-      KC_REQUIRE(gpc->L == S, KC_EINVAL, "gpc surrogate state length differs from N*Nx");
-      gpc_predict_impl(ctx, gpc, xi, M, U);
-      break;
-    default:
-      throw Error{KC_EINVAL, "unknown init mode"};
-  }
-  double* Fv = (double*)ctx->ws.get(WS_FINE, sizeof(double) * M * S);
-  double* D = (double*)ctx->ws.get(WS_DEFECT, sizeof(double) * M * S);
-  double* spec = (double*)ctx->ws.get(WS_SPEC, sizeof(double) * 2 * M * K * Nx);
-  size_t small_bytes = 256 + (size_t)M * (1 + 16);
-  uint8_t* small = (uint8_t*)ctx->ws.get(WS_SMALL, small_bytes);
-  unsigned long long* maxima = (unsigned long long*)small;          // [M][2]
-  uint8_t* active = small + 16 * M;                                 // [M]
-  std::vector<uint8_t> act(M, 1);
-  std::vector<unsigned long long> hmax(2 * M);
-  for (int64_t m = 0; m < M; ++m) {
-    iters[m] = 0;
-    status[m] = KC_SAMPLE_MAXITER;
-  }
-  if (hist) std::fill(hist, hist + M * p.max_iter, 0.0);
-  KC_TRY_HIP(hipMemcpyAsync(active, act.data(), M, hipMemcpyHostToDevice, st));
-  int64_t n_active = M;
-  // The driver solves the coarse system for the correction U^{k+1} - U^k, whose
-  // right-hand side is the defect; errors of the shifted solves then only perturb the
-  // contraction (by ~ cgc_rtol / alpha), not the fixed point, so a relative 1e-7
-  // suffices by default.
-  klecgc_problem pb = p;
-  if (pb.cgc_rtol <= 0) pb.cgc_rtol = 1e-7;
-  for (int k = 0; k < p.max_iter && n_active > 0; ++k) {
-    FineArgs fa{a, U, u0, true, k > 0 ? 1 : 0, active, Fv, M};
-    int r = fine_propagate_impl(ctx, p, fa);
-    if (r != KC_OK) rc = r;
-    timed(ctx, KT_DEFECT, [&] { launch_defect(st, p, a, Fv, U, active, M, D); });
-    timed(ctx, KT_FFT_FWD, [&] { launch_fft_forward(st, p, D, active, M, spec); });
-    r = shifted_solve_impl(ctx, pb, a, active, M, spec);
-    if (r != KC_OK) rc = r;
-    KC_TRY_HIP(hipMemsetAsync(maxima, 0, sizeof(unsigned long long) * 2 * M, st));
-    timed(ctx, KT_FFT_INV, [&] { launch_fft_inverse(st, p, spec, active, M, U, true, maxima); });
-    KC_TRY_HIP(hipMemcpyAsync(hmax.data(), maxima, sizeof(unsigned long long) * 2 * M,
-                              hipMemcpyDeviceToHost, st));
-    KC_TRY_HIP(hipStreamSynchronize(st));
-    for (int64_t m = 0; m < M; ++m) {
-      if (!act[m]) continue;
-      double cmax, umax;
-      std::memcpy(&cmax, &hmax[2 * m], 8);
-      std::memcpy(&umax, &hmax[2 * m + 1], 8);
-      double delta = cmax / (umax > 0 ? umax : 1.0);
-      iters[m] = k + 1;
-      if (hist) hist[m * p.max_iter + k] = delta;
-      if (!std::isfinite(delta)) {
-        status[m] = KC_SAMPLE_NONFINITE;
-        act[m] = 0;
-        --n_active;
-      } else if (delta <= p.tol) {
-        status[m] = KC_SAMPLE_CONVERGED;
-        act[m] = 0;
-        --n_active;
-      }
-    }
-    KC_TRY_HIP(hipMemcpyAsync(active, act.data(), M, hipMemcpyHostToDevice, st));
-  }
-  KC_TRY_HIP(hipStreamSynchronize(st));
-  return rc;
 }
 
 }  // namespace kc
@@ -554,6 +467,18 @@ int serial_fine_propagate(klecgc_ctx* ctx, const klecgc_problem* prob, const dou
     KC_REQUIRE(M >= 1, KC_EINVAL, "M must be >= 1");
     validate_problem(*prob);
     return serial_fine_impl(ctx, *prob, a_dev, u0_dev, M, U_dev);
+  });
+}
+
+int parareal_solve_batch(klecgc_ctx* ctx, const klecgc_problem* base, const klecgc_task* tasks, int64_t M,
+                         const double* a_dev, int32_t init, double* U_dev, int32_t flags, int32_t* iters_host,
+                         int32_t* status_host, double* latency_ms_host, double* total_ms_host) {
+  return guarded(ctx, [&] {
+    KC_REQUIRE(base && tasks && a_dev && U_dev && iters_host && status_host, KC_EINVAL, "null argument");
+    KC_REQUIRE(M >= 1, KC_EINVAL, "M must be >= 1");
+    KC_REQUIRE((flags & ~KC_BATCH_GRAPH) == 0, KC_EINVAL, "unknown flags");
+    return parareal_batch_impl(ctx, *base, tasks, M, a_dev, init, U_dev, flags, iters_host, status_host,
+                               latency_ms_host, total_ms_host);
   });
 }
 

@@ -1,0 +1,622 @@
+// Parareal driver (Algorithm 2 iterated as in Algorithm 3 step 7) for one or several
+// uniform classes of samples, with the convergence test on the device.
+//
+// Each iteration of a class enqueues: fine sweep over its active (sample, slice) pairs,
+// defect, forward slice FFT, shifted solves, inverse FFT accumulating the correction
+// into U together with per-sample maxima, and `converge_kernel`, which turns the maxima
+// into the increment delta = max|U^{k+1}-U^k| / max|U^{k+1}|, records it, and retires the
+// sample (converged, non-finite or at the iteration cap) by clearing its mask.  No
+// iteration needs the host, so after one eager iteration (which also sizes every
+// workspace) the iteration of all classes is captured once into a hipGraph, one branch
+// per class on its own stream, and replayed until every sample has retired.
+//
+// Ragged batches (samples of different grid size n and slice count N) are grouped into
+// classes of equal (n, N); each class is gathered into contiguous buffers, run on its own
+// context and stream, and scattered back.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <numeric>
+#include <vector>
+
+#include "common.h"
+
+namespace kc {
+
+namespace {
+
+__global__ void converge_kernel(int64_t M, int max_iter, double tol, unsigned long long* __restrict__ maxima,
+                                uint8_t* __restrict__ active, int32_t* __restrict__ its,
+                                int32_t* __restrict__ status, double* __restrict__ hist,
+                                unsigned long long* __restrict__ tconv, int* __restrict__ counts, int cls) {
+  for (int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; m < M; m += (int64_t)gridDim.x * blockDim.x) {
+    if (!active[m]) continue;
+    const double cmax = __longlong_as_double((long long)maxima[2 * m]);
+    const double umax = __longlong_as_double((long long)maxima[2 * m + 1]);
+    maxima[2 * m] = 0ull;
+    maxima[2 * m + 1] = 0ull;
+    const double delta = cmax / (umax > 0 ? umax : 1.0);
+    const int k = its[m];
+    its[m] = k + 1;
+    if (hist) hist[m * max_iter + k] = delta;
+    bool stop = false;
+    if (!isfinite(delta)) {
+      status[m] = KC_SAMPLE_NONFINITE;
+      stop = true;
+    } else if (delta <= tol) {
+      status[m] = KC_SAMPLE_CONVERGED;
+      stop = true;
+    } else if (k + 1 >= max_iter) {
+      stop = true;  // status stays KC_SAMPLE_MAXITER
+    }
+    if (stop) {
+      active[m] = 0;
+      if (tconv) tconv[m] = wall_clock64();
+      atomicSub(&counts[cls], 1);
+      atomicSub(&counts[0], 1);
+    }
+  }
+}
+
+// per-class state set-up: active = 1, its = 0, status = MAXITER, maxima = 0
+__global__ void class_init_kernel(int64_t M, uint8_t* active, int32_t* its, int32_t* status,
+                                  unsigned long long* maxima) {
+  for (int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; m < M; m += (int64_t)gridDim.x * blockDim.x) {
+    active[m] = 1;
+    its[m] = 0;
+    status[m] = KC_SAMPLE_MAXITER;
+    maxima[2 * m] = 0ull;
+    maxima[2 * m + 1] = 0ull;
+  }
+}
+
+__global__ void stamp_kernel(unsigned long long* t) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *t = wall_clock64();
+}
+
+// dst[j][0..len) = src[off[j] .. off[j]+len), j < R   (and the reverse for scatter)
+__global__ void gather_rows_kernel(const double* __restrict__ src, const int64_t* __restrict__ off, int64_t len,
+                                   int64_t R, double* __restrict__ dst) {
+  const int64_t j = blockIdx.y;
+  if (j >= R) return;
+  const double* s = src + off[j];
+  double* d = dst + j * len;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += (int64_t)gridDim.x * blockDim.x)
+    d[i] = s[i];
+}
+
+__global__ void scatter_rows_kernel(const double* __restrict__ src, const int64_t* __restrict__ off, int64_t len,
+                                    int64_t R, double* __restrict__ dst) {
+  const int64_t j = blockIdx.y;
+  if (j >= R) return;
+  const double* s = src + j * len;
+  double* d = dst + off[j];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += (int64_t)gridDim.x * blockDim.x)
+    d[i] = s[i];
+}
+
+__global__ void zero_kernel(double* __restrict__ x, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    x[i] = 0.0;
+}
+
+unsigned blocks_of(int64_t n, int64_t cap = 4096) {
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, cap));
+}
+
+void launch_rows(bool gather, hipStream_t s, const double* src, const int64_t* off, int64_t len, int64_t R,
+                 double* dst) {
+  for (int64_t r0 = 0; r0 < R; r0 += 65535) {
+    const int64_t Rc = std::min<int64_t>(65535, R - r0);
+    const dim3 grid(blocks_of(len, 64), (unsigned)Rc);
+    if (gather)
+      gather_rows_kernel<<<grid, 256, 0, s>>>(src, off + r0, len, Rc, dst + r0 * len);
+    else
+      scatter_rows_kernel<<<grid, 256, 0, s>>>(src + r0 * len, off + r0, len, Rc, dst);
+    KC_LAUNCH_CHECK();
+  }
+}
+
+// device state of one class (owned allocation)
+struct ClassState {
+  uint8_t* active = nullptr;
+  int32_t* its = nullptr;
+  int32_t* status = nullptr;
+  double* hist = nullptr;
+  unsigned long long* maxima = nullptr;
+  unsigned long long* tconv = nullptr;
+  void* base = nullptr;
+  void alloc(int64_t M, int max_iter, bool want_hist) {
+    const size_t b_act = (M + 255) / 256 * 256, b_i32 = (4 * M + 255) / 256 * 256;
+    const size_t b_hist = want_hist ? (8 * (size_t)M * max_iter + 255) / 256 * 256 : 0;
+    const size_t b_u64 = (8 * M + 255) / 256 * 256;
+    const size_t total = b_act + 2 * b_i32 + b_hist + 3 * b_u64;
+    if (hipMalloc(&base, total) != hipSuccess) {
+      (void)hipGetLastError();
+      base = nullptr;
+      throw Error{KC_ENOMEM, "parareal driver state allocation failed"};
+    }
+    char* p = (char*)base;
+    active = (uint8_t*)p;
+    p += b_act;
+    its = (int32_t*)p;
+    p += b_i32;
+    status = (int32_t*)p;
+    p += b_i32;
+    hist = want_hist ? (double*)p : nullptr;
+    p += b_hist;
+    maxima = (unsigned long long*)p;
+    p += 2 * b_u64;
+    tconv = (unsigned long long*)p;
+  }
+  ~ClassState() {
+    if (base) (void)hipFree(base);
+  }
+};
+
+}  // namespace
+
+// One uniform class of samples: problem p (n, N fixed), M samples, faces a [M][Fc],
+// states U [M][N][Nx] (initial guess on entry, iterate on exit).
+struct ParaClass {
+  klecgc_ctx* c = nullptr;  // execution context (its stream and workspace)
+  klecgc_problem p{};
+  klecgc_problem pb{};      // p with the default correction tolerance of the shifted solves
+  int64_t M = 0;
+  const double* a = nullptr;
+  const double* u0 = nullptr;
+  double* U = nullptr;
+  ClassState st;
+  int index = 1;            // slot in the device counter array (0 = all classes)
+};
+
+static void enqueue_iteration(ParaClass& pc, int k, int* counts, int& rc) {
+  klecgc_ctx* c = pc.c;
+  hipStream_t s = c->stream;
+  const klecgc_problem& p = pc.p;
+  const int64_t Nx = n_unknowns(p);
+  const int64_t S = (int64_t)p.N * Nx;
+  const int K = p.N / 2 + 1;
+  double* Fv = (double*)c->ws.get(WS_FINE, sizeof(double) * pc.M * S);
+  double* D = (double*)c->ws.get(WS_DEFECT, sizeof(double) * pc.M * S);
+  double* spec = (double*)c->ws.get(WS_SPEC, sizeof(double) * 2 * pc.M * K * Nx);
+  FineArgs fa{pc.a, pc.U, pc.u0, true, k > 0 ? 1 : 0, pc.st.active, Fv, pc.M};
+  int r = fine_propagate_impl(c, p, fa);
+  if (r != KC_OK) rc = r;
+  timed(c, KT_DEFECT, [&] { launch_defect(s, p, pc.a, Fv, pc.U, pc.st.active, pc.M, D); });
+  timed(c, KT_FFT_FWD, [&] { launch_fft_forward(s, p, D, pc.st.active, pc.M, spec); });
+  r = shifted_solve_impl(c, pc.pb, pc.a, pc.st.active, pc.M, spec);
+  if (r != KC_OK) rc = r;
+  timed(c, KT_FFT_INV, [&] { launch_fft_inverse(s, p, spec, pc.st.active, pc.M, pc.U, true, pc.st.maxima); });
+  converge_kernel<<<blocks_of(pc.M), 256, 0, s>>>(pc.M, p.max_iter, p.tol, pc.st.maxima, pc.st.active, pc.st.its,
+                                                  pc.st.status, pc.st.hist, pc.st.tconv, counts, pc.index);
+  KC_LAUNCH_CHECK();
+}
+
+struct DriverOut {
+  std::vector<int32_t> its, status;   // per class, concatenated in class order
+  std::vector<double> hist;
+  std::vector<unsigned long long> tconv;
+  unsigned long long t0 = 0;
+  int iterations = 0;                 // driver iterations (graph replays + 1)
+  double graph_ms = 0;                // capture + instantiate time
+};
+
+// Runs the parareal iteration over the classes.  `main` is the stream that orders the
+// whole run (the caller's); with use_graph the classes' iterations after the first are
+// replayed from one captured graph.
+static int run_classes(klecgc_ctx* ctx, std::vector<ParaClass*>& cls, bool use_graph, bool want_hist,
+                       DriverOut& out) {
+  hipStream_t main = ctx->stream;
+  const int C = (int)cls.size();
+  int max_iter = 1;
+  int64_t total = 0;
+  for (auto* pc : cls) {
+    max_iter = std::max(max_iter, pc->p.max_iter);
+    total += pc->M;
+  }
+  // device counters: [0] active samples of all classes, [1 + i] of class i; stamp at [C+1]
+  char* cbuf = (char*)ctx->ws.get(WS_SMALL, 256 + sizeof(int) * (C + 1));
+  unsigned long long* t0dev = (unsigned long long*)cbuf;
+  int* counts = (int*)(cbuf + 256);
+  std::vector<int> hc(C + 1);
+  hc[0] = (int)total;
+  for (int i = 0; i < C; ++i) hc[i + 1] = (int)cls[i]->M;
+  KC_TRY_HIP(hipMemcpyAsync(counts, hc.data(), sizeof(int) * (C + 1), hipMemcpyHostToDevice, main));
+  stamp_kernel<<<1, 64, 0, main>>>(t0dev);
+  KC_LAUNCH_CHECK();
+  hipEvent_t fork = nullptr;
+  std::vector<hipEvent_t> join(C, nullptr);
+  struct EvGuard {
+    hipEvent_t* e;
+    ~EvGuard() {
+      if (*e) (void)hipEventDestroy(*e);
+    }
+  };
+  KC_TRY_HIP(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+  EvGuard fg{&fork};
+  std::vector<std::unique_ptr<EvGuard>> jg;
+  for (int i = 0; i < C; ++i) {
+    KC_TRY_HIP(hipEventCreateWithFlags(&join[i], hipEventDisableTiming));
+    jg.emplace_back(new EvGuard{&join[i]});
+  }
+  // `order` is the stream that sequences the iterations: the caller's stream while
+  // iterating eagerly, a driver-owned stream for the graph (capture is not allowed on
+  // the legacy null stream a caller may pass)
+  hipStream_t order = main;
+  auto fork_all = [&]() {
+    KC_TRY_HIP(hipEventRecord(fork, order));
+    for (auto* pc : cls)
+      if (pc->c->stream != order) KC_TRY_HIP(hipStreamWaitEvent(pc->c->stream, fork, 0));
+  };
+  auto join_all = [&]() {
+    for (int i = 0; i < C; ++i)
+      if (cls[i]->c->stream != order) {
+        KC_TRY_HIP(hipEventRecord(join[i], cls[i]->c->stream));
+        KC_TRY_HIP(hipStreamWaitEvent(order, join[i], 0));
+      }
+  };
+  for (int i = 0; i < C; ++i) {
+    ParaClass& pc = *cls[i];
+    pc.index = i + 1;
+    pc.st.alloc(pc.M, pc.p.max_iter, want_hist);
+  }
+  fork_all();
+  for (auto* pc : cls) {
+    class_init_kernel<<<blocks_of(pc->M), 256, 0, pc->c->stream>>>(pc->M, pc->st.active, pc->st.its, pc->st.status,
+                                                                   pc->st.maxima);
+    KC_LAUNCH_CHECK();
+    if (pc->st.hist)
+      zero_kernel<<<blocks_of(pc->M * pc->p.max_iter), 256, 0, pc->c->stream>>>(pc->st.hist,
+                                                                               pc->M * pc->p.max_iter);
+    KC_LAUNCH_CHECK();
+  }
+  join_all();
+  int rc = KC_OK;
+  int k = 0;
+  auto read_counts = [&]() {
+    KC_TRY_HIP(hipMemcpyAsync(hc.data(), counts, sizeof(int) * (C + 1), hipMemcpyDeviceToHost, order));
+    KC_TRY_HIP(hipStreamSynchronize(order));
+  };
+  // eager iterations (all of them without a graph; the first one with a graph)
+  while (k < max_iter) {
+    fork_all();
+    for (int i = 0; i < C; ++i)
+      if (hc[i + 1] > 0) enqueue_iteration(*cls[i], k, counts, rc);
+    join_all();
+    read_counts();
+    ++k;
+    if (hc[0] == 0 || use_graph) break;
+  }
+  const bool replay = use_graph && hc[0] > 0 && k < max_iter;
+  if (replay) {
+    // the replays accumulate solver counters into status blocks cleared here
+    for (auto* pc : cls) {
+      status_reset(pc->c, status_block(pc->c, WS_STATUS));
+      status_reset(pc->c, status_block(pc->c, WS_STATUS_CGC));
+    }
+    for (auto* pc : cls)
+      if (pc->c->stream != main) KC_TRY_HIP(hipStreamSynchronize(pc->c->stream));
+  }
+  if (replay) {
+    // capture one iteration of every class (iteration index >= 1: the first slice's
+    // fine propagation is not repeated), one branch per class
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t g0, g1;
+    KC_TRY_HIP(hipEventCreate(&g0));
+    EvGuard g0g{&g0};
+    KC_TRY_HIP(hipEventCreate(&g1));
+    EvGuard g1g{&g1};
+    struct StreamGuard {
+      hipStream_t s = nullptr;
+      ~StreamGuard() {
+        if (s) {
+          (void)hipStreamSynchronize(s);
+          (void)hipStreamDestroy(s);
+        }
+      }
+    } cs;
+    KC_TRY_HIP(hipStreamCreateWithFlags(&cs.s, hipStreamNonBlocking));
+    KC_TRY_HIP(hipEventRecord(g0, main));
+    KC_TRY_HIP(hipStreamWaitEvent(cs.s, g0, 0));
+    order = cs.s;
+    KC_TRY_HIP(hipStreamBeginCapture(order, hipStreamCaptureModeRelaxed));
+    for (auto* pc : cls) pc->c->capturing = true;
+    try {
+      fork_all();
+      for (int i = 0; i < C; ++i) enqueue_iteration(*cls[i], 1, counts, rc);
+      join_all();
+    } catch (...) {
+      for (auto* pc : cls) pc->c->capturing = false;
+      hipGraph_t g = nullptr;
+      (void)hipStreamEndCapture(order, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    for (auto* pc : cls) pc->c->capturing = false;
+    KC_TRY_HIP(hipStreamEndCapture(order, &graph));
+    hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (ie != hipSuccess) {
+      (void)hipGraphDestroy(graph);
+      throw Error{KC_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie)};
+    }
+    KC_TRY_HIP(hipEventRecord(g1, order));
+    try {
+      while (k < max_iter && hc[0] > 0) {
+        KC_TRY_HIP(hipGraphLaunch(exec, order));
+        read_counts();
+        ++k;
+      }
+    } catch (...) {
+      (void)hipGraphExecDestroy(exec);
+      (void)hipGraphDestroy(graph);
+      throw;
+    }
+    float gms = 0.f;
+    (void)hipEventElapsedTime(&gms, g0, g1);
+    out.graph_ms = gms;
+    (void)hipGraphExecDestroy(exec);
+    (void)hipGraphDestroy(graph);
+    // the caller's stream resumes after the replays
+    KC_TRY_HIP(hipEventRecord(g1, order));
+    KC_TRY_HIP(hipStreamWaitEvent(main, g1, 0));
+    order = main;
+  }
+  out.iterations = k;
+  if (replay)
+    for (auto* pc : cls) {
+      if (status_collect(pc->c, status_block(pc->c, WS_STATUS), 0)) rc = KC_ENOCONV;
+      if (pc->p.dim == 2 && status_collect(pc->c, status_block(pc->c, WS_STATUS_CGC), 4)) rc = KC_ENOCONV;
+    }
+  // solver counters and kernel times of the class contexts
+  for (auto* pc : cls) {
+    const bool own = pc->c != ctx;
+    if (!own) continue;
+    for (int i = 0; i < 16; ++i) ctx->stats[i] += pc->c->stats[i];
+    for (int i = 0; i < 8; ++i) {
+      ctx->ktime[i] += pc->c->ktime[i];
+      ctx->kcount[i] += pc->c->kcount[i];
+    }
+  }
+  // results
+  out.its.clear();
+  out.status.clear();
+  out.tconv.clear();
+  out.hist.clear();
+  for (auto* pc : cls) {
+    const size_t o = out.its.size();
+    out.its.resize(o + pc->M);
+    out.status.resize(o + pc->M);
+    out.tconv.resize(o + pc->M);
+    KC_TRY_HIP(hipMemcpyAsync(&out.its[o], pc->st.its, sizeof(int32_t) * pc->M, hipMemcpyDeviceToHost, main));
+    KC_TRY_HIP(hipMemcpyAsync(&out.status[o], pc->st.status, sizeof(int32_t) * pc->M, hipMemcpyDeviceToHost, main));
+    KC_TRY_HIP(hipMemcpyAsync(&out.tconv[o], pc->st.tconv, sizeof(unsigned long long) * pc->M,
+                              hipMemcpyDeviceToHost, main));
+    if (want_hist) {
+      const size_t oh = out.hist.size();
+      out.hist.resize(oh + (size_t)pc->M * pc->p.max_iter);
+      KC_TRY_HIP(hipMemcpyAsync(&out.hist[oh], pc->st.hist, sizeof(double) * pc->M * pc->p.max_iter,
+                                hipMemcpyDeviceToHost, main));
+    }
+  }
+  KC_TRY_HIP(hipMemcpyAsync(&out.t0, t0dev, sizeof(unsigned long long), hipMemcpyDeviceToHost, main));
+  KC_TRY_HIP(hipStreamSynchronize(main));
+  return rc;
+}
+
+// ---------------------------------------------------------------- uniform batch
+int parareal_impl(klecgc_ctx* ctx, const klecgc_problem& p, const double* a, const double* u0, int64_t M,
+                  int32_t init, const double* init_dev, const klecgc_gpc* gpc, const double* xi, double* U,
+                  int32_t* iters, int32_t* status, double* hist) {
+  hipStream_t st = ctx->stream;
+  const int64_t S = (int64_t)p.N * n_unknowns(p);
+  int rc = KC_OK;
+  switch (init) {
+    case KC_INIT_GIVEN:
+      KC_REQUIRE(init_dev, KC_EINVAL, "init_dev required for KC_INIT_GIVEN");
+      if (init_dev != U)
+        KC_TRY_HIP(hipMemcpyAsync(U, init_dev, sizeof(double) * M * S, hipMemcpyDeviceToDevice, st));
+      break;
+    case KC_INIT_ZERO:
+      KC_TRY_HIP(hipMemsetAsync(U, 0, sizeof(double) * M * S, st));
+      break;
+    case KC_INIT_COARSE: {
+      int r = coarse_sweep_impl(ctx, p, a, u0, M, U);
+      if (r != KC_OK) rc = r;
+      break;
+    }
+    case KC_INIT_GPC:
+      KC_REQUIRE(gpc && xi, KC_EINVAL, "gpc handle and xi_dev required for KC_INIT_GPC");
+      KC_REQUIRE(gpc->L == S, KC_EINVAL, "gpc surrogate state length differs from N*Nx");
+      gpc_predict_impl(ctx, gpc, xi, M, U);
+      break;
+    default:
+      throw Error{KC_EINVAL, "unknown init mode"};
+  }
+  ParaClass pc;
+  pc.c = ctx;
+  pc.p = p;
+  pc.pb = p;
+  // The driver solves the coarse system for the correction U^{k+1} - U^k, whose
+  // right-hand side is the defect; errors of the shifted solves then only perturb the
+  // contraction (by ~ cgc_rtol / alpha), not the fixed point, so a relative 1e-7
+  // suffices by default.
+  if (pc.pb.cgc_rtol <= 0) pc.pb.cgc_rtol = 1e-7;
+  pc.M = M;
+  pc.a = a;
+  pc.u0 = u0;
+  pc.U = U;
+  std::vector<ParaClass*> cls{&pc};
+  DriverOut out;
+  int r = run_classes(ctx, cls, false, hist != nullptr, out);
+  if (r != KC_OK) rc = r;
+  std::memcpy(iters, out.its.data(), sizeof(int32_t) * M);
+  std::memcpy(status, out.status.data(), sizeof(int32_t) * M);
+  if (hist) std::memcpy(hist, out.hist.data(), sizeof(double) * M * p.max_iter);
+  return rc;
+}
+
+// ---------------------------------------------------------------- ragged batch
+namespace {
+struct SubCtx {
+  klecgc_ctx c;
+  SubCtx(int device, int num_cus) {
+    c.device = device;
+    c.num_cus = num_cus;
+    KC_TRY_HIP(hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking));
+    KC_TRY_HIP(hipEventCreate(&c.ev[0]));
+    KC_TRY_HIP(hipEventCreate(&c.ev[1]));
+  }
+  ~SubCtx() {
+    if (c.stream) (void)hipStreamSynchronize(c.stream);
+    c.ws.release();
+    for (auto& e : c.ev)
+      if (e) (void)hipEventDestroy(e);
+    if (c.stream) (void)hipStreamDestroy(c.stream);
+  }
+};
+}  // namespace
+
+int parareal_batch_impl(klecgc_ctx* ctx, const klecgc_problem& base, const klecgc_task* tasks, int64_t M,
+                        const double* a, int32_t init, double* U, int32_t flags, int32_t* iters, int32_t* status,
+                        double* latency_ms, double* total_ms) {
+  KC_REQUIRE(init == KC_INIT_ZERO || init == KC_INIT_COARSE || init == KC_INIT_GIVEN, KC_EUNSUPPORTED,
+             "parareal_solve_batch supports KC_INIT_ZERO, KC_INIT_COARSE and KC_INIT_GIVEN");
+  hipStream_t main = ctx->stream;
+  // classes of equal (n, N), largest estimated cost first
+  std::map<std::pair<int, int>, std::vector<int64_t>> groups;
+  for (int64_t m = 0; m < M; ++m) {
+    const klecgc_task& t = tasks[m];
+    KC_REQUIRE(t.face_off >= 0 && t.state_off >= 0, KC_EINVAL, "task offsets must be >= 0");
+    klecgc_problem q = base;
+    q.n = t.n;
+    q.N = t.N;
+    validate_problem(q);
+    groups[{t.n, t.N}].push_back(m);
+  }
+  std::vector<std::pair<std::pair<int, int>, std::vector<int64_t>>> order(groups.begin(), groups.end());
+  auto cost = [&](const std::pair<int, int>& k) {
+    const double nn = base.dim == 1 ? k.first : (double)k.first * k.first;
+    return nn * k.second * (base.dim == 1 ? 1.0 : k.first);  // ~ unknowns x slices x Krylov its
+  };
+  std::stable_sort(order.begin(), order.end(), [&](const auto& x, const auto& y) {
+    return cost(x.first) * x.second.size() > cost(y.first) * y.second.size();
+  });
+  const int C = (int)order.size();
+  std::vector<std::unique_ptr<SubCtx>> subs;
+  std::vector<std::unique_ptr<ParaClass>> pcs;
+  struct Bufs {
+    void* p = nullptr;
+    ~Bufs() {
+      if (p) (void)hipFree(p);
+    }
+  };
+  std::vector<std::unique_ptr<Bufs>> bufs;
+  hipEvent_t e0, e1;
+  KC_TRY_HIP(hipEventCreate(&e0));
+  KC_TRY_HIP(hipEventCreate(&e1));
+  struct EvPair {
+    hipEvent_t a, b;
+    ~EvPair() {
+      (void)hipEventDestroy(a);
+      (void)hipEventDestroy(b);
+    }
+  } evp{e0, e1};
+  KC_TRY_HIP(hipEventRecord(e0, main));
+  int rc = KC_OK;
+  for (int i = 0; i < C; ++i) {
+    const auto& key = order[i].first;
+    const auto& idx = order[i].second;
+    subs.emplace_back(new SubCtx(ctx->device, ctx->num_cus));
+    klecgc_ctx* sc = &subs.back()->c;
+    auto pc = std::make_unique<ParaClass>();
+    pc->c = sc;
+    pc->p = base;
+    pc->p.n = key.first;
+    pc->p.N = key.second;
+    pc->pb = pc->p;
+    if (pc->pb.cgc_rtol <= 0) pc->pb.cgc_rtol = 1e-7;
+    const int64_t Mc = (int64_t)idx.size();
+    const int64_t Nx = n_unknowns(pc->p), Fc = n_faces(base.dim, key.first);
+    const int64_t S = (int64_t)key.second * Nx;
+    pc->M = Mc;
+    // gather faces (and the given guess) into contiguous class buffers
+    bufs.emplace_back(new Bufs);
+    const size_t bytes = sizeof(double) * (size_t)Mc * (Fc + S) + 2 * sizeof(int64_t) * Mc + 512;
+    if (hipMalloc(&bufs.back()->p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      bufs.back()->p = nullptr;
+      throw Error{KC_ENOMEM, "ragged class buffer allocation failed"};
+    }
+    double* ac = (double*)bufs.back()->p;
+    double* Uc = ac + Mc * Fc;
+    int64_t* offs = (int64_t*)(((uintptr_t)(Uc + Mc * S) + 255) & ~(uintptr_t)255);
+    std::vector<int64_t> ho(2 * Mc);
+    for (int64_t j = 0; j < Mc; ++j) {
+      ho[j] = tasks[idx[j]].face_off;
+      ho[Mc + j] = tasks[idx[j]].state_off;
+    }
+    KC_TRY_HIP(hipMemcpyAsync(offs, ho.data(), sizeof(int64_t) * 2 * Mc, hipMemcpyHostToDevice, main));
+    launch_rows(true, main, a, offs, Fc, Mc, ac);
+    if (init == KC_INIT_GIVEN) launch_rows(true, main, U, offs + Mc, S, Mc, Uc);
+    pc->a = ac;
+    pc->u0 = nullptr;
+    pc->U = Uc;
+    pcs.push_back(std::move(pc));
+  }
+  KC_TRY_HIP(hipStreamSynchronize(main));
+  std::vector<ParaClass*> cls;
+  for (auto& pc : pcs) {
+    cls.push_back(pc.get());
+    if (init == KC_INIT_ZERO) {
+      zero_kernel<<<blocks_of(pc->M * pc->p.N * n_unknowns(pc->p)), 256, 0, pc->c->stream>>>(
+          pc->U, pc->M * pc->p.N * n_unknowns(pc->p));
+      KC_LAUNCH_CHECK();
+    } else if (init == KC_INIT_COARSE) {
+      int r = coarse_sweep_impl(pc->c, pc->p, pc->a, nullptr, pc->M, pc->U);
+      if (r != KC_OK) rc = r;
+    }
+    // status blocks are reset once: replays of a captured iteration accumulate into them
+    status_reset(pc->c, status_block(pc->c, WS_STATUS));
+    status_reset(pc->c, status_block(pc->c, WS_STATUS_CGC));
+    KC_TRY_HIP(hipStreamSynchronize(pc->c->stream));
+  }
+  DriverOut out;
+  int r = run_classes(ctx, cls, (flags & KC_BATCH_GRAPH) != 0, false, out);
+  if (r != KC_OK) rc = r;
+  // scatter the iterates back
+  for (int i = 0; i < C; ++i) {
+    ParaClass& pc = *pcs[i];
+    const int64_t S = (int64_t)pc.p.N * n_unknowns(pc.p);
+    const int64_t Fc = n_faces(base.dim, pc.p.n);
+    double* Uc = pc.U;
+    int64_t* offs = (int64_t*)(((uintptr_t)(Uc + pc.M * S) + 255) & ~(uintptr_t)255);
+    (void)Fc;
+    launch_rows(false, main, Uc, offs + pc.M, S, pc.M, U);
+  }
+  KC_TRY_HIP(hipEventRecord(e1, main));
+  KC_TRY_HIP(hipEventSynchronize(e1));
+  float ms = 0.f;
+  KC_TRY_HIP(hipEventElapsedTime(&ms, e0, e1));
+  if (total_ms) *total_ms = ms;
+  int rate_khz = 0;
+  KC_TRY_HIP(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, ctx->device));
+  size_t o = 0;
+  for (int i = 0; i < C; ++i) {
+    for (int64_t j : order[i].second) {
+      iters[j] = out.its[o];
+      status[j] = out.status[o];
+      if (latency_ms) {
+        const unsigned long long t = out.tconv[o];
+        latency_ms[j] = (t > out.t0 && rate_khz > 0) ? (double)(t - out.t0) / (double)rate_khz : -1.0;
+      }
+      ++o;
+    }
+  }
+  return rc;
+}
+
+}  // namespace kc

@@ -11,6 +11,8 @@
 // Layout: spectra are [M][N/2+1][Nx] complex128 (interleaved re, im).
 #include <cmath>
 
+#include <atomic>
+
 #include "common.h"
 #include "reduce.h"
 
@@ -885,8 +887,15 @@ void launch_cocg_resident(hipStream_t st, int64_t nsys, const double* a, const d
                           int N, double alpha, double rtol, float inner_rtol, int maxit, const uint8_t* active,
                           double* spec, double* resbuf, int* flag, unsigned long long* cnt) {
   const size_t lds = sizeof(float2) * (size_t)n * n;
-  KC_TRY_HIP(hipFuncSetAttribute((const void*)cocg_resident_kernel<NW, CPL, RPW>,
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  // the attribute is set once per variant, to the largest tile it serves (n = 64 CPL RPW
+  // / 8 columns by rows), before any launch that a graph capture could record
+  static std::atomic<bool> attr_set{false};
+  if (!attr_set.load()) {
+    const int max_lds = (int)(sizeof(float2) * (size_t)(64 * CPL) * (size_t)(NW * RPW));
+    KC_TRY_HIP(hipFuncSetAttribute((const void*)cocg_resident_kernel<NW, CPL, RPW>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, max_lds));
+    attr_set.store(true);
+  }
   cocg_resident_kernel<NW, CPL, RPW><<<dim3((unsigned)nsys), dim3(64 * NW), lds, st>>>(
       a, dr, n, cT, N, alpha, rtol, inner_rtol, maxit, active, spec, resbuf, flag, cnt);
   KC_LAUNCH_CHECK();
@@ -967,7 +976,7 @@ int shifted_solve_impl(klecgc_ctx* ctx, const klecgc_problem& p, const double* a
     });
     return KC_OK;
   }
-  DevStatus ds = status_block(ctx);
+  DevStatus ds = status_block(ctx, WS_STATUS_CGC);
   status_reset(ctx, ds);
   const double rtol = p.cgc_rtol > 0 ? p.cgc_rtol : 1e-13;
   const int maxit = p.cgc_max_iter > 0 ? p.cgc_max_iter : 20000;

@@ -53,7 +53,8 @@ enum WsSlot {
   WS_START,         // start buffer for the coarse sweep
   WS_GEMM_A,
   WS_GEMM_B,
-  WS_STATUS,
+  WS_STATUS,        // status block of the fine propagator
+  WS_STATUS_CGC,    // status block of the shifted solves
   WS_FINE_AUX,      // float32 correction tiles of the shifted solves
   WS_MLP,           // MLP predictions before prolongation
   WS_COUNT
@@ -77,6 +78,9 @@ struct klecgc_ctx {
   int64_t kcount[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   hipEvent_t ev[2] = {nullptr, nullptr};
   void* blas = nullptr;   // rocblas handle of the offline eigen-solver (created on first use)
+  // true while the context's launches are being captured into a graph: no event timing,
+  // no status resets or read-backs (the driver does them around the captured region)
+  bool capturing = false;
 };
 
 struct klecgc_kle {
@@ -114,10 +118,11 @@ struct DevStatus {
   int* flag;
   unsigned long long* cnt;
 };
-DevStatus status_block(klecgc_ctx* ctx);
+DevStatus status_block(klecgc_ctx* ctx, int slot = WS_STATUS);
+// zeroes the block (no-op while capturing)
 void status_reset(klecgc_ctx* ctx, const DevStatus& st);
 // copies the block to the host, adds the counters into ctx->stats[base..base+3] (and
-// the cycle counters 8, 9 for base 0); returns flag
+// the cycle counters 8, 9 for base 0); returns flag (0 without reading while capturing)
 int status_collect(klecgc_ctx* ctx, const DevStatus& st, int base);
 
 // Kernel classes timed with HIP events on the context stream.
@@ -126,6 +131,10 @@ enum KClass { KT_FINE = 0, KT_SHIFTED = 1, KT_FFT_FWD = 2, KT_FFT_INV = 3, KT_DE
 // (synchronises the stream).
 template <class F>
 void timed(klecgc_ctx* ctx, int cls, F&& launch) {
+  if (ctx->capturing) {
+    launch();
+    return;
+  }
   KC_TRY_HIP(hipEventRecord(ctx->ev[0], ctx->stream));
   launch();
   KC_TRY_HIP(hipEventRecord(ctx->ev[1], ctx->stream));
@@ -188,6 +197,16 @@ void launch_hermite(hipStream_t s, const double* xi, int64_t M, int d, const int
                     int pmax, double* Psi);
 void launch_col_mean_center(hipStream_t s, const double* S, int64_t n_t, int64_t L, double* mean,
                             double* Sc);
+
+// gPC prediction U0 = mean + Psi(xi) H W (abi.cpp)
+int gpc_predict_impl(klecgc_ctx* ctx, const klecgc_gpc* g, const double* xi, int64_t M, double* U0);
+// parareal drivers (batch.hip)
+int parareal_impl(klecgc_ctx* ctx, const klecgc_problem& p, const double* a, const double* u0, int64_t M,
+                  int32_t init, const double* init_dev, const klecgc_gpc* gpc, const double* xi, double* U,
+                  int32_t* iters, int32_t* status, double* hist);
+int parareal_batch_impl(klecgc_ctx* ctx, const klecgc_problem& base, const klecgc_task* tasks, int64_t M,
+                        const double* a, int32_t init, double* U, int32_t flags, int32_t* iters, int32_t* status,
+                        double* latency_ms, double* total_ms);
 
 // MLP initial guess (BF16 MFMA)
 int64_t mlp_param_count(const klecgc_mlp* h);

@@ -43,11 +43,14 @@ def test_struct_layouts_match_the_c_compiler(tmp_path):
         pytest.skip("no C compiler")
     fields_p = [f for f, _ in _lib.Problem._fields_]
     fields_k = [f for f, _ in _lib.KleDesc._fields_]
+    fields_t = [f for f, _ in _lib.Task._fields_]
     src = ["#include <stdio.h>", "#include <stddef.h>", '#include "klecgc.h"', "int main(void){"]
     src.append('printf("%zu\\n", sizeof(klecgc_problem));')
     src += ['printf("%%zu\\n", offsetof(klecgc_problem, %s));' % f for f in fields_p]
     src.append('printf("%zu\\n", sizeof(klecgc_kle_desc));')
     src += ['printf("%%zu\\n", offsetof(klecgc_kle_desc, %s));' % f for f in fields_k]
+    src.append('printf("%zu\\n", sizeof(klecgc_task));')
+    src += ['printf("%%zu\\n", offsetof(klecgc_task, %s));' % f for f in fields_t]
     src.append("return 0;}")
     c = tmp_path / "layout.c"
     c.write_text("\n".join(src))
@@ -56,6 +59,7 @@ def test_struct_layouts_match_the_c_compiler(tmp_path):
     vals = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
     want = [ctypes.sizeof(_lib.Problem)] + [getattr(_lib.Problem, f).offset for f in fields_p]
     want += [ctypes.sizeof(_lib.KleDesc)] + [getattr(_lib.KleDesc, f).offset for f in fields_k]
+    want += [ctypes.sizeof(_lib.Task)] + [getattr(_lib.Task, f).offset for f in fields_t]
     assert vals == want
 
 

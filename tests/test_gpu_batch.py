@@ -1,0 +1,134 @@
+"""GPU tests of ragged batches (parareal_solve_batch): samples of different grid size and
+slice count, grouped into classes that run on their own streams, with the iterations
+after the first replayed from a captured HIP graph and the convergence test on the device.
+
+Every sample must reproduce, bit for bit, what parareal_solve returns for its class run
+alone (same kernels on the same data), with and without the graph; a few samples are
+also checked against the oracle's Algorithm 2 iterate and serial fine solution.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import parareal as opar, prop
+from tests.gpu_helpers import dev, host, log, oracle_faces, rel
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2510_26180_amd as K
+    c = K.Context(0)
+    yield c
+    c.close()
+
+
+def _ragged(w, grids, slices, M, seed):
+    """Tasks with per-sample (n, N) drawn uniformly, laid out in a shuffled order."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ns = np.asarray(grids)[rng.integers(0, len(grids), M)]
+    Ns = np.asarray(slices)[rng.integers(0, len(slices), M)]
+    xi = W.draw_xi(M, w.d, seed + 1)
+    f_off = s_off = 0
+    order = rng.permutation(M)
+    fo = np.zeros(M, np.int64)
+    so = np.zeros(M, np.int64)
+    for m in order:                       # buffer layout order differs from task order
+        nx = ns[m] ** w.dim
+        fc = ns[m] + 1 if w.dim == 1 else 2 * ns[m] * (ns[m] + 1)
+        fo[m], so[m] = f_off, s_off
+        f_off += fc + 3                   # gaps between samples
+        s_off += Ns[m] * nx + 5
+    a = np.zeros(f_off)
+    for m in range(M):
+        wm = w.replace(n=int(ns[m]))
+        a[fo[m]:fo[m] + wm.n_faces] = oracle_faces(wm, xi[m:m + 1])[0]
+    return ns, Ns, xi, a, fo, so, s_off
+
+
+def _case(ctx, w, grids, slices, M, seed, graph, init_name="zero"):
+    import paper_2510_26180_amd as K
+    ns, Ns, xi, a, fo, so, s_len = _ragged(w, grids, slices, M, seed)
+    base = K.ProblemSpec.from_workload(w)
+    tasks = [(int(ns[m]), int(Ns[m]), int(fo[m]), int(so[m])) for m in range(M)]
+    a_d = dev(a)
+    U_d = torch.full((s_len,), 7.0, dtype=torch.float64, device="cuda")
+    init = {"zero": K.KC_INIT_ZERO, "coarse": K.KC_INIT_COARSE}[init_name]
+    its, st, lat, total, rc = ctx.parareal_solve_batch(base, tasks, a_d, U_d, init=init, graph=graph)
+    log(f"  batch M={M} graph={graph}: iterations {its.min()}..{its.max()}, total {total:.1f} ms, "
+        f"latency p50 {np.percentile(lat, 50):.1f} p99 {np.percentile(lat, 99):.1f} ms")
+    U = host(U_d)
+    # per class: the uniform driver on the same samples
+    for (n, N) in sorted(set(zip(ns.tolist(), Ns.tolist()))):
+        idx = [m for m in range(M) if ns[m] == n and Ns[m] == N]
+        wc = w.replace(n=n, N=N)
+        pc = K.ProblemSpec.from_workload(wc)
+        ac = dev(np.stack([a[fo[m]:fo[m] + wc.n_faces] for m in idx]))
+        Uc = torch.empty((len(idx), N, wc.Nx), dtype=torch.float64, device="cuda")
+        itc, stc, _, _ = ctx.parareal_solve(pc, ac, Uc, init=init)
+        Uh = host(Uc)
+        for j, m in enumerate(idx):
+            assert its[m] == itc[j] and st[m] == stc[j], (n, N, m)
+            got = U[so[m]:so[m] + N * wc.Nx].reshape(N, wc.Nx)
+            assert np.array_equal(got, Uh[j]), (n, N, m)
+    # the gaps between samples are untouched
+    mask = np.ones(s_len, bool)
+    for m in range(M):
+        mask[so[m]:so[m] + Ns[m] * ns[m] ** w.dim] = False
+    assert np.all(U[mask] == 7.0)
+    assert (st == K.KC_SAMPLE_CONVERGED).all()
+    assert np.all(lat > 0) and np.all(lat <= total * (1 + 1e-6))
+    return ns, Ns, xi, U, so, its, lat
+
+
+@pytest.mark.parametrize("graph", [True, False])
+def test_ragged_1d_matches_uniform_and_oracle(ctx, graph):
+    w = W.small_1d(alpha=1e-2, J=8)
+    log(f"ragged 1D graph={graph}")
+    ns, Ns, xi, U, so, its, lat = _case(ctx, w, (15, 31, 40), (4, 8, 16), 24, 101, graph)
+    for m in range(3):
+        wm = w.replace(n=int(ns[m]), N=int(Ns[m]))
+        a0 = oracle_faces(wm, xi[m:m + 1])[0]
+        P = prop.Propagators(1, wm.n, a0, wm.T, wm.N, wm.J, wm.forcing)
+        res = opar.parareal_diag(P, wm.alpha, np.zeros(wm.Nx), np.zeros((wm.N, wm.Nx)), wm.tol, wm.max_iter)
+        got = U[so[m]:so[m] + wm.N * wm.Nx].reshape(wm.N, wm.Nx)
+        assert its[m] == res.iters
+        assert rel(got, res.iterates[-1]) <= 1e-10
+        assert rel(got, prop.serial_fine(P, np.zeros(wm.Nx), wm.N)) <= 1e-8
+
+
+@pytest.mark.parametrize("graph", [True, False])
+def test_ragged_2d_f64_matches_uniform(ctx, graph):
+    w = W.small_2d(alpha=1e-2, J=4, d=6)
+    log(f"ragged 2D f64 graph={graph}")
+    _case(ctx, w, (9, 16, 20), (4, 8), 12, 202, graph)
+
+
+def test_ragged_2d_f32_refined_matches_uniform(ctx):
+    w = W.small_2d(alpha=1e-2, J=4, d=6, precision="f32_refined")
+    log("ragged 2D f32-refined (resident fine and shifted kernels)")
+    _case(ctx, w, (12, 33, 65), (4, 8), 10, 303, True, init_name="coarse")
+
+
+def test_ragged_latency_ordered_within_class(ctx):
+    w = W.small_1d(alpha=1e-2, J=8)
+    ns, Ns, xi, U, so, its, lat = _case(ctx, w, (31,), (8,), 16, 404, True)
+    order = np.argsort(its, kind="stable")
+    assert np.all(np.diff(lat[order]) >= -1e-9) or len(set(its)) == 1
+
+
+def test_ragged_rejects_bad_tasks(ctx):
+    import paper_2510_26180_amd as K
+    w = W.small_1d()
+    base = K.ProblemSpec.from_workload(w)
+    a_d = torch.ones(64, dtype=torch.float64, device="cuda")
+    U_d = torch.zeros(256, dtype=torch.float64, device="cuda")
+    with pytest.raises(K.KlecgcError) as e:
+        ctx.parareal_solve_batch(base, [(15, 6, 0, 0)], a_d, U_d)          # N not a power of two
+    assert e.value.code == -1
+    with pytest.raises(K.KlecgcError) as e:
+        ctx.parareal_solve_batch(base, [(15, 4, 0, 0)], a_d, U_d, init=K.KC_INIT_GPC)
+    assert e.value.code == -7
