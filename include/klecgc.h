@@ -122,6 +122,37 @@ int klecgc_last_stats(const klecgc_ctx* ctx, int64_t* out16);
  * step (b), 2 forward slice FFT, 3 inverse slice FFT, 4 defect stencil, 5 prediction GEMM,
  * 6 MLP forward/backward/Adam. */
 int klecgc_last_times(const klecgc_ctx* ctx, double* ms8, int64_t* count8);
+/* Kernel choices for 2D KC_PREC_F32_REFINED problems of one grid size n, and the
+ * float32 residual reduction each refinement pass asks of the inner Krylov loop (the
+ * float64 residual targets inner_rtol / cgc_rtol are unaffected: they alone decide
+ * when a solve stops).  Variants (-1 = built-in choice by n):
+ *   fine:  KC_FINE_STREAM64 float64 PCG streaming through device memory (any n);
+ *          KC_FINE_RES16/32/64/128 work-group-resident float32 PCG for n <= 16/32/64/128;
+ *   shifted solves of step (b): KC_CGC_STREAM64 float64 COCG (any n);
+ *          KC_CGC_RES16/32/64 work-group-resident float32 COCG for n <= 16/32/64;
+ *          KC_CGC_STREAM32 float32 COCG streaming through device memory (any n). */
+enum { KC_FINE_STREAM64 = 0, KC_FINE_RES16 = 1, KC_FINE_RES32 = 2, KC_FINE_RES64 = 3, KC_FINE_RES128 = 4 };
+enum { KC_CGC_STREAM64 = 0, KC_CGC_RES16 = 1, KC_CGC_RES32 = 2, KC_CGC_RES64 = 3, KC_CGC_STREAM32 = 4 };
+typedef struct {
+  int32_t fine_variant;    /* -1 or KC_FINE_* */
+  float   fine_pcg_rtol;   /* in (0, 0.5); default 1e-6 */
+  int32_t cgc_variant;     /* -1 or KC_CGC_* */
+  float   cgc_inner_rtol;  /* in (0, 0.5); default 1e-5 */
+} klecgc_tuning;
+/* Set / read the tuning the context uses for grid size n (KC_EINVAL if a variant does
+ * not fit n or a tolerance is out of range).  klecgc_get_tuning returns the defaults
+ * (-1, 1e-6, -1, 1e-5) for an n never tuned. */
+int klecgc_set_tuning(klecgc_ctx* ctx, int32_t n, const klecgc_tuning* t);
+int klecgc_get_tuning(const klecgc_ctx* ctx, int32_t n, klecgc_tuning* t);
+/* Autotuner: times every fitting fine variant x per-pass reduction {1e-5, 3e-6, 1e-6,
+ * 3e-7} on the first min(M, 4) samples of a_dev (fine sweep over all N slices from the
+ * coarse-propagator states), then every fitting shifted-solve variant x {1e-4, 3e-5,
+ * 1e-5, 3e-6} on the defect those states leave (correction tolerance cgc_rtol, default
+ * 1e-7), keeps the fastest of each for prob->n in the context and returns it in *out
+ * (nullable).  ms_out[2] (nullable): the winning fine and shifted-solve times.
+ * prob must be 2D and KC_PREC_F32_REFINED (else KC_EUNSUPPORTED). */
+int klecgc_autotune(klecgc_ctx* ctx, const klecgc_problem* prob, const double* a_dev, int64_t M,
+                    klecgc_tuning* out, double* ms_out);
 /* Library version string (static storage). */
 const char* klecgc_version(void);
 

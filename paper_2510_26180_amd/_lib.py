@@ -44,6 +44,13 @@ class Task(ctypes.Structure):
 
 
 KC_BATCH_GRAPH = 1
+KC_FINE_STREAM64, KC_FINE_RES16, KC_FINE_RES32, KC_FINE_RES64, KC_FINE_RES128 = 0, 1, 2, 3, 4
+KC_CGC_STREAM64, KC_CGC_RES16, KC_CGC_RES32, KC_CGC_RES64, KC_CGC_STREAM32 = 0, 1, 2, 3, 4
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("fine_variant", ctypes.c_int32), ("fine_pcg_rtol", ctypes.c_float),
+                ("cgc_variant", ctypes.c_int32), ("cgc_inner_rtol", ctypes.c_float)]
 
 _vp = ctypes.c_void_p
 _i64 = ctypes.c_int64
@@ -61,6 +68,9 @@ SIGNATURES = {
     "klecgc_version": (ctypes.c_char_p, []),
     "klecgc_last_stats": (ctypes.c_int, [_vp, _P(ctypes.c_int64)]),
     "klecgc_last_times": (ctypes.c_int, [_vp, _P(ctypes.c_double), _P(ctypes.c_int64)]),
+    "klecgc_set_tuning": (ctypes.c_int, [_vp, _i32, _P(Tuning)]),
+    "klecgc_get_tuning": (ctypes.c_int, [_vp, _i32, _P(Tuning)]),
+    "klecgc_autotune": (ctypes.c_int, [_vp, _P(Problem), _vp, _i64, _P(Tuning), _P(ctypes.c_double)]),
     "serial_fine_propagate": (ctypes.c_int, [_vp, _P(Problem), _vp, _vp, _i64, _vp]),
     "kle_build": (ctypes.c_int, [_vp, _P(KleDesc), _vp, _i64, _P(_vp), _P(_i32)]),
     "kle_synthesize": (ctypes.c_int, [_vp, _vp, _vp, _i64, _vp]),

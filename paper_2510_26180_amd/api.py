@@ -132,6 +132,25 @@ class Context:
         self._check(self.lib.klecgc_last_times(self.h, ms, cnt))
         return {k: (ms[i], cnt[i]) for i, k in enumerate(self.KCLASSES)}
 
+    # ---- tuning
+    def set_tuning(self, n: int, fine_variant=-1, fine_pcg_rtol=1e-6, cgc_variant=-1, cgc_inner_rtol=1e-5):
+        t = L.Tuning(fine_variant, fine_pcg_rtol, cgc_variant, cgc_inner_rtol)
+        self._check(self.lib.klecgc_set_tuning(self.h, n, ctypes.byref(t)))
+
+    def get_tuning(self, n: int) -> dict:
+        t = L.Tuning()
+        self._check(self.lib.klecgc_get_tuning(self.h, n, ctypes.byref(t)))
+        return {f: getattr(t, f) for f, _ in L.Tuning._fields_}
+
+    def autotune(self, prob: ProblemSpec, a) -> dict:
+        t = L.Tuning()
+        ms = (ctypes.c_double * 2)()
+        pc = prob.c()
+        self._check(self.lib.klecgc_autotune(self.h, ctypes.byref(pc), _ptr(a), a.shape[0], ctypes.byref(t), ms))
+        out = {f: getattr(t, f) for f, _ in L.Tuning._fields_}
+        out.update(fine_ms=ms[0], cgc_ms=ms[1])
+        return out
+
     def close(self):
         if getattr(self, "h", None):
             self.lib.klecgc_destroy(self.h)

@@ -230,6 +230,47 @@ int klecgc_last_times(const klecgc_ctx* ctx, double* ms8, int64_t* count8) {
   return KC_OK;
 }
 
+int klecgc_set_tuning(klecgc_ctx* ctx, int32_t n, const klecgc_tuning* t) {
+  return guarded(ctx, [&] {
+    KC_REQUIRE(t, KC_EINVAL, "null argument");
+    KC_REQUIRE(n >= 1, KC_EINVAL, "n must be >= 1");
+    KC_REQUIRE(t->fine_variant == -1 || fine_variant_fits(t->fine_variant, n), KC_EINVAL,
+               "fine variant does not fit this grid size");
+    KC_REQUIRE(t->cgc_variant == -1 || cgc_variant_fits(t->cgc_variant, n), KC_EINVAL,
+               "shifted-solve variant does not fit this grid size");
+    KC_REQUIRE(t->fine_pcg_rtol > 0.f && t->fine_pcg_rtol < 0.5f && t->cgc_inner_rtol > 0.f &&
+                   t->cgc_inner_rtol < 0.5f,
+               KC_EINVAL, "per-pass reductions must lie in (0, 0.5)");
+    KcTuning k;
+    k.fine_variant = t->fine_variant;
+    k.fine_pcg_rtol = t->fine_pcg_rtol;
+    k.cgc_variant = t->cgc_variant;
+    k.cgc_inner_rtol = t->cgc_inner_rtol;
+    ctx->tuning[n] = k;
+    return KC_OK;
+  });
+}
+
+int klecgc_get_tuning(const klecgc_ctx* ctx, int32_t n, klecgc_tuning* t) {
+  if (!ctx || !t) return KC_EINVAL;
+  const KcTuning k = tuning_for(ctx, n);
+  t->fine_variant = k.fine_variant;
+  t->fine_pcg_rtol = k.fine_pcg_rtol;
+  t->cgc_variant = k.cgc_variant;
+  t->cgc_inner_rtol = k.cgc_inner_rtol;
+  return KC_OK;
+}
+
+int klecgc_autotune(klecgc_ctx* ctx, const klecgc_problem* prob, const double* a_dev, int64_t M, klecgc_tuning* out,
+                    double* ms_out) {
+  return guarded(ctx, [&] {
+    KC_REQUIRE(prob && a_dev, KC_EINVAL, "null argument");
+    KC_REQUIRE(M >= 1, KC_EINVAL, "M must be >= 1");
+    validate_problem(*prob);
+    return autotune_impl(ctx, *prob, a_dev, M, out, ms_out);
+  });
+}
+
 int klecgc_last_stats(const klecgc_ctx* ctx, int64_t* out16) {
   if (!ctx || !out16) return KC_EINVAL;
   for (int i = 0; i < 16; ++i) out16[i] = ctx->stats[i];

@@ -532,6 +532,7 @@ int parareal_batch_impl(klecgc_ctx* ctx, const klecgc_problem& base, const klecg
     const auto& idx = order[i].second;
     subs.emplace_back(new SubCtx(ctx->device, ctx->num_cus));
     klecgc_ctx* sc = &subs.back()->c;
+    sc->tuning = ctx->tuning;
     auto pc = std::make_unique<ParaClass>();
     pc->c = sc;
     pc->p = base;

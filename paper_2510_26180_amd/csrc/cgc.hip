@@ -980,7 +980,10 @@ int shifted_solve_impl(klecgc_ctx* ctx, const klecgc_problem& p, const double* a
   status_reset(ctx, ds);
   const double rtol = p.cgc_rtol > 0 ? p.cgc_rtol : 1e-13;
   const int maxit = p.cgc_max_iter > 0 ? p.cgc_max_iter : 20000;
-  if (p.precision == KC_PREC_F32_REFINED && p.n > 64) {
+  const KcTuning tu = tuning_for(ctx, p.n);
+  const int variant = p.precision == KC_PREC_F32_REFINED ? cgc_variant_for(p.n, tu.cgc_variant) : KC_CGC_STREAM64;
+  const float inner = tu.cgc_inner_rtol;
+  if (variant == KC_CGC_STREAM32) {
     double* dr = (double*)ctx->ws.get(WS_DINV, sizeof(double) * Nx * nsys);
     double* resb = (double*)ctx->ws.get(WS_KRYLOV, sizeof(double) * 2 * Nx * nsys);
     float* scr = (float*)ctx->ws.get(WS_FINE_AUX, sizeof(float) * 11 * Nx * nsys);
@@ -989,24 +992,23 @@ int shifted_solve_impl(klecgc_ctx* ctx, const klecgc_problem& p, const double* a
     KC_LAUNCH_CHECK();
     timed(ctx, KT_SHIFTED, [&] {
       cocg32_stream_kernel<<<dim3((unsigned)nsys), dim3(512), 0, st>>>(
-          a, dr, p.n, cT, p.N, p.alpha, rtol, 1e-5f, maxit, active, spec, resb, scr, ds.flag, ds.cnt);
+          a, dr, p.n, cT, p.N, p.alpha, rtol, inner, maxit, active, spec, resb, scr, ds.flag, ds.cnt);
       KC_LAUNCH_CHECK();
     });
     return status_collect(ctx, ds, 4) ? KC_ENOCONV : KC_OK;
   }
-  if (p.precision == KC_PREC_F32_REFINED && p.n <= 64) {
+  if (variant != KC_CGC_STREAM64) {
     double* dr = (double*)ctx->ws.get(WS_DINV, sizeof(double) * Nx * nsys);
     double* resb = (double*)ctx->ws.get(WS_KRYLOV, sizeof(double) * 2 * Nx * nsys);
     shift_dinv_kernel<<<dim3((unsigned)((Nx + 255) / 256), (unsigned)nsys), dim3(256), 0, st>>>(
         a, p.n, cT, p.N, p.alpha, M, dr);
     KC_LAUNCH_CHECK();
-    const float inner = 1e-5f;
     timed(ctx, KT_SHIFTED, [&] {
       // 8 waves; one grid row block of RPW rows per wave, one column per lane
-      if (p.n <= 16)
+      if (variant == KC_CGC_RES16)
         launch_cocg_resident<8, 1, 2>(st, nsys, a, dr, p.n, cT, p.N, p.alpha, rtol, inner, maxit, active, spec,
                                       resb, ds.flag, ds.cnt);
-      else if (p.n <= 32)
+      else if (variant == KC_CGC_RES32)
         launch_cocg_resident<8, 1, 4>(st, nsys, a, dr, p.n, cT, p.N, p.alpha, rtol, inner, maxit, active, spec,
                                       resb, ds.flag, ds.cnt);
       else
@@ -1022,6 +1024,25 @@ int shifted_solve_impl(klecgc_ctx* ctx, const klecgc_problem& p, const double* a
     KC_LAUNCH_CHECK();
   });
   return status_collect(ctx, ds, 4) ? KC_ENOCONV : KC_OK;
+}
+
+bool cgc_variant_fits(int v, int n) {
+  switch (v) {
+    case KC_CGC_STREAM64: return true;
+    case KC_CGC_RES16: return n <= 16;
+    case KC_CGC_RES32: return n <= 32;
+    case KC_CGC_RES64: return n <= 64;
+    case KC_CGC_STREAM32: return true;
+    default: return false;
+  }
+}
+
+int cgc_variant_for(int n, int requested) {
+  if (requested >= 0 && cgc_variant_fits(requested, n)) return requested;
+  if (n <= 16) return KC_CGC_RES16;
+  if (n <= 32) return KC_CGC_RES32;
+  if (n <= 64) return KC_CGC_RES64;
+  return KC_CGC_STREAM32;
 }
 
 }  // namespace kc

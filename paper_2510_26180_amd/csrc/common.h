@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -62,6 +63,15 @@ enum WsSlot {
 
 }  // namespace kc
 
+// Kernel choices and inner tolerances for 2D float32-refined problems of one grid size
+// (set by the autotuner or klecgc_set_tuning; the defaults are the built-in heuristic).
+struct KcTuning {
+  int fine_variant = -1;        // -1 heuristic; KC_FINE_* otherwise
+  float fine_pcg_rtol = 1e-6f;  // float32 PCG residual reduction per refinement pass
+  int cgc_variant = -1;         // -1 heuristic; KC_CGC_* otherwise
+  float cgc_inner_rtol = 1e-5f; // float32 COCG residual reduction per refinement pass
+};
+
 struct klecgc_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -81,6 +91,7 @@ struct klecgc_ctx {
   // true while the context's launches are being captured into a graph: no event timing,
   // no status resets or read-backs (the driver does them around the captured region)
   bool capturing = false;
+  std::map<int, KcTuning> tuning;   // by grid size n
 };
 
 struct klecgc_kle {
@@ -145,6 +156,16 @@ void timed(klecgc_ctx* ctx, int cls, F&& launch) {
   ctx->kcount[cls] += 1;
 }
 
+inline KcTuning tuning_for(const klecgc_ctx* ctx, int n) {
+  auto it = ctx->tuning.find(n);
+  return it == ctx->tuning.end() ? KcTuning{} : it->second;
+}
+// the fine / shifted-solve kernel a 2D float32-refined problem of grid size n runs
+int fine_variant_for(int n, int requested);
+int cgc_variant_for(int n, int requested);
+bool fine_variant_fits(int v, int n);
+bool cgc_variant_fits(int v, int n);
+
 inline int64_t n_unknowns(const klecgc_problem& p) { return p.dim == 1 ? p.n : (int64_t)p.n * p.n; }
 inline int64_t n_faces(int dim, int n) { return dim == 1 ? n + 1 : 2LL * n * (n + 1); }
 
@@ -207,6 +228,10 @@ int parareal_impl(klecgc_ctx* ctx, const klecgc_problem& p, const double* a, con
 int parareal_batch_impl(klecgc_ctx* ctx, const klecgc_problem& base, const klecgc_task* tasks, int64_t M,
                         const double* a, int32_t init, double* U, int32_t flags, int32_t* iters, int32_t* status,
                         double* latency_ms, double* total_ms);
+
+// autotuner (tune.cpp)
+int autotune_impl(klecgc_ctx* ctx, const klecgc_problem& p, const double* a, int64_t M, klecgc_tuning* out,
+                  double* ms_out);
 
 // MLP initial guess (BF16 MFMA)
 int64_t mlp_param_count(const klecgc_mlp* h);

@@ -612,34 +612,60 @@ int propagate_impl(klecgc_ctx* ctx, const klecgc_problem& p, const FineArgs& fa,
   const double tol = p.inner_rtol > 0 ? p.inner_rtol : 1e-13;
   const int maxit = p.inner_max_iter > 0 ? p.inner_max_iter : 4000;
   double* dinv = (double*)ctx->ws.get(WS_DINV, sizeof(double) * Nx * M);
-  bool resident = (p.precision == KC_PREC_F32_REFINED) && n <= 128;
+  const KcTuning tu = tuning_for(ctx, n);
+  const int variant = p.precision == KC_PREC_F32_REFINED ? fine_variant_for(n, tu.fine_variant) : KC_FINE_STREAM64;
+  const bool resident = variant != KC_FINE_STREAM64;
   float* sf = resident ? (float*)ctx->ws.get(WS_FSCALED, sizeof(float) * Fc * M) : nullptr;
   build_tables_2d(st, fa.a, n, c, M, dinv, sf);
   double* resbuf = resident ? (double*)ctx->ws.get(WS_KRYLOV, sizeof(double) * Nx * nsys) : nullptr;
   double* scr = resident ? nullptr : (double*)ctx->ws.get(WS_KRYLOV, sizeof(double) * 3 * Nx * nsys);
-  const float pcg_rtol = 1e-6f;
+  const float pcg_rtol = tu.fine_pcg_rtol;
   timed(ctx, KT_FINE, [&] {
-  if (resident) {
-    if (n <= 16)
-      launch_resident<8, 1, 2>(st, nsys, fa.a, sf, dinv, n, c, tauf, J, tol, pcg_rtol, maxit, sr,
-                               fa.out, resbuf, M, N, fa.skip_first, fa.active, flag, cnt);
-    else if (n <= 32)
-      launch_resident<8, 1, 4>(st, nsys, fa.a, sf, dinv, n, c, tauf, J, tol, pcg_rtol, maxit, sr,
-                               fa.out, resbuf, M, N, fa.skip_first, fa.active, flag, cnt);
-    else if (n <= 64)
-      launch_resident<8, 1, 8>(st, nsys, fa.a, sf, dinv, n, c, tauf, J, tol, pcg_rtol, maxit, sr,
-                               fa.out, resbuf, M, N, fa.skip_first, fa.active, flag, cnt);
-    else
-      launch_resident<KC_RES128_NW, 2, 128 / KC_RES128_NW>(st, nsys, fa.a, sf, dinv, n, c, tauf, J, tol,
-                                                           pcg_rtol, maxit, sr, fa.out, resbuf, M, N,
-                                                           fa.skip_first, fa.active, flag, cnt);
-  } else {
-    fine2d_pcg64_kernel<<<dim3((unsigned)nsys), dim3(kStreamThreads), 0, st>>>(
-        fa.a, dinv, n, c, tauf, J, tol, maxit, sr, fa.out, scr, M, N, fa.skip_first, fa.active, flag, cnt);
-    KC_LAUNCH_CHECK();
-  }
+    switch (variant) {
+      case KC_FINE_RES16:
+        launch_resident<8, 1, 2>(st, nsys, fa.a, sf, dinv, n, c, tauf, J, tol, pcg_rtol, maxit, sr, fa.out, resbuf,
+                                 M, N, fa.skip_first, fa.active, flag, cnt);
+        break;
+      case KC_FINE_RES32:
+        launch_resident<8, 1, 4>(st, nsys, fa.a, sf, dinv, n, c, tauf, J, tol, pcg_rtol, maxit, sr, fa.out, resbuf,
+                                 M, N, fa.skip_first, fa.active, flag, cnt);
+        break;
+      case KC_FINE_RES64:
+        launch_resident<8, 1, 8>(st, nsys, fa.a, sf, dinv, n, c, tauf, J, tol, pcg_rtol, maxit, sr, fa.out, resbuf,
+                                 M, N, fa.skip_first, fa.active, flag, cnt);
+        break;
+      case KC_FINE_RES128:
+        launch_resident<KC_RES128_NW, 2, 128 / KC_RES128_NW>(st, nsys, fa.a, sf, dinv, n, c, tauf, J, tol, pcg_rtol,
+                                                             maxit, sr, fa.out, resbuf, M, N, fa.skip_first,
+                                                             fa.active, flag, cnt);
+        break;
+      default:
+        fine2d_pcg64_kernel<<<dim3((unsigned)nsys), dim3(kStreamThreads), 0, st>>>(
+            fa.a, dinv, n, c, tauf, J, tol, maxit, sr, fa.out, scr, M, N, fa.skip_first, fa.active, flag, cnt);
+        KC_LAUNCH_CHECK();
+    }
   });
   return status_collect(ctx, ds, 0) ? KC_ENOCONV : KC_OK;
+}
+
+bool fine_variant_fits(int v, int n) {
+  switch (v) {
+    case KC_FINE_STREAM64: return true;
+    case KC_FINE_RES16: return n <= 16;
+    case KC_FINE_RES32: return n <= 32;
+    case KC_FINE_RES64: return n <= 64;
+    case KC_FINE_RES128: return n <= 128;
+    default: return false;
+  }
+}
+
+int fine_variant_for(int n, int requested) {
+  if (requested >= 0 && fine_variant_fits(requested, n)) return requested;
+  if (n <= 16) return KC_FINE_RES16;
+  if (n <= 32) return KC_FINE_RES32;
+  if (n <= 64) return KC_FINE_RES64;
+  if (n <= 128) return KC_FINE_RES128;
+  return KC_FINE_STREAM64;
 }
 
 int fine_propagate_impl(klecgc_ctx* ctx, const klecgc_problem& p, const FineArgs& fa) {

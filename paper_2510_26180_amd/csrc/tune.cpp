@@ -1,0 +1,142 @@
+// Autotuner for the 2D float32-refined path: for one grid size it times the kernel
+// variants that fit (work-group-resident or streaming Krylov solvers) and the float32
+// residual reduction asked of each refinement pass, on a small probe batch of the
+// caller's samples, and keeps the fastest in the context's tuning table.  The float64
+// residual targets, and so the results' accuracy, do not depend on these choices.
+#include <algorithm>
+#include <cmath>
+#include <limits>
+#include <vector>
+
+#include "common.h"
+
+namespace kc {
+
+namespace {
+struct Buf {
+  void* p = nullptr;
+  explicit Buf(size_t bytes) {
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      p = nullptr;
+      throw Error{KC_ENOMEM, "autotuner buffer allocation failed"};
+    }
+  }
+  ~Buf() {
+    if (p) (void)hipFree(p);
+  }
+  Buf(const Buf&) = delete;
+  Buf& operator=(const Buf&) = delete;
+};
+}  // namespace
+
+int autotune_impl(klecgc_ctx* ctx, const klecgc_problem& p, const double* a, int64_t M, klecgc_tuning* out,
+                  double* ms_out) {
+  KC_REQUIRE(p.dim == 2 && p.precision == KC_PREC_F32_REFINED, KC_EUNSUPPORTED,
+             "the autotuner serves 2D float32-refined problems");
+  hipStream_t st = ctx->stream;
+  const int n = p.n;
+  const int64_t Mp = std::min<int64_t>(M, 4);
+  const int64_t Nx = n_unknowns(p);
+  const int64_t S = (int64_t)p.N * Nx;
+  const int K = p.N / 2 + 1;
+  Buf U(sizeof(double) * Mp * S), Fv(sizeof(double) * Mp * S), D(sizeof(double) * Mp * S);
+  Buf spec0(sizeof(double) * 2 * Mp * K * Nx), spec(sizeof(double) * 2 * Mp * K * Nx);
+  // probe states: one coarse sweep from zero (the states parareal starts from)
+  coarse_sweep_impl(ctx, p, a, nullptr, Mp, (double*)U.p);
+  const bool had = ctx->tuning.count(n) > 0;
+  const KcTuning saved = tuning_for(ctx, n);
+  KcTuning best = saved;
+  double best_fine = std::numeric_limits<double>::infinity();
+  double best_cgc = std::numeric_limits<double>::infinity();
+  const float fine_rtols[] = {1e-5f, 3e-6f, 1e-6f, 3e-7f};
+  const float cgc_rtols[] = {1e-4f, 3e-5f, 1e-5f, 3e-6f};
+  auto restore = [&]() {   // on an error: the tuning the context had before
+    if (had)
+      ctx->tuning[n] = saved;
+    else
+      ctx->tuning.erase(n);
+  };
+  try {
+    // ---- fine propagator
+    bool resident_fits = false;
+    for (int v : {KC_FINE_RES16, KC_FINE_RES32, KC_FINE_RES64, KC_FINE_RES128})
+      resident_fits = resident_fits || fine_variant_fits(v, n);
+    for (int v : {KC_FINE_RES16, KC_FINE_RES32, KC_FINE_RES64, KC_FINE_RES128, KC_FINE_STREAM64}) {
+      if (!fine_variant_fits(v, n) || (v == KC_FINE_STREAM64 && resident_fits)) continue;
+      bool warmed = false;
+      for (float r : fine_rtols) {
+        if (v == KC_FINE_STREAM64 && r != fine_rtols[0]) break;   // no float32 pass to tune
+        KcTuning t = saved;
+        t.fine_variant = v;
+        t.fine_pcg_rtol = r;
+        ctx->tuning[n] = t;
+        FineArgs fa{a, (const double*)U.p, nullptr, true, 0, nullptr, (double*)Fv.p, Mp};
+        if (!warmed) {
+          (void)fine_propagate_impl(ctx, p, fa);
+          warmed = true;
+        }
+        const double t0 = ctx->ktime[KT_FINE];
+        const int rc = fine_propagate_impl(ctx, p, fa);
+        const double ms = ctx->ktime[KT_FINE] - t0;
+        if (rc == KC_OK && ms < best_fine) {
+          best_fine = ms;
+          best.fine_variant = v;
+          best.fine_pcg_rtol = r;
+        }
+      }
+    }
+    KC_REQUIRE(best_fine < std::numeric_limits<double>::infinity(), KC_ENOCONV,
+               "no fine-propagator variant converged on the probe batch");
+    // ---- shifted solves of step (b), on the defect the probe states leave
+    ctx->tuning[n] = best;
+    FineArgs fa{a, (const double*)U.p, nullptr, true, 0, nullptr, (double*)Fv.p, Mp};
+    (void)fine_propagate_impl(ctx, p, fa);
+    launch_defect(st, p, a, (const double*)Fv.p, (const double*)U.p, nullptr, Mp, (double*)D.p);
+    launch_fft_forward(st, p, (const double*)D.p, nullptr, Mp, (double*)spec0.p);
+    klecgc_problem pb = p;
+    if (pb.cgc_rtol <= 0) pb.cgc_rtol = 1e-7;
+    for (int v : {KC_CGC_RES16, KC_CGC_RES32, KC_CGC_RES64, KC_CGC_STREAM32}) {
+      if (!cgc_variant_fits(v, n)) continue;
+      bool warmed = false;
+      for (float r : cgc_rtols) {
+        KcTuning t = best;
+        t.cgc_variant = v;
+        t.cgc_inner_rtol = r;
+        ctx->tuning[n] = t;
+        if (!warmed) {
+          KC_TRY_HIP(hipMemcpyAsync(spec.p, spec0.p, sizeof(double) * 2 * Mp * K * Nx, hipMemcpyDeviceToDevice, st));
+          (void)shifted_solve_impl(ctx, pb, a, nullptr, Mp, (double*)spec.p);
+          warmed = true;
+        }
+        KC_TRY_HIP(hipMemcpyAsync(spec.p, spec0.p, sizeof(double) * 2 * Mp * K * Nx, hipMemcpyDeviceToDevice, st));
+        const double t0 = ctx->ktime[KT_SHIFTED];
+        const int rc = shifted_solve_impl(ctx, pb, a, nullptr, Mp, (double*)spec.p);
+        const double ms = ctx->ktime[KT_SHIFTED] - t0;
+        if (rc == KC_OK && ms < best_cgc) {
+          best_cgc = ms;
+          best.cgc_variant = v;
+          best.cgc_inner_rtol = r;
+        }
+      }
+    }
+  } catch (...) {
+    restore();
+    throw;
+  }
+  KC_TRY_HIP(hipStreamSynchronize(st));
+  ctx->tuning[n] = best;
+  if (out) {
+    out->fine_variant = best.fine_variant;
+    out->fine_pcg_rtol = best.fine_pcg_rtol;
+    out->cgc_variant = best.cgc_variant;
+    out->cgc_inner_rtol = best.cgc_inner_rtol;
+  }
+  if (ms_out) {
+    ms_out[0] = best_fine;
+    ms_out[1] = best_cgc;
+  }
+  return KC_OK;
+}
+
+}  // namespace kc

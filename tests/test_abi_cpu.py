@@ -44,6 +44,7 @@ def test_struct_layouts_match_the_c_compiler(tmp_path):
     fields_p = [f for f, _ in _lib.Problem._fields_]
     fields_k = [f for f, _ in _lib.KleDesc._fields_]
     fields_t = [f for f, _ in _lib.Task._fields_]
+    fields_u = [f for f, _ in _lib.Tuning._fields_]
     src = ["#include <stdio.h>", "#include <stddef.h>", '#include "klecgc.h"', "int main(void){"]
     src.append('printf("%zu\\n", sizeof(klecgc_problem));')
     src += ['printf("%%zu\\n", offsetof(klecgc_problem, %s));' % f for f in fields_p]
@@ -51,6 +52,8 @@ def test_struct_layouts_match_the_c_compiler(tmp_path):
     src += ['printf("%%zu\\n", offsetof(klecgc_kle_desc, %s));' % f for f in fields_k]
     src.append('printf("%zu\\n", sizeof(klecgc_task));')
     src += ['printf("%%zu\\n", offsetof(klecgc_task, %s));' % f for f in fields_t]
+    src.append('printf("%zu\\n", sizeof(klecgc_tuning));')
+    src += ['printf("%%zu\\n", offsetof(klecgc_tuning, %s));' % f for f in fields_u]
     src.append("return 0;}")
     c = tmp_path / "layout.c"
     c.write_text("\n".join(src))
@@ -60,6 +63,7 @@ def test_struct_layouts_match_the_c_compiler(tmp_path):
     want = [ctypes.sizeof(_lib.Problem)] + [getattr(_lib.Problem, f).offset for f in fields_p]
     want += [ctypes.sizeof(_lib.KleDesc)] + [getattr(_lib.KleDesc, f).offset for f in fields_k]
     want += [ctypes.sizeof(_lib.Task)] + [getattr(_lib.Task, f).offset for f in fields_t]
+    want += [ctypes.sizeof(_lib.Tuning)] + [getattr(_lib.Tuning, f).offset for f in fields_u]
     assert vals == want
 
 
