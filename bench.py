@@ -83,6 +83,7 @@ def main():
     ap.add_argument("--init", choices=["gpc", "mlp", "both"], default=None,
                     help="initial guess (default: gpc; both for the MLP workload)")
     ap.add_argument("--epochs", type=int, default=0, help="override the MLP epochs (0 = spec)")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the built-in kernel choices")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-oracle-check", action="store_true")
     args = ap.parse_args()
@@ -124,15 +125,22 @@ def main():
     if args.epochs:
         spec = W.MlpSpec(**{**spec.__dict__, "epochs": args.epochs})
 
-    # ---- offline stage (untimed): training solutions, snapshot KL + gPC fit, MLP training
+    # ---- offline stage (untimed): autotuning, training solutions, snapshot KL + gPC fit, MLP training
     torch.cuda.synchronize()
+    tuning = None
+    t_tune = 0.0
+    if not args.no_autotune and w.dim == 2 and w.precision == "f32_refined":
+        t0 = time.perf_counter()
+        tuning = ctx.autotune(prob, a_train[:4].contiguous())
+        t_tune = time.perf_counter() - t0
+        log(f"offline: autotune {t_tune:.1f} s -> {tuning}")
     t0 = time.perf_counter()
     S = torch.empty((w.n_train, w.N * w.Nx), dtype=torch.float64, device=dev)
     ctx.serial_fine_propagate(prob, a_train, None, S.view(w.n_train, w.N, w.Nx))
     torch.cuda.synchronize()
     t_snap = time.perf_counter() - t0
     log(f"offline: {w.n_train} training solutions {t_snap:.1f} s")
-    offline = {"training_solutions_s": t_snap}
+    offline = {"autotune_s": t_tune, "training_solutions_s": t_snap}
     gpc = mlp = None
     learned = None
     if "mlp" in inits:
@@ -268,6 +276,7 @@ def main():
         "offline": offline,
         "kernel_ms": {k: v[0] for k, v in ktimes.items()},
         "solver_stats": stats,
+        "tuning": tuning,
         "roofline": roof,
     }
     line["init"] = inits[0]

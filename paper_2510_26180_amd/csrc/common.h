@@ -58,6 +58,7 @@ enum WsSlot {
   WS_STATUS_CGC,    // status block of the shifted solves
   WS_FINE_AUX,      // float32 correction tiles of the shifted solves
   WS_MLP,           // MLP predictions before prolongation
+  WS_FINE_INC,      // fine propagator: per-system increment of the current step
   WS_COUNT
 };
 

@@ -361,8 +361,9 @@ template <int NW, int CPL, int RPW>
 __global__ __launch_bounds__(64 * NW) void fine2d_resident_kernel(
     const double* __restrict__ a, const float* __restrict__ sf, const double* __restrict__ dinv,
     int n, double c, double tauf, int J, double tol, float pcg_rtol, int maxit, StartRef sr,
-    double* __restrict__ out, double* __restrict__ resbuf, int64_t M, int N, int skip_first,
-    const uint8_t* __restrict__ active, int* __restrict__ flag, unsigned long long* __restrict__ cnt) {
+    double* __restrict__ out, double* __restrict__ resbuf, double* __restrict__ incbuf, int64_t M, int N,
+    int skip_first, const uint8_t* __restrict__ active, int* __restrict__ flag,
+    unsigned long long* __restrict__ cnt) {
   using RS = Resident<NW, CPL, RPW>;
   const long long t_start = clock64();
   long long t_cg = 0;
@@ -387,6 +388,7 @@ __global__ __launch_bounds__(64 * NW) void fine2d_resident_kernel(
   const double* dv = dinv + m * Nx;
   double* w = out + sys * Nx;
   double* res = resbuf + sys * Nx;
+  double* inc = incbuf + sys * Nx;   // increment w_{j+1} - w_j of the current step
   const int j0 = wave * RPW;
   const int i0 = lane * CPL;
 
@@ -409,6 +411,7 @@ __global__ __launch_bounds__(64 * NW) void fine2d_resident_kernel(
   const bool mxd[1] = {true};
   for (int64_t p = threadIdx.x; p < Nx; p += blockDim.x) {
     w[p] = src ? src[p] : 0.0;
+    inc[p] = 0.0;
     dmx[0] = nanmax(dmx[0], 1.0 / (dv[p] * dv[p]));
   }
   block_reduce<1>(dmx, mxd, dslots);   // also orders the copy before the first stencil
@@ -418,7 +421,22 @@ __global__ __launch_bounds__(64 * NW) void fine2d_resident_kernel(
   bool fail = false;
 
   for (int step = 0; step < J; ++step) {
-    // float64 residual of the increment equation: M e = tau f - tau A w
+    // Start from the previous step's increment: w_{j+1} - w_j = R (w_j - w_{j-1}) with
+    // R = (I + tau A)^{-1} for a constant source, so the starting residual is only
+    // tau A (w_j - w_{j-1}) (zero increment at the first step of a slice).
+    if (step > 0) {
+#pragma unroll 1
+      for (int k = 0; k < RPW * CPL; ++k) {
+        const int j = j0 + k / CPL, i = i0 + k % CPL;
+        if (j < n && i < n) {
+          const int64_t p = (int64_t)j * n + i;
+          w[p] += inc[p];
+        }
+      }
+      __syncthreads();   // the stencil below reads neighbours' w
+    }
+    // float64 residual of the step equation (I + tau A) w_{j+1} = w_j + tau f at the
+    // start w_j + inc:  tau f - tau A (w_j + inc) - inc
     double acc[3] = {0.0, 0.0, 0.0};
     const bool mx[3] = {true, true, true};
 #pragma unroll 1
@@ -426,7 +444,7 @@ __global__ __launch_bounds__(64 * NW) void fine2d_resident_kernel(
       const int j = j0 + k / CPL, i = i0 + k % CPL;
       if (j < n && i < n) {
         int64_t p = (int64_t)j * n + i;
-        double rv = tauf - c * stencil64(af, w, g, i, j);
+        double rv = tauf - c * stencil64(af, w, g, i, j) - inc[p];
         res[p] = rv;
         acc[0] = nanmax(acc[0], fabs(rv));
         acc[1] = nanmax(acc[1], fabs(w[p]));
@@ -528,6 +546,7 @@ __global__ __launch_bounds__(64 * NW) void fine2d_resident_kernel(
           double rv = res[p] - Me;
           res[p] = rv;
           w[p] += ep;
+          inc[p] += ep;
           emax[0] = nanmax(emax[0], fabs(rv));
           emax[1] = nanmax(emax[1], dv[p] * fabs(rv));
         }
@@ -555,11 +574,11 @@ template <int NW, int CPL, int RPW>
 void launch_resident(hipStream_t st, int64_t nsys, const double* a, const float* sf,
                      const double* dinv, int n, double c, double tauf, int J, double tol,
                      float pcg_rtol, int maxit, StartRef sr, double* out, double* resbuf,
-                     int64_t M, int N, int skip_first, const uint8_t* active, int* flag,
+                     double* incbuf, int64_t M, int N, int skip_first, const uint8_t* active, int* flag,
                      unsigned long long* cnt) {
   size_t lds = sizeof(float) * (size_t)n * n;
   fine2d_resident_kernel<NW, CPL, RPW><<<dim3((unsigned)nsys), dim3(64 * NW), lds, st>>>(
-      a, sf, dinv, n, c, tauf, J, tol, pcg_rtol, maxit, sr, out, resbuf, M, N, skip_first, active,
+      a, sf, dinv, n, c, tauf, J, tol, pcg_rtol, maxit, sr, out, resbuf, incbuf, M, N, skip_first, active,
       flag, cnt);
   KC_LAUNCH_CHECK();
 }
@@ -618,25 +637,26 @@ int propagate_impl(klecgc_ctx* ctx, const klecgc_problem& p, const FineArgs& fa,
   float* sf = resident ? (float*)ctx->ws.get(WS_FSCALED, sizeof(float) * Fc * M) : nullptr;
   build_tables_2d(st, fa.a, n, c, M, dinv, sf);
   double* resbuf = resident ? (double*)ctx->ws.get(WS_KRYLOV, sizeof(double) * Nx * nsys) : nullptr;
+  double* incbuf = resident ? (double*)ctx->ws.get(WS_FINE_INC, sizeof(double) * Nx * nsys) : nullptr;
   double* scr = resident ? nullptr : (double*)ctx->ws.get(WS_KRYLOV, sizeof(double) * 3 * Nx * nsys);
   const float pcg_rtol = tu.fine_pcg_rtol;
   timed(ctx, KT_FINE, [&] {
     switch (variant) {
       case KC_FINE_RES16:
-        launch_resident<8, 1, 2>(st, nsys, fa.a, sf, dinv, n, c, tauf, J, tol, pcg_rtol, maxit, sr, fa.out, resbuf,
+        launch_resident<8, 1, 2>(st, nsys, fa.a, sf, dinv, n, c, tauf, J, tol, pcg_rtol, maxit, sr, fa.out, resbuf, incbuf,
                                  M, N, fa.skip_first, fa.active, flag, cnt);
         break;
       case KC_FINE_RES32:
-        launch_resident<8, 1, 4>(st, nsys, fa.a, sf, dinv, n, c, tauf, J, tol, pcg_rtol, maxit, sr, fa.out, resbuf,
+        launch_resident<8, 1, 4>(st, nsys, fa.a, sf, dinv, n, c, tauf, J, tol, pcg_rtol, maxit, sr, fa.out, resbuf, incbuf,
                                  M, N, fa.skip_first, fa.active, flag, cnt);
         break;
       case KC_FINE_RES64:
-        launch_resident<8, 1, 8>(st, nsys, fa.a, sf, dinv, n, c, tauf, J, tol, pcg_rtol, maxit, sr, fa.out, resbuf,
+        launch_resident<8, 1, 8>(st, nsys, fa.a, sf, dinv, n, c, tauf, J, tol, pcg_rtol, maxit, sr, fa.out, resbuf, incbuf,
                                  M, N, fa.skip_first, fa.active, flag, cnt);
         break;
       case KC_FINE_RES128:
         launch_resident<KC_RES128_NW, 2, 128 / KC_RES128_NW>(st, nsys, fa.a, sf, dinv, n, c, tauf, J, tol, pcg_rtol,
-                                                             maxit, sr, fa.out, resbuf, M, N, fa.skip_first,
+                                                             maxit, sr, fa.out, resbuf, incbuf, M, N, fa.skip_first,
                                                              fa.active, flag, cnt);
         break;
       default:
