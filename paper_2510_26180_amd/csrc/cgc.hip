@@ -882,6 +882,425 @@ __global__ __launch_bounds__(512) void cocg32_stream_kernel(
   }
 }
 
+// ---------------------------------------------------------------- multigrid-preconditioned COCG
+// Float32 COCG on the Jacobi-scaled shifted system L = (1 + i theta) I - C, preconditioned
+// by one V-cycle of aggregation multigrid, inside the same float64 residual refinement as
+// the kernels above.  Level l+1 aggregates 2x2 blocks of level l (a last 1-wide block when
+// the level size is odd); its operator is the Galerkin product P^T L P for the piecewise-
+// constant prolongation P, again a 5-point operator: couplings summed across aggregate
+// faces, complex diagonal summed over the block minus twice its internal couplings.  The
+// V-cycle smooths with damped Jacobi (2 sweeps down and up, 2 on the coarsest level of at
+// most 2x2), restricts by summation and prolongates by injection scaled by kMgScale
+// (aggregation coarse spaces are too stiff by about that factor); pre- and post-smoothing
+// are the same symmetric operator, so the preconditioner is complex symmetric as COCG
+// requires.
+constexpr int kMgMaxLevels = 12;
+constexpr float kMgOmega = 0.7f;
+constexpr float kMgScale = 1.8f;
+constexpr int kMgSweeps = 2;
+
+struct MgLevels {
+  int L;
+  int m[kMgMaxLevels];
+  int64_t off[kMgMaxLevels];   // float offset of each level's block in a system's scratch
+  int64_t per_sys;             // floats of scratch per system
+};
+
+// system scratch: X, R, P, Q (complex, n^2 each), then per level l (m = m_l):
+// cw[m^2], cs[m^2], dg[m^2] (complex), di[m^2] (complex), xa, xb, b (complex)
+MgLevels mg_levels(int n) {
+  MgLevels h{};
+  int m = n, L = 0;
+  int64_t off = 8LL * n * n;
+  while (true) {
+    h.m[L] = m;
+    h.off[L] = off;
+    off += 12LL * m * m;
+    ++L;
+    if (m <= 2 || L == kMgMaxLevels) break;
+    m = (m + 1) / 2;
+  }
+  h.L = L;
+  h.per_sys = off;
+  return h;
+}
+
+struct MgLv {
+  int m;
+  float *cw, *cs;
+  float2 *dg, *di, *xa, *xb, *b;
+};
+
+__device__ __forceinline__ MgLv mg_lv(float* base, const MgLevels& h, int l) {
+  MgLv v;
+  v.m = h.m[l];
+  const int64_t mm = (int64_t)v.m * v.m;
+  float* p = base + h.off[l];
+  v.cw = p;
+  v.cs = p + mm;
+  v.dg = (float2*)(p + 2 * mm);
+  v.di = v.dg + mm;
+  v.xa = v.di + mm;
+  v.xb = v.xa + mm;
+  v.b = v.xb + mm;
+  return v;
+}
+
+__device__ __forceinline__ float2 cmulf(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// (L x)_p on a level; X(q) yields x at node q
+template <class XF>
+__device__ __forceinline__ float2 mg_apply(const MgLv& v, int64_t p, int i, int j, XF X) {
+  const int m = v.m;
+  const float2 xp = X(p, i, j);
+  float2 acc = cmulf(v.dg[p], xp);
+  if (i > 0) {
+    const float c = v.cw[p];
+    const float2 q = X(p - 1, i - 1, j);
+    acc.x -= c * q.x;
+    acc.y -= c * q.y;
+  }
+  if (i < m - 1) {
+    const float c = v.cw[p + 1];
+    const float2 q = X(p + 1, i + 1, j);
+    acc.x -= c * q.x;
+    acc.y -= c * q.y;
+  }
+  if (j > 0) {
+    const float c = v.cs[p];
+    const float2 q = X(p - m, i, j - 1);
+    acc.x -= c * q.x;
+    acc.y -= c * q.y;
+  }
+  if (j < m - 1) {
+    const float c = v.cs[p + m];
+    const float2 q = X(p + m, i, j + 1);
+    acc.x -= c * q.x;
+    acc.y -= c * q.y;
+  }
+  return acc;
+}
+
+// z = V-cycle applied to rhs0 (level 0); returns the level-0 buffer holding z
+__device__ float2* mg_vcycle(float* base, const MgLevels& h, const float2* rhs0) {
+  int cur[kMgMaxLevels];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int l = 0; l < h.L; ++l) {
+    const MgLv v = mg_lv(base, h, l);
+    const float2* b = l == 0 ? rhs0 : v.b;
+    const int m = v.m;
+    const int64_t mm = (int64_t)m * m;
+    for (int64_t p = tid; p < mm; p += nt) {
+      const float2 t = cmulf(v.di[p], b[p]);
+      v.xa[p] = make_float2(kMgOmega * t.x, kMgOmega * t.y);
+    }
+    __syncthreads();
+    float2* xc = v.xa;
+    float2* xn = v.xb;
+    for (int s = 1; s < kMgSweeps; ++s) {
+      for (int64_t p = tid; p < mm; p += nt) {
+        const int i = (int)(p % m), j = (int)(p / m);
+        const float2 lx = mg_apply(v, p, i, j, [&](int64_t q, int, int) { return xc[q]; });
+        const float2 r = make_float2(b[p].x - lx.x, b[p].y - lx.y);
+        const float2 t = cmulf(v.di[p], r);
+        xn[p] = make_float2(xc[p].x + kMgOmega * t.x, xc[p].y + kMgOmega * t.y);
+      }
+      __syncthreads();
+      float2* tmp = xc;
+      xc = xn;
+      xn = tmp;
+    }
+    cur[l] = xc == v.xa ? 0 : 1;
+    if (l + 1 < h.L) {   // restrict the residual: b_{l+1}[I,J] = sum over the block of (b - L x)
+      const MgLv c = mg_lv(base, h, l + 1);
+      const int mc = c.m;
+      for (int64_t P = tid; P < (int64_t)mc * mc; P += nt) {
+        const int I = (int)(P % mc), J = (int)(P / mc);
+        float2 sum = make_float2(0.f, 0.f);
+        for (int dj = 0; dj < 2; ++dj)
+          for (int di = 0; di < 2; ++di) {
+            const int i = 2 * I + di, j = 2 * J + dj;
+            if (i < m && j < m) {
+              const int64_t p = (int64_t)j * m + i;
+              const float2 lx = mg_apply(v, p, i, j, [&](int64_t q, int, int) { return xc[q]; });
+              sum.x += b[p].x - lx.x;
+              sum.y += b[p].y - lx.y;
+            }
+          }
+        c.b[P] = sum;
+      }
+      __syncthreads();
+    }
+  }
+  for (int l = h.L - 2; l >= 0; --l) {
+    const MgLv v = mg_lv(base, h, l);
+    const MgLv c = mg_lv(base, h, l + 1);
+    const float2* ec = cur[l + 1] ? c.xb : c.xa;
+    const float2* b = l == 0 ? rhs0 : v.b;
+    const int m = v.m, mc = c.m;
+    const int64_t mm = (int64_t)m * m;
+    float2* xc = cur[l] ? v.xb : v.xa;
+    float2* xn = cur[l] ? v.xa : v.xb;
+    // first post-smoothing sweep on x + s P e (the prolongated correction folded in)
+    auto xp = [&](int64_t q, int qi, int qj) {
+      const float2 e = ec[(int64_t)(qj >> 1) * mc + (qi >> 1)];
+      return make_float2(xc[q].x + kMgScale * e.x, xc[q].y + kMgScale * e.y);
+    };
+    for (int64_t p = tid; p < mm; p += nt) {
+      const int i = (int)(p % m), j = (int)(p / m);
+      const float2 lx = mg_apply(v, p, i, j, xp);
+      const float2 y = xp(p, i, j);
+      const float2 t = cmulf(v.di[p], make_float2(b[p].x - lx.x, b[p].y - lx.y));
+      xn[p] = make_float2(y.x + kMgOmega * t.x, y.y + kMgOmega * t.y);
+    }
+    __syncthreads();
+    float2* tmp = xc;
+    xc = xn;
+    xn = tmp;
+    for (int s = 1; s < kMgSweeps; ++s) {
+      for (int64_t p = tid; p < mm; p += nt) {
+        const int i = (int)(p % m), j = (int)(p / m);
+        const float2 lx = mg_apply(v, p, i, j, [&](int64_t q, int, int) { return xc[q]; });
+        const float2 t = cmulf(v.di[p], make_float2(b[p].x - lx.x, b[p].y - lx.y));
+        xn[p] = make_float2(xc[p].x + kMgOmega * t.x, xc[p].y + kMgOmega * t.y);
+      }
+      __syncthreads();
+      tmp = xc;
+      xc = xn;
+      xn = tmp;
+    }
+    cur[l] = xc == v.xa ? 0 : 1;
+  }
+  const MgLv v0 = mg_lv(base, h, 0);
+  return cur[0] ? v0.xb : v0.xa;
+}
+
+template <int NW, int WPE>
+__global__ __launch_bounds__(64 * NW, WPE) void cocg_mg_kernel(
+    const double* __restrict__ a, const double* __restrict__ dinvr, int n, double cT, int N, double alpha,
+    double rtol, float inner_rtol, int maxit, const uint8_t* __restrict__ active, double* __restrict__ spec,
+    double* __restrict__ resbuf, float* __restrict__ scr, MgLevels h, int* __restrict__ flag,
+    unsigned long long* __restrict__ cnt) {
+  __shared__ float fsl[2][3 * NW];
+  __shared__ double dsl[4 * NW];
+  const int K = N / 2 + 1;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t sys = blockIdx.x;
+  const int64_t m = sys / K;
+  const int k = (int)(sys % K);
+  if (active && !active[m]) return;
+  const int64_t Nx = (int64_t)n * n;
+  const int64_t nx = (int64_t)n * (n + 1);
+  const double* af = a + m * 2 * nx;
+  const double* dr = dinvr + sys * Nx;
+  double2* q = (double2*)spec + sys * Nx;
+  double2* res = (double2*)resbuf + sys * Nx;
+  float* base = scr + sys * h.per_sys;
+  float2* X = (float2*)base;
+  float2* R = X + Nx;
+  float2* P = R + Nx;
+  float2* Q = P + Nx;
+  double sv, cv;
+  sincospi(-2.0 * k / N, &sv, &cv);
+  const double an = exp(log(alpha) / N);
+  const double lre = 1.0 - an * cv, lim = -an * sv;
+
+  // level 0 operator, float64 residual, zero solution
+  const MgLv v0 = mg_lv(base, h, 0);
+  double bn[2] = {0.0, 0.0};
+  const bool sm[2] = {false, true};
+  for (int64_t p = threadIdx.x; p < Nx; p += blockDim.x) {
+    const int i = (int)(p % n), j = (int)(p / n);
+    v0.cw[p] = i >= 1 ? (float)(cT * af[(int64_t)j * (n + 1) + i] * dr[p - 1] * dr[p]) : 0.f;
+    v0.cs[p] = j >= 1 ? (float)(cT * af[nx + (int64_t)j * n + i] * dr[p - n] * dr[p]) : 0.f;
+    const float th = (float)(lim * dr[p] * dr[p]);
+    v0.dg[p] = make_float2(1.f, th);
+    const float den = 1.f + th * th;
+    v0.di[p] = make_float2(1.f / den, -th / den);
+    const double2 vv = q[p];
+    res[p] = vv;
+    q[p] = make_double2(0.0, 0.0);
+    bn[0] += vv.x * vv.x + vv.y * vv.y;
+    bn[1] = nanmax(bn[1], dr[p] * fmax(fabs(vv.x), fabs(vv.y)));
+  }
+  block_reduce<2>(bn, sm, dsl);   // its barriers also publish level 0
+  // coarse levels: Galerkin products of 2x2 aggregation
+  for (int l = 1; l < h.L; ++l) {
+    const MgLv f = mg_lv(base, h, l - 1);
+    const MgLv c = mg_lv(base, h, l);
+    const int mf = f.m, mc = c.m;
+    for (int64_t Pn = threadIdx.x; Pn < (int64_t)mc * mc; Pn += blockDim.x) {
+      const int I = (int)(Pn % mc), J = (int)(Pn / mc);
+      const int i0 = 2 * I, j0 = 2 * J;
+      const bool two_i = i0 + 1 < mf, two_j = j0 + 1 < mf;
+      float2 dg = make_float2(0.f, 0.f);
+      float cwc = 0.f, csc = 0.f, inner = 0.f;
+      for (int dj = 0; dj < (two_j ? 2 : 1); ++dj)
+        for (int di = 0; di < (two_i ? 2 : 1); ++di) {
+          const int64_t p = (int64_t)(j0 + dj) * mf + (i0 + di);
+          dg.x += f.dg[p].x;
+          dg.y += f.dg[p].y;
+          if (di == 1) inner += f.cw[p];            // coupling inside the block (x)
+          if (dj == 1) inner += f.cs[p];            // coupling inside the block (y)
+          if (di == 0 && I > 0) cwc += f.cw[p];     // couplings across the west face
+          if (dj == 0 && J > 0) csc += f.cs[p];     // couplings across the south face
+        }
+      dg.x -= 2.f * inner;
+      c.dg[Pn] = dg;
+      const float den = dg.x * dg.x + dg.y * dg.y;
+      c.di[Pn] = make_float2(dg.x / den, -dg.y / den);
+      c.cw[Pn] = cwc;
+      c.cs[Pn] = csc;
+    }
+    __syncthreads();
+  }
+  const double stop2 = rtol * rtol * bn[0];
+  double rn2 = bn[0];
+  double sig = bn[1];
+  unsigned long long tot_it = 0, max_it = 0;
+  int pass = 0;
+  while (rn2 > stop2 && sig > 0.0 && pass < 12) {
+    const double isig = 1.0 / sig;
+    float r0 = 0.f;
+    for (int64_t p = threadIdx.x; p < Nx; p += blockDim.x) {
+      const double2 rv = res[p];
+      const float2 vv = make_float2((float)(isig * dr[p] * rv.x), (float)(isig * dr[p] * rv.y));
+      R[p] = vv;
+      X[p] = make_float2(0.f, 0.f);
+      r0 += vv.x * vv.x + vv.y * vv.y;
+    }
+    {
+      float t[1] = {r0};
+      block_sum_fk<NW, 1>(t, fsl[1], lane, wave);   // its barrier also publishes R
+      r0 = t[0];
+    }
+    float2* Z = mg_vcycle(base, h, R);
+    float acc2[2] = {0.f, 0.f};
+    for (int64_t p = threadIdx.x; p < Nx; p += blockDim.x) {
+      const float2 rv = R[p], zv = Z[p];
+      P[p] = zv;
+      acc2[0] += rv.x * zv.x - rv.y * zv.y;
+      acc2[1] += rv.x * zv.y + rv.y * zv.x;
+    }
+    // one-barrier sums alternate between the two slot arrays: this one and the p.q sum
+    // that follows with no barrier in between must not share slots
+    block_sum_fk<NW, 2>(acc2, fsl[1], lane, wave);
+    cf rz = {acc2[0], acc2[1]};
+    float rr = r0;
+    const float stop_in = inner_rtol * inner_rtol * r0;
+    int it = 0;
+    const int cap = maxit < 400 ? maxit : 400;
+    bool bad = false;
+    while (rr > stop_in && it < cap) {
+      float pq2[2] = {0.f, 0.f};
+      for (int64_t p = threadIdx.x; p < Nx; p += blockDim.x) {
+        const int i = (int)(p % n), j = (int)(p / n);
+        const float2 qv = mg_apply(v0, p, i, j, [&](int64_t s, int, int) { return P[s]; });
+        Q[p] = qv;
+        const float2 pv = P[p];
+        pq2[0] += pv.x * qv.x - pv.y * qv.y;
+        pq2[1] += pv.x * qv.y + pv.y * qv.x;
+      }
+      block_sum_fk<NW, 2>(pq2, fsl[0], lane, wave);
+      const cf al = cf_div(rz, cf{pq2[0], pq2[1]});
+      float racc[1] = {0.f};
+      for (int64_t p = threadIdx.x; p < Nx; p += blockDim.x) {
+        const float2 pv = P[p], qv = Q[p];
+        float2 xv = X[p], rv = R[p];
+        xv.x += al.x * pv.x - al.y * pv.y;
+        xv.y += al.x * pv.y + al.y * pv.x;
+        rv.x -= al.x * qv.x - al.y * qv.y;
+        rv.y -= al.x * qv.y + al.y * qv.x;
+        X[p] = xv;
+        R[p] = rv;
+        racc[0] += rv.x * rv.x + rv.y * rv.y;
+      }
+      block_sum_fk<NW, 1>(racc, fsl[1], lane, wave);   // its barrier also publishes R
+      rr = racc[0];
+      ++it;
+      if (!(rr < 3.0e38f)) {
+        bad = true;
+        break;
+      }
+      if (rr <= stop_in) break;
+      Z = mg_vcycle(base, h, R);
+      float rz2[2] = {0.f, 0.f};
+      for (int64_t p = threadIdx.x; p < Nx; p += blockDim.x) {
+        const float2 rv = R[p], zv = Z[p];
+        rz2[0] += rv.x * zv.x - rv.y * zv.y;
+        rz2[1] += rv.x * zv.y + rv.y * zv.x;
+      }
+      block_sum_fk<NW, 2>(rz2, fsl[0], lane, wave);
+      const cf rzn = {rz2[0], rz2[1]};
+      const cf be = cf_div(rzn, rz);
+      rz = rzn;
+      if (!(fabsf(rz.x) + fabsf(rz.y) < 3.0e38f)) {
+        bad = true;
+        break;
+      }
+      for (int64_t p = threadIdx.x; p < Nx; p += blockDim.x) {
+        const float2 pv = P[p], zv = Z[p];
+        P[p] = make_float2(zv.x + be.x * pv.x - be.y * pv.y, zv.y + be.x * pv.y + be.y * pv.x);
+      }
+      __syncthreads();
+    }
+    tot_it += it;
+    max_it = it > (int)max_it ? it : max_it;
+    if (bad) {   // keep the last good q and report
+      if (threadIdx.x == 0) atomicOr(flag, 1);
+      break;
+    }
+    __syncthreads();   // X complete before neighbours are read below
+    double acc[2] = {0.0, 0.0};
+    for (int64_t p = threadIdx.x; p < Nx; p += blockDim.x) {
+      const int i = (int)(p % n), j = (int)(p / n);
+      const float2 xp = X[p];
+      const double ex = sig * dr[p] * xp.x, ey = sig * dr[p] * xp.y;
+      double sx = 0.0, sy = 0.0;
+      const double aW = af[(int64_t)j * (n + 1) + i], aE = af[(int64_t)j * (n + 1) + i + 1];
+      const double aS = af[nx + (int64_t)j * n + i], aN = af[nx + (int64_t)(j + 1) * n + i];
+      double nxv = 0.0, nyv = 0.0;
+      if (i > 0) { const float2 t = X[p - 1]; nxv = sig * dr[p - 1] * t.x; nyv = sig * dr[p - 1] * t.y; }
+      sx += aW * (ex - nxv); sy += aW * (ey - nyv);
+      nxv = nyv = 0.0;
+      if (i < n - 1) { const float2 t = X[p + 1]; nxv = sig * dr[p + 1] * t.x; nyv = sig * dr[p + 1] * t.y; }
+      sx += aE * (ex - nxv); sy += aE * (ey - nyv);
+      nxv = nyv = 0.0;
+      if (j > 0) { const float2 t = X[p - n]; nxv = sig * dr[p - n] * t.x; nyv = sig * dr[p - n] * t.y; }
+      sx += aS * (ex - nxv); sy += aS * (ey - nyv);
+      nxv = nyv = 0.0;
+      if (j < n - 1) { const float2 t = X[p + n]; nxv = sig * dr[p + n] * t.x; nyv = sig * dr[p + n] * t.y; }
+      sx += aN * (ex - nxv); sy += aN * (ey - nyv);
+      const double mex = lre * ex - lim * ey + cT * sx;
+      const double mey = lre * ey + lim * ex + cT * sy;
+      double2 rv = res[p];
+      rv.x -= mex;
+      rv.y -= mey;
+      res[p] = rv;
+      double2 qv = q[p];
+      qv.x += ex;
+      qv.y += ey;
+      q[p] = qv;
+      acc[0] += rv.x * rv.x + rv.y * rv.y;
+      acc[1] = nanmax(acc[1], dr[p] * fmax(fabs(rv.x), fabs(rv.y)));
+    }
+    block_reduce<2>(acc, sm, dsl);
+    rn2 = acc[0];
+    sig = acc[1];
+    ++pass;
+  }
+  if (threadIdx.x == 0) {
+    if (rn2 > stop2) atomicOr(flag, 1);
+    atomicAdd(&cnt[0], tot_it);
+    atomicAdd(&cnt[1], (unsigned long long)pass);
+    atomicAdd(&cnt[2], 1ull);
+    atomicMax(&cnt[3], max_it);
+  }
+}
+
 template <int NW, int CPL, int RPW>
 void launch_cocg_resident(hipStream_t st, int64_t nsys, const double* a, const double* dr, int n, double cT,
                           int N, double alpha, double rtol, float inner_rtol, int maxit, const uint8_t* active,
@@ -983,6 +1402,23 @@ int shifted_solve_impl(klecgc_ctx* ctx, const klecgc_problem& p, const double* a
   const KcTuning tu = tuning_for(ctx, p.n);
   const int variant = p.precision == KC_PREC_F32_REFINED ? cgc_variant_for(p.n, tu.cgc_variant) : KC_CGC_STREAM64;
   const float inner = tu.cgc_inner_rtol;
+  if (variant == KC_CGC_MG32) {
+    const MgLevels h = mg_levels(p.n);
+    double* dr = (double*)ctx->ws.get(WS_DINV, sizeof(double) * Nx * nsys);
+    double* resb = (double*)ctx->ws.get(WS_KRYLOV, sizeof(double) * 2 * Nx * nsys);
+    float* scr = (float*)ctx->ws.get(WS_FINE_AUX, sizeof(float) * h.per_sys * nsys);
+    shift_dinv_kernel<<<dim3((unsigned)((Nx + 255) / 256), (unsigned)nsys), dim3(256), 0, st>>>(
+        a, p.n, cT, p.N, p.alpha, M, dr);
+    KC_LAUNCH_CHECK();
+    timed(ctx, KT_SHIFTED, [&] {
+      // 16 waves per system, one work-group per CU: the node loops are latency-bound and
+      // gain most from the waves one system can keep in flight
+      cocg_mg_kernel<16, 4><<<dim3((unsigned)nsys), dim3(1024), 0, st>>>(
+          a, dr, p.n, cT, p.N, p.alpha, rtol, inner, maxit, active, spec, resb, scr, h, ds.flag, ds.cnt);
+      KC_LAUNCH_CHECK();
+    });
+    return status_collect(ctx, ds, 4) ? KC_ENOCONV : KC_OK;
+  }
   if (variant == KC_CGC_STREAM32) {
     double* dr = (double*)ctx->ws.get(WS_DINV, sizeof(double) * Nx * nsys);
     double* resb = (double*)ctx->ws.get(WS_KRYLOV, sizeof(double) * 2 * Nx * nsys);
@@ -1033,6 +1469,7 @@ bool cgc_variant_fits(int v, int n) {
     case KC_CGC_RES32: return n <= 32;
     case KC_CGC_RES64: return n <= 64;
     case KC_CGC_STREAM32: return true;
+    case KC_CGC_MG32: return true;
     default: return false;
   }
 }
@@ -1042,7 +1479,7 @@ int cgc_variant_for(int n, int requested) {
   if (n <= 16) return KC_CGC_RES16;
   if (n <= 32) return KC_CGC_RES32;
   if (n <= 64) return KC_CGC_RES64;
-  return KC_CGC_STREAM32;
+  return KC_CGC_MG32;
 }
 
 }  // namespace kc

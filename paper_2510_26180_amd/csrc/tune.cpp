@@ -96,7 +96,7 @@ int autotune_impl(klecgc_ctx* ctx, const klecgc_problem& p, const double* a, int
     launch_fft_forward(st, p, (const double*)D.p, nullptr, Mp, (double*)spec0.p);
     klecgc_problem pb = p;
     if (pb.cgc_rtol <= 0) pb.cgc_rtol = 1e-7;
-    for (int v : {KC_CGC_RES16, KC_CGC_RES32, KC_CGC_RES64, KC_CGC_STREAM32}) {
+    for (int v : {KC_CGC_RES16, KC_CGC_RES32, KC_CGC_RES64, KC_CGC_STREAM32, KC_CGC_MG32}) {
       if (!cgc_variant_fits(v, n)) continue;
       bool warmed = false;
       for (float r : cgc_rtols) {

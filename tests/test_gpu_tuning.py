@@ -18,7 +18,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 FINE = {"stream64": 0, "res16": 1, "res32": 2, "res64": 3, "res128": 4}
-CGC = {"stream64": 0, "res16": 1, "res32": 2, "res64": 3, "stream32": 4}
+CGC = {"stream64": 0, "res16": 1, "res32": 2, "res64": 3, "stream32": 4, "mg32": 5}
 
 
 @pytest.fixture()
@@ -57,7 +57,9 @@ def test_fine_variants(ctx, n, variant, rtol):
 @pytest.mark.parametrize("n,variant,rtol", [(13, "res16", 1e-4), (13, "res32", 1e-5), (13, "res64", 3e-6),
                                             (13, "stream32", 1e-5), (13, "stream64", 1e-5), (40, "res64", 3e-5),
                                             (40, "stream32", 1e-4), (100, "stream32", 3e-6),
-                                            (100, "stream64", 1e-5)])
+                                            (100, "stream64", 1e-5), (1, "mg32", 1e-5), (2, "mg32", 1e-5),
+                                            (13, "mg32", 1e-4), (40, "mg32", 1e-5), (100, "mg32", 3e-6),
+                                            (128, "mg32", 3e-5)])
 def test_cgc_variants(ctx, n, variant, rtol):
     log(f"shifted-solve variant {variant} n={n} pass reduction {rtol}")
     ctx.set_tuning(n, cgc_variant=CGC[variant], cgc_inner_rtol=rtol)
