@@ -24,7 +24,7 @@ namespace {
 constexpr int kStreamThreads = 256;
 constexpr int kMaxRefinePasses = 12;
 #ifndef KC_RES128_NW
-#define KC_RES128_NW 8
+#define KC_RES128_NW 16
 #endif
 
 struct StartRef {
@@ -446,6 +446,7 @@ __global__ __launch_bounds__(64 * NW) void fine2d_resident_kernel(
         int64_t p = (int64_t)j * n + i;
         double rv = tauf - c * stencil64(af, w, g, i, j) - inc[p];
         res[p] = rv;
+        xs[p] = (float)(dv[p] * rv);   // the first pass's right-hand side, unnormalised
         acc[0] = nanmax(acc[0], fabs(rv));
         acc[1] = nanmax(acc[1], fabs(w[p]));
         acc[2] = nanmax(acc[2], dv[p] * fabs(rv));
@@ -458,17 +459,25 @@ __global__ __launch_bounds__(64 * NW) void fine2d_resident_kernel(
     const double target = residual_target(tol, acc[1], tauf, dmax);
     int pass = 0;
     while (rmax > target && sig > 0.0 && pass < kMaxRefinePasses) {
-      const double isig = 1.0 / sig;
-      // scaled right-hand side D^{-1/2} res / sig, staged through LDS
+      // scaled right-hand side D^{-1/2} res / sig, staged through LDS.  The first pass
+      // takes the tile the residual sweep wrote (scale 1): a fresh step's residual is far
+      // from the float32 range limits.  Later passes normalise by sig, since their
+      // residuals shrink towards the float64 floor and their squares would underflow.
+      const bool prestaged = pass == 0 && sig > 1e-18 && sig < 1e18;
+      if (prestaged) {
+        sig = 1.0;
+      } else {
+        const double isig = 1.0 / sig;
 #pragma unroll 1
-      for (int k = 0; k < RPW * CPL; ++k) {
-        const int j = j0 + k / CPL, i = i0 + k % CPL;
-        if (j < n && i < n) {
-          int64_t p = (int64_t)j * n + i;
-          xs[p] = (float)(isig * dv[p] * res[p]);
+        for (int k = 0; k < RPW * CPL; ++k) {
+          const int j = j0 + k / CPL, i = i0 + k % CPL;
+          if (j < n && i < n) {
+            int64_t p = (int64_t)j * n + i;
+            xs[p] = (float)(isig * dv[p] * res[p]);
+          }
         }
+        __syncthreads();
       }
-      __syncthreads();
       float rr = 0.f;
 #pragma unroll
       for (int r = 0; r < RPW; ++r) {
