@@ -14,6 +14,7 @@
 #include <atomic>
 
 #include "common.h"
+#include "mg.h"
 #include "reduce.h"
 
 namespace kc {
@@ -884,199 +885,8 @@ __global__ __launch_bounds__(512) void cocg32_stream_kernel(
 
 // ---------------------------------------------------------------- multigrid-preconditioned COCG
 // Float32 COCG on the Jacobi-scaled shifted system L = (1 + i theta) I - C, preconditioned
-// by one V-cycle of aggregation multigrid, inside the same float64 residual refinement as
-// the kernels above.  Level l+1 aggregates 2x2 blocks of level l (a last 1-wide block when
-// the level size is odd); its operator is the Galerkin product P^T L P for the piecewise-
-// constant prolongation P, again a 5-point operator: couplings summed across aggregate
-// faces, complex diagonal summed over the block minus twice its internal couplings.  The
-// V-cycle smooths with damped Jacobi (2 sweeps down and up, 2 on the coarsest level of at
-// most 2x2), restricts by summation and prolongates by injection scaled by kMgScale
-// (aggregation coarse spaces are too stiff by about that factor); pre- and post-smoothing
-// are the same symmetric operator, so the preconditioner is complex symmetric as COCG
-// requires.
-constexpr int kMgMaxLevels = 12;
-constexpr float kMgOmega = 0.7f;
-constexpr float kMgScale = 1.8f;
-constexpr int kMgSweeps = 2;
-
-struct MgLevels {
-  int L;
-  int m[kMgMaxLevels];
-  int64_t off[kMgMaxLevels];   // float offset of each level's block in a system's scratch
-  int64_t per_sys;             // floats of scratch per system
-};
-
-// system scratch: X, R, P, Q (complex, n^2 each), then per level l (m = m_l):
-// cw[m^2], cs[m^2], dg[m^2] (complex), di[m^2] (complex), xa, xb, b (complex)
-MgLevels mg_levels(int n) {
-  MgLevels h{};
-  int m = n, L = 0;
-  int64_t off = 8LL * n * n;
-  while (true) {
-    h.m[L] = m;
-    h.off[L] = off;
-    off += 12LL * m * m;
-    ++L;
-    if (m <= 2 || L == kMgMaxLevels) break;
-    m = (m + 1) / 2;
-  }
-  h.L = L;
-  h.per_sys = off;
-  return h;
-}
-
-struct MgLv {
-  int m;
-  float *cw, *cs;
-  float2 *dg, *di, *xa, *xb, *b;
-};
-
-__device__ __forceinline__ MgLv mg_lv(float* base, const MgLevels& h, int l) {
-  MgLv v;
-  v.m = h.m[l];
-  const int64_t mm = (int64_t)v.m * v.m;
-  float* p = base + h.off[l];
-  v.cw = p;
-  v.cs = p + mm;
-  v.dg = (float2*)(p + 2 * mm);
-  v.di = v.dg + mm;
-  v.xa = v.di + mm;
-  v.xb = v.xa + mm;
-  v.b = v.xb + mm;
-  return v;
-}
-
-__device__ __forceinline__ float2 cmulf(float2 a, float2 b) {
-  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-
-// (L x)_p on a level; X(q) yields x at node q
-template <class XF>
-__device__ __forceinline__ float2 mg_apply(const MgLv& v, int64_t p, int i, int j, XF X) {
-  const int m = v.m;
-  const float2 xp = X(p, i, j);
-  float2 acc = cmulf(v.dg[p], xp);
-  if (i > 0) {
-    const float c = v.cw[p];
-    const float2 q = X(p - 1, i - 1, j);
-    acc.x -= c * q.x;
-    acc.y -= c * q.y;
-  }
-  if (i < m - 1) {
-    const float c = v.cw[p + 1];
-    const float2 q = X(p + 1, i + 1, j);
-    acc.x -= c * q.x;
-    acc.y -= c * q.y;
-  }
-  if (j > 0) {
-    const float c = v.cs[p];
-    const float2 q = X(p - m, i, j - 1);
-    acc.x -= c * q.x;
-    acc.y -= c * q.y;
-  }
-  if (j < m - 1) {
-    const float c = v.cs[p + m];
-    const float2 q = X(p + m, i, j + 1);
-    acc.x -= c * q.x;
-    acc.y -= c * q.y;
-  }
-  return acc;
-}
-
-// z = V-cycle applied to rhs0 (level 0); returns the level-0 buffer holding z
-__device__ float2* mg_vcycle(float* base, const MgLevels& h, const float2* rhs0) {
-  int cur[kMgMaxLevels];
-  const int tid = threadIdx.x, nt = blockDim.x;
-  for (int l = 0; l < h.L; ++l) {
-    const MgLv v = mg_lv(base, h, l);
-    const float2* b = l == 0 ? rhs0 : v.b;
-    const int m = v.m;
-    const int64_t mm = (int64_t)m * m;
-    for (int64_t p = tid; p < mm; p += nt) {
-      const float2 t = cmulf(v.di[p], b[p]);
-      v.xa[p] = make_float2(kMgOmega * t.x, kMgOmega * t.y);
-    }
-    __syncthreads();
-    float2* xc = v.xa;
-    float2* xn = v.xb;
-    for (int s = 1; s < kMgSweeps; ++s) {
-      for (int64_t p = tid; p < mm; p += nt) {
-        const int i = (int)(p % m), j = (int)(p / m);
-        const float2 lx = mg_apply(v, p, i, j, [&](int64_t q, int, int) { return xc[q]; });
-        const float2 r = make_float2(b[p].x - lx.x, b[p].y - lx.y);
-        const float2 t = cmulf(v.di[p], r);
-        xn[p] = make_float2(xc[p].x + kMgOmega * t.x, xc[p].y + kMgOmega * t.y);
-      }
-      __syncthreads();
-      float2* tmp = xc;
-      xc = xn;
-      xn = tmp;
-    }
-    cur[l] = xc == v.xa ? 0 : 1;
-    if (l + 1 < h.L) {   // restrict the residual: b_{l+1}[I,J] = sum over the block of (b - L x)
-      const MgLv c = mg_lv(base, h, l + 1);
-      const int mc = c.m;
-      for (int64_t P = tid; P < (int64_t)mc * mc; P += nt) {
-        const int I = (int)(P % mc), J = (int)(P / mc);
-        float2 sum = make_float2(0.f, 0.f);
-        for (int dj = 0; dj < 2; ++dj)
-          for (int di = 0; di < 2; ++di) {
-            const int i = 2 * I + di, j = 2 * J + dj;
-            if (i < m && j < m) {
-              const int64_t p = (int64_t)j * m + i;
-              const float2 lx = mg_apply(v, p, i, j, [&](int64_t q, int, int) { return xc[q]; });
-              sum.x += b[p].x - lx.x;
-              sum.y += b[p].y - lx.y;
-            }
-          }
-        c.b[P] = sum;
-      }
-      __syncthreads();
-    }
-  }
-  for (int l = h.L - 2; l >= 0; --l) {
-    const MgLv v = mg_lv(base, h, l);
-    const MgLv c = mg_lv(base, h, l + 1);
-    const float2* ec = cur[l + 1] ? c.xb : c.xa;
-    const float2* b = l == 0 ? rhs0 : v.b;
-    const int m = v.m, mc = c.m;
-    const int64_t mm = (int64_t)m * m;
-    float2* xc = cur[l] ? v.xb : v.xa;
-    float2* xn = cur[l] ? v.xa : v.xb;
-    // first post-smoothing sweep on x + s P e (the prolongated correction folded in)
-    auto xp = [&](int64_t q, int qi, int qj) {
-      const float2 e = ec[(int64_t)(qj >> 1) * mc + (qi >> 1)];
-      return make_float2(xc[q].x + kMgScale * e.x, xc[q].y + kMgScale * e.y);
-    };
-    for (int64_t p = tid; p < mm; p += nt) {
-      const int i = (int)(p % m), j = (int)(p / m);
-      const float2 lx = mg_apply(v, p, i, j, xp);
-      const float2 y = xp(p, i, j);
-      const float2 t = cmulf(v.di[p], make_float2(b[p].x - lx.x, b[p].y - lx.y));
-      xn[p] = make_float2(y.x + kMgOmega * t.x, y.y + kMgOmega * t.y);
-    }
-    __syncthreads();
-    float2* tmp = xc;
-    xc = xn;
-    xn = tmp;
-    for (int s = 1; s < kMgSweeps; ++s) {
-      for (int64_t p = tid; p < mm; p += nt) {
-        const int i = (int)(p % m), j = (int)(p / m);
-        const float2 lx = mg_apply(v, p, i, j, [&](int64_t q, int, int) { return xc[q]; });
-        const float2 t = cmulf(v.di[p], make_float2(b[p].x - lx.x, b[p].y - lx.y));
-        xn[p] = make_float2(xc[p].x + kMgOmega * t.x, xc[p].y + kMgOmega * t.y);
-      }
-      __syncthreads();
-      tmp = xc;
-      xc = xn;
-      xn = tmp;
-    }
-    cur[l] = xc == v.xa ? 0 : 1;
-  }
-  const MgLv v0 = mg_lv(base, h, 0);
-  return cur[0] ? v0.xb : v0.xa;
-}
-
+// by one aggregation-multigrid V-cycle (mg.h), inside the same float64 residual refinement
+// as the kernels above.  System scratch: X, R, P, Q (complex, n^2 each), then the levels.
 template <int NW, int WPE>
 __global__ __launch_bounds__(64 * NW, WPE) void cocg_mg_kernel(
     const double* __restrict__ a, const double* __restrict__ dinvr, int n, double cT, int N, double alpha,
@@ -1109,7 +919,7 @@ __global__ __launch_bounds__(64 * NW, WPE) void cocg_mg_kernel(
   const double lre = 1.0 - an * cv, lim = -an * sv;
 
   // level 0 operator, float64 residual, zero solution
-  const MgLv v0 = mg_lv(base, h, 0);
+  const MgLv<float2> v0 = mg_lv<float2>(base, h, 0);
   double bn[2] = {0.0, 0.0};
   const bool sm[2] = {false, true};
   for (int64_t p = threadIdx.x; p < Nx; p += blockDim.x) {
@@ -1127,36 +937,7 @@ __global__ __launch_bounds__(64 * NW, WPE) void cocg_mg_kernel(
     bn[1] = nanmax(bn[1], dr[p] * fmax(fabs(vv.x), fabs(vv.y)));
   }
   block_reduce<2>(bn, sm, dsl);   // its barriers also publish level 0
-  // coarse levels: Galerkin products of 2x2 aggregation
-  for (int l = 1; l < h.L; ++l) {
-    const MgLv f = mg_lv(base, h, l - 1);
-    const MgLv c = mg_lv(base, h, l);
-    const int mf = f.m, mc = c.m;
-    for (int64_t Pn = threadIdx.x; Pn < (int64_t)mc * mc; Pn += blockDim.x) {
-      const int I = (int)(Pn % mc), J = (int)(Pn / mc);
-      const int i0 = 2 * I, j0 = 2 * J;
-      const bool two_i = i0 + 1 < mf, two_j = j0 + 1 < mf;
-      float2 dg = make_float2(0.f, 0.f);
-      float cwc = 0.f, csc = 0.f, inner = 0.f;
-      for (int dj = 0; dj < (two_j ? 2 : 1); ++dj)
-        for (int di = 0; di < (two_i ? 2 : 1); ++di) {
-          const int64_t p = (int64_t)(j0 + dj) * mf + (i0 + di);
-          dg.x += f.dg[p].x;
-          dg.y += f.dg[p].y;
-          if (di == 1) inner += f.cw[p];            // coupling inside the block (x)
-          if (dj == 1) inner += f.cs[p];            // coupling inside the block (y)
-          if (di == 0 && I > 0) cwc += f.cw[p];     // couplings across the west face
-          if (dj == 0 && J > 0) csc += f.cs[p];     // couplings across the south face
-        }
-      dg.x -= 2.f * inner;
-      c.dg[Pn] = dg;
-      const float den = dg.x * dg.x + dg.y * dg.y;
-      c.di[Pn] = make_float2(dg.x / den, -dg.y / den);
-      c.cw[Pn] = cwc;
-      c.cs[Pn] = csc;
-    }
-    __syncthreads();
-  }
+  mg_build_coarse<float2>(base, h);
   const double stop2 = rtol * rtol * bn[0];
   double rn2 = bn[0];
   double sig = bn[1];
@@ -1177,7 +958,7 @@ __global__ __launch_bounds__(64 * NW, WPE) void cocg_mg_kernel(
       block_sum_fk<NW, 1>(t, fsl[1], lane, wave);   // its barrier also publishes R
       r0 = t[0];
     }
-    float2* Z = mg_vcycle(base, h, R);
+    float2* Z = mg_vcycle<float2>(base, h, R);
     float acc2[2] = {0.f, 0.f};
     for (int64_t p = threadIdx.x; p < Nx; p += blockDim.x) {
       const float2 rv = R[p], zv = Z[p];
@@ -1198,7 +979,7 @@ __global__ __launch_bounds__(64 * NW, WPE) void cocg_mg_kernel(
       float pq2[2] = {0.f, 0.f};
       for (int64_t p = threadIdx.x; p < Nx; p += blockDim.x) {
         const int i = (int)(p % n), j = (int)(p / n);
-        const float2 qv = mg_apply(v0, p, i, j, [&](int64_t s, int, int) { return P[s]; });
+        const float2 qv = mg_apply<float2>(v0, p, i, j, [&](int64_t s, int, int) { return P[s]; });
         Q[p] = qv;
         const float2 pv = P[p];
         pq2[0] += pv.x * qv.x - pv.y * qv.y;
@@ -1226,7 +1007,7 @@ __global__ __launch_bounds__(64 * NW, WPE) void cocg_mg_kernel(
         break;
       }
       if (rr <= stop_in) break;
-      Z = mg_vcycle(base, h, R);
+      Z = mg_vcycle<float2>(base, h, R);
       float rz2[2] = {0.f, 0.f};
       for (int64_t p = threadIdx.x; p < Nx; p += blockDim.x) {
         const float2 rv = R[p], zv = Z[p];
@@ -1403,7 +1184,7 @@ int shifted_solve_impl(klecgc_ctx* ctx, const klecgc_problem& p, const double* a
   const int variant = p.precision == KC_PREC_F32_REFINED ? cgc_variant_for(p.n, tu.cgc_variant) : KC_CGC_STREAM64;
   const float inner = tu.cgc_inner_rtol;
   if (variant == KC_CGC_MG32) {
-    const MgLevels h = mg_levels(p.n);
+    const MgLevels h = mg_levels(p.n, 2, 8LL * Nx);
     double* dr = (double*)ctx->ws.get(WS_DINV, sizeof(double) * Nx * nsys);
     double* resb = (double*)ctx->ws.get(WS_KRYLOV, sizeof(double) * 2 * Nx * nsys);
     float* scr = (float*)ctx->ws.get(WS_FINE_AUX, sizeof(float) * h.per_sys * nsys);

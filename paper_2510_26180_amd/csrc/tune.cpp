@@ -59,14 +59,10 @@ int autotune_impl(klecgc_ctx* ctx, const klecgc_problem& p, const double* a, int
   };
   try {
     // ---- fine propagator
-    bool resident_fits = false;
-    for (int v : {KC_FINE_RES16, KC_FINE_RES32, KC_FINE_RES64, KC_FINE_RES128})
-      resident_fits = resident_fits || fine_variant_fits(v, n);
-    for (int v : {KC_FINE_RES16, KC_FINE_RES32, KC_FINE_RES64, KC_FINE_RES128, KC_FINE_STREAM64}) {
-      if (!fine_variant_fits(v, n) || (v == KC_FINE_STREAM64 && resident_fits)) continue;
+    for (int v : {KC_FINE_RES16, KC_FINE_RES32, KC_FINE_RES64, KC_FINE_RES128, KC_FINE_MG}) {
+      if (!fine_variant_fits(v, n)) continue;
       bool warmed = false;
       for (float r : fine_rtols) {
-        if (v == KC_FINE_STREAM64 && r != fine_rtols[0]) break;   // no float32 pass to tune
         KcTuning t = saved;
         t.fine_variant = v;
         t.fine_pcg_rtol = r;

@@ -73,7 +73,7 @@ def test_fine_2d_f64(ctx, n):
     assert _fine_case(ctx, w, 2, 7, dict(precision=0, inner_rtol=1e-14)) < 1e-11
 
 
-@pytest.mark.parametrize("n", [1, 9, 20, 33, 64, 100, 128])
+@pytest.mark.parametrize("n", [1, 9, 20, 33, 64, 100, 128, 129, 200])
 def test_fine_2d_f32_refined(ctx, n):
     log(f"fine 2D f32-refined n={n}")
     w = W.small_2d(n=n, N=4, J=16)   # dt = 1/64, the c2 slice length

@@ -17,7 +17,7 @@ pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 
-FINE = {"stream64": 0, "res16": 1, "res32": 2, "res64": 3, "res128": 4}
+FINE = {"stream64": 0, "res16": 1, "res32": 2, "res64": 3, "res128": 4, "mg": 5}
 CGC = {"stream64": 0, "res16": 1, "res32": 2, "res64": 3, "stream32": 4, "mg32": 5}
 
 
@@ -36,7 +36,9 @@ def spec_of(w, **kw):
 
 @pytest.mark.parametrize("n,variant,rtol", [(13, "res16", 1e-5), (13, "res32", 3e-7), (13, "res64", 1e-6),
                                             (13, "res128", 1e-6), (13, "stream64", 1e-6), (20, "res32", 3e-6),
-                                            (40, "res64", 1e-5), (40, "res128", 3e-7), (100, "res128", 1e-5)])
+                                            (40, "res64", 1e-5), (40, "res128", 3e-7), (100, "res128", 1e-5),
+                                            (1, "mg", 1e-5), (13, "mg", 1e-6), (40, "mg", 1e-5), (100, "mg", 3e-6),
+                                            (150, "mg", 1e-5), (150, "stream64", 1e-6)])
 def test_fine_variants(ctx, n, variant, rtol):
     log(f"fine variant {variant} n={n} pass reduction {rtol}")
     ctx.set_tuning(n, fine_variant=FINE[variant], fine_pcg_rtol=rtol)
