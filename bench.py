@@ -72,6 +72,102 @@ def cpu_baseline(w, xi_row, iters_mean):
                       f" = {t_iter:.1f} s, scaled by the measured mean iteration count {iters_mean:.2f}"}
 
 
+def run_ragged(args):
+    """Ragged batch (uneven grid sizes and slice counts): one parareal_solve_batch call,
+    iterations captured into a HIP graph; per-solve latency p50/p99 from the device clock."""
+    import numpy as np
+    import torch
+
+    import paper_2510_26180_amd as K
+    import workloads as W
+    spec = W.C3_RAGGED
+    bw = spec.base
+    grids = tuple(int(g) for g in args.grids.split(",")) if args.grids else spec.grids
+    M = args.M or bw.M
+    ns, Ns = W.draw_ragged(M, bw.seed_eval, grids, spec.slices)
+    xi = W.draw_xi(M, bw.d, bw.seed_eval + 1000)
+    dev = torch.device("cuda:0")
+    ctx = K.Context(0)
+    log(f"ragged batch: M={M}, grids {grids}, slices {spec.slices}, J={bw.J}, alpha={bw.alpha}")
+    fc = [2 * int(n) * (int(n) + 1) for n in ns]
+    sz = [int(N) * int(n) * int(n) for n, N in zip(ns, Ns)]
+    fo = np.concatenate([[0], np.cumsum(fc)[:-1]]).astype(np.int64)
+    so = np.concatenate([[0], np.cumsum(sz)[:-1]]).astype(np.int64)
+    a_d = torch.empty(int(sum(fc)), dtype=torch.float64, device=dev)
+    U = torch.empty(int(sum(sz)), dtype=torch.float64, device=dev)
+    base = K.ProblemSpec.from_workload(bw.replace(n=grids[0], N=spec.slices[0]))
+    classes = {}
+    for m in range(M):
+        classes.setdefault((int(ns[m]), int(Ns[m])), []).append(m)
+    t0 = time.perf_counter()
+    faces = {}
+    for g in grids:
+        idx = [m for m in range(M) if ns[m] == g]
+        if not idx:
+            continue
+        fh = ctx.kle_build_field(2, g, bw.d, bw.corr_len, bw.sigma)
+        ac = torch.empty((len(idx), 2 * g * (g + 1)), dtype=torch.float64, device=dev)
+        ctx.kle_synthesize(fh, torch.as_tensor(xi[idx]).to(dev), ac)
+        for j, m in enumerate(idx):
+            a_d[fo[m]:fo[m] + fc[m]] = ac[j]
+        faces[g] = ac
+        if not args.no_autotune:
+            pg = K.ProblemSpec.from_workload(bw.replace(n=g, N=max(Ns[idx])))
+            log(f"autotune n={g}: {ctx.autotune(pg, ac[:4].contiguous())}")
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    tasks = [(int(ns[m]), int(Ns[m]), int(fo[m]), int(so[m])) for m in range(M)]
+    runs = {}
+    for graph in ([True, False] if args.compare_eager else [True]):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        its, st, lat, total, rc = ctx.parareal_solve_batch(base, tasks, a_d, U, init=K.KC_INIT_COARSE, graph=graph,
+                                                           allow_noconv=True)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        runs[graph] = dict(its=its, st=st, lat=lat, total=total, wall=wall, rc=rc)
+        log(f"graph={graph}: {wall:.2f} s, iterations mean {its.mean():.2f} max {its.max()}, "
+            f"latency p50 {np.percentile(lat, 50) / 1e3:.2f} s p99 {np.percentile(lat, 99) / 1e3:.2f} s")
+    # accuracy: GPU serial fine per class
+    err = np.zeros(M)
+    t0 = time.perf_counter()
+    for (n, N), idx in classes.items():
+        pc = K.ProblemSpec.from_workload(bw.replace(n=n, N=N))
+        ac = torch.stack([a_d[fo[m]:fo[m] + fc[m]] for m in idx])
+        ref = torch.empty((len(idx), N, n * n), dtype=torch.float64, device=dev)
+        ctx.serial_fine_propagate(pc, ac, None, ref)
+        for j, m in enumerate(idx):
+            got = U[so[m]:so[m] + sz[m]].view(N, n * n)
+            err[m] = float((got - ref[j]).abs().max() / ref[j].abs().max())
+    t_ref = time.perf_counter() - t0
+    r = runs[True]
+    n_ok = int((err <= 1e-8).sum())
+    cls_stats = {f"{n}x{n},N={N}": {"samples": len(idx), "iters_mean": float(r["its"][idx].mean()),
+                                    "latency_p50_ms": float(np.percentile(r["lat"][idx], 50))}
+                 for (n, N), idx in sorted(classes.items())}
+    line = {
+        "metric": "parareal solves/s at 1e-8 vs serial fine (ragged batch)",
+        "value": n_ok / r["wall"], "unit": "solves/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": 1e3 * r["wall"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64+f32", "data": "synthetic",
+        "config": {"workload": f"c3_ragged: 2D grids {grids} x N {spec.slices}, J={bw.J}, KL d={bw.d}, "
+                               f"alpha={bw.alpha}, M={M}, coarse-sweep guess, one parareal_solve_batch "
+                               "(HIP-graph iterations)", "samples": M},
+        "latency_ms": {"p50": float(np.percentile(r["lat"], 50)), "p99": float(np.percentile(r["lat"], 99)),
+                       "max": float(r["lat"].max())},
+        "iters": {"mean": float(r["its"].mean()), "max": int(r["its"].max()), "min": int(r["its"].min())},
+        "accuracy": {"n_within_1e-8": n_ok, "max_rel_err_vs_serial_fine": float(err.max())},
+        "classes": cls_stats, "setup_s": t_setup, "serial_fine_reference_s": t_ref,
+    }
+    if False in runs:
+        e = runs[False]
+        line["eager"] = {"ms": 1e3 * e["wall"], "latency_p50_ms": float(np.percentile(e["lat"], 50)),
+                         "latency_p99_ms": float(np.percentile(e["lat"], 99)),
+                         "same_iterations": bool((e["its"] == r["its"]).all())}
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -84,6 +180,8 @@ def main():
                     help="initial guess (default: gpc; both for the MLP workload)")
     ap.add_argument("--epochs", type=int, default=0, help="override the MLP epochs (0 = spec)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the built-in kernel choices")
+    ap.add_argument("--grids", default="", help="ragged batch: comma-separated grid sizes (default 64,128,256)")
+    ap.add_argument("--compare-eager", action="store_true", help="ragged batch: also run without the HIP graph")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-oracle-check", action="store_true")
     args = ap.parse_args()
@@ -91,6 +189,10 @@ def main():
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU sharding is "
                                    "described in DESIGN.md but not built"}))
         sys.exit(2)
+
+    if args.config == "c3_ragged":
+        run_ragged(args)
+        return
 
     import numpy as np
     import torch

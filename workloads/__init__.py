@@ -20,7 +20,7 @@ from typing import Optional
 
 import numpy as np
 
-__all__ = ["Workload", "CONFIGS", "MlpSpec", "MLP_C4", "draw_xi", "draw_mlp_init", "draw_perms", "get",
+__all__ = ["Workload", "CONFIGS", "MlpSpec", "MLP_C4", "RaggedSpec", "C3_RAGGED", "draw_xi", "draw_mlp_init", "draw_perms", "get",
            "small_1d", "small_2d"]
 
 
@@ -89,6 +89,21 @@ class MlpSpec:
     lr_final: float          # geometric per-epoch decay from lr to lr_final
     seed_init: int
     seed_perm: int
+
+
+@dataclasses.dataclass(frozen=True)
+class RaggedSpec:
+    """Uneven batch: per-sample grid size and slice count drawn uniformly."""
+    base: Workload           # the shared parameters (n and N are drawn per sample)
+    grids: tuple
+    slices: tuple
+
+
+# 1024 samples mixing 64^2, 128^2, 256^2 grids and N in {32, 64, 128}, J = 32, KL d = 10
+# (corr 0.3, sigma 1), alpha = 1e-4, f = 1, FP32-refined fine path, coarse-sweep guess.
+C3_RAGGED = RaggedSpec(Workload("c3_ragged", 2, 0, 1.0, 0, 32, 1e-4, 1.0, 10, 0.3, 1.0,
+                                1024, "f32_refined", 1e-8, 60, 0, 0, 1e-10, 1003, 2003),
+                       grids=(64, 128, 256), slices=(32, 64, 128))
 
 
 MLP_C4 = MlpSpec(hidden=256, nc=32, epochs=1000, batch=64, lr=1e-3, lr_final=1e-5, seed_init=3004, seed_perm=4004)
