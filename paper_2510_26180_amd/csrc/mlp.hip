@@ -168,13 +168,26 @@ __global__ void splitk_reduce_kernel(const float* __restrict__ P, int S, int64_t
   }
 }
 
-// Xb[b][0..in_pad) = bf16(xi[row(b)][..]), zero padded; row(b) = perm[off+b] or off+b
-__global__ void gather_x_kernel(const double* __restrict__ xi, const int32_t* __restrict__ perm, int64_t off, int B,
-                                int n_in, int in_pad, kc_bf16* __restrict__ Xb) {
+// Training counters in device memory, so that one epoch of steps can be replayed from a
+// captured graph: t = Adam steps taken before the current one, ep = epoch of this call.
+struct TrainCtr {
+  int64_t t;
+  int64_t ep;
+};
+
+// row of mini-batch entry b: perm[ep n + off + b] with a permutation, else off + b
+__device__ __forceinline__ int64_t batch_row(const int32_t* perm, const TrainCtr* ctr, int64_t n, int64_t off, int b) {
+  return perm ? (int64_t)perm[ctr->ep * n + off + b] : off + b;
+}
+
+// Xb[b][0..in_pad) = bf16(xi[row(b)][..]), zero padded
+__global__ void gather_x_kernel(const double* __restrict__ xi, const int32_t* __restrict__ perm,
+                                const TrainCtr* __restrict__ ctr, int64_t n_rows, int64_t off, int B, int n_in,
+                                int in_pad, kc_bf16* __restrict__ Xb) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (int64_t)B * in_pad;
        i += (int64_t)gridDim.x * blockDim.x) {
     const int b = (int)(i / in_pad), c = (int)(i % in_pad);
-    const int64_t src = perm ? perm[off + b] : off + b;
+    const int64_t src = batch_row(perm, ctr, n_rows, off, b);
     Xb[i] = c < n_in ? f2bf((float)xi[src * n_in + c]) : (kc_bf16)0;
   }
 }
@@ -185,15 +198,17 @@ __global__ void check_perm_kernel(const int32_t* __restrict__ perm, int64_t tota
     if (perm[i] < 0 || perm[i] >= n) *flag = 1;
 }
 
-// dY = scale (Y - T) in FP32 and BF16, T row = Tg[row(b)]; per-block sum of squares
-// added to *loss.  grid (x blocks over columns, B rows), 256 threads.
+// dY = scale (Y - T) in FP32 and BF16, T row = Tg[row(b)]; the block's sum of squares goes
+// to part[block] (summed in a fixed order by loss_reduce_kernel: no contended atomics).
+// grid (x blocks over columns, B rows), 256 threads.
 __global__ __launch_bounds__(256) void mse_grad_kernel(const float* __restrict__ Y, const float* __restrict__ Tg,
-                                                       const int32_t* __restrict__ perm, int64_t off, int64_t O,
-                                                       float scale, float* __restrict__ dY, kc_bf16* __restrict__ dYb,
-                                                       double* __restrict__ loss) {
-  __shared__ double part[4];
+                                                       const int32_t* __restrict__ perm,
+                                                       const TrainCtr* __restrict__ ctr, int64_t n_rows,
+                                                       int64_t off, int64_t O, float scale, float* __restrict__ dY,
+                                                       kc_bf16* __restrict__ dYb, double* __restrict__ part) {
+  __shared__ double wsum[4];
   const int b = blockIdx.y;
-  const int64_t src = perm ? perm[off + b] : off + b;
+  const int64_t src = batch_row(perm, ctr, n_rows, off, b);
   const float* y = Y + (int64_t)b * O;
   const float* t = Tg + src * O;
   double s = 0.0;
@@ -205,9 +220,21 @@ __global__ __launch_bounds__(256) void mse_grad_kernel(const float* __restrict__
     dYb[(int64_t)b * O + j] = f2bf(gv);
   }
   for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);
-  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = s;
   __syncthreads();
-  if (threadIdx.x == 0) atomicAdd(loss, part[0] + part[1] + part[2] + part[3]);
+  if (threadIdx.x == 0) part[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+}
+
+// *loss += sum of part[0..count) (one work-group of 256 threads, fixed order)
+__global__ __launch_bounds__(256) void loss_reduce_kernel(const double* __restrict__ part, int64_t count,
+                                                          double* __restrict__ loss) {
+  __shared__ double wsum[4];
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < count; i += blockDim.x) s += part[i];
+  for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) *loss += wsum[0] + wsum[1] + wsum[2] + wsum[3];
 }
 
 // dpre = dH * GELU'(pre), FP32 and BF16
@@ -220,13 +247,23 @@ __global__ void gelu_bwd_kernel(const float* __restrict__ dH, const float* __res
   }
 }
 
-// db[j] = sum_i D[i][j]
-__global__ void colsum_kernel(const float* __restrict__ D, int rows, int64_t cols, float* __restrict__ db) {
-  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < cols; j += (int64_t)gridDim.x * blockDim.x) {
-    float s = 0.f;
-    for (int i = 0; i < rows; ++i) s += D[(int64_t)i * cols + j];
-    db[j] = s;
+// db[j] = sum_i D[i][j]: 64 columns per work-group, the rows split over 16 slices of
+// threads and summed by a fixed LDS tree (deterministic; many loads in flight per column)
+__global__ __launch_bounds__(1024) void colsum_kernel(const float* __restrict__ D, int rows, int64_t cols,
+                                                      float* __restrict__ db) {
+  __shared__ float acc[16][64];
+  const int c = threadIdx.x & 63, r0 = threadIdx.x >> 6;
+  const int64_t j = (int64_t)blockIdx.x * 64 + c;
+  float s = 0.f;
+  if (j < cols)
+    for (int i = r0; i < rows; i += 16) s += D[(int64_t)i * cols + j];
+  acc[r0][c] = s;
+  __syncthreads();
+  for (int h = 8; h >= 1; h >>= 1) {
+    if (r0 < h) acc[r0][c] += acc[r0 + h][c];
+    __syncthreads();
   }
+  if (r0 == 0 && j < cols) db[j] = acc[0][c];
 }
 
 // Adam on the FP32 masters; the BF16 copies of the weight blocks are refreshed in the
@@ -234,9 +271,18 @@ __global__ void colsum_kernel(const float* __restrict__ D, int rows, int64_t col
 struct AdamSeg {
   int64_t oW2, ob2, oW3, ob3, bW2, bW3;
 };
+// Step t+1 with bias corrections c1 = 1 - b1^(t+1), c2 = 1 - b2^(t+1) and the epoch's learning
+// rate lr0 (lr_final/lr0)^(ep/(epochs-1)) (constant lr0 if lr_final <= 0), read from ctr.
 __global__ void adam_kernel(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m,
-                            float* __restrict__ v, int64_t total, float lr, float b1, float b2, float eps, float c1,
-                            float c2, int64_t nW1, AdamSeg sg, kc_bf16* __restrict__ wb) {
+                            float* __restrict__ v, int64_t total, float lr0, float lr_final, int epochs, float b1,
+                            float b2, float eps, const TrainCtr* __restrict__ ctr, int64_t nW1, AdamSeg sg,
+                            kc_bf16* __restrict__ wb) {
+  const double t = (double)(ctr->t + 1);
+  const float c1 = (float)(1.0 - pow((double)b1, t));
+  const float c2 = (float)(1.0 - pow((double)b2, t));
+  const float lr = (lr_final > 0.f && epochs > 1)
+                       ? (float)(lr0 * pow((double)lr_final / lr0, (double)ctr->ep / (epochs - 1)))
+                       : lr0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
     const float gi = g[i];
     const float mi = b1 * m[i] + (1.f - b1) * gi;
@@ -251,6 +297,20 @@ __global__ void adam_kernel(float* __restrict__ w, const float* __restrict__ g, 
       wb[sg.bW2 + (i - sg.oW2)] = f2bf(wi);
     else if (i >= sg.oW3 && i < sg.ob3)
       wb[sg.bW3 + (i - sg.oW3)] = f2bf(wi);
+  }
+}
+
+__global__ void step_kernel(TrainCtr* __restrict__ ctr) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) ctr->t += 1;
+}
+
+// end of an epoch: record its mean loss, reset the accumulator, advance the epoch
+__global__ void epoch_end_kernel(TrainCtr* __restrict__ ctr, double* __restrict__ loss, double* __restrict__ hist,
+                                 double scale) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    hist[ctr->ep] = *loss * scale;
+    *loss = 0.0;
+    ctr->ep += 1;
   }
 }
 
@@ -361,12 +421,14 @@ Layout layout_of(const klecgc_mlp* h) {
   return L;
 }
 
-constexpr int kSplitK = 32;   // partial sums for the K = n_out product
+constexpr int kSplitK = 32;      // partial sums for the K = n_out product
+constexpr int kMseBlocksX = 64;  // column blocks of the loss-gradient kernel
 
 struct Work {
   kc_bf16 *Xb, *h1b, *h2b, *dYb, *dp2b, *dp1b;
   float *pre1, *pre2, *Y, *dY, *dH2, *dp2, *dH1, *dp1, *part;
   double* loss;
+  double* lpart;   // per-block loss partial sums [kMseBlocksX * B]
 };
 
 template <class T>
@@ -380,7 +442,7 @@ size_t work_bytes(const klecgc_mlp* h, int B) {
   const int64_t H = h->hidden, O = h->n_out, P = h->in_pad;
   const int64_t nb = (int64_t)B * (P + 2 * H + O + 2 * H);
   const int64_t nf = (int64_t)B * (2 * H + 2 * O + 4 * H) + (int64_t)kSplitK * B * H;
-  return (size_t)nb * 2 + (size_t)nf * 4 + 17 * 256;
+  return (size_t)nb * 2 + (size_t)nf * 4 + (size_t)8 * kMseBlocksX * B + 18 * 256;
 }
 
 Work work_for(klecgc_ctx* ctx, klecgc_mlp* h, int B) {
@@ -419,6 +481,7 @@ Work work_for(klecgc_ctx* ctx, klecgc_mlp* h, int B) {
   w.dp1 = carve<float>(p, (int64_t)B * H);
   w.part = carve<float>(p, (int64_t)kSplitK * B * H);
   w.loss = carve<double>(p, 1);
+  w.lpart = carve<double>(p, (int64_t)kMseBlocksX * B);
   if ((size_t)(p - (char*)h->ws) > h->ws_bytes) throw Error{KC_EINVAL, "MLP work buffer layout overflow"};
   return w;
 }
@@ -468,36 +531,41 @@ void forward(hipStream_t s, const klecgc_mlp* h, const Work& w, int B, float* Yo
 }
 
 // gradient of the batch loss into h->g; adds the batch sum of squared errors to w.loss
-void backward(hipStream_t s, klecgc_mlp* h, const Work& w, int B, const float* Tg, const int32_t* perm, int64_t off) {
+void backward(hipStream_t s, klecgc_mlp* h, const Work& w, int B, const float* Tg, const int32_t* perm,
+              const TrainCtr* ctr, int64_t n_rows, int64_t off) {
   const Layout L = layout_of(h);
   const int H = h->hidden, O = (int)h->n_out;
   const float scale = (float)(2.0 / ((double)B * O));
-  mse_grad_kernel<<<dim3((unsigned)std::min<int64_t>((O + 255) / 256, 64), (unsigned)B), 256, 0, s>>>(
-      w.Y, Tg, perm, off, O, scale, w.dY, w.dYb, w.loss);
+  const unsigned gx = (unsigned)std::min<int64_t>((O + 255) / 256, kMseBlocksX);
+  mse_grad_kernel<<<dim3(gx, (unsigned)B), 256, 0, s>>>(w.Y, Tg, perm, ctr, n_rows, off, O, scale, w.dY, w.dYb,
+                                                       w.lpart);
+  KC_LAUNCH_CHECK();
+  loss_reduce_kernel<<<1, 256, 0, s>>>(w.lpart, (int64_t)gx * B, w.loss);
   KC_LAUNCH_CHECK();
   // layer 3: dW3 = h2b^T dYb, db3 = column sums of dY, dH2 = dYb W3b^T
   gemm<true, false, EPI_STORE>(s, H, O, B, w.h2b, H, w.dYb, O, h->g + L.oW3, O);
-  colsum_kernel<<<grid1d(O, 1 << 20), 256, 0, s>>>(w.dY, B, O, h->g + L.ob3);
+  colsum_kernel<<<(unsigned)((O + 63) / 64), 1024, 0, s>>>(w.dY, B, O, h->g + L.ob3);
   KC_LAUNCH_CHECK();
   gemm_nt_splitk(s, B, H, O, w.dYb, O, h->wb + L.bW3, O, w.part, w.dH2);
   gelu_bwd_kernel<<<grid1d((int64_t)B * H), 256, 0, s>>>(w.dH2, w.pre2, (int64_t)B * H, w.dp2, w.dp2b);
   KC_LAUNCH_CHECK();
   // layer 2
   gemm<true, false, EPI_STORE>(s, H, H, B, w.h1b, H, w.dp2b, H, h->g + L.oW2, H);
-  colsum_kernel<<<grid1d(H, 1 << 20), 256, 0, s>>>(w.dp2, B, H, h->g + L.ob2);
+  colsum_kernel<<<(unsigned)((H + 63) / 64), 1024, 0, s>>>(w.dp2, B, H, h->g + L.ob2);
   KC_LAUNCH_CHECK();
   gemm<false, true, EPI_STORE>(s, B, H, H, w.dp2b, H, h->wb + L.bW2, H, w.dH1, H);
   gelu_bwd_kernel<<<grid1d((int64_t)B * H), 256, 0, s>>>(w.dH1, w.pre1, (int64_t)B * H, w.dp1, w.dp1b);
   KC_LAUNCH_CHECK();
   // layer 1 (the n_in real rows of W1)
   gemm<true, false, EPI_STORE>(s, h->n_in, H, B, w.Xb, h->in_pad, w.dp1b, H, h->g + L.oW1, H);
-  colsum_kernel<<<grid1d(H, 1 << 20), 256, 0, s>>>(w.dp1, B, H, h->g + L.ob1);
+  colsum_kernel<<<(unsigned)((H + 63) / 64), 1024, 0, s>>>(w.dp1, B, H, h->g + L.ob1);
   KC_LAUNCH_CHECK();
 }
 
-void stage_x(hipStream_t s, const klecgc_mlp* h, const Work& w, const double* xi, const int32_t* perm, int64_t off,
-             int B) {
-  gather_x_kernel<<<grid1d((int64_t)B * h->in_pad, 1 << 20), 256, 0, s>>>(xi, perm, off, B, h->n_in, h->in_pad, w.Xb);
+void stage_x(hipStream_t s, const klecgc_mlp* h, const Work& w, const double* xi, const int32_t* perm,
+             const TrainCtr* ctr, int64_t n_rows, int64_t off, int B) {
+  gather_x_kernel<<<grid1d((int64_t)B * h->in_pad, 1 << 20), 256, 0, s>>>(xi, perm, ctr, n_rows, off, B, h->n_in,
+                                                                          h->in_pad, w.Xb);
   KC_LAUNCH_CHECK();
 }
 
@@ -583,7 +651,7 @@ int mlp_predict_impl(klecgc_ctx* ctx, klecgc_mlp* h, const double* xi, int64_t M
   for (int64_t off = 0; off < M; off += chunk) {
     const int B = (int)std::min<int64_t>(chunk, M - off);
     Work w = work_for(ctx, h, B);
-    stage_x(s, h, w, xi, nullptr, off, B);
+    stage_x(s, h, w, xi, nullptr, nullptr, M, off, B);
     timed(ctx, KT_MLP, [&] { forward(s, h, w, B, Y + off * h->n_out); });
   }
   return KC_OK;
@@ -595,10 +663,10 @@ int mlp_grad_impl(klecgc_ctx* ctx, klecgc_mlp* h, const double* xi, const float*
   KC_REQUIRE(n >= 1 && n <= 65535, KC_EINVAL, "mlp_grad: n must be in [1, 65535]");
   Work w = work_for(ctx, h, (int)n);
   KC_TRY_HIP(hipMemsetAsync(w.loss, 0, sizeof(double), s));
-  stage_x(s, h, w, xi, nullptr, 0, (int)n);
+  stage_x(s, h, w, xi, nullptr, nullptr, n, 0, (int)n);
   timed(ctx, KT_MLP, [&] {
     forward(s, h, w, (int)n, w.Y);
-    backward(s, h, w, (int)n, Y, nullptr, 0);
+    backward(s, h, w, (int)n, Y, nullptr, nullptr, n, 0);
   });
   if (grads) KC_TRY_HIP(hipMemcpyAsync(grads, h->g, sizeof(float) * h->n_params, hipMemcpyDeviceToDevice, s));
   double hl = 0;
@@ -630,35 +698,78 @@ int mlp_train_impl(klecgc_ctx* ctx, klecgc_mlp* h, const double* xi, const float
     KC_TRY_HIP(hipStreamSynchronize(s));
     KC_REQUIRE(hf == 0, KC_EINVAL, "perm_dev holds a row index outside [0, n)");
   }
-  for (int ep = 0; ep < epochs; ++ep) {
-    KC_TRY_HIP(hipMemsetAsync(w.loss, 0, sizeof(double), s));
-    const int32_t* pe = perm ? perm + (int64_t)ep * n : nullptr;
-    const float lr_ep = (lr_final > 0.f && epochs > 1)
-                            ? (float)(lr * std::pow((double)lr_final / lr, (double)ep / (epochs - 1)))
-                            : lr;
-    timed(ctx, KT_MLP, [&] {
-      for (int64_t bi = 0; bi < nbatch; ++bi) {
-        const int64_t off = bi * batch;
-        const int B = (int)std::min<int64_t>(batch, n - off);
-        stage_x(s, h, w, xi, pe, off, B);
-        forward(s, h, w, B, w.Y);
-        backward(s, h, w, B, Y, pe, off);
-        h->t += 1;
-        const float c1 = (float)(1.0 - std::pow(0.9, (double)h->t));
-        const float c2 = (float)(1.0 - std::pow(0.999, (double)h->t));
-        adam_kernel<<<grid1d(h->n_params), 256, 0, s>>>(h->w, h->g, h->m, h->v, h->n_params, lr_ep, 0.9f, 0.999f, 1e-8f,
-                                                        c1, c2, L.ob1, sg, h->wb);
-        KC_LAUNCH_CHECK();
-      }
-    });
-    if (loss_host) {
-      double hl = 0;
-      KC_TRY_HIP(hipMemcpyAsync(&hl, w.loss, sizeof(double), hipMemcpyDeviceToHost, s));
-      KC_TRY_HIP(hipStreamSynchronize(s));
-      loss_host[ep] = (float)(hl / ((double)n * h->n_out));
+  if (epochs == 0) return KC_OK;
+  // One epoch of steps is captured into a graph on a library-owned stream (a caller's
+  // legacy null stream cannot be captured) and replayed `epochs` times; the step count,
+  // the epoch index and the loss accumulator live in device memory.
+  struct Owned {
+    void* buf = nullptr;
+    hipStream_t cs = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipGraph_t g = nullptr;
+    hipGraphExec_t x = nullptr;
+    ~Owned() {
+      if (cs) (void)hipStreamSynchronize(cs);
+      if (x) (void)hipGraphExecDestroy(x);
+      if (g) (void)hipGraphDestroy(g);
+      if (e0) (void)hipEventDestroy(e0);
+      if (e1) (void)hipEventDestroy(e1);
+      if (cs) (void)hipStreamDestroy(cs);
+      if (buf) (void)hipFree(buf);
     }
+  } o;
+  KC_TRY_HIP(hipMalloc(&o.buf, 256 + sizeof(double) * (size_t)epochs));
+  TrainCtr* ctr = (TrainCtr*)o.buf;
+  double* hist = (double*)((char*)o.buf + 256);
+  KC_TRY_HIP(hipStreamCreateWithFlags(&o.cs, hipStreamNonBlocking));
+  KC_TRY_HIP(hipEventCreate(&o.e0));
+  KC_TRY_HIP(hipEventCreate(&o.e1));
+  const TrainCtr c0{h->t, 0};
+  KC_TRY_HIP(hipMemcpyAsync(ctr, &c0, sizeof(c0), hipMemcpyHostToDevice, s));
+  KC_TRY_HIP(hipMemsetAsync(w.loss, 0, sizeof(double), s));
+  KC_TRY_HIP(hipEventRecord(o.e0, s));
+  KC_TRY_HIP(hipStreamWaitEvent(o.cs, o.e0, 0));
+  hipStream_t cs = o.cs;
+  KC_TRY_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
+  try {
+    for (int64_t bi = 0; bi < nbatch; ++bi) {
+      const int64_t off = bi * batch;
+      const int B = (int)std::min<int64_t>(batch, n - off);
+      stage_x(cs, h, w, xi, perm, ctr, n, off, B);
+      forward(cs, h, w, B, w.Y);
+      backward(cs, h, w, B, Y, perm, ctr, n, off);
+      adam_kernel<<<grid1d(h->n_params), 256, 0, cs>>>(h->w, h->g, h->m, h->v, h->n_params, lr, lr_final, epochs,
+                                                       0.9f, 0.999f, 1e-8f, ctr, L.ob1, sg, h->wb);
+      KC_LAUNCH_CHECK();
+      step_kernel<<<1, 64, 0, cs>>>(ctr);
+      KC_LAUNCH_CHECK();
+    }
+    epoch_end_kernel<<<1, 64, 0, cs>>>(ctr, w.loss, hist, 1.0 / ((double)n * h->n_out));
+    KC_LAUNCH_CHECK();
+  } catch (...) {
+    hipGraph_t g = nullptr;
+    (void)hipStreamEndCapture(cs, &g);
+    if (g) (void)hipGraphDestroy(g);
+    throw;
   }
-  KC_TRY_HIP(hipStreamSynchronize(s));
+  KC_TRY_HIP(hipStreamEndCapture(cs, &o.g));
+  KC_TRY_HIP(hipGraphInstantiate(&o.x, o.g, nullptr, nullptr, 0));
+  KC_TRY_HIP(hipEventRecord(o.e0, cs));
+  for (int ep = 0; ep < epochs; ++ep) KC_TRY_HIP(hipGraphLaunch(o.x, cs));
+  KC_TRY_HIP(hipEventRecord(o.e1, cs));
+  std::vector<double> hl((size_t)epochs);
+  KC_TRY_HIP(hipMemcpyAsync(hl.data(), hist, sizeof(double) * epochs, hipMemcpyDeviceToHost, cs));
+  KC_TRY_HIP(hipStreamSynchronize(cs));
+  float ms = 0.f;
+  KC_TRY_HIP(hipEventElapsedTime(&ms, o.e0, o.e1));
+  ctx->ktime[KT_MLP] += ms;
+  ctx->kcount[KT_MLP] += epochs;
+  h->t += (int64_t)epochs * nbatch;
+  if (loss_host)
+    for (int ep = 0; ep < epochs; ++ep) loss_host[ep] = (float)hl[ep];
+  // the caller's stream resumes after the training
+  KC_TRY_HIP(hipEventRecord(o.e1, cs));
+  KC_TRY_HIP(hipStreamWaitEvent(s, o.e1, 0));
   return KC_OK;
 }
 
