@@ -345,12 +345,17 @@ def main():
     if dom == "fine":
         flops = FLOPS_PER_PCG_UNKNOWN_IT * w.Nx * stats["fine_krylov_its"]
         achieved = flops / (dom_ms / 1e3) / 1e12
+        traffic = profiled_traffic("fine.hip", "fine2d_resident_c2_traffic.json")
+        ms_launch = dom_ms / max(dom_n, 1)
+        fine_hbm = None if traffic is None else {
+            "GB_per_s": traffic / (ms_launch / 1e3), "frac_of_peak": traffic / (ms_launch / 1e3) / PEAK_HBM_GBS,
+            "source": "profiled FETCH_SIZE + WRITE_SIZE bytes per launch / live launch time"}
         roof = {"kernel": "fine2d_resident_kernel", "bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
-                "traffic": profiled_traffic("fine.hip", "fine2d_resident_c2_traffic.json"),
+                "traffic": traffic,
                 "traffic_unit": "GB/launch (HBM FETCH+WRITE, copy-calibrated)",
                 "algorithmic_tflop_per_launch": flops / 1e12 / max(dom_n, 1),
-                "launches": dom_n, "ms_per_launch": dom_ms / max(dom_n, 1)}
+                "launches": dom_n, "ms_per_launch": ms_launch, "fine_prop_hbm": fine_hbm}
     elif dom == "shifted":
         byts = BYTES_PER_COCG_UNKNOWN_IT * w.Nx * stats["cgc_krylov_its"]
         achieved = byts / (dom_ms / 1e3) / 1e9

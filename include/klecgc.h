@@ -261,7 +261,9 @@ int parareal_solve(klecgc_ctx* ctx, const klecgc_problem* prob, const double* a_
  *   iters_host [M], status_host [M] (KC_SAMPLE_*) as in parareal_solve;
  *   latency_ms_host [M] (nullable): time from the start of the call to the iteration
  *   at which the sample stopped (device clock); total_ms_host (nullable): wall time of
- *   the call on the context stream. */
+ *   the call on the context stream.
+ * With KC_BATCH_GRAPH the call must not be made while the context stream is being
+ * captured by the caller (it captures on a library-owned stream of its own). */
 typedef struct {
   int32_t n;          /* interior nodes per dimension */
   int32_t N;          /* coarse slices (power of two, 2..256) */
@@ -307,7 +309,9 @@ int mlp_normalize_targets(klecgc_ctx* ctx, klecgc_mlp* h, float* Y_dev, int64_t 
  * rows of the order perm_dev [epochs][n] int32 (nullable = identity; each row a
  * permutation of 0..n-1), one Adam step per mini-batch.  Learning rate of epoch e:
  * lr (lr_final/lr)^(e/(epochs-1)) (geometric decay; lr_final <= 0 keeps lr).
- * KC_EINVAL if a perm entry lies outside [0, n).
+ * KC_EINVAL if a perm entry lies outside [0, n).  One epoch is captured into a HIP graph on
+ * a library-owned stream and replayed, so the call must not be made while the context
+ * stream is being captured by the caller.
  * xi_dev [n][n_in] float64, Y_dev [n][n_out] z-scored FP32 targets.
  * loss_host [epochs] (nullable) receives the mean of the per-batch losses weighted by
  * batch size (evaluated before each step). */

@@ -109,8 +109,8 @@ def test_ragged_2d_f64_matches_uniform(ctx, graph):
 
 def test_ragged_2d_f32_refined_matches_uniform(ctx):
     w = W.small_2d(alpha=1e-2, J=4, d=6, precision="f32_refined")
-    log("ragged 2D f32-refined (resident fine and shifted kernels)")
-    _case(ctx, w, (12, 33, 65), (4, 8), 10, 303, True, init_name="coarse")
+    log("ragged 2D f32-refined (resident and multigrid fine and shifted kernels)")
+    _case(ctx, w, (12, 33, 65, 130), (4, 8), 10, 303, True, init_name="coarse")
 
 
 def test_ragged_latency_ordered_within_class(ctx):

@@ -169,12 +169,13 @@ def test_parareal_1d_c1(ctx, init):
         assert np.allclose(hg, ho, rtol=1e-5, atol=1e-13)
 
 
-@pytest.mark.parametrize("prec", [0, 1])
-def test_parareal_2d_small(ctx, prec):
-    w = W.small_2d(n=12, N=8, J=6, alpha=1e-2)
-    log(f"parareal 2D small prec={prec}")
+@pytest.mark.parametrize("prec,n", [(0, 12), (1, 12), (1, 72), (1, 130)])
+def test_parareal_2d_small(ctx, prec, n):
+    # n = 72: resident fine kernel + multigrid COCG; n = 130: multigrid fine kernel too
+    w = W.small_2d(n=n, N=8 if n < 100 else 4, J=6 if n < 100 else 3, alpha=1e-2)
+    log(f"parareal 2D small prec={prec} n={n}")
     for it_gpu, it_or, e_or, e_ref, st, hg, ho in _parareal_case(
-            ctx, w, 3, "zero", dict(precision=prec, inner_rtol=1e-14, cgc_rtol=1e-14)):
+            ctx, w, 3 if n < 100 else 1, "zero", dict(precision=prec, inner_rtol=1e-14, cgc_rtol=1e-14)):
         assert st == 0
         assert abs(it_gpu - it_or) <= 1
         assert e_ref < 1e-8
