@@ -241,11 +241,13 @@ int klecgc_set_tuning(klecgc_ctx* ctx, int32_t n, const klecgc_tuning* t) {
     KC_REQUIRE(t->fine_pcg_rtol > 0.f && t->fine_pcg_rtol < 0.5f && t->cgc_inner_rtol > 0.f &&
                    t->cgc_inner_rtol < 0.5f,
                KC_EINVAL, "per-pass reductions must lie in (0, 0.5)");
+    KC_REQUIRE(t->mg_sweeps >= 0 && t->mg_sweeps <= 4, KC_EINVAL, "mg_sweeps must lie in [0, 4]");
     KcTuning k;
     k.fine_variant = t->fine_variant;
     k.fine_pcg_rtol = t->fine_pcg_rtol;
     k.cgc_variant = t->cgc_variant;
     k.cgc_inner_rtol = t->cgc_inner_rtol;
+    k.mg_sweeps = t->mg_sweeps;
     ctx->tuning[n] = k;
     return KC_OK;
   });
@@ -258,6 +260,7 @@ int klecgc_get_tuning(const klecgc_ctx* ctx, int32_t n, klecgc_tuning* t) {
   t->fine_pcg_rtol = k.fine_pcg_rtol;
   t->cgc_variant = k.cgc_variant;
   t->cgc_inner_rtol = k.cgc_inner_rtol;
+  t->mg_sweeps = k.mg_sweeps;
   return KC_OK;
 }
 

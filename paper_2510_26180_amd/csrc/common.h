@@ -71,6 +71,7 @@ struct KcTuning {
   float fine_pcg_rtol = 1e-6f;  // float32 PCG residual reduction per refinement pass
   int cgc_variant = -1;         // -1 heuristic; KC_CGC_* otherwise
   float cgc_inner_rtol = 1e-5f; // float32 COCG residual reduction per refinement pass
+  int mg_sweeps = 0;            // multigrid smoothing sweeps per level (0 = default 2)
 };
 
 struct klecgc_ctx {

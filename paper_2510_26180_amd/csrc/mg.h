@@ -8,8 +8,8 @@
 // Level l+1 aggregates 2x2 blocks of level l (a last 1-wide block when m is odd); its
 // operator is the Galerkin product P^T L P for the piecewise-constant prolongation P,
 // again 5-point: couplings summed across aggregate faces, diagonal summed over the block
-// minus twice its internal couplings.  The V-cycle smooths with damped Jacobi (kMgSweeps
-// sweeps down and up, the same on the coarsest level of at most 2x2), restricts by
+// minus twice its internal couplings.  The V-cycle smooths with damped Jacobi (h.sweeps,
+// default 2, sweeps down and up, the same on the coarsest level of at most 2x2), restricts by
 // summation and prolongates by injection scaled by kMgScale (aggregation coarse spaces
 // are too stiff by about that factor).  Pre- and post-smoothing are the same symmetric
 // operator, so the preconditioner is symmetric (complex symmetric for T = float2), as
@@ -26,10 +26,11 @@ namespace kc {
 constexpr int kMgMaxLevels = 12;
 constexpr float kMgOmega = 0.7f;
 constexpr float kMgScale = 1.8f;
-constexpr int kMgSweeps = 2;
+constexpr int kMgSweeps = 2;   // default damped-Jacobi sweeps per level and direction
 
 struct MgLevels {
   int L;
+  int sweeps;                  // damped-Jacobi sweeps per level and direction (>= 1)
   int m[kMgMaxLevels];
   int64_t off[kMgMaxLevels];   // float offset of each level's block in a system's scratch
   int64_t per_sys;             // floats of scratch per system
@@ -73,8 +74,9 @@ struct MgT<float2> {
 // Level table for an n x n grid; `head` floats of Krylov vectors precede the levels in a
 // system's scratch.  Level block (m = m_l): cw[m^2], cs[m^2] (float), then dg, di, xa,
 // xb, b (T each).
-inline MgLevels mg_levels(int n, int words, int64_t head) {
+inline MgLevels mg_levels(int n, int words, int64_t head, int sweeps) {
   MgLevels h{};
+  h.sweeps = sweeps >= 1 ? sweeps : kMgSweeps;
   int m = n, L = 0;
   int64_t off = head;
   while (true) {
@@ -176,7 +178,7 @@ __device__ T* mg_vcycle(float* base, const MgLevels& h, const T* rhs0) {
     __syncthreads();
     T* xc = v.xa;
     T* xn = v.xb;
-    for (int s = 1; s < kMgSweeps; ++s) {
+    for (int s = 1; s < h.sweeps; ++s) {
       for (int64_t p = tid; p < mm; p += nt) {
         const int i = (int)(p % m), j = (int)(p / m);
         const T lx = mg_apply<T>(v, p, i, j, [&](int64_t q, int, int) { return xc[q]; });
@@ -230,7 +232,7 @@ __device__ T* mg_vcycle(float* base, const MgLevels& h, const T* rhs0) {
     T* tmp = xc;
     xc = xn;
     xn = tmp;
-    for (int s = 1; s < kMgSweeps; ++s) {
+    for (int s = 1; s < h.sweeps; ++s) {
       for (int64_t p = tid; p < mm; p += nt) {
         const int i = (int)(p % m), j = (int)(p / m);
         const T lx = mg_apply<T>(v, p, i, j, [&](int64_t q, int, int) { return xc[q]; });

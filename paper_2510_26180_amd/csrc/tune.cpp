@@ -95,10 +95,13 @@ int autotune_impl(klecgc_ctx* ctx, const klecgc_problem& p, const double* a, int
     for (int v : {KC_CGC_RES16, KC_CGC_RES32, KC_CGC_RES64, KC_CGC_STREAM32, KC_CGC_MG32}) {
       if (!cgc_variant_fits(v, n)) continue;
       bool warmed = false;
+      for (int sw : {2, 1})
       for (float r : cgc_rtols) {
+        if (v != KC_CGC_MG32 && sw != 2) continue;   // only the multigrid variant smooths
         KcTuning t = best;
         t.cgc_variant = v;
         t.cgc_inner_rtol = r;
+        t.mg_sweeps = v == KC_CGC_MG32 ? sw : best.mg_sweeps;
         ctx->tuning[n] = t;
         if (!warmed) {
           KC_TRY_HIP(hipMemcpyAsync(spec.p, spec0.p, sizeof(double) * 2 * Mp * K * Nx, hipMemcpyDeviceToDevice, st));
@@ -113,6 +116,7 @@ int autotune_impl(klecgc_ctx* ctx, const klecgc_problem& p, const double* a, int
           best_cgc = ms;
           best.cgc_variant = v;
           best.cgc_inner_rtol = r;
+          best.mg_sweeps = t.mg_sweeps;
         }
       }
     }
@@ -127,6 +131,7 @@ int autotune_impl(klecgc_ctx* ctx, const klecgc_problem& p, const double* a, int
     out->fine_pcg_rtol = best.fine_pcg_rtol;
     out->cgc_variant = best.cgc_variant;
     out->cgc_inner_rtol = best.cgc_inner_rtol;
+    out->mg_sweeps = best.mg_sweeps;
   }
   if (ms_out) {
     ms_out[0] = best_fine;
