@@ -114,7 +114,8 @@ void klecgc_mlp_free(klecgc_mlp* h);
  * solves: total Krylov iterations, total float64 refinement passes, number of implicit
  * steps, max iterations of one solve; [4..7] the same for the shifted solves of step (b)
  * (2D only; passes unused); [8] shader-clock cycles of the 2D resident fine kernel summed
- * over work-groups, [9] of which inside its float32 Krylov loops; [10..15] reserved (0). */
+ * over work-groups, [9] of which inside its float32 Krylov loops; [10] fine implicit steps
+ * and [11] shifted solves that ended above their residual target; [12..15] reserved (0). */
 int klecgc_last_stats(const klecgc_ctx* ctx, int64_t* out16);
 /* Device time of the last call on ctx, measured with HIP events on the context stream
  * around each kernel launch (instrumentation): ms8[c] milliseconds and count8[c] launches

@@ -122,7 +122,7 @@ class Context:
         v = list(out)
         return {"fine_krylov_its": v[0], "fine_passes": v[1], "fine_solves": v[2], "fine_max_its": v[3],
                 "cgc_krylov_its": v[4], "cgc_solves": v[6], "cgc_max_its": v[7],
-                "fine_cycles": v[8], "fine_krylov_cycles": v[9]}
+                "fine_cycles": v[8], "fine_krylov_cycles": v[9], "fine_missed": v[10], "cgc_missed": v[11]}
 
     KCLASSES = ("fine", "shifted", "fft_fwd", "fft_inv", "defect", "gemm", "mlp")
 

@@ -71,6 +71,7 @@ int status_collect(klecgc_ctx* ctx, const DevStatus& st, int base) {
   unsigned long long c[10];
   std::memcpy(&flag, h, sizeof(int));
   std::memcpy(c, h + 8, sizeof(c));
+  ctx->stats[base == 0 ? 10 : 11] += (int64_t)c[5];   // solves that missed their target
   if (base == 0) {
     ctx->stats[8] += (int64_t)c[8];
     ctx->stats[9] += (int64_t)c[9];

@@ -692,7 +692,10 @@ __global__ __launch_bounds__(64 * NW) void cocg_resident_kernel(
     ++pass;
   }
   if (threadIdx.x == 0) {
-    if (rn2 > stop2) atomicOr(flag, 1);
+    if (rn2 > stop2) {
+      atomicOr(flag, 1);
+      atomicAdd(&cnt[5], 1ull);
+    }
     atomicAdd(&cnt[0], tot_it);
     atomicAdd(&cnt[1], (unsigned long long)pass);
     atomicAdd(&cnt[2], 1ull);
@@ -875,7 +878,10 @@ __global__ __launch_bounds__(512) void cocg32_stream_kernel(
     ++pass;
   }
   if (threadIdx.x == 0) {
-    if (rn2 > stop2) atomicOr(flag, 1);
+    if (rn2 > stop2) {
+      atomicOr(flag, 1);
+      atomicAdd(&cnt[5], 1ull);
+    }
     atomicAdd(&cnt[0], tot_it);
     atomicAdd(&cnt[1], (unsigned long long)pass);
     atomicAdd(&cnt[2], 1ull);
@@ -1074,7 +1080,10 @@ __global__ __launch_bounds__(64 * NW, WPE) void cocg_mg_kernel(
     ++pass;
   }
   if (threadIdx.x == 0) {
-    if (rn2 > stop2) atomicOr(flag, 1);
+    if (rn2 > stop2) {
+      atomicOr(flag, 1);
+      atomicAdd(&cnt[5], 1ull);
+    }
     atomicAdd(&cnt[0], tot_it);
     atomicAdd(&cnt[1], (unsigned long long)pass);
     atomicAdd(&cnt[2], 1ull);

@@ -5,13 +5,16 @@
 //  * 1D: direct tridiagonal (Thomas) solves in float64, one thread per system, the
 //    factorisation tables built once per sample (the matrix is the same for every slice).
 //  * 2D, float64: Jacobi-PCG, one work-group per system streaming its vectors.
-//  * 2D, float32-refined: one work-group of 8 waves per system keeps the whole system
-//    on the CU.  The float32 Jacobi-PCG state (x, r, p, q) and the float32 scaled
-//    stencil coefficients live in registers; neighbours cross lanes with shuffles and
-//    cross waves through LDS halo rows.  Each step is refined in float64: the residual
-//    of the step equation is formed in float64 with float64 coefficients, float32 PCG
-//    solves for a correction, the correction is added in float64 and the float64
-//    residual is updated, until it meets inner_rtol * (|w|_inf + tau |f|).
+//  * 2D, float32-refined: one work-group of up to 16 waves per system keeps the whole
+//    system on the CU.  The float32 Jacobi-PCG state (x, r, p, q) and the float32 scaled
+//    stencil coefficients live in registers; neighbours cross lanes with DPP shifts and
+//    cross waves through LDS halo rows.  Each step is solved for its increment and
+//    refined in float64: every pass forms the true residual of the step equation in
+//    float64 with float64 coefficients from the state and the increment, float32 PCG
+//    solves for a correction and the increment takes it in float64, until the residual
+//    meets inner_rtol * (|w|_inf + tau |f|) (plus the float64 rounding floor).
+//  * 2D, multigrid-preconditioned: one work-group per system streams float32 vectors and
+//    the V-cycle levels through device memory, for grids too large to stay on the CU.
 #include <cmath>
 
 #include "common.h"
@@ -167,7 +170,7 @@ __global__ __launch_bounds__(kStreamThreads) void fine2d_pcg64_kernel(
     int64_t M, int N, int skip_first, const uint8_t* __restrict__ active, int* __restrict__ flag,
     unsigned long long* __restrict__ cnt) {
   __shared__ double slots[3 * (kStreamThreads / 64)];
-  unsigned long long tot_it = 0, max_it = 0;
+  unsigned long long tot_it = 0, max_it = 0, missed = 0;
   const int64_t sys = blockIdx.x;
   const int64_t m = sys / N;
   const int s = (int)(sys % N);
@@ -236,7 +239,10 @@ __global__ __launch_bounds__(kStreamThreads) void fine2d_pcg64_kernel(
       __syncthreads();
       ++it;
     }
-    if (rmax > target && threadIdx.x == 0) atomicOr(flag, 1);
+    if (rmax > target) {
+      ++missed;
+      if (threadIdx.x == 0) atomicOr(flag, 1);
+    }
     tot_it += it;
     max_it = it > (int)max_it ? it : max_it;
     __syncthreads();
@@ -246,6 +252,7 @@ __global__ __launch_bounds__(kStreamThreads) void fine2d_pcg64_kernel(
     atomicAdd(&cnt[1], (unsigned long long)J);
     atomicAdd(&cnt[2], (unsigned long long)J);
     atomicMax(&cnt[3], max_it);
+    atomicAdd(&cnt[5], missed);
   }
 }
 
@@ -362,8 +369,7 @@ template <int NW, int CPL, int RPW>
 __global__ __launch_bounds__(64 * NW) void fine2d_resident_kernel(
     const double* __restrict__ a, const float* __restrict__ sf, const double* __restrict__ dinv,
     int n, double c, double tauf, int J, double tol, float pcg_rtol, int maxit, StartRef sr,
-    double* __restrict__ out, double* __restrict__ resbuf, double* __restrict__ incbuf, int64_t M, int N,
-    int skip_first, const uint8_t* __restrict__ active, int* __restrict__ flag,
+    double* __restrict__ out, double* __restrict__ incbuf, int64_t M, int N, int skip_first, const uint8_t* __restrict__ active, int* __restrict__ flag,
     unsigned long long* __restrict__ cnt) {
   using RS = Resident<NW, CPL, RPW>;
   const long long t_start = clock64();
@@ -373,7 +379,7 @@ __global__ __launch_bounds__(64 * NW) void fine2d_resident_kernel(
   __shared__ float hr_bot[NW * RS::ROWW], hp_bot[NW * RS::ROWW];
   __shared__ float fslots[2][NW];
   __shared__ double dslots[4 * NW];
-  unsigned long long tot_it = 0, tot_pass = 0, max_it = 0;
+  unsigned long long tot_it = 0, tot_pass = 0, max_it = 0, missed = 0;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int64_t sys = blockIdx.x;
@@ -388,7 +394,6 @@ __global__ __launch_bounds__(64 * NW) void fine2d_resident_kernel(
   const float* sfm = sf + m * Fc;
   const double* dv = dinv + m * Nx;
   double* w = out + sys * Nx;
-  double* res = resbuf + sys * Nx;
   double* inc = incbuf + sys * Nx;   // increment w_{j+1} - w_j of the current step
   const int j0 = wave * RPW;
   const int i0 = lane * CPL;
@@ -421,64 +426,57 @@ __global__ __launch_bounds__(64 * NW) void fine2d_resident_kernel(
   float X[RPW][CPL], R[RPW][CPL], P[RPW][CPL], Q[RPW][CPL];
   bool fail = false;
 
-  for (int step = 0; step < J; ++step) {
-    // Start from the previous step's increment: w_{j+1} - w_j = R (w_j - w_{j-1}) with
-    // R = (I + tau A)^{-1} for a constant source, so the starting residual is only
-    // tau A (w_j - w_{j-1}) (zero increment at the first step of a slice).
-    if (step > 0) {
-#pragma unroll 1
-      for (int k = 0; k < RPW * CPL; ++k) {
-        const int j = j0 + k / CPL, i = i0 + k % CPL;
-        if (j < n && i < n) {
-          const int64_t p = (int64_t)j * n + i;
-          w[p] += inc[p];
-        }
-      }
-      __syncthreads();   // the stencil below reads neighbours' w
-    }
-    // float64 residual of the step equation (I + tau A) w_{j+1} = w_j + tau f at the
-    // start w_j + inc:  tau f - tau A (w_j + inc) - inc
-    double acc[3] = {0.0, 0.0, 0.0};
+  // float64 residual of the step equation (I + tau A) w_{j+1} = w_j + tau f at
+  // w_j + inc:  tau f - tau A (w_j + inc) - inc, for the nodes this thread owns; it also
+  // writes the unnormalised float32 right-hand side D^{-1/2} r of the next pass to xs.
+  // acc: max |r|, max |w_j + inc|, max D^{-1/2} |r| over the work-group.
+  auto residual = [&](double (&acc)[3]) {
+    acc[0] = acc[1] = acc[2] = 0.0;
     const bool mx[3] = {true, true, true};
 #pragma unroll 1
     for (int k = 0; k < RPW * CPL; ++k) {
       const int j = j0 + k / CPL, i = i0 + k % CPL;
       if (j < n && i < n) {
-        int64_t p = (int64_t)j * n + i;
-        double rv = tauf - c * stencil64(af, w, g, i, j) - inc[p];
-        res[p] = rv;
-        xs[p] = (float)(dv[p] * rv);   // the first pass's right-hand side, unnormalised
+        const int64_t p = (int64_t)j * n + i;
+        // neighbour differences of w and of inc taken separately: forming w + inc first
+        // would round at the scale of |w| before the stencil amplifies it
+        const double wp = w[p], ip = inc[p];
+        const double dW = (wp - (i > 0 ? w[p - 1] : 0.0)) + (ip - (i > 0 ? inc[p - 1] : 0.0));
+        const double dE = (wp - (i < n - 1 ? w[p + 1] : 0.0)) + (ip - (i < n - 1 ? inc[p + 1] : 0.0));
+        const double dS = (wp - (j > 0 ? w[p - n] : 0.0)) + (ip - (j > 0 ? inc[p - n] : 0.0));
+        const double dN = (wp - (j < n - 1 ? w[p + n] : 0.0)) + (ip - (j < n - 1 ? inc[p + n] : 0.0));
+        const double au = af[g.fW(i, j)] * dW + af[g.fE(i, j)] * dE + af[g.fS(i, j)] * dS + af[g.fN(i, j)] * dN;
+        const double up = wp + ip;
+        const double rv = tauf - c * au - ip;
+        xs[p] = (float)(dv[p] * rv);
         acc[0] = nanmax(acc[0], fabs(rv));
-        acc[1] = nanmax(acc[1], fabs(w[p]));
+        acc[1] = nanmax(acc[1], fabs(up));
         acc[2] = nanmax(acc[2], dv[p] * fabs(rv));
       }
     }
     block_reduce<3>(acc, mx, dslots);
+  };
+
+  for (int step = 0; step < J; ++step) {
+    // The step is solved for its increment inc = w_{j+1} - w_j, starting from the previous
+    // step's increment: w_{j+1} - w_j = R (w_j - w_{j-1}) with R = (I + tau A)^{-1} for a
+    // constant source, so the starting residual is only tau A (w_j - w_{j-1}) (zero
+    // increment at the first step of a slice).  Each pass recomputes the true float64
+    // residual from w_j and inc; only inc changes during the step.
+    double acc[3];
+    residual(acc);
     double rmax = acc[0];
-    // float32 right-hand sides are normalised by their max (no underflow late in the passes)
-    double sig = acc[2];
-    const double target = residual_target(tol, acc[1], tauf, dmax);
+    double sig = acc[2];   // float32 right-hand sides are normalised by their max
+    // The rounding allowance scales with the largest |w_j + inc| the step has reached: a
+    // slice that starts from a zero state has none at its first sweep, while the
+    // recomputed residual of the grown increment cannot fall below its float64 floor.
+    double wref = acc[1];
+    double target = residual_target(tol, wref, tauf, dmax);
     int pass = 0;
     while (rmax > target && sig > 0.0 && pass < kMaxRefinePasses) {
-      // scaled right-hand side D^{-1/2} res / sig, staged through LDS.  The first pass
-      // takes the tile the residual sweep wrote (scale 1): a fresh step's residual is far
-      // from the float32 range limits.  Later passes normalise by sig, since their
-      // residuals shrink towards the float64 floor and their squares would underflow.
-      const bool prestaged = pass == 0 && sig > 1e-18 && sig < 1e18;
-      if (prestaged) {
-        sig = 1.0;
-      } else {
-        const double isig = 1.0 / sig;
-#pragma unroll 1
-        for (int k = 0; k < RPW * CPL; ++k) {
-          const int j = j0 + k / CPL, i = i0 + k % CPL;
-          if (j < n && i < n) {
-            int64_t p = (int64_t)j * n + i;
-            xs[p] = (float)(isig * dv[p] * res[p]);
-          }
-        }
-        __syncthreads();
-      }
+      // the owner's right-hand side: the residual sweep's tile scaled by 1/sig (late
+      // residuals shrink towards the float64 floor and their squares would underflow)
+      const float fis = (float)(1.0 / sig);
       float rr = 0.f;
 #pragma unroll
       for (int r = 0; r < RPW; ++r) {
@@ -486,7 +484,7 @@ __global__ __launch_bounds__(64 * NW) void fine2d_resident_kernel(
 #pragma unroll
         for (int t = 0; t < CPL; ++t) {
           int i = i0 + t;
-          float v = (j < n && i < n) ? xs[j * n + i] : 0.f;
+          float v = (j < n && i < n) ? xs[j * n + i] * fis : 0.f;
           R[r][t] = v;
           P[r][t] = v;
           X[r][t] = 0.f;
@@ -526,8 +524,8 @@ __global__ __launch_bounds__(64 * NW) void fine2d_resident_kernel(
       if (it >= maxit && rr > stop) fail = true;
       tot_it += it;
       max_it = it > (int)max_it ? it : max_it;
-      // float64 update with the correction e = D^{-1/2} X:  res -= M e,  w += e
-      __syncthreads();   // every wave is done reading xs as the right-hand side
+      // correction of the owned nodes: inc += sig D^{-1/2} X (through the thread's own xs
+      // entries, so the float64 loop needs no register copy of X)
 #pragma unroll
       for (int r = 0; r < RPW; ++r) {
         int j = j0 + r;
@@ -537,37 +535,37 @@ __global__ __launch_bounds__(64 * NW) void fine2d_resident_kernel(
           if (j < n && i < n) xs[j * n + i] = X[r][t];
         }
       }
-      __syncthreads();
-      double emax[2] = {0.0, 0.0};
-      const bool mx1[2] = {true, true};
-      const double sdv = sig;
 #pragma unroll 1
       for (int k = 0; k < RPW * CPL; ++k) {
         const int j = j0 + k / CPL, i = i0 + k % CPL;
         if (j < n && i < n) {
-          int64_t p = (int64_t)j * n + i;
-          double ep = sdv * dv[p] * (double)xs[p];
-          double ew = i > 0 ? sdv * dv[p - 1] * (double)xs[p - 1] : 0.0;
-          double ee = i < n - 1 ? sdv * dv[p + 1] * (double)xs[p + 1] : 0.0;
-          double es = j > 0 ? sdv * dv[p - n] * (double)xs[p - n] : 0.0;
-          double en = j < n - 1 ? sdv * dv[p + n] * (double)xs[p + n] : 0.0;
-          double Me = ep + c * (af[g.fW(i, j)] * (ep - ew) + af[g.fE(i, j)] * (ep - ee) +
-                                af[g.fS(i, j)] * (ep - es) + af[g.fN(i, j)] * (ep - en));
-          double rv = res[p] - Me;
-          res[p] = rv;
-          w[p] += ep;
-          inc[p] += ep;
-          emax[0] = nanmax(emax[0], fabs(rv));
-          emax[1] = nanmax(emax[1], dv[p] * fabs(rv));
+          const int64_t p = (int64_t)j * n + i;
+          inc[p] += sig * dv[p] * (double)xs[p];
         }
       }
-      block_reduce<2>(emax, mx1, dslots);
-      rmax = emax[0];
-      sig = emax[1];
+      __syncthreads();   // the residual sweep reads neighbours' inc
+      residual(acc);
+      rmax = acc[0];
+      sig = acc[2];
+      wref = fmax(wref, acc[1]);
+      target = residual_target(tol, wref, tauf, dmax);
       ++pass;
     }
     tot_pass += pass;
-    if (rmax > target) fail = true;
+    if (rmax > target) {
+      fail = true;
+      ++missed;
+    }
+    // w_{j+1} = w_j + inc
+#pragma unroll 1
+    for (int k = 0; k < RPW * CPL; ++k) {
+      const int j = j0 + k / CPL, i = i0 + k % CPL;
+      if (j < n && i < n) {
+        const int64_t p = (int64_t)j * n + i;
+        w[p] += inc[p];
+      }
+    }
+    __syncthreads();   // the next residual sweep reads neighbours' w
   }
   if (threadIdx.x == 0) {
     if (fail) atomicOr(flag, 1);
@@ -575,6 +573,7 @@ __global__ __launch_bounds__(64 * NW) void fine2d_resident_kernel(
     atomicAdd(&cnt[1], tot_pass);
     atomicAdd(&cnt[2], (unsigned long long)J);
     atomicMax(&cnt[3], max_it);
+    atomicAdd(&cnt[5], missed);
     atomicAdd(&cnt[8], (unsigned long long)(clock64() - t_start));
     atomicAdd(&cnt[9], (unsigned long long)t_cg);
   }
@@ -600,7 +599,7 @@ __global__ __launch_bounds__(64 * NW, WPE) void fine2d_mg_kernel(
   __shared__ double dslots[4 * NW];
   const long long t_start = clock64();
   long long t_cg = 0;
-  unsigned long long tot_it = 0, tot_pass = 0, max_it = 0;
+  unsigned long long tot_it = 0, tot_pass = 0, max_it = 0, missed = 0;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int64_t sys = sys0 + blockIdx.x;
@@ -758,7 +757,10 @@ __global__ __launch_bounds__(64 * NW, WPE) void fine2d_mg_kernel(
       ++pass;
     }
     tot_pass += pass;
-    if (rmax > target) fail = true;
+    if (rmax > target) {
+      fail = true;
+      ++missed;
+    }
   }
   if (threadIdx.x == 0) {
     if (fail) atomicOr(flag, 1);
@@ -766,6 +768,7 @@ __global__ __launch_bounds__(64 * NW, WPE) void fine2d_mg_kernel(
     atomicAdd(&cnt[1], tot_pass);
     atomicAdd(&cnt[2], (unsigned long long)J);
     atomicMax(&cnt[3], max_it);
+    atomicAdd(&cnt[5], missed);
     atomicAdd(&cnt[8], (unsigned long long)(clock64() - t_start));
     atomicAdd(&cnt[9], (unsigned long long)t_cg);
   }
@@ -774,12 +777,11 @@ __global__ __launch_bounds__(64 * NW, WPE) void fine2d_mg_kernel(
 template <int NW, int CPL, int RPW>
 void launch_resident(hipStream_t st, int64_t nsys, const double* a, const float* sf,
                      const double* dinv, int n, double c, double tauf, int J, double tol,
-                     float pcg_rtol, int maxit, StartRef sr, double* out, double* resbuf,
-                     double* incbuf, int64_t M, int N, int skip_first, const uint8_t* active, int* flag,
-                     unsigned long long* cnt) {
+                     float pcg_rtol, int maxit, StartRef sr, double* out, double* incbuf, int64_t M, int N,
+                     int skip_first, const uint8_t* active, int* flag, unsigned long long* cnt) {
   size_t lds = sizeof(float) * (size_t)n * n;
   fine2d_resident_kernel<NW, CPL, RPW><<<dim3((unsigned)nsys), dim3(64 * NW), lds, st>>>(
-      a, sf, dinv, n, c, tauf, J, tol, pcg_rtol, maxit, sr, out, resbuf, incbuf, M, N, skip_first, active,
+      a, sf, dinv, n, c, tauf, J, tol, pcg_rtol, maxit, sr, out, incbuf, M, N, skip_first, active,
       flag, cnt);
   KC_LAUNCH_CHECK();
 }
@@ -838,7 +840,6 @@ int propagate_impl(klecgc_ctx* ctx, const klecgc_problem& p, const FineArgs& fa,
   const bool scaled = variant != KC_FINE_STREAM64;
   float* sf = scaled ? (float*)ctx->ws.get(WS_FSCALED, sizeof(float) * Fc * M) : nullptr;
   build_tables_2d(st, fa.a, n, c, M, dinv, sf);
-  double* resbuf = resident ? (double*)ctx->ws.get(WS_KRYLOV, sizeof(double) * Nx * nsys) : nullptr;
   double* incbuf = resident ? (double*)ctx->ws.get(WS_FINE_INC, sizeof(double) * Nx * nsys) : nullptr;
   double* scr = variant == KC_FINE_STREAM64 ? (double*)ctx->ws.get(WS_KRYLOV, sizeof(double) * 3 * Nx * nsys)
                                             : nullptr;
@@ -846,20 +847,20 @@ int propagate_impl(klecgc_ctx* ctx, const klecgc_problem& p, const FineArgs& fa,
   timed(ctx, KT_FINE, [&] {
     switch (variant) {
       case KC_FINE_RES16:
-        launch_resident<8, 1, 2>(st, nsys, fa.a, sf, dinv, n, c, tauf, J, tol, pcg_rtol, maxit, sr, fa.out, resbuf, incbuf,
+        launch_resident<8, 1, 2>(st, nsys, fa.a, sf, dinv, n, c, tauf, J, tol, pcg_rtol, maxit, sr, fa.out, incbuf,
                                  M, N, fa.skip_first, fa.active, flag, cnt);
         break;
       case KC_FINE_RES32:
-        launch_resident<8, 1, 4>(st, nsys, fa.a, sf, dinv, n, c, tauf, J, tol, pcg_rtol, maxit, sr, fa.out, resbuf, incbuf,
+        launch_resident<8, 1, 4>(st, nsys, fa.a, sf, dinv, n, c, tauf, J, tol, pcg_rtol, maxit, sr, fa.out, incbuf,
                                  M, N, fa.skip_first, fa.active, flag, cnt);
         break;
       case KC_FINE_RES64:
-        launch_resident<8, 1, 8>(st, nsys, fa.a, sf, dinv, n, c, tauf, J, tol, pcg_rtol, maxit, sr, fa.out, resbuf, incbuf,
+        launch_resident<8, 1, 8>(st, nsys, fa.a, sf, dinv, n, c, tauf, J, tol, pcg_rtol, maxit, sr, fa.out, incbuf,
                                  M, N, fa.skip_first, fa.active, flag, cnt);
         break;
       case KC_FINE_RES128:
         launch_resident<KC_RES128_NW, 2, 128 / KC_RES128_NW>(st, nsys, fa.a, sf, dinv, n, c, tauf, J, tol, pcg_rtol,
-                                                             maxit, sr, fa.out, resbuf, incbuf, M, N, fa.skip_first,
+                                                             maxit, sr, fa.out, incbuf, M, N, fa.skip_first,
                                                              fa.active, flag, cnt);
         break;
       case KC_FINE_MG: {
