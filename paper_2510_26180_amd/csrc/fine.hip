@@ -269,30 +269,39 @@ __device__ __forceinline__ float dppf(float v) {
 __device__ __forceinline__ float from_west(float v) { return dppf<0x138>(v); }   // wave_shr:1
 __device__ __forceinline__ float from_east(float v) { return dppf<0x130>(v); }   // wave_shl:1
 
-// Sum over the 64 lanes, uniform result: butterflies within 16-lane rows by DPP, then
-// the four row sums read into scalar registers.
-__device__ __forceinline__ float wave_sum_dpp(float v) {
+// Butterfly sum within each 16-lane row by DPP: every lane of a row ends with the row's
+// sum (the same bits in all 16 lanes, since each step adds two equal partial sums).
+__device__ __forceinline__ float row_sum_dpp(float v) {
   v += dppf<0xB1>(v);    // quad_perm [1,0,3,2]
   v += dppf<0x4E>(v);    // quad_perm [2,3,0,1]
   v += dppf<0x141>(v);   // row_half_mirror
   v += dppf<0x140>(v);   // row_mirror
-  const int iv = __builtin_bit_cast(int, v);
-  const float s0 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(iv, 0));
-  const float s1 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(iv, 16));
-  const float s2 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(iv, 32));
-  const float s3 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(iv, 48));
-  return (s0 + s1) + (s2 + s3);
+  return v;
 }
 
+// DPP move restricted to the rows in ROWMASK; other lanes read 0.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ float dppf_rows(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, ROWMASK, 0xf, false));
+}
+
+// Sum over the work-group of NW <= 16 waves, uniform result.  Each wave reduces its four
+// 16-lane rows and writes the four row sums; after the barrier lane l of every wave
+// reads row sum l, the rows reduce again, and two row broadcasts (row 0 into row 1,
+// rows 0..1 into rows 2..3) collect the total in lane 63.  slots: 4 NW floats.  One
+// barrier: consecutive sums must alternate between two slot arrays unless another
+// barrier separates them.
 template <int NW>
 __device__ __forceinline__ float block_sum_f(float v, float* slots, int lane, int wave) {
-  v = wave_sum_dpp(v);
-  if (lane == 0) slots[wave] = v;
+  static_assert(NW <= 16, "one row sum per lane");
+  v = row_sum_dpp(v);
+  if ((lane & 15) == 0) slots[wave * 4 + (lane >> 4)] = v;
   __syncthreads();
-  float acc = slots[0];
-#pragma unroll
-  for (int w = 1; w < NW; ++w) acc += slots[w];
-  return acc;
+  float acc = lane < 4 * NW ? slots[lane] : 0.f;
+  acc = row_sum_dpp(acc);
+  acc += dppf_rows<0x142, 0xa>(acc);   // row_bcast:15 into rows 1 and 3
+  acc += dppf_rows<0x143, 0xc>(acc);   // row_bcast:31 into rows 2 and 3
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, acc), 63));
 }
 
 template <int NW, int CPL, int RPW>
@@ -300,8 +309,9 @@ struct Resident {
   static constexpr int ROWW = 64 * CPL;   // halo row width per wave
 
   // Q = P - sum_f s_f P_nbr (scaled operator with unit diagonal); returns the lane's P.Q.
-  // EW[s][t] is the coefficient of the face west of column t, NS[s][t] that of the face
-  // south of row s.  The faces east of the lane's last column and north of the wave's
+  // EW[s][t] is the negated coefficient -s_f of the face west of column t, NS[s][t] that
+  // of the face south of row s (stored negated so each neighbour term is one
+  // multiply-add whose lane-shifted operand can ride on the instruction as DPP).  The faces east of the lane's last column and north of the wave's
   // last row belong to the neighbouring lane / wave, which supplies the products
   // coefficient * value: across lanes by a DPP shift, across waves through LDS halos.
   // The halos hold the previous iteration's r and p rows; the current p row is
@@ -319,13 +329,11 @@ struct Resident {
       const float ep = from_east(EW[s][0] * P[s][0]);
 #pragma unroll
       for (int t = 0; t < CPL; ++t) {
-        const float left = (t == 0) ? wv : P[s][t - 1];
+        // terms within the lane first; the lane-shifted ones last, where they feed an
+        // accumulating multiply-add / add that can take them as a DPP operand
         float q = P[s][t];
-        q = fmaf(-EW[s][t], left, q);
-        if (t == CPL - 1)
-          q -= ep;
-        else
-          q = fmaf(-EW[s][t + 1], P[s][t + 1], q);
+        if (t > 0) q = fmaf(EW[s][t], P[s][t - 1], q);
+        if (t < CPL - 1) q = fmaf(EW[s][t + 1], P[s][t + 1], q);
         float down;
         if (s == 0) {
           const int h = (wave - 1) * ROWW + lane * CPL + t;
@@ -333,13 +341,15 @@ struct Resident {
         } else {
           down = P[s - 1][t];
         }
-        q = fmaf(-NS[s][t], down, q);
+        q = fmaf(NS[s][t], down, q);
         if (s == RPW - 1) {
           const int h = (wave + 1) * ROWW + lane * CPL + t;
-          q -= (wave < NW - 1) ? fmaf(beta, hp_top[h], hr_top[h]) : 0.f;
+          q += (wave < NW - 1) ? fmaf(beta, hp_top[h], hr_top[h]) : 0.f;
         } else {
-          q = fmaf(-NS[s + 1][t], P[s + 1][t], q);
+          q = fmaf(NS[s + 1][t], P[s + 1][t], q);
         }
+        if (t == 0) q = fmaf(EW[s][0], wv, q);
+        if (t == CPL - 1) q += ep;
         Q[s][t] = q;
         pq = fmaf(P[s][t], q, pq);
       }
@@ -347,8 +357,8 @@ struct Resident {
     return pq;
   }
 
-  // top: south-face coefficient times the row-0 value (the wave below the boundary
-  // needs it as its northern term); bot: the last row's values.
+  // top: negated south-face coefficient times the row-0 value (the wave below the
+  // boundary needs it as its northern term); bot: the last row's values.
   static __device__ __forceinline__ void store_halo(const float (&Rv)[RPW][CPL], const float (&Pv)[RPW][CPL],
                                                     const float (&NS)[RPW][CPL], float* hr_top,
                                                     float* hp_top, float* hr_bot, float* hp_bot,
@@ -377,7 +387,7 @@ __global__ __launch_bounds__(64 * NW) void fine2d_resident_kernel(
   extern __shared__ float xs[];                       // [n*n]
   __shared__ float hr_top[NW * RS::ROWW], hp_top[NW * RS::ROWW];
   __shared__ float hr_bot[NW * RS::ROWW], hp_bot[NW * RS::ROWW];
-  __shared__ float fslots[2][NW];
+  __shared__ float fslots[2][4 * NW];
   __shared__ double dslots[4 * NW];
   unsigned long long tot_it = 0, tot_pass = 0, max_it = 0, missed = 0;
   const int lane = threadIdx.x & 63;
@@ -398,7 +408,7 @@ __global__ __launch_bounds__(64 * NW) void fine2d_resident_kernel(
   const int j0 = wave * RPW;
   const int i0 = lane * CPL;
 
-  // scaled coefficients into registers (0 on boundary faces and outside the grid)
+  // negated scaled coefficients into registers (0 on boundary faces and outside the grid)
   float EW[RPW][CPL];
   float NS[RPW][CPL];
 #pragma unroll
@@ -407,8 +417,8 @@ __global__ __launch_bounds__(64 * NW) void fine2d_resident_kernel(
 #pragma unroll
     for (int t = 0; t < CPL; ++t) {
       int col = i0 + t;
-      EW[r][t] = (j < n && col >= 1 && col <= n - 1) ? sfm[(int64_t)j * (n + 1) + col] : 0.f;
-      NS[r][t] = (col < n && j >= 1 && j <= n - 1) ? sfm[g.nx + (int64_t)j * n + col] : 0.f;
+      EW[r][t] = (j < n && col >= 1 && col <= n - 1) ? -sfm[(int64_t)j * (n + 1) + col] : 0.f;
+      NS[r][t] = (col < n && j >= 1 && j <= n - 1) ? -sfm[g.nx + (int64_t)j * n + col] : 0.f;
     }
   }
 
@@ -500,7 +510,9 @@ __global__ __launch_bounds__(64 * NW) void fine2d_resident_kernel(
       while (rr > stop && it < maxit) {
         float pq = RS::matvec(P, Q, EW, NS, hr_top, hp_top, hr_bot, hp_bot, beta, lane, wave);
         pq = block_sum_f<NW>(pq, fslots[0], lane, wave);
-        const float alpha = rr / pq;
+        // CG scalars through the hardware reciprocal (about 1 ulp): an IEEE division
+        // costs some ten instructions per iteration of an issue-bound loop
+        const float alpha = rr * __builtin_amdgcn_rcpf(pq);
         float rn = 0.f;
 #pragma unroll
         for (int r = 0; r < RPW; ++r)
@@ -512,7 +524,7 @@ __global__ __launch_bounds__(64 * NW) void fine2d_resident_kernel(
           }
         RS::store_halo(R, P, NS, hr_top, hp_top, hr_bot, hp_bot, lane, wave);
         rn = block_sum_f<NW>(rn, fslots[1], lane, wave);
-        beta = rn / rr;
+        beta = rn * __builtin_amdgcn_rcpf(rr);
         rr = rn;
 #pragma unroll
         for (int r = 0; r < RPW; ++r)
@@ -595,7 +607,7 @@ __global__ __launch_bounds__(64 * NW, WPE) void fine2d_mg_kernel(
     double* __restrict__ resbuf, double* __restrict__ incbuf, float* __restrict__ scr, MgLevels h, int64_t sys0,
     int64_t M, int N, int skip_first, const uint8_t* __restrict__ active, int* __restrict__ flag,
     unsigned long long* __restrict__ cnt) {
-  __shared__ float fslots[2][NW];
+  __shared__ float fslots[2][4 * NW];
   __shared__ double dslots[4 * NW];
   const long long t_start = clock64();
   long long t_cg = 0;
