@@ -269,6 +269,20 @@ __device__ __forceinline__ float dppf(float v) {
 __device__ __forceinline__ float from_west(float v) { return dppf<0x138>(v); }   // wave_shr:1
 __device__ __forceinline__ float from_east(float v) { return dppf<0x130>(v); }   // wave_shl:1
 
+// float64 lane shift (both halves moved by DPP; the shifted-in lane reads 0.0)
+template <int CTRL>
+__device__ __forceinline__ double dppd(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, true);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+__device__ __forceinline__ double2 ld2(const double* p) { return *reinterpret_cast<const double2*>(p); }
+__device__ __forceinline__ void st2(double* p, double x, double y) {
+  *reinterpret_cast<double2*>(p) = make_double2(x, y);
+}
+
 // Butterfly sum within each 16-lane row by DPP: every lane of a row ends with the row's
 // sum (the same bits in all 16 lanes, since each step adds two equal partial sums).
 __device__ __forceinline__ float row_sum_dpp(float v) {
@@ -374,7 +388,8 @@ struct Resident {
   }
 };
 
-// LDS: xs[n*n] float32 staging tile of the whole system, halo rows, reduction slots.
+// LDS: xs[n*n + 2] float32 staging tile of the whole system (+ a spare word pair for lanes
+// outside the grid), halo rows, reduction slots.
 template <int NW, int CPL, int RPW>
 __global__ __launch_bounds__(64 * NW) void fine2d_resident_kernel(
     const double* __restrict__ a, const float* __restrict__ sf, const double* __restrict__ dinv,
@@ -384,7 +399,7 @@ __global__ __launch_bounds__(64 * NW) void fine2d_resident_kernel(
   using RS = Resident<NW, CPL, RPW>;
   const long long t_start = clock64();
   long long t_cg = 0;
-  extern __shared__ float xs[];                       // [n*n]
+  extern __shared__ float xs[];                       // [n*n + 2]
   __shared__ float hr_top[NW * RS::ROWW], hp_top[NW * RS::ROWW];
   __shared__ float hr_bot[NW * RS::ROWW], hp_bot[NW * RS::ROWW];
   __shared__ float fslots[2][4 * NW];
@@ -435,6 +450,13 @@ __global__ __launch_bounds__(64 * NW) void fine2d_resident_kernel(
 
   float X[RPW][CPL], R[RPW][CPL], P[RPW][CPL], Q[RPW][CPL];
   bool fail = false;
+  // owned nodes per group of the float64 loops (residual sweep; increment / state updates)
+  constexpr int KG = RPW * CPL < 4 ? RPW * CPL : 4;
+  constexpr int KU = RPW * CPL < 8 ? RPW * CPL : 8;
+  // column pairs per lane, 16-byte aligned in every row (even n)
+  const bool pairs = CPL == 2 && (n & 1) == 0;
+  constexpr int KR = 4;   // rows per group of the paired update loops
+  static_assert((RPW * CPL) % KG == 0 && (RPW * CPL) % KU == 0, "whole groups");
 
   // float64 residual of the step equation (I + tau A) w_{j+1} = w_j + tau f at
   // w_j + inc:  tau f - tau A (w_j + inc) - inc, for the nodes this thread owns; it also
@@ -443,26 +465,91 @@ __global__ __launch_bounds__(64 * NW) void fine2d_resident_kernel(
   auto residual = [&](double (&acc)[3]) {
     acc[0] = acc[1] = acc[2] = 0.0;
     const bool mx[3] = {true, true, true};
+    if (pairs) {
+      // A lane's two columns (i0, i0 + 1) together: 16-byte loads of w, inc, D^{-1/2} and
+      // the y-faces use every byte of the cache lines a wave touches (two 8-byte loads
+      // with a 16-byte lane stride would each touch twice the lines for half the data);
+      // the west / east neighbour columns come from the adjacent lanes by DPP.
+      const bool hw0 = i0 > 0, he1 = i0 + 1 < n - 1;
 #pragma unroll 1
-    for (int k = 0; k < RPW * CPL; ++k) {
-      const int j = j0 + k / CPL, i = i0 + k % CPL;
-      if (j < n && i < n) {
-        const int64_t p = (int64_t)j * n + i;
+      for (int r = 0; r < RPW; ++r) {
+        const int j = j0 + r;
+        const bool ok = j < n && i0 < n;
+        const int ic = ok ? i0 : 0, jc = ok ? j : 0;   // clamped: every load in bounds
+        const int64_t p = (int64_t)jc * n + ic;
+        const bool hs = jc > 0, hn = jc < n - 1;
+        const int64_t ps = hs ? p - n : p, pn = hn ? p + n : p;
+        const double2 W = ld2(w + p), I = ld2(inc + p);
+        const double2 WS = ld2(w + ps), IS = ld2(inc + ps), WN = ld2(w + pn), IN = ld2(inc + pn);
+        const double2 D = ld2(dv + p);
+        const double2 FS = ld2(af + g.fS(ic, jc)), FN = ld2(af + g.fN(ic, jc));
+        const int64_t fx = g.fW(ic, jc);
+        const double a0 = af[fx], a1 = af[fx + 1], a2 = af[fx + 2];
+        const double wW = dppd<0x138>(W.y), iW = dppd<0x138>(I.y);   // column i0 - 1
+        const double wE = dppd<0x130>(W.x), iE = dppd<0x130>(I.x);   // column i0 + 2
+        const double dW0 = (W.x - (hw0 ? wW : 0.0)) + (I.x - (hw0 ? iW : 0.0));
+        const double dE0 = (W.x - W.y) + (I.x - I.y);
+        const double dS0 = (W.x - (hs ? WS.x : 0.0)) + (I.x - (hs ? IS.x : 0.0));
+        const double dN0 = (W.x - (hn ? WN.x : 0.0)) + (I.x - (hn ? IN.x : 0.0));
+        const double dW1 = (W.y - W.x) + (I.y - I.x);
+        const double dE1 = (W.y - (he1 ? wE : 0.0)) + (I.y - (he1 ? iE : 0.0));
+        const double dS1 = (W.y - (hs ? WS.y : 0.0)) + (I.y - (hs ? IS.y : 0.0));
+        const double dN1 = (W.y - (hn ? WN.y : 0.0)) + (I.y - (hn ? IN.y : 0.0));
+        const double au0 = a0 * dW0 + a1 * dE0 + FS.x * dS0 + FN.x * dN0;
+        const double au1 = a1 * dW1 + a2 * dE1 + FS.y * dS1 + FN.y * dN1;
+        const double rv0 = tauf - c * au0 - I.x, rv1 = tauf - c * au1 - I.y;
+        // invalid lanes write the spare word pair after the n^2 tile
+        *reinterpret_cast<float2*>(xs + (ok ? j * n + i0 : n * n)) =
+            make_float2((float)(D.x * rv0), (float)(D.y * rv1));
+        if (ok) {
+          acc[0] = nanmax(acc[0], nanmax(fabs(rv0), fabs(rv1)));
+          acc[1] = nanmax(acc[1], nanmax(fabs(W.x + I.x), fabs(W.y + I.y)));
+          acc[2] = nanmax(acc[2], nanmax(D.x * fabs(rv0), D.y * fabs(rv1)));
+        }
+      }
+      block_reduce<3>(acc, mx, dslots);
+      return;
+    }
+#pragma unroll 1
+    for (int k0 = 0; k0 < RPW * CPL; k0 += KG) {
+      float rhs[KG];
+      int64_t pp[KG];
+      bool okk[KG];
+#pragma unroll
+      for (int u = 0; u < KG; ++u) {
+        const int k = k0 + u;
+        const int j = j0 + k / CPL, i = i0 + k % CPL;
+        const bool ok = j < n && i < n;
+        // clamped indices keep every load in bounds without a branch, so a group's loads
+        // are in flight together; neighbours outside the grid are selected away (0)
+        const int ic = ok ? i : 0, jc = ok ? j : 0;
+        const int64_t p = (int64_t)jc * n + ic;
+        const bool hw = ic > 0, he = ic < n - 1, hs = jc > 0, hn = jc < n - 1;
+        const int64_t pw = hw ? p - 1 : p, pe = he ? p + 1 : p;
+        const int64_t ps = hs ? p - n : p, pn = hn ? p + n : p;
+        const double wp = w[p], ip = inc[p];
+        const double ww = w[pw], iw = inc[pw], we = w[pe], ie = inc[pe];
+        const double wsv = w[ps], isv = inc[ps], wnv = w[pn], inv = inc[pn];
         // neighbour differences of w and of inc taken separately: forming w + inc first
         // would round at the scale of |w| before the stencil amplifies it
-        const double wp = w[p], ip = inc[p];
-        const double dW = (wp - (i > 0 ? w[p - 1] : 0.0)) + (ip - (i > 0 ? inc[p - 1] : 0.0));
-        const double dE = (wp - (i < n - 1 ? w[p + 1] : 0.0)) + (ip - (i < n - 1 ? inc[p + 1] : 0.0));
-        const double dS = (wp - (j > 0 ? w[p - n] : 0.0)) + (ip - (j > 0 ? inc[p - n] : 0.0));
-        const double dN = (wp - (j < n - 1 ? w[p + n] : 0.0)) + (ip - (j < n - 1 ? inc[p + n] : 0.0));
-        const double au = af[g.fW(i, j)] * dW + af[g.fE(i, j)] * dE + af[g.fS(i, j)] * dS + af[g.fN(i, j)] * dN;
-        const double up = wp + ip;
+        const double dW = (wp - (hw ? ww : 0.0)) + (ip - (hw ? iw : 0.0));
+        const double dE = (wp - (he ? we : 0.0)) + (ip - (he ? ie : 0.0));
+        const double dS = (wp - (hs ? wsv : 0.0)) + (ip - (hs ? isv : 0.0));
+        const double dN = (wp - (hn ? wnv : 0.0)) + (ip - (hn ? inv : 0.0));
+        const double au = af[g.fW(ic, jc)] * dW + af[g.fE(ic, jc)] * dE + af[g.fS(ic, jc)] * dS +
+                          af[g.fN(ic, jc)] * dN;
         const double rv = tauf - c * au - ip;
-        xs[p] = (float)(dv[p] * rv);
-        acc[0] = nanmax(acc[0], fabs(rv));
-        acc[1] = nanmax(acc[1], fabs(up));
-        acc[2] = nanmax(acc[2], dv[p] * fabs(rv));
+        const double dp = dv[p];
+        rhs[u] = (float)(dp * rv);
+        pp[u] = p;
+        okk[u] = ok;
+        acc[0] = ok ? nanmax(acc[0], fabs(rv)) : acc[0];
+        acc[1] = ok ? nanmax(acc[1], fabs(wp + ip)) : acc[1];
+        acc[2] = ok ? nanmax(acc[2], dp * fabs(rv)) : acc[2];
       }
+#pragma unroll
+      for (int u = 0; u < KG; ++u)
+        if (okk[u]) xs[pp[u]] = rhs[u];
     }
     block_reduce<3>(acc, mx, dslots);
   };
@@ -547,13 +634,47 @@ __global__ __launch_bounds__(64 * NW) void fine2d_resident_kernel(
           if (j < n && i < n) xs[j * n + i] = X[r][t];
         }
       }
+      if (pairs) {
 #pragma unroll 1
-      for (int k = 0; k < RPW * CPL; ++k) {
-        const int j = j0 + k / CPL, i = i0 + k % CPL;
-        if (j < n && i < n) {
-          const int64_t p = (int64_t)j * n + i;
-          inc[p] += sig * dv[p] * (double)xs[p];
+        for (int r0 = 0; r0 < RPW; r0 += KR) {   // KR rows' loads in flight, then the stores
+          double2 I[KR], D[KR];
+          float2 Xv[KR];
+#pragma unroll
+          for (int u = 0; u < KR && r0 + u < RPW; ++u) {
+            const int j = j0 + r0 + u;
+            const bool ok = j < n && i0 < n;
+            const int64_t p = ok ? (int64_t)j * n + i0 : 0;
+            I[u] = ld2(inc + p);
+            D[u] = ld2(dv + p);
+            Xv[u] = *reinterpret_cast<const float2*>(xs + (ok ? j * n + i0 : n * n));
+          }
+#pragma unroll
+          for (int u = 0; u < KR && r0 + u < RPW; ++u) {
+            const int j = j0 + r0 + u;
+            if (j < n && i0 < n)
+              st2(inc + (int64_t)j * n + i0, I[u].x + sig * D[u].x * (double)Xv[u].x,
+                  I[u].y + sig * D[u].y * (double)Xv[u].y);
+          }
         }
+      } else
+#pragma unroll 1
+      for (int k0 = 0; k0 < RPW * CPL; k0 += KU) {
+        double v[KU];
+        int64_t pp[KU];
+        bool okk[KU];
+#pragma unroll
+        for (int u = 0; u < KU; ++u) {   // branch-free loads (clamped), guarded stores
+          const int k = k0 + u;
+          const int j = j0 + k / CPL, i = i0 + k % CPL;
+          const bool ok = j < n && i < n;
+          const int64_t p = ok ? (int64_t)j * n + i : 0;
+          v[u] = inc[p] + sig * dv[p] * (double)xs[p];
+          pp[u] = p;
+          okk[u] = ok;
+        }
+#pragma unroll
+        for (int u = 0; u < KU; ++u)
+          if (okk[u]) inc[pp[u]] = v[u];
       }
       __syncthreads();   // the residual sweep reads neighbours' inc
       residual(acc);
@@ -569,13 +690,42 @@ __global__ __launch_bounds__(64 * NW) void fine2d_resident_kernel(
       ++missed;
     }
     // w_{j+1} = w_j + inc
+    if (pairs) {
 #pragma unroll 1
-    for (int k = 0; k < RPW * CPL; ++k) {
-      const int j = j0 + k / CPL, i = i0 + k % CPL;
-      if (j < n && i < n) {
-        const int64_t p = (int64_t)j * n + i;
-        w[p] += inc[p];
+      for (int r0 = 0; r0 < RPW; r0 += KR) {
+        double2 Wv[KR], I[KR];
+#pragma unroll
+        for (int u = 0; u < KR && r0 + u < RPW; ++u) {
+          const int j = j0 + r0 + u;
+          const int64_t p = (j < n && i0 < n) ? (int64_t)j * n + i0 : 0;
+          Wv[u] = ld2(w + p);
+          I[u] = ld2(inc + p);
+        }
+#pragma unroll
+        for (int u = 0; u < KR && r0 + u < RPW; ++u) {
+          const int j = j0 + r0 + u;
+          if (j < n && i0 < n) st2(w + (int64_t)j * n + i0, Wv[u].x + I[u].x, Wv[u].y + I[u].y);
+        }
       }
+    } else
+#pragma unroll 1
+    for (int k0 = 0; k0 < RPW * CPL; k0 += KU) {
+      double v[KU];
+      int64_t pp[KU];
+      bool okk[KU];
+#pragma unroll
+      for (int u = 0; u < KU; ++u) {
+        const int k = k0 + u;
+        const int j = j0 + k / CPL, i = i0 + k % CPL;
+        const bool ok = j < n && i < n;
+        const int64_t p = ok ? (int64_t)j * n + i : 0;
+        v[u] = w[p] + inc[p];
+        pp[u] = p;
+        okk[u] = ok;
+      }
+#pragma unroll
+      for (int u = 0; u < KU; ++u)
+        if (okk[u]) w[pp[u]] = v[u];
     }
     __syncthreads();   // the next residual sweep reads neighbours' w
   }
@@ -791,7 +941,7 @@ void launch_resident(hipStream_t st, int64_t nsys, const double* a, const float*
                      const double* dinv, int n, double c, double tauf, int J, double tol,
                      float pcg_rtol, int maxit, StartRef sr, double* out, double* incbuf, int64_t M, int N,
                      int skip_first, const uint8_t* active, int* flag, unsigned long long* cnt) {
-  size_t lds = sizeof(float) * (size_t)n * n;
+  size_t lds = sizeof(float) * ((size_t)n * n + 2);   // n^2 tile + a spare word pair
   fine2d_resident_kernel<NW, CPL, RPW><<<dim3((unsigned)nsys), dim3(64 * NW), lds, st>>>(
       a, sf, dinv, n, c, tauf, J, tol, pcg_rtol, maxit, sr, out, incbuf, M, N, skip_first, active,
       flag, cnt);
