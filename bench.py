@@ -32,7 +32,7 @@ if ROOT not in sys.path:
 PEAK_HBM_GBS = 8000.0
 PEAK_FP32_TFLOPS = 157.3
 PEAK_BF16_TFLOPS = 2500.0
-# algorithmic work per unit
+# algorithmic work per unit of the dominant kernels
 FLOPS_PER_PCG_UNKNOWN_IT = 18.0        # 5-point scaled matvec 8, two dots 4, three axpys 6
 BYTES_PER_COCG_UNKNOWN_IT = 128.0      # complex128 vectors streamed per COCG iteration
 
@@ -186,8 +186,8 @@ def main():
     ap.add_argument("--no-oracle-check", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU sharding is "
-                                   "described in DESIGN.md but not built"}))
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; sharding the batch over "
+                                   "several GPUs is not built"}))
         sys.exit(2)
 
     if args.config == "c3_ragged":

@@ -440,7 +440,7 @@ int parareal_impl(klecgc_ctx* ctx, const klecgc_problem& p, const double* a, con
   pc.c = ctx;
   pc.p = p;
   pc.pb = p;
-  // The driver solves the coarse system for the correction U^{k+1} - U^k, whose
+  // The parareal loop solves the coarse system for the correction U^{k+1} - U^k, whose
   // right-hand side is the defect; errors of the shifted solves then only perturb the
   // contraction (by ~ cgc_rtol / alpha), not the fixed point, so a relative 1e-7
   // suffices by default.

@@ -91,7 +91,7 @@ struct klecgc_ctx {
   hipEvent_t ev[2] = {nullptr, nullptr};
   void* blas = nullptr;   // rocblas handle of the offline eigen-solver (created on first use)
   // true while the context's launches are being captured into a graph: no event timing,
-  // no status resets or read-backs (the driver does them around the captured region)
+  // no status resets or read-backs (the parareal loop does them around the captured region)
   bool capturing = false;
   std::map<int, KcTuning> tuning;   // by grid size n
 };
