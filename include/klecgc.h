@@ -129,6 +129,8 @@ int klecgc_last_times(const klecgc_ctx* ctx, double* ms8, int64_t* count8);
  * when a solve stops).  Variants (-1 = built-in choice by n):
  *   fine:  KC_FINE_STREAM64 float64 PCG streaming through device memory (any n);
  *          KC_FINE_RES16/32/64/128 work-group-resident float32 PCG for n <= 16/32/64/128;
+ *          KC_FINE_RB128 work-group-resident float32 CG on the red-black reduced system
+ *          (odd-coloured nodes eliminated) for n <= 128;
  *          KC_FINE_MG float32 CG preconditioned by an aggregation-multigrid V-cycle,
  *          streaming through device memory (any n);
  *   shifted solves of step (b): KC_CGC_STREAM64 float64 COCG (any n);
@@ -137,7 +139,7 @@ int klecgc_last_times(const klecgc_ctx* ctx, double* ms8, int64_t* count8);
  *          KC_CGC_MG32 float32 COCG preconditioned by an aggregation-multigrid V-cycle,
  *          streaming through device memory (any n). */
 enum { KC_FINE_STREAM64 = 0, KC_FINE_RES16 = 1, KC_FINE_RES32 = 2, KC_FINE_RES64 = 3, KC_FINE_RES128 = 4,
-       KC_FINE_MG = 5 };
+       KC_FINE_MG = 5, KC_FINE_RB128 = 6 };
 enum { KC_CGC_STREAM64 = 0, KC_CGC_RES16 = 1, KC_CGC_RES32 = 2, KC_CGC_RES64 = 3, KC_CGC_STREAM32 = 4,
        KC_CGC_MG32 = 5 };
 typedef struct {

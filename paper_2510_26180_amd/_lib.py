@@ -44,7 +44,7 @@ class Task(ctypes.Structure):
 
 
 KC_BATCH_GRAPH = 1
-KC_FINE_STREAM64, KC_FINE_RES16, KC_FINE_RES32, KC_FINE_RES64, KC_FINE_RES128, KC_FINE_MG = 0, 1, 2, 3, 4, 5
+KC_FINE_STREAM64, KC_FINE_RES16, KC_FINE_RES32, KC_FINE_RES64, KC_FINE_RES128, KC_FINE_MG, KC_FINE_RB128 = 0, 1, 2, 3, 4, 5, 6
 KC_CGC_STREAM64, KC_CGC_RES16, KC_CGC_RES32, KC_CGC_RES64, KC_CGC_STREAM32, KC_CGC_MG32 = 0, 1, 2, 3, 4, 5
 
 

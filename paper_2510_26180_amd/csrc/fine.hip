@@ -392,9 +392,110 @@ struct Resident {
   }
 };
 
+// Red-black reduced system for two columns per lane (Section 3.1 step equation, Jacobi-
+// scaled: I + N with N the negated scaled couplings, which join only nodes of opposite
+// colour (i + j) mod 2).  With even nodes e and odd nodes o, eliminating o leaves
+// S x_e = b_e - N_eo b_o with S = I - N_eo N_oe, whose condition number is about a quarter
+// of that of I + N (eigenvalues 1 - mu^2 against 1 +- mu), so CG needs about half the
+// iterations on half the unknowns; then x_o = b_o - N_oe x_e.  Wave w owns rows
+// [w RPW, (w+1) RPW) with RPW even, so row s of a lane has its even node in column
+// i0 + (s & 1) and its odd node in the other one, and the direction of each lane shift is
+// fixed per row.  Halo arrays hold one value per lane and wave: "bot" the wave's last row
+// (read by the wave above), "top" the wave's first row times its south-face coupling (read
+// by the wave below).
+template <int NW, int RPW>
+struct RedBlack {
+  static_assert(RPW % 2 == 0, "rows of both parities in every wave");
+  static constexpr int HW = 64 * NW;
+
+  // T = N_oe P (odd node of every row).  The neighbouring waves' boundary rows of P arrive
+  // as r + beta p from the halos of the previous iteration (as in the full-system kernel).
+  static __device__ __forceinline__ void gather_odd(const float (&P)[RPW], float (&T)[RPW],
+                                                    const float (&EW)[RPW][2], const float (&NS)[RPW][2],
+                                                    const float* hr_top, const float* hp_top,
+                                                    const float* hr_bot, const float* hp_bot, float beta,
+                                                    int lane, int wave) {
+#pragma unroll
+    for (int s = 0; s < RPW; ++s) {
+      float t;
+      if ((s & 1) == 0) {   // odd node in column i0 + 1
+        const float south = s > 0 ? P[s - 1]
+                                  : (wave > 0 ? fmaf(beta, hp_bot[(wave - 1) * 64 + lane], hr_bot[(wave - 1) * 64 + lane])
+                                              : 0.f);
+        t = EW[s][1] * P[s];
+        t = fmaf(NS[s][1], south, t);
+        t = fmaf(NS[s + 1][1], P[s + 1], t);
+        t += from_east(EW[s][0] * P[s]);
+      } else {              // odd node in column i0
+        t = EW[s][1] * P[s];
+        t = fmaf(NS[s][0], P[s - 1], t);
+        if (s < RPW - 1)
+          t = fmaf(NS[s + 1][0], P[s + 1], t);
+        else
+          t += wave < NW - 1 ? fmaf(beta, hp_top[(wave + 1) * 64 + lane], hr_top[(wave + 1) * 64 + lane]) : 0.f;
+        t = fmaf(EW[s][0], from_west(P[s]), t);
+      }
+      T[s] = t;
+    }
+  }
+
+  // Q = P - N_eo T (even node of every row); returns the lane's P.Q.
+  static __device__ __forceinline__ float gather_even(const float (&P)[RPW], const float (&T)[RPW],
+                                                      float (&Q)[RPW], const float (&EW)[RPW][2],
+                                                      const float (&NS)[RPW][2], const float* ht_top,
+                                                      const float* ht_bot, int lane, int wave) {
+    float pq = 0.f;
+#pragma unroll
+    for (int s = 0; s < RPW; ++s) {
+      float u;
+      if ((s & 1) == 0) {   // even node in column i0
+        const float south = s > 0 ? T[s - 1] : (wave > 0 ? ht_bot[(wave - 1) * 64 + lane] : 0.f);
+        u = EW[s][1] * T[s];
+        u = fmaf(NS[s][0], south, u);
+        u = fmaf(NS[s + 1][0], T[s + 1], u);
+        u = fmaf(EW[s][0], from_west(T[s]), u);
+      } else {              // even node in column i0 + 1
+        u = EW[s][1] * T[s];
+        u = fmaf(NS[s][1], T[s - 1], u);
+        if (s < RPW - 1)
+          u = fmaf(NS[s + 1][1], T[s + 1], u);
+        else
+          u += wave < NW - 1 ? ht_top[(wave + 1) * 64 + lane] : 0.f;
+        u += from_east(EW[s][0] * T[s]);
+      }
+      const float q = P[s] - u;
+      Q[s] = q;
+      pq = fmaf(P[s], q, pq);
+    }
+    return pq;
+  }
+
+  // halo rows of an even-node vector pair (R, P): last rows and first rows times the
+  // coupling to the odd node below them (column i0: row 0 is even)
+  static __device__ __forceinline__ void store_even_halo(const float (&Rv)[RPW], const float (&Pv)[RPW],
+                                                         const float (&NS)[RPW][2], float* hr_top, float* hp_top,
+                                                         float* hr_bot, float* hp_bot, int lane, int wave) {
+    const int h = wave * 64 + lane;
+    hr_bot[h] = Rv[RPW - 1];
+    hp_bot[h] = Pv[RPW - 1];
+    hr_top[h] = NS[0][0] * Rv[0];
+    hp_top[h] = NS[0][0] * Pv[0];
+  }
+
+  // halo rows of an odd-node vector (row 0's odd node is in column i0 + 1)
+  static __device__ __forceinline__ void store_odd_halo(const float (&Tv)[RPW], const float (&NS)[RPW][2],
+                                                        float* ht_top, float* ht_bot, int lane, int wave) {
+    const int h = wave * 64 + lane;
+    ht_bot[h] = Tv[RPW - 1];
+    ht_top[h] = NS[0][1] * Tv[0];
+  }
+};
+
 // LDS: xs[n*n + 2] float32 staging tile of the whole system (+ a spare word pair for lanes
 // outside the grid), halo rows, reduction slots.
-template <int NW, int CPL, int RPW>
+// RB: the float32 solve runs CG on the red-black reduced system (CPL == 2), else Jacobi-PCG
+// on the full system.
+template <int NW, int CPL, int RPW, bool RB = false>
 __global__ __launch_bounds__(64 * NW) void fine2d_resident_kernel(
     const double* __restrict__ a, const float* __restrict__ sf, const double* __restrict__ dinv,
     int n, double c, double tauf, int J, double tol, float pcg_rtol, int maxit, StartRef sr,
@@ -406,6 +507,8 @@ __global__ __launch_bounds__(64 * NW) void fine2d_resident_kernel(
   extern __shared__ float xs[];                       // [n*n + 2]
   __shared__ float hr_top[NW * RS::ROWW], hp_top[NW * RS::ROWW];
   __shared__ float hr_bot[NW * RS::ROWW], hp_bot[NW * RS::ROWW];
+  __shared__ float ht_top[RB ? NW * 64 : 1], ht_bot[RB ? NW * 64 : 1];   // odd-node halos (RB)
+  static_assert(!RB || CPL == 2, "the red-black solve pairs two columns per lane");
   __shared__ float fslots[2][4 * NW];
   __shared__ double dslots[4 * NW];
   unsigned long long tot_it = 0, tot_pass = 0, max_it = 0, missed = 0;
@@ -453,6 +556,7 @@ __global__ __launch_bounds__(64 * NW) void fine2d_resident_kernel(
   const double dmax = dmx[0];
 
   float X[RPW][CPL], R[RPW][CPL], P[RPW][CPL], Q[RPW][CPL];
+  float Xr[RPW], Rr[RPW], Pr[RPW], Qr[RPW], Tr[RPW], Bo[RPW];   // reduced system (RB)
   bool fail = false;
   // owned nodes per group of the float64 loops (residual sweep; increment / state updates)
   constexpr int KG = RPW * CPL < 4 ? RPW * CPL : 4;
@@ -608,65 +712,136 @@ __global__ __launch_bounds__(64 * NW) void fine2d_resident_kernel(
       // the owner's right-hand side: the residual sweep's tile scaled by 1/sig (late
       // residuals shrink towards the float64 floor and their squares would underflow)
       const float fis = (float)(1.0 / sig);
-      float rr = 0.f;
+      if constexpr (!RB) {
+        float rr = 0.f;
 #pragma unroll
-      for (int r = 0; r < RPW; ++r) {
-        int j = j0 + r;
-#pragma unroll
-        for (int t = 0; t < CPL; ++t) {
-          int i = i0 + t;
-          float v = (j < n && i < n) ? xs[j * n + i] * fis : 0.f;
-          R[r][t] = v;
-          P[r][t] = v;
-          X[r][t] = 0.f;
-          rr = fmaf(v, v, rr);
-        }
-      }
-      RS::store_halo(R, P, NS, hr_top, hp_top, hr_bot, hp_bot, lane, wave);
-      rr = block_sum_f<NW>(rr, fslots[1], lane, wave);
-      const float rel = (float)fmin(0.5, fmax((double)pcg_rtol, kPassMargin * target / rmax));
-      const float stop = rel * rel * rr;
-      float beta = 0.f;
-      int it = 0;
-      const long long t0 = clock64();
-      while (rr > stop && it < maxit) {
-        float pq = RS::matvec(P, Q, EW, NS, hr_top, hp_top, hr_bot, hp_bot, beta, lane, wave);
-        pq = block_sum_f<NW>(pq, fslots[0], lane, wave);
-        // CG scalars through the hardware reciprocal (about 1 ulp): an IEEE division
-        // costs some ten instructions per iteration of an issue-bound loop
-        const float alpha = rr * __builtin_amdgcn_rcpf(pq);
-        float rn = 0.f;
-#pragma unroll
-        for (int r = 0; r < RPW; ++r)
+        for (int r = 0; r < RPW; ++r) {
+          int j = j0 + r;
 #pragma unroll
           for (int t = 0; t < CPL; ++t) {
-            X[r][t] = fmaf(alpha, P[r][t], X[r][t]);
-            R[r][t] = fmaf(-alpha, Q[r][t], R[r][t]);
-            rn = fmaf(R[r][t], R[r][t], rn);
+            int i = i0 + t;
+            float v = (j < n && i < n) ? xs[j * n + i] * fis : 0.f;
+            R[r][t] = v;
+            P[r][t] = v;
+            X[r][t] = 0.f;
+            rr = fmaf(v, v, rr);
           }
+        }
         RS::store_halo(R, P, NS, hr_top, hp_top, hr_bot, hp_bot, lane, wave);
-        rn = block_sum_f<NW>(rn, fslots[1], lane, wave);
-        beta = rn * __builtin_amdgcn_rcpf(rr);
-        rr = rn;
+        rr = block_sum_f<NW>(rr, fslots[1], lane, wave);
+        const float rel = (float)fmin(0.5, fmax((double)pcg_rtol, kPassMargin * target / rmax));
+        const float stop = rel * rel * rr;
+        float beta = 0.f;
+        int it = 0;
+        const long long t0 = clock64();
+        while (rr > stop && it < maxit) {
+          float pq = RS::matvec(P, Q, EW, NS, hr_top, hp_top, hr_bot, hp_bot, beta, lane, wave);
+          pq = block_sum_f<NW>(pq, fslots[0], lane, wave);
+          // CG scalars through the hardware reciprocal (about 1 ulp): an IEEE division
+          // costs some ten instructions per iteration of an issue-bound loop
+          const float alpha = rr * __builtin_amdgcn_rcpf(pq);
+          float rn = 0.f;
 #pragma unroll
-        for (int r = 0; r < RPW; ++r)
+          for (int r = 0; r < RPW; ++r)
 #pragma unroll
-          for (int t = 0; t < CPL; ++t) P[r][t] = fmaf(beta, P[r][t], R[r][t]);
-        ++it;
-      }
-      t_cg += clock64() - t0;
-      if (it >= maxit && rr > stop) fail = true;
-      tot_it += it;
-      max_it = it > (int)max_it ? it : max_it;
-      // correction of the owned nodes: inc += sig D^{-1/2} X (through the thread's own xs
-      // entries, so the float64 loop needs no register copy of X)
+            for (int t = 0; t < CPL; ++t) {
+              X[r][t] = fmaf(alpha, P[r][t], X[r][t]);
+              R[r][t] = fmaf(-alpha, Q[r][t], R[r][t]);
+              rn = fmaf(R[r][t], R[r][t], rn);
+            }
+          RS::store_halo(R, P, NS, hr_top, hp_top, hr_bot, hp_bot, lane, wave);
+          rn = block_sum_f<NW>(rn, fslots[1], lane, wave);
+          beta = rn * __builtin_amdgcn_rcpf(rr);
+          rr = rn;
 #pragma unroll
-      for (int r = 0; r < RPW; ++r) {
-        int j = j0 + r;
+          for (int r = 0; r < RPW; ++r)
 #pragma unroll
-        for (int t = 0; t < CPL; ++t) {
-          int i = i0 + t;
-          if (j < n && i < n) xs[j * n + i] = X[r][t];
+            for (int t = 0; t < CPL; ++t) P[r][t] = fmaf(beta, P[r][t], R[r][t]);
+          ++it;
+        }
+        t_cg += clock64() - t0;
+        if (it >= maxit && rr > stop) fail = true;
+        tot_it += it;
+        max_it = it > (int)max_it ? it : max_it;
+        // correction of the owned nodes: inc += sig D^{-1/2} X (through the thread's own xs
+        // entries, so the float64 loop needs no register copy of X)
+#pragma unroll
+        for (int r = 0; r < RPW; ++r) {
+          int j = j0 + r;
+#pragma unroll
+          for (int t = 0; t < CPL; ++t) {
+            int i = i0 + t;
+            if (j < n && i < n) xs[j * n + i] = X[r][t];
+          }
+        }
+      } else {
+        using RBS = RedBlack<NW, RPW>;
+        // right-hand side b (scaled by 1/sig) split by colour, then the reduced right-hand
+        // side R = b_e - N_eo b_o (the odd values of the boundary rows through the halos)
+        float Be[RPW];
+#pragma unroll
+        for (int r = 0; r < RPW; ++r) {
+          const int j = j0 + r;
+          const int ce = i0 + (r & 1), co = i0 + 1 - (r & 1);
+          Be[r] = (j < n && ce < n) ? xs[j * n + ce] * fis : 0.f;
+          Bo[r] = (j < n && co < n) ? xs[j * n + co] * fis : 0.f;
+        }
+        RBS::store_odd_halo(Bo, NS, ht_top, ht_bot, lane, wave);
+        __syncthreads();
+        (void)RBS::gather_even(Be, Bo, Rr, EW, NS, ht_top, ht_bot, lane, wave);
+        float rr = 0.f;
+#pragma unroll
+        for (int r = 0; r < RPW; ++r) {
+          Pr[r] = Rr[r];
+          Xr[r] = 0.f;
+          rr = fmaf(Rr[r], Rr[r], rr);
+        }
+        RBS::store_even_halo(Rr, Pr, NS, hr_top, hp_top, hr_bot, hp_bot, lane, wave);
+        rr = block_sum_f<NW>(rr, fslots[1], lane, wave);
+        // the odd residual of the full system is zero after the back-substitution, so the
+        // reduced residual is the full one
+        const float rel = (float)fmin(0.5, fmax((double)pcg_rtol, kPassMargin * target / rmax));
+        const float stop = rel * rel * rr;
+        float beta = 0.f;
+        int it = 0;
+        const long long t0 = clock64();
+        while (rr > stop && it < maxit) {
+          RBS::gather_odd(Pr, Tr, EW, NS, hr_top, hp_top, hr_bot, hp_bot, beta, lane, wave);
+          RBS::store_odd_halo(Tr, NS, ht_top, ht_bot, lane, wave);
+          __syncthreads();
+          float pq = RBS::gather_even(Pr, Tr, Qr, EW, NS, ht_top, ht_bot, lane, wave);
+          pq = block_sum_f<NW>(pq, fslots[0], lane, wave);
+          const float alpha = rr * __builtin_amdgcn_rcpf(pq);
+          float rn = 0.f;
+#pragma unroll
+          for (int r = 0; r < RPW; ++r) {
+            Xr[r] = fmaf(alpha, Pr[r], Xr[r]);
+            Rr[r] = fmaf(-alpha, Qr[r], Rr[r]);
+            rn = fmaf(Rr[r], Rr[r], rn);
+          }
+          RBS::store_even_halo(Rr, Pr, NS, hr_top, hp_top, hr_bot, hp_bot, lane, wave);
+          rn = block_sum_f<NW>(rn, fslots[1], lane, wave);
+          beta = rn * __builtin_amdgcn_rcpf(rr);
+          rr = rn;
+#pragma unroll
+          for (int r = 0; r < RPW; ++r) Pr[r] = fmaf(beta, Pr[r], Rr[r]);
+          ++it;
+        }
+        t_cg += clock64() - t0;
+        if (it >= maxit && rr > stop) fail = true;
+        tot_it += it;
+        max_it = it > (int)max_it ? it : max_it;
+        // back-substitution x_o = b_o - N_oe x_e (even halo rows of x, beta = 0), then the
+        // whole correction into the owners' xs entries
+        RBS::store_even_halo(Xr, Xr, NS, hr_top, hp_top, hr_bot, hp_bot, lane, wave);
+        __syncthreads();
+        RBS::gather_odd(Xr, Tr, EW, NS, hr_top, hp_top, hr_bot, hp_bot, 0.f, lane, wave);
+#pragma unroll
+        for (int r = 0; r < RPW; ++r) {
+          const int j = j0 + r;
+          const int ce = i0 + (r & 1), co = i0 + 1 - (r & 1);
+          if (j < n && ce < n) xs[j * n + ce] = Xr[r];
+          if (j < n && co < n) xs[j * n + co] = Bo[r] - Tr[r];
         }
       }
       if (pairs) {
@@ -971,13 +1146,13 @@ __global__ __launch_bounds__(64 * NW, WPE) void fine2d_mg_kernel(
   }
 }
 
-template <int NW, int CPL, int RPW>
+template <int NW, int CPL, int RPW, bool RB = false>
 void launch_resident(hipStream_t st, int64_t nsys, const double* a, const float* sf,
                      const double* dinv, int n, double c, double tauf, int J, double tol,
                      float pcg_rtol, int maxit, StartRef sr, double* out, double* incbuf, int64_t M, int N,
                      int skip_first, const uint8_t* active, int* flag, unsigned long long* cnt) {
   size_t lds = sizeof(float) * ((size_t)n * n + 2);   // n^2 tile + a spare word pair
-  fine2d_resident_kernel<NW, CPL, RPW><<<dim3((unsigned)nsys), dim3(64 * NW), lds, st>>>(
+  fine2d_resident_kernel<NW, CPL, RPW, RB><<<dim3((unsigned)nsys), dim3(64 * NW), lds, st>>>(
       a, sf, dinv, n, c, tauf, J, tol, pcg_rtol, maxit, sr, out, incbuf, M, N, skip_first, active,
       flag, cnt);
   KC_LAUNCH_CHECK();
@@ -1060,6 +1235,11 @@ int propagate_impl(klecgc_ctx* ctx, const klecgc_problem& p, const FineArgs& fa,
                                                              maxit, sr, fa.out, incbuf, M, N, fa.skip_first,
                                                              fa.active, flag, cnt);
         break;
+      case KC_FINE_RB128:
+        launch_resident<KC_RES128_NW, 2, 128 / KC_RES128_NW, true>(st, nsys, fa.a, sf, dinv, n, c, tauf, J, tol, pcg_rtol,
+                                                             maxit, sr, fa.out, incbuf, M, N, fa.skip_first,
+                                                             fa.active, flag, cnt);
+        break;
       case KC_FINE_MG: {
         // 16 waves per system (the node loops are latency-bound); scratch for at most
         // `chunk` systems at a time, and never fewer than the device keeps in flight
@@ -1095,6 +1275,7 @@ bool fine_variant_fits(int v, int n) {
     case KC_FINE_RES32: return n <= 32;
     case KC_FINE_RES64: return n <= 64;
     case KC_FINE_RES128: return n <= 128;
+    case KC_FINE_RB128: return n <= 128;
     case KC_FINE_MG: return true;
     default: return false;
   }

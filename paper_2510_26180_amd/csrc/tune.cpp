@@ -59,7 +59,7 @@ int autotune_impl(klecgc_ctx* ctx, const klecgc_problem& p, const double* a, int
   };
   try {
     // ---- fine propagator
-    for (int v : {KC_FINE_RES16, KC_FINE_RES32, KC_FINE_RES64, KC_FINE_RES128, KC_FINE_MG}) {
+    for (int v : {KC_FINE_RES16, KC_FINE_RES32, KC_FINE_RES64, KC_FINE_RES128, KC_FINE_RB128, KC_FINE_MG}) {
       if (!fine_variant_fits(v, n)) continue;
       bool warmed = false;
       for (float r : fine_rtols) {

@@ -17,7 +17,7 @@ pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 
-FINE = {"stream64": 0, "res16": 1, "res32": 2, "res64": 3, "res128": 4, "mg": 5}
+FINE = {"stream64": 0, "res16": 1, "res32": 2, "res64": 3, "res128": 4, "mg": 5, "rb128": 6}
 CGC = {"stream64": 0, "res16": 1, "res32": 2, "res64": 3, "stream32": 4, "mg32": 5}
 
 
@@ -38,7 +38,11 @@ def spec_of(w, **kw):
                                             (13, "res128", 1e-6), (13, "stream64", 1e-6), (20, "res32", 3e-6),
                                             (40, "res64", 1e-5), (40, "res128", 3e-7), (100, "res128", 1e-5),
                                             (1, "mg", 1e-5), (13, "mg", 1e-6), (40, "mg", 1e-5), (100, "mg", 3e-6),
-                                            (150, "mg", 1e-5), (150, "stream64", 1e-6)])
+                                            (150, "mg", 1e-5), (150, "stream64", 1e-6),
+                                            # red-black reduced system: odd and even n, padding
+                                            # rows and lanes, one node, the full 128 tile
+                                            (1, "rb128", 1e-6), (13, "rb128", 1e-6), (40, "rb128", 3e-7),
+                                            (100, "rb128", 1e-5), (101, "rb128", 1e-6), (128, "rb128", 3e-6)])
 def test_fine_variants(ctx, n, variant, rtol):
     log(f"fine variant {variant} n={n} pass reduction {rtol}")
     ctx.set_tuning(n, fine_variant=FINE[variant], fine_pcg_rtol=rtol, mg_sweeps=1 if n == 100 else 0)
@@ -101,8 +105,8 @@ def test_autotune_then_parareal_matches_oracle(ctx, n):
     prob = spec_of(w)
     t = ctx.autotune(prob, dev(a))
     log(f"  autotune n={n}: {t}")
-    assert t["fine_variant"] in (FINE["res32"], FINE["res64"], FINE["res128"]) if n == 20 else \
-        t["fine_variant"] == FINE["res128"]
+    assert t["fine_variant"] in (FINE["res32"], FINE["res64"], FINE["res128"], FINE["rb128"]) if n == 20 else \
+        t["fine_variant"] in (FINE["res128"], FINE["rb128"])
     assert t["fine_ms"] > 0 and t["cgc_ms"] > 0
     assert ctx.get_tuning(n)["fine_variant"] == t["fine_variant"]
     U = torch.empty((M, w.N, w.Nx), dtype=torch.float64, device="cuda")
