@@ -34,6 +34,10 @@ PEAK_FP32_TFLOPS = 157.3
 PEAK_BF16_TFLOPS = 2500.0
 # algorithmic work per unit of the dominant kernels
 FLOPS_PER_PCG_UNKNOWN_IT = 18.0        # 5-point scaled matvec 8, two dots 4, three axpys 6
+# red-black reduced system, per grid unknown and iteration: odd-node gather 7 and even-node
+# gather 9 (each on half the nodes), two dots 4 and three axpys 6 on the even half
+FLOPS_PER_RB_UNKNOWN_IT = 13.0
+KC_FINE_RB128 = 6
 BYTES_PER_COCG_UNKNOWN_IT = 128.0      # complex128 vectors streamed per COCG iteration
 
 
@@ -343,7 +347,11 @@ def main():
     dom = max(ktimes, key=lambda k: ktimes[k][0])
     dom_ms, dom_n = ktimes[dom]
     if dom == "fine":
-        flops = FLOPS_PER_PCG_UNKNOWN_IT * w.Nx * stats["fine_krylov_its"]
+        fv = (tuning or {}).get("fine_variant", -1)
+        if fv < 0:   # the library's built-in choice by grid size
+            fv = KC_FINE_RB128 if 64 < w.n <= 128 else -1
+        per_it = FLOPS_PER_RB_UNKNOWN_IT if fv == KC_FINE_RB128 else FLOPS_PER_PCG_UNKNOWN_IT
+        flops = per_it * w.Nx * stats["fine_krylov_its"]
         achieved = flops / (dom_ms / 1e3) / 1e12
         traffic = profiled_traffic("fine.hip", "fine2d_resident_c2_traffic.json")
         ms_launch = dom_ms / max(dom_n, 1)
@@ -355,6 +363,7 @@ def main():
                 "traffic": traffic,
                 "traffic_unit": "GB/launch (HBM FETCH+WRITE, copy-calibrated)",
                 "algorithmic_tflop_per_launch": flops / 1e12 / max(dom_n, 1),
+                "solver": "red-black reduced CG" if fv == KC_FINE_RB128 else "Jacobi PCG",
                 "launches": dom_n, "ms_per_launch": ms_launch, "fine_prop_hbm": fine_hbm}
     elif dom == "shifted":
         byts = BYTES_PER_COCG_UNKNOWN_IT * w.Nx * stats["cgc_krylov_its"]

@@ -1286,7 +1286,7 @@ int fine_variant_for(int n, int requested) {
   if (n <= 16) return KC_FINE_RES16;
   if (n <= 32) return KC_FINE_RES32;
   if (n <= 64) return KC_FINE_RES64;
-  if (n <= 128) return KC_FINE_RES128;
+  if (n <= 128) return KC_FINE_RB128;
   return KC_FINE_MG;
 }
 
