@@ -147,18 +147,20 @@ typedef struct {
   float   fine_pcg_rtol;   /* in (0, 0.5); default 1e-6 */
   int32_t cgc_variant;     /* -1 or KC_CGC_* */
   float   cgc_inner_rtol;  /* in (0, 0.5); default 1e-5 */
-  int32_t mg_sweeps;       /* damped-Jacobi sweeps per level of the multigrid variants, 1..4;
-                              0 selects 2 */
+  int32_t mg_sweeps;       /* smoothing sweeps per level and direction of the multigrid
+                              variants, 1..4; 0 selects 2 */
+  int32_t mg_smoother;     /* multigrid smoother: 0 red-black Gauss-Seidel, 1 damped Jacobi */
 } klecgc_tuning;
 /* Set / read the tuning the context uses for grid size n (KC_EINVAL if a variant does
  * not fit n or a tolerance or sweep count is out of range).  klecgc_get_tuning returns
- * the defaults (-1, 1e-6, -1, 1e-5, 0) for an n never tuned. */
+ * the defaults (-1, 1e-6, -1, 1e-5, 0, 0) for an n never tuned. */
 int klecgc_set_tuning(klecgc_ctx* ctx, int32_t n, const klecgc_tuning* t);
 int klecgc_get_tuning(const klecgc_ctx* ctx, int32_t n, klecgc_tuning* t);
 /* Autotuner: times every fitting fine variant x per-pass reduction {1e-5, 3e-6, 1e-6,
  * 3e-7} on the first min(M, 4) samples of a_dev (fine sweep over all N slices from the
  * coarse-propagator states), then every fitting shifted-solve variant x {1e-4, 3e-5,
- * 1e-5, 3e-6} (x multigrid sweeps {1, 2} for KC_CGC_MG32) on the defect those states
+ * 1e-5, 3e-6} (x multigrid smoothing {Gauss-Seidel 2, Gauss-Seidel 1, Jacobi 2} for
+ * KC_CGC_MG32) on the defect those states
  * leave (correction tolerance cgc_rtol, default 1e-7), keeps the fastest of each for
  * prob->n in the context and returns it in *out
  * (nullable).  ms_out[2] (nullable): the winning fine and shifted-solve times.

@@ -50,7 +50,8 @@ KC_CGC_STREAM64, KC_CGC_RES16, KC_CGC_RES32, KC_CGC_RES64, KC_CGC_STREAM32, KC_C
 
 class Tuning(ctypes.Structure):
     _fields_ = [("fine_variant", ctypes.c_int32), ("fine_pcg_rtol", ctypes.c_float),
-                ("cgc_variant", ctypes.c_int32), ("cgc_inner_rtol", ctypes.c_float), ("mg_sweeps", ctypes.c_int32)]
+                ("cgc_variant", ctypes.c_int32), ("cgc_inner_rtol", ctypes.c_float), ("mg_sweeps", ctypes.c_int32),
+                ("mg_smoother", ctypes.c_int32)]
 
 _vp = ctypes.c_void_p
 _i64 = ctypes.c_int64

@@ -134,8 +134,8 @@ class Context:
 
     # ---- tuning
     def set_tuning(self, n: int, fine_variant=-1, fine_pcg_rtol=1e-6, cgc_variant=-1, cgc_inner_rtol=1e-5,
-                   mg_sweeps=0):
-        t = L.Tuning(fine_variant, fine_pcg_rtol, cgc_variant, cgc_inner_rtol, mg_sweeps)
+                   mg_sweeps=0, mg_smoother=0):
+        t = L.Tuning(fine_variant, fine_pcg_rtol, cgc_variant, cgc_inner_rtol, mg_sweeps, mg_smoother)
         self._check(self.lib.klecgc_set_tuning(self.h, n, ctypes.byref(t)))
 
     def get_tuning(self, n: int) -> dict:

@@ -243,12 +243,14 @@ int klecgc_set_tuning(klecgc_ctx* ctx, int32_t n, const klecgc_tuning* t) {
                    t->cgc_inner_rtol < 0.5f,
                KC_EINVAL, "per-pass reductions must lie in (0, 0.5)");
     KC_REQUIRE(t->mg_sweeps >= 0 && t->mg_sweeps <= 4, KC_EINVAL, "mg_sweeps must lie in [0, 4]");
+    KC_REQUIRE(t->mg_smoother == 0 || t->mg_smoother == 1, KC_EINVAL, "mg_smoother must be 0 or 1");
     KcTuning k;
     k.fine_variant = t->fine_variant;
     k.fine_pcg_rtol = t->fine_pcg_rtol;
     k.cgc_variant = t->cgc_variant;
     k.cgc_inner_rtol = t->cgc_inner_rtol;
     k.mg_sweeps = t->mg_sweeps;
+    k.mg_smoother = t->mg_smoother;
     ctx->tuning[n] = k;
     return KC_OK;
   });
@@ -262,6 +264,7 @@ int klecgc_get_tuning(const klecgc_ctx* ctx, int32_t n, klecgc_tuning* t) {
   t->cgc_variant = k.cgc_variant;
   t->cgc_inner_rtol = k.cgc_inner_rtol;
   t->mg_sweeps = k.mg_sweeps;
+  t->mg_smoother = k.mg_smoother;
   return KC_OK;
 }
 

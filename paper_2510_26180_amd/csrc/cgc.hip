@@ -1193,7 +1193,7 @@ int shifted_solve_impl(klecgc_ctx* ctx, const klecgc_problem& p, const double* a
   const int variant = p.precision == KC_PREC_F32_REFINED ? cgc_variant_for(p.n, tu.cgc_variant) : KC_CGC_STREAM64;
   const float inner = tu.cgc_inner_rtol;
   if (variant == KC_CGC_MG32) {
-    const MgLevels h = mg_levels(p.n, 2, 8LL * Nx, tu.mg_sweeps);
+    const MgLevels h = mg_levels(p.n, 2, 8LL * Nx, tu.mg_sweeps, tu.mg_smoother);
     double* dr = (double*)ctx->ws.get(WS_DINV, sizeof(double) * Nx * nsys);
     double* resb = (double*)ctx->ws.get(WS_KRYLOV, sizeof(double) * 2 * Nx * nsys);
     float* scr = (float*)ctx->ws.get(WS_FINE_AUX, sizeof(float) * h.per_sys * nsys);

@@ -72,6 +72,7 @@ struct KcTuning {
   int cgc_variant = -1;         // -1 heuristic; KC_CGC_* otherwise
   float cgc_inner_rtol = 1e-5f; // float32 COCG residual reduction per refinement pass
   int mg_sweeps = 0;            // multigrid smoothing sweeps per level (0 = default 2)
+  int mg_smoother = 0;          // 0 red-black Gauss-Seidel, 1 damped Jacobi
 };
 
 struct klecgc_ctx {

@@ -1243,7 +1243,7 @@ int propagate_impl(klecgc_ctx* ctx, const klecgc_problem& p, const FineArgs& fa,
       case KC_FINE_MG: {
         // 16 waves per system (the node loops are latency-bound); scratch for at most
         // `chunk` systems at a time, and never fewer than the device keeps in flight
-        const MgLevels h = mg_levels(n, 1, 4 * Nx, tu.mg_sweeps);
+        const MgLevels h = mg_levels(n, 1, 4 * Nx, tu.mg_sweeps, tu.mg_smoother);
         const int64_t per_sys = (int64_t)sizeof(float) * h.per_sys + 2 * (int64_t)sizeof(double) * Nx;
         const int64_t cap_bytes = (int64_t)16 << 30;
         const int64_t chunk = std::min<int64_t>(nsys, std::max<int64_t>(4LL * ctx->num_cus, cap_bytes / per_sys));

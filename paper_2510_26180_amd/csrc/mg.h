@@ -8,11 +8,13 @@
 // Level l+1 aggregates 2x2 blocks of level l (a last 1-wide block when m is odd); its
 // operator is the Galerkin product P^T L P for the piecewise-constant prolongation P,
 // again 5-point: couplings summed across aggregate faces, diagonal summed over the block
-// minus twice its internal couplings.  The V-cycle smooths with damped Jacobi (h.sweeps,
-// default 2, sweeps down and up, the same on the coarsest level of at most 2x2), restricts by
-// summation and prolongates by injection scaled by kMgScale (aggregation coarse spaces
-// are too stiff by about that factor).  Pre- and post-smoothing are the same symmetric
-// operator, so the preconditioner is symmetric (complex symmetric for T = float2), as
+// minus twice its internal couplings.  The V-cycle restricts by summation and prolongates
+// by injection scaled by kMgScale (aggregation coarse spaces are too stiff by about that
+// factor).  Smoother (h.sweeps sweeps per level and direction, default 2, the same on the
+// coarsest level of at most 2x2): red-black Gauss-Seidel (default; colour (i + j) mod 2,
+// red then black going down, black then red going up, so the post-smoother is the
+// transpose of the pre-smoother) or damped Jacobi (the same symmetric operator down and
+// up).  Either way the preconditioner is symmetric (complex symmetric for T = float2), as
 // CG and COCG require.  All device functions are executed by every thread of the work-
 // group and contain work-group barriers.
 #pragma once
@@ -26,11 +28,13 @@ namespace kc {
 constexpr int kMgMaxLevels = 12;
 constexpr float kMgOmega = 0.7f;
 constexpr float kMgScale = 1.8f;
-constexpr int kMgSweeps = 2;   // default damped-Jacobi sweeps per level and direction
+constexpr int kMgSweeps = 2;   // default smoothing sweeps per level and direction
+constexpr int kMgGaussSeidel = 0, kMgJacobi = 1;
 
 struct MgLevels {
   int L;
-  int sweeps;                  // damped-Jacobi sweeps per level and direction (>= 1)
+  int sweeps;                  // smoothing sweeps per level and direction (>= 1)
+  int smoother;                // kMgGaussSeidel or kMgJacobi
   int m[kMgMaxLevels];
   int64_t off[kMgMaxLevels];   // float offset of each level's block in a system's scratch
   int64_t per_sys;             // floats of scratch per system
@@ -74,9 +78,10 @@ struct MgT<float2> {
 // Level table for an n x n grid; `head` floats of Krylov vectors precede the levels in a
 // system's scratch.  Level block (m = m_l): cw[m^2], cs[m^2] (float), then dg, di, xa,
 // xb, b (T each).
-inline MgLevels mg_levels(int n, int words, int64_t head, int sweeps) {
+inline MgLevels mg_levels(int n, int words, int64_t head, int sweeps, int smoother) {
   MgLevels h{};
   h.sweeps = sweeps >= 1 ? sweeps : kMgSweeps;
+  h.smoother = smoother == kMgJacobi ? kMgJacobi : kMgGaussSeidel;
   int m = n, L = 0;
   int64_t off = head;
   while (true) {
@@ -162,10 +167,97 @@ __device__ void mg_build_coarse(float* base, const MgLevels& h) {
   }
 }
 
+// One red-black Gauss-Seidel half sweep on a level: the nodes of colour col take
+// x_p += di_p (b_p - (L x)_p); their neighbours all have the other colour, so the update
+// is exact Gauss-Seidel.  Work items run over the nodes of that colour only (row j holds
+// them at i = 2k + ((col + j) & 1)).  Ends with a barrier.
+template <class T>
+__device__ __forceinline__ void mg_gs_half(const MgLv<T>& v, const T* b, T* x, int col) {
+  using O = MgT<T>;
+  const int m = v.m, hw = (m + 1) / 2;
+  for (int64_t q = threadIdx.x; q < (int64_t)m * hw; q += blockDim.x) {
+    const int j = (int)(q / hw);
+    const int i = 2 * (int)(q % hw) + ((col + j) & 1);
+    if (i < m) {
+      const int64_t p = (int64_t)j * m + i;
+      const T lx = mg_apply<T>(v, p, i, j, [&](int64_t s, int, int) { return x[s]; });
+      x[p] = O::add(x[p], O::mul(v.di[p], O::sub(b[p], lx)));
+    }
+  }
+  __syncthreads();
+}
+
+// Red-black Gauss-Seidel V-cycle; the iterate of every level lives in its xa buffer.
+template <class T>
+__device__ T* mg_vcycle_gs(float* base, const MgLevels& h, const T* rhs0) {
+  using O = MgT<T>;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int l = 0; l < h.L; ++l) {
+    const MgLv<T> v = mg_lv<T>(base, h, l);
+    const T* b = l == 0 ? rhs0 : v.b;
+    const int m = v.m;
+    const int64_t mm = (int64_t)m * m;
+    // first sweep from x = 0: the red half is x_r = di_r b_r, the black nodes start at 0
+    for (int64_t p = tid; p < mm; p += nt) {
+      const int i = (int)(p % m), j = (int)(p / m);
+      v.xa[p] = ((i + j) & 1) == 0 ? O::mul(v.di[p], b[p]) : O::zero();
+    }
+    __syncthreads();
+    mg_gs_half<T>(v, b, v.xa, 1);
+    for (int s = 1; s < h.sweeps; ++s) {
+      mg_gs_half<T>(v, b, v.xa, 0);
+      mg_gs_half<T>(v, b, v.xa, 1);
+    }
+    if (l + 1 < h.L) {   // restrict the residual: b_{l+1}[I,J] = sum over the block of (b - L x)
+      const MgLv<T> c = mg_lv<T>(base, h, l + 1);
+      const int mc = c.m;
+      const T* xc = v.xa;
+      for (int64_t P = tid; P < (int64_t)mc * mc; P += nt) {
+        const int I = (int)(P % mc), J = (int)(P / mc);
+        T sum = O::zero();
+        for (int dj = 0; dj < 2; ++dj)
+          for (int di = 0; di < 2; ++di) {
+            const int i = 2 * I + di, j = 2 * J + dj;
+            if (i < m && j < m) {
+              const int64_t p = (int64_t)j * m + i;
+              const T lx = mg_apply<T>(v, p, i, j, [&](int64_t q, int, int) { return xc[q]; });
+              sum = O::add(sum, O::sub(b[p], lx));
+            }
+          }
+        c.b[P] = sum;
+      }
+      __syncthreads();
+    } else {             // coarsest level: the transposed sweeps complete its smoothing
+      for (int s = 0; s < h.sweeps; ++s) {
+        mg_gs_half<T>(v, b, v.xa, 1);
+        mg_gs_half<T>(v, b, v.xa, 0);
+      }
+    }
+  }
+  for (int l = h.L - 2; l >= 0; --l) {
+    const MgLv<T> v = mg_lv<T>(base, h, l);
+    const MgLv<T> c = mg_lv<T>(base, h, l + 1);
+    const T* b = l == 0 ? rhs0 : v.b;
+    const int m = v.m, mc = c.m;
+    const int64_t mm = (int64_t)m * m;
+    for (int64_t p = tid; p < mm; p += nt) {   // x += s P e
+      const int i = (int)(p % m), j = (int)(p / m);
+      v.xa[p] = O::axpy(kMgScale, c.xa[(int64_t)(j >> 1) * mc + (i >> 1)], v.xa[p]);
+    }
+    __syncthreads();
+    for (int s = 0; s < h.sweeps; ++s) {
+      mg_gs_half<T>(v, b, v.xa, 1);
+      mg_gs_half<T>(v, b, v.xa, 0);
+    }
+  }
+  return mg_lv<T>(base, h, 0).xa;
+}
+
 // z = V-cycle applied to rhs0 (level 0); returns the level-0 buffer holding z.
 // rhs0 must be visible to the whole work-group; z is visible on return.
 template <class T>
 __device__ T* mg_vcycle(float* base, const MgLevels& h, const T* rhs0) {
+  if (h.smoother == kMgGaussSeidel) return mg_vcycle_gs<T>(base, h, rhs0);
   using O = MgT<T>;
   int cur[kMgMaxLevels];
   const int tid = threadIdx.x, nt = blockDim.x;

@@ -95,13 +95,17 @@ int autotune_impl(klecgc_ctx* ctx, const klecgc_problem& p, const double* a, int
     for (int v : {KC_CGC_RES16, KC_CGC_RES32, KC_CGC_RES64, KC_CGC_STREAM32, KC_CGC_MG32}) {
       if (!cgc_variant_fits(v, n)) continue;
       bool warmed = false;
-      for (int sw : {2, 1})
+      // multigrid smoothing (sweeps, smoother): Gauss-Seidel 2 and 1, Jacobi 2
+      const int smoothing[3][2] = {{2, 0}, {1, 0}, {2, 1}};
+      for (const auto& sm : smoothing)
       for (float r : cgc_rtols) {
-        if (v != KC_CGC_MG32 && sw != 2) continue;   // only the multigrid variant smooths
+        // only the multigrid variant smooths
+        if (v != KC_CGC_MG32 && (sm[0] != 2 || sm[1] != 0)) continue;
         KcTuning t = best;
         t.cgc_variant = v;
         t.cgc_inner_rtol = r;
-        t.mg_sweeps = v == KC_CGC_MG32 ? sw : best.mg_sweeps;
+        t.mg_sweeps = v == KC_CGC_MG32 ? sm[0] : best.mg_sweeps;
+        t.mg_smoother = v == KC_CGC_MG32 ? sm[1] : best.mg_smoother;
         ctx->tuning[n] = t;
         if (!warmed) {
           KC_TRY_HIP(hipMemcpyAsync(spec.p, spec0.p, sizeof(double) * 2 * Mp * K * Nx, hipMemcpyDeviceToDevice, st));
@@ -117,6 +121,7 @@ int autotune_impl(klecgc_ctx* ctx, const klecgc_problem& p, const double* a, int
           best.cgc_variant = v;
           best.cgc_inner_rtol = r;
           best.mg_sweeps = t.mg_sweeps;
+          best.mg_smoother = t.mg_smoother;
         }
       }
     }
@@ -132,6 +137,7 @@ int autotune_impl(klecgc_ctx* ctx, const klecgc_problem& p, const double* a, int
     out->cgc_variant = best.cgc_variant;
     out->cgc_inner_rtol = best.cgc_inner_rtol;
     out->mg_sweeps = best.mg_sweeps;
+    out->mg_smoother = best.mg_smoother;
   }
   if (ms_out) {
     ms_out[0] = best_fine;

@@ -45,7 +45,9 @@ def spec_of(w, **kw):
                                             (100, "rb128", 1e-5), (101, "rb128", 1e-6), (128, "rb128", 3e-6)])
 def test_fine_variants(ctx, n, variant, rtol):
     log(f"fine variant {variant} n={n} pass reduction {rtol}")
-    ctx.set_tuning(n, fine_variant=FINE[variant], fine_pcg_rtol=rtol, mg_sweeps=1 if n == 100 else 0)
+    # multigrid smoothing: Gauss-Seidel (default) except damped Jacobi at n = 40
+    ctx.set_tuning(n, fine_variant=FINE[variant], fine_pcg_rtol=rtol, mg_sweeps=1 if n == 100 else 0,
+                   mg_smoother=1 if n == 40 else 0)
     w = W.small_2d(n=n, N=4, J=16)
     M = 2
     xi = W.draw_xi(M, w.d, 41)
@@ -68,7 +70,9 @@ def test_fine_variants(ctx, n, variant, rtol):
                                             (128, "mg32", 3e-5)])
 def test_cgc_variants(ctx, n, variant, rtol):
     log(f"shifted-solve variant {variant} n={n} pass reduction {rtol}")
-    ctx.set_tuning(n, cgc_variant=CGC[variant], cgc_inner_rtol=rtol, mg_sweeps=1 if n in (40, 128) else 0)
+    # multigrid smoothing: Gauss-Seidel (default) except damped Jacobi at n = 100
+    ctx.set_tuning(n, cgc_variant=CGC[variant], cgc_inner_rtol=rtol, mg_sweeps=1 if n in (40, 128) else 0,
+                   mg_smoother=1 if n == 100 else 0)
     N, alpha = 8, 1e-4
     w = W.small_2d(n=n, N=N, alpha=alpha)
     M = 2
@@ -92,8 +96,11 @@ def test_tuning_rejects_variants_that_do_not_fit(ctx):
         assert e.value.code == -1
     with pytest.raises(K.KlecgcError):
         ctx.set_tuning(100, mg_sweeps=5)
+    with pytest.raises(K.KlecgcError):
+        ctx.set_tuning(100, mg_smoother=2)
     assert ctx.get_tuning(100) == {"fine_variant": -1, "fine_pcg_rtol": pytest.approx(1e-6),
-                                   "cgc_variant": -1, "cgc_inner_rtol": pytest.approx(1e-5), "mg_sweeps": 0}
+                                   "cgc_variant": -1, "cgc_inner_rtol": pytest.approx(1e-5), "mg_sweeps": 0,
+                                   "mg_smoother": 0}
 
 
 @pytest.mark.parametrize("n", [20, 72])
