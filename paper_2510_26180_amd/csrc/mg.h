@@ -180,8 +180,16 @@ __device__ __forceinline__ void mg_gs_half(const MgLv<T>& v, const T* b, T* x, i
     const int i = 2 * (int)(q % hw) + ((col + j) & 1);
     if (i < m) {
       const int64_t p = (int64_t)j * m + i;
-      const T lx = mg_apply<T>(v, p, i, j, [&](int64_t s, int, int) { return x[s]; });
-      x[p] = O::add(x[p], O::mul(v.di[p], O::sub(b[p], lx)));
+      // the diagonal's reciprocal from the diagonal mg_apply reads anyway (the kernel is
+      // bound by memory traffic, not by the few extra operations)
+      const T dgp = v.dg[p];
+      const T xp = x[p];
+      T acc = O::mul(dgp, xp);
+      if (i > 0) acc = O::axpy(-v.cw[p], x[p - 1], acc);
+      if (i < m - 1) acc = O::axpy(-v.cw[p + 1], x[p + 1], acc);
+      if (j > 0) acc = O::axpy(-v.cs[p], x[p - m], acc);
+      if (j < m - 1) acc = O::axpy(-v.cs[p + m], x[p + m], acc);
+      x[p] = O::add(xp, O::mul(O::recip(dgp), O::sub(b[p], acc)));
     }
   }
   __syncthreads();
@@ -200,7 +208,7 @@ __device__ T* mg_vcycle_gs(float* base, const MgLevels& h, const T* rhs0) {
     // first sweep from x = 0: the red half is x_r = di_r b_r, the black nodes start at 0
     for (int64_t p = tid; p < mm; p += nt) {
       const int i = (int)(p % m), j = (int)(p / m);
-      v.xa[p] = ((i + j) & 1) == 0 ? O::mul(v.di[p], b[p]) : O::zero();
+      v.xa[p] = ((i + j) & 1) == 0 ? O::mul(O::recip(v.dg[p]), b[p]) : O::zero();
     }
     __syncthreads();
     mg_gs_half<T>(v, b, v.xa, 1);
