@@ -237,7 +237,7 @@ def main():
     t_tune = 0.0
     if not args.no_autotune and w.dim == 2 and w.precision == "f32_refined":
         t0 = time.perf_counter()
-        tuning = ctx.autotune(prob, a_train[:4].contiguous())
+        tuning = ctx.autotune(prob, a_train[:16].contiguous())
         t_tune = time.perf_counter() - t0
         log(f"offline: autotune {t_tune:.1f} s -> {tuning}")
     t0 = time.perf_counter()

@@ -157,7 +157,8 @@ typedef struct {
 int klecgc_set_tuning(klecgc_ctx* ctx, int32_t n, const klecgc_tuning* t);
 int klecgc_get_tuning(const klecgc_ctx* ctx, int32_t n, klecgc_tuning* t);
 /* Autotuner: times every fitting fine variant x per-pass reduction {1e-5, 3e-6, 1e-6,
- * 3e-7} on the first min(M, 4) samples of a_dev (fine sweep over all N slices from the
+ * 3e-7} (the faster of two timings each) on the first min(M, 16) samples of a_dev (fine
+ * sweep over all N slices from the
  * coarse-propagator states), then every fitting shifted-solve variant x {1e-4, 3e-5,
  * 1e-5, 3e-6} (x multigrid smoothing {Gauss-Seidel 2, Gauss-Seidel 1, Jacobi 2} for
  * KC_CGC_MG32) on the defect those states

@@ -36,7 +36,9 @@ int autotune_impl(klecgc_ctx* ctx, const klecgc_problem& p, const double* a, int
              "the autotuner serves 2D float32-refined problems");
   hipStream_t st = ctx->stream;
   const int n = p.n;
-  const int64_t Mp = std::min<int64_t>(M, 4);
+  // up to 16 samples: at 128^2 and 64 slices that is four rounds of work-groups over the
+  // device, so a timing is not decided by the slowest single work-group
+  const int64_t Mp = std::min<int64_t>(M, 16);
   const int64_t Nx = n_unknowns(p);
   const int64_t S = (int64_t)p.N * Nx;
   const int K = p.N / 2 + 1;
@@ -72,9 +74,14 @@ int autotune_impl(klecgc_ctx* ctx, const klecgc_problem& p, const double* a, int
           (void)fine_propagate_impl(ctx, p, fa);
           warmed = true;
         }
-        const double t0 = ctx->ktime[KT_FINE];
-        const int rc = fine_propagate_impl(ctx, p, fa);
-        const double ms = ctx->ktime[KT_FINE] - t0;
+        // the faster of two timings
+        double ms = std::numeric_limits<double>::infinity();
+        int rc = KC_OK;
+        for (int rep = 0; rep < 2 && rc == KC_OK; ++rep) {
+          const double t0 = ctx->ktime[KT_FINE];
+          rc = fine_propagate_impl(ctx, p, fa);
+          ms = std::min(ms, ctx->ktime[KT_FINE] - t0);
+        }
         if (rc == KC_OK && ms < best_fine) {
           best_fine = ms;
           best.fine_variant = v;
@@ -112,10 +119,14 @@ int autotune_impl(klecgc_ctx* ctx, const klecgc_problem& p, const double* a, int
           (void)shifted_solve_impl(ctx, pb, a, nullptr, Mp, (double*)spec.p);
           warmed = true;
         }
-        KC_TRY_HIP(hipMemcpyAsync(spec.p, spec0.p, sizeof(double) * 2 * Mp * K * Nx, hipMemcpyDeviceToDevice, st));
-        const double t0 = ctx->ktime[KT_SHIFTED];
-        const int rc = shifted_solve_impl(ctx, pb, a, nullptr, Mp, (double*)spec.p);
-        const double ms = ctx->ktime[KT_SHIFTED] - t0;
+        double ms = std::numeric_limits<double>::infinity();
+        int rc = KC_OK;
+        for (int rep = 0; rep < 2 && rc == KC_OK; ++rep) {   // the faster of two timings
+          KC_TRY_HIP(hipMemcpyAsync(spec.p, spec0.p, sizeof(double) * 2 * Mp * K * Nx, hipMemcpyDeviceToDevice, st));
+          const double t0 = ctx->ktime[KT_SHIFTED];
+          rc = shifted_solve_impl(ctx, pb, a, nullptr, Mp, (double*)spec.p);
+          ms = std::min(ms, ctx->ktime[KT_SHIFTED] - t0);
+        }
         if (rc == KC_OK && ms < best_cgc) {
           best_cgc = ms;
           best.cgc_variant = v;
