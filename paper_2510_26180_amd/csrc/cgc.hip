@@ -1013,12 +1013,19 @@ __global__ __launch_bounds__(64 * NW, WPE) void cocg_mg_kernel(
         break;
       }
       if (rr <= stop_in) break;
-      Z = mg_vcycle<float2>(base, h, R);
       float rz2[2] = {0.f, 0.f};
-      for (int64_t p = threadIdx.x; p < Nx; p += blockDim.x) {
-        const float2 rv = R[p], zv = Z[p];
-        rz2[0] += rv.x * zv.x - rv.y * zv.y;
-        rz2[1] += rv.x * zv.y + rv.y * zv.x;
+      if (h.smoother == kMgGaussSeidel) {   // r.z accumulated by the V-cycle's last sweeps
+        float2 d = make_float2(0.f, 0.f);
+        Z = mg_vcycle_gs<float2>(base, h, R, &d);
+        rz2[0] = d.x;
+        rz2[1] = d.y;
+      } else {
+        Z = mg_vcycle<float2>(base, h, R);
+        for (int64_t p = threadIdx.x; p < Nx; p += blockDim.x) {
+          const float2 rv = R[p], zv = Z[p];
+          rz2[0] += rv.x * zv.x - rv.y * zv.y;
+          rz2[1] += rv.x * zv.y + rv.y * zv.x;
+        }
       }
       block_sum_fk<NW, 2>(rz2, fsl[0], lane, wave);
       const cf rzn = {rz2[0], rz2[1]};

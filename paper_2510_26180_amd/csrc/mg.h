@@ -170,9 +170,10 @@ __device__ void mg_build_coarse(float* base, const MgLevels& h) {
 // One red-black Gauss-Seidel half sweep on a level: the nodes of colour col take
 // x_p += di_p (b_p - (L x)_p); their neighbours all have the other colour, so the update
 // is exact Gauss-Seidel.  Work items run over the nodes of that colour only (row j holds
-// them at i = 2k + ((col + j) & 1)).  Ends with a barrier.
-template <class T>
-__device__ __forceinline__ void mg_gs_half(const MgLv<T>& v, const T* b, T* x, int col) {
+// them at i = 2k + ((col + j) & 1)).  With DOT, the work item also adds b_p x_p of its
+// updated nodes to dot.  Ends with a barrier.
+template <class T, bool DOT = false>
+__device__ __forceinline__ void mg_gs_half(const MgLv<T>& v, const T* b, T* x, int col, T* dot = nullptr) {
   using O = MgT<T>;
   const int m = v.m, hw = (m + 1) / 2;
   for (int64_t q = threadIdx.x; q < (int64_t)m * hw; q += blockDim.x) {
@@ -189,15 +190,20 @@ __device__ __forceinline__ void mg_gs_half(const MgLv<T>& v, const T* b, T* x, i
       if (i < m - 1) acc = O::axpy(-v.cw[p + 1], x[p + 1], acc);
       if (j > 0) acc = O::axpy(-v.cs[p], x[p - m], acc);
       if (j < m - 1) acc = O::axpy(-v.cs[p + m], x[p + m], acc);
-      x[p] = O::add(xp, O::mul(O::recip(dgp), O::sub(b[p], acc)));
+      const T bp = b[p];
+      const T xn = O::add(xp, O::mul(O::recip(dgp), O::sub(bp, acc)));
+      x[p] = xn;
+      if constexpr (DOT) *dot = O::add(*dot, O::mul(bp, xn));
     }
   }
   __syncthreads();
 }
 
-// Red-black Gauss-Seidel V-cycle; the iterate of every level lives in its xa buffer.
+// Red-black Gauss-Seidel V-cycle; the iterate of every level lives in its xa buffer.  With
+// dot non-null the work item's share of sum_p rhs0_p z_p is added to *dot (every level-0
+// node takes its final value in one of the last two half sweeps, which read rhs0_p anyway).
 template <class T>
-__device__ T* mg_vcycle_gs(float* base, const MgLevels& h, const T* rhs0) {
+__device__ T* mg_vcycle_gs(float* base, const MgLevels& h, const T* rhs0, T* dot = nullptr) {
   using O = MgT<T>;
   const int tid = threadIdx.x, nt = blockDim.x;
   for (int l = 0; l < h.L; ++l) {
@@ -237,8 +243,13 @@ __device__ T* mg_vcycle_gs(float* base, const MgLevels& h, const T* rhs0) {
       __syncthreads();
     } else {             // coarsest level: the transposed sweeps complete its smoothing
       for (int s = 0; s < h.sweeps; ++s) {
-        mg_gs_half<T>(v, b, v.xa, 1);
-        mg_gs_half<T>(v, b, v.xa, 0);
+        if (l == 0 && dot && s == h.sweeps - 1) {   // a one-level hierarchy ends here
+          mg_gs_half<T, true>(v, b, v.xa, 1, dot);
+          mg_gs_half<T, true>(v, b, v.xa, 0, dot);
+        } else {
+          mg_gs_half<T>(v, b, v.xa, 1);
+          mg_gs_half<T>(v, b, v.xa, 0);
+        }
       }
     }
   }
@@ -254,8 +265,13 @@ __device__ T* mg_vcycle_gs(float* base, const MgLevels& h, const T* rhs0) {
     }
     __syncthreads();
     for (int s = 0; s < h.sweeps; ++s) {
-      mg_gs_half<T>(v, b, v.xa, 1);
-      mg_gs_half<T>(v, b, v.xa, 0);
+      if (l == 0 && dot && s == h.sweeps - 1) {
+        mg_gs_half<T, true>(v, b, v.xa, 1, dot);
+        mg_gs_half<T, true>(v, b, v.xa, 0, dot);
+      } else {
+        mg_gs_half<T>(v, b, v.xa, 1);
+        mg_gs_half<T>(v, b, v.xa, 0);
+      }
     }
   }
   return mg_lv<T>(base, h, 0).xa;
