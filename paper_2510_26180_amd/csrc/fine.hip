@@ -1087,9 +1087,13 @@ __global__ __launch_bounds__(64 * NW, WPE) void fine2d_mg_kernel(
           break;
         }
         if (rr <= stop) break;
-        Z = mg_vcycle<float>(base, h, R);
         float rzn = 0.f;
-        for (int64_t p = threadIdx.x; p < Nx; p += blockDim.x) rzn = fmaf(R[p], Z[p], rzn);
+        if (h.smoother == kMgGaussSeidel) {   // r.z accumulated by the V-cycle's last sweeps
+          Z = mg_vcycle_gs<float>(base, h, R, &rzn);
+        } else {
+          Z = mg_vcycle<float>(base, h, R);
+          for (int64_t p = threadIdx.x; p < Nx; p += blockDim.x) rzn = fmaf(R[p], Z[p], rzn);
+        }
         rzn = block_sum_f<NW>(rzn, fslots[0], lane, wave);
         const float be = rzn / rz;
         rz = rzn;
