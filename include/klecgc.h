@@ -161,7 +161,8 @@ int klecgc_get_tuning(const klecgc_ctx* ctx, int32_t n, klecgc_tuning* t);
  * sweep over all N slices from the
  * coarse-propagator states), then every fitting shifted-solve variant x {1e-4, 3e-5,
  * 1e-5, 3e-6} (x multigrid smoothing {Gauss-Seidel 2, Gauss-Seidel 1, Jacobi 2} for
- * KC_CGC_MG32) on the defect those states
+ * KC_CGC_MG32; a variant whose first timing is more than twice the best so far is not
+ * timed further) on the defect those states
  * leave (correction tolerance cgc_rtol, default 1e-7), keeps the fastest of each for
  * prob->n in the context and returns it in *out
  * (nullable).  ms_out[2] (nullable): the winning fine and shifted-solve times.

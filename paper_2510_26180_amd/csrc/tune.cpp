@@ -87,6 +87,8 @@ int autotune_impl(klecgc_ctx* ctx, const klecgc_problem& p, const double* a, int
           best.fine_variant = v;
           best.fine_pcg_rtol = r;
         }
+        // a variant more than twice as slow as the best so far is not timed further
+        if (rc == KC_OK && ms > 2.0 * best_fine) break;
       }
     }
     KC_REQUIRE(best_fine < std::numeric_limits<double>::infinity(), KC_ENOCONV,
@@ -134,6 +136,7 @@ int autotune_impl(klecgc_ctx* ctx, const klecgc_problem& p, const double* a, int
           best.mg_sweeps = t.mg_sweeps;
           best.mg_smoother = t.mg_smoother;
         }
+        if (rc == KC_OK && ms > 2.0 * best_cgc) break;   // as for the fine variants
       }
     }
   } catch (...) {
