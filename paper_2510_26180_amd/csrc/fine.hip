@@ -491,6 +491,111 @@ struct RedBlack {
   }
 };
 
+typedef float __attribute__((address_space(3))) lds_float;   // a pointer into LDS
+
+struct RbPassOut {
+  int it;            // reduced-system CG iterations
+  int capped;        // the iteration cap ended the pass above its stop
+  long long cycles;  // shader clocks inside the Krylov loop
+};
+
+// One float32 correction pass of the red-black reduced solve (see RedBlack), outlined from the
+// resident kernel so that its registers are allocated apart from the float64 refinement
+// around it: the caller's live values are saved once per pass instead of spilling into the
+// Krylov loop.  In: the pass's right-hand side D^{-1/2} r / sig in xs (scaled by fis here).
+// Out: the correction of every owned node in xs.  Called by every thread of the work-group.
+template <int NW, int RPW>
+__device__ __attribute__((noinline)) RbPassOut rb_pass(lds_float* xs_l, float fis, const float* __restrict__ sfm,
+                                                     int n, int64_t gnx, float rel, int maxit, lds_float* hr_top_l,
+                                                     lds_float* hp_top_l, lds_float* hr_bot_l, lds_float* hp_bot_l,
+                                                     lds_float* ht_top_l, lds_float* ht_bot_l, lds_float* fs0_l,
+                                                     lds_float* fs1_l) {
+  using RBS = RedBlack<NW, RPW>;
+  float* xs = (float*)xs_l;
+  float *hr_top = (float*)hr_top_l, *hp_top = (float*)hp_top_l, *hr_bot = (float*)hr_bot_l, *hp_bot = (float*)hp_bot_l;
+  float *ht_top = (float*)ht_top_l, *ht_bot = (float*)ht_bot_l, *fs0 = (float*)fs0_l, *fs1 = (float*)fs1_l;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int j0 = wave * RPW, i0 = lane * 2;
+  // negated scaled couplings (0 on boundary faces and outside the grid)
+  float EW[RPW][2], NS[RPW][2];
+#pragma unroll
+  for (int r = 0; r < RPW; ++r) {
+    const int j = j0 + r;
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int col = i0 + t;
+      EW[r][t] = (j < n && col >= 1 && col <= n - 1) ? -sfm[(int64_t)j * (n + 1) + col] : 0.f;
+      NS[r][t] = (col < n && j >= 1 && j <= n - 1) ? -sfm[gnx + (int64_t)j * n + col] : 0.f;
+    }
+  }
+  // right-hand side b split by colour, then the reduced right-hand side R = b_e - N_eo b_o
+  // (the odd values of the boundary rows through the halos)
+  float Be[RPW], Bo[RPW], Xr[RPW], Rr[RPW], Pr[RPW], Qr[RPW], Tr[RPW];
+#pragma unroll
+  for (int r = 0; r < RPW; ++r) {
+    const int j = j0 + r;
+    const int ce = i0 + (r & 1), co = i0 + 1 - (r & 1);
+    Be[r] = (j < n && ce < n) ? xs[j * n + ce] * fis : 0.f;
+    Bo[r] = (j < n && co < n) ? xs[j * n + co] * fis : 0.f;
+  }
+  RBS::store_odd_halo(Bo, NS, ht_top, ht_bot, lane, wave);
+  __syncthreads();
+  (void)RBS::gather_even(Be, Bo, Rr, EW, NS, ht_top, ht_bot, lane, wave);
+  float rr = 0.f;
+#pragma unroll
+  for (int r = 0; r < RPW; ++r) {
+    Pr[r] = Rr[r];
+    Xr[r] = 0.f;
+    rr = fmaf(Rr[r], Rr[r], rr);
+  }
+  RBS::store_even_halo(Rr, Pr, NS, hr_top, hp_top, hr_bot, hp_bot, lane, wave);
+  rr = block_sum_f<NW>(rr, fs1, lane, wave);
+  // the odd residual of the full system is zero after the back-substitution, so the reduced
+  // residual is the full one
+  const float stop = rel * rel * rr;
+  float beta = 0.f;
+  int it = 0;
+  const long long t0 = clock64();
+  while (rr > stop && it < maxit) {
+    RBS::gather_odd(Pr, Tr, EW, NS, hr_top, hp_top, hr_bot, hp_bot, beta, lane, wave);
+    RBS::store_odd_halo(Tr, NS, ht_top, ht_bot, lane, wave);
+    __syncthreads();
+    float pq = RBS::gather_even(Pr, Tr, Qr, EW, NS, ht_top, ht_bot, lane, wave);
+    pq = block_sum_f<NW>(pq, fs0, lane, wave);
+    // CG scalars through the hardware reciprocal (about 1 ulp)
+    const float alpha = rr * __builtin_amdgcn_rcpf(pq);
+    float rn = 0.f;
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) {
+      Xr[r] = fmaf(alpha, Pr[r], Xr[r]);
+      Rr[r] = fmaf(-alpha, Qr[r], Rr[r]);
+      rn = fmaf(Rr[r], Rr[r], rn);
+    }
+    RBS::store_even_halo(Rr, Pr, NS, hr_top, hp_top, hr_bot, hp_bot, lane, wave);
+    rn = block_sum_f<NW>(rn, fs1, lane, wave);
+    beta = rn * __builtin_amdgcn_rcpf(rr);
+    rr = rn;
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) Pr[r] = fmaf(beta, Pr[r], Rr[r]);
+    ++it;
+  }
+  const long long cycles = clock64() - t0;
+  // back-substitution x_o = b_o - N_oe x_e (even halo rows of x, beta = 0), then the whole
+  // correction into the owners' xs entries
+  RBS::store_even_halo(Xr, Xr, NS, hr_top, hp_top, hr_bot, hp_bot, lane, wave);
+  __syncthreads();
+  RBS::gather_odd(Xr, Tr, EW, NS, hr_top, hp_top, hr_bot, hp_bot, 0.f, lane, wave);
+#pragma unroll
+  for (int r = 0; r < RPW; ++r) {
+    const int j = j0 + r;
+    const int ce = i0 + (r & 1), co = i0 + 1 - (r & 1);
+    if (j < n && ce < n) xs[j * n + ce] = Xr[r];
+    if (j < n && co < n) xs[j * n + co] = Bo[r] - Tr[r];
+  }
+  return RbPassOut{it, (it >= maxit && rr > stop) ? 1 : 0, cycles};
+}
+
 // LDS: xs[n*n + 2] float32 staging tile of the whole system (+ a spare word pair for lanes
 // outside the grid), halo rows, reduction slots.
 // RB: the float32 solve runs CG on the red-black reduced system (CPL == 2), else Jacobi-PCG
@@ -556,7 +661,6 @@ __global__ __launch_bounds__(64 * NW) void fine2d_resident_kernel(
   const double dmax = dmx[0];
 
   float X[RPW][CPL], R[RPW][CPL], P[RPW][CPL], Q[RPW][CPL];
-  float Xr[RPW], Rr[RPW], Pr[RPW], Qr[RPW], Tr[RPW], Bo[RPW];   // reduced system (RB)
   bool fail = false;
   // owned nodes per group of the float64 loops (residual sweep; increment / state updates)
   constexpr int KG = RPW * CPL < 4 ? RPW * CPL : 4;
@@ -775,74 +879,15 @@ __global__ __launch_bounds__(64 * NW) void fine2d_resident_kernel(
           }
         }
       } else {
-        using RBS = RedBlack<NW, RPW>;
-        // right-hand side b (scaled by 1/sig) split by colour, then the reduced right-hand
-        // side R = b_e - N_eo b_o (the odd values of the boundary rows through the halos)
-        float Be[RPW];
-#pragma unroll
-        for (int r = 0; r < RPW; ++r) {
-          const int j = j0 + r;
-          const int ce = i0 + (r & 1), co = i0 + 1 - (r & 1);
-          Be[r] = (j < n && ce < n) ? xs[j * n + ce] * fis : 0.f;
-          Bo[r] = (j < n && co < n) ? xs[j * n + co] * fis : 0.f;
-        }
-        RBS::store_odd_halo(Bo, NS, ht_top, ht_bot, lane, wave);
-        __syncthreads();
-        (void)RBS::gather_even(Be, Bo, Rr, EW, NS, ht_top, ht_bot, lane, wave);
-        float rr = 0.f;
-#pragma unroll
-        for (int r = 0; r < RPW; ++r) {
-          Pr[r] = Rr[r];
-          Xr[r] = 0.f;
-          rr = fmaf(Rr[r], Rr[r], rr);
-        }
-        RBS::store_even_halo(Rr, Pr, NS, hr_top, hp_top, hr_bot, hp_bot, lane, wave);
-        rr = block_sum_f<NW>(rr, fslots[1], lane, wave);
-        // the odd residual of the full system is zero after the back-substitution, so the
-        // reduced residual is the full one
         const float rel = (float)fmin(0.5, fmax((double)pcg_rtol, kPassMargin * target / rmax));
-        const float stop = rel * rel * rr;
-        float beta = 0.f;
-        int it = 0;
-        const long long t0 = clock64();
-        while (rr > stop && it < maxit) {
-          RBS::gather_odd(Pr, Tr, EW, NS, hr_top, hp_top, hr_bot, hp_bot, beta, lane, wave);
-          RBS::store_odd_halo(Tr, NS, ht_top, ht_bot, lane, wave);
-          __syncthreads();
-          float pq = RBS::gather_even(Pr, Tr, Qr, EW, NS, ht_top, ht_bot, lane, wave);
-          pq = block_sum_f<NW>(pq, fslots[0], lane, wave);
-          const float alpha = rr * __builtin_amdgcn_rcpf(pq);
-          float rn = 0.f;
-#pragma unroll
-          for (int r = 0; r < RPW; ++r) {
-            Xr[r] = fmaf(alpha, Pr[r], Xr[r]);
-            Rr[r] = fmaf(-alpha, Qr[r], Rr[r]);
-            rn = fmaf(Rr[r], Rr[r], rn);
-          }
-          RBS::store_even_halo(Rr, Pr, NS, hr_top, hp_top, hr_bot, hp_bot, lane, wave);
-          rn = block_sum_f<NW>(rn, fslots[1], lane, wave);
-          beta = rn * __builtin_amdgcn_rcpf(rr);
-          rr = rn;
-#pragma unroll
-          for (int r = 0; r < RPW; ++r) Pr[r] = fmaf(beta, Pr[r], Rr[r]);
-          ++it;
-        }
-        t_cg += clock64() - t0;
-        if (it >= maxit && rr > stop) fail = true;
-        tot_it += it;
-        max_it = it > (int)max_it ? it : max_it;
-        // back-substitution x_o = b_o - N_oe x_e (even halo rows of x, beta = 0), then the
-        // whole correction into the owners' xs entries
-        RBS::store_even_halo(Xr, Xr, NS, hr_top, hp_top, hr_bot, hp_bot, lane, wave);
-        __syncthreads();
-        RBS::gather_odd(Xr, Tr, EW, NS, hr_top, hp_top, hr_bot, hp_bot, 0.f, lane, wave);
-#pragma unroll
-        for (int r = 0; r < RPW; ++r) {
-          const int j = j0 + r;
-          const int ce = i0 + (r & 1), co = i0 + 1 - (r & 1);
-          if (j < n && ce < n) xs[j * n + ce] = Xr[r];
-          if (j < n && co < n) xs[j * n + co] = Bo[r] - Tr[r];
-        }
+        const RbPassOut po = rb_pass<NW, RPW>(
+            (lds_float*)xs, fis, sfm, n, g.nx, rel, maxit, (lds_float*)hr_top, (lds_float*)hp_top,
+            (lds_float*)hr_bot, (lds_float*)hp_bot, (lds_float*)ht_top, (lds_float*)ht_bot,
+            (lds_float*)fslots[0], (lds_float*)fslots[1]);
+        t_cg += po.cycles;
+        if (po.capped) fail = true;
+        tot_it += po.it;
+        max_it = po.it > (int)max_it ? po.it : max_it;
       }
       if (pairs) {
 #pragma unroll 1
