@@ -632,6 +632,7 @@ __global__ __launch_bounds__(64 * NW) void fine2d_resident_kernel(
   const double* dv = dinv + m * Nx;
   double* w = out + sys * Nx;
   double* inc = incbuf + sys * Nx;   // increment w_{j+1} - w_j of the current step
+  double* incp = incbuf + ((int64_t)gridDim.x + sys) * Nx;   // the previous step's increment
   const int j0 = wave * RPW;
   const int i0 = lane * CPL;
 
@@ -655,6 +656,7 @@ __global__ __launch_bounds__(64 * NW) void fine2d_resident_kernel(
   for (int64_t p = threadIdx.x; p < Nx; p += blockDim.x) {
     w[p] = src ? src[p] : 0.0;
     inc[p] = 0.0;
+    incp[p] = 0.0;
     dmx[0] = nanmax(dmx[0], 1.0 / (dv[p] * dv[p]));
   }
   block_reduce<1>(dmx, mxd, dslots);   // also orders the copy before the first stencil
@@ -797,11 +799,13 @@ __global__ __launch_bounds__(64 * NW) void fine2d_resident_kernel(
   };
 
   for (int step = 0; step < J; ++step) {
-    // The step is solved for its increment inc = w_{j+1} - w_j, starting from the previous
-    // step's increment: w_{j+1} - w_j = R (w_j - w_{j-1}) with R = (I + tau A)^{-1} for a
-    // constant source, so the starting residual is only tau A (w_j - w_{j-1}) (zero
-    // increment at the first step of a slice).  Each pass recomputes the true float64
-    // residual from w_j and inc; only inc changes during the step.
+    // The step is solved for its increment inc = w_{j+1} - w_j, starting from the earlier
+    // increments: for a constant source inc_j = R inc_{j-1} with R = (I + tau A)^{-1}, so a
+    // mode damped by rho per step leaves (1 - rho) of itself in the guess inc_{j-1} and
+    // (1 - rho)^2 in 2 inc_{j-1} - inc_{j-2}; the slowest modes (rho near 1) dominate
+    // what is left, and the second guess shrinks them by another factor 1 - rho (zero
+    // increment at the first step of a slice, inc_0 at the second).  Each pass recomputes
+    // the true float64 residual from w_j and inc; only inc changes during the step.
     double acc[3];
     residual(acc);
     double rmax = acc[0];
@@ -944,28 +948,36 @@ __global__ __launch_bounds__(64 * NW) void fine2d_resident_kernel(
       fail = true;
       ++missed;
     }
-    // w_{j+1} = w_j + inc
+    // w_{j+1} = w_j + inc, and the next step's starting increment: extrapolated linearly
+    // in the increments, 2 inc_j - inc_{j-1} (inc_j itself after the first step of a slice)
+    const double ka = step > 0 ? 2.0 : 1.0, kb = step > 0 ? -1.0 : 0.0;
     if (pairs) {
 #pragma unroll 1
       for (int r0 = 0; r0 < RPW; r0 += KR) {
-        double2 Wv[KR], I[KR];
+        double2 Wv[KR], I[KR], IP[KR];
 #pragma unroll
         for (int u = 0; u < KR && r0 + u < RPW; ++u) {
           const int j = j0 + r0 + u;
           const int64_t p = (j < n && i0 < n) ? (int64_t)j * n + i0 : 0;
           Wv[u] = ld2(w + p);
           I[u] = ld2(inc + p);
+          IP[u] = ld2(incp + p);
         }
 #pragma unroll
         for (int u = 0; u < KR && r0 + u < RPW; ++u) {
           const int j = j0 + r0 + u;
-          if (j < n && i0 < n) st2(w + (int64_t)j * n + i0, Wv[u].x + I[u].x, Wv[u].y + I[u].y);
+          if (j < n && i0 < n) {
+            const int64_t p = (int64_t)j * n + i0;
+            st2(w + p, Wv[u].x + I[u].x, Wv[u].y + I[u].y);
+            st2(inc + p, ka * I[u].x + kb * IP[u].x, ka * I[u].y + kb * IP[u].y);
+            st2(incp + p, I[u].x, I[u].y);
+          }
         }
       }
     } else
 #pragma unroll 1
     for (int k0 = 0; k0 < RPW * CPL; k0 += KU) {
-      double v[KU];
+      double v[KU], ic[KU], ip[KU];
       int64_t pp[KU];
       bool okk[KU];
 #pragma unroll
@@ -974,15 +986,21 @@ __global__ __launch_bounds__(64 * NW) void fine2d_resident_kernel(
         const int j = j0 + k / CPL, i = i0 + k % CPL;
         const bool ok = j < n && i < n;
         const int64_t p = ok ? (int64_t)j * n + i : 0;
-        v[u] = w[p] + inc[p];
+        ic[u] = inc[p];
+        ip[u] = incp[p];
+        v[u] = w[p] + ic[u];
         pp[u] = p;
         okk[u] = ok;
       }
 #pragma unroll
       for (int u = 0; u < KU; ++u)
-        if (okk[u]) w[pp[u]] = v[u];
+        if (okk[u]) {
+          w[pp[u]] = v[u];
+          inc[pp[u]] = ka * ic[u] + kb * ip[u];
+          incp[pp[u]] = ic[u];
+        }
     }
-    __syncthreads();   // the next residual sweep reads neighbours' w
+    __syncthreads();   // the next residual sweep reads neighbours' w and inc
   }
   if (threadIdx.x == 0) {
     if (fail) atomicOr(flag, 1);
@@ -1261,7 +1279,8 @@ int propagate_impl(klecgc_ctx* ctx, const klecgc_problem& p, const FineArgs& fa,
   const bool scaled = variant != KC_FINE_STREAM64;
   float* sf = scaled ? (float*)ctx->ws.get(WS_FSCALED, sizeof(float) * Fc * M) : nullptr;
   build_tables_2d(st, fa.a, n, c, M, dinv, sf);
-  double* incbuf = resident ? (double*)ctx->ws.get(WS_FINE_INC, sizeof(double) * Nx * nsys) : nullptr;
+  // increments of the current and the previous step per system ([2][nsys][Nx])
+  double* incbuf = resident ? (double*)ctx->ws.get(WS_FINE_INC, 2 * sizeof(double) * Nx * nsys) : nullptr;
   double* scr = variant == KC_FINE_STREAM64 ? (double*)ctx->ws.get(WS_KRYLOV, sizeof(double) * 3 * Nx * nsys)
                                             : nullptr;
   const float pcg_rtol = tu.fine_pcg_rtol;
