@@ -519,14 +519,37 @@ __device__ __attribute__((noinline)) RbPassOut rb_pass(lds_float* xs_l, float fi
   const int j0 = wave * RPW, i0 = lane * 2;
   // negated scaled couplings (0 on boundary faces and outside the grid)
   float EW[RPW][2], NS[RPW][2];
+  if ((n & 1) == 0) {
+    // even n: one 8-byte load per row and kind, every byte of the touched lines used.  The
+    // y-face pair (i0, i0 + 1) is aligned in every row; the x-face pair (i0, i0 + 1) only on
+    // even rows (rows hold n + 1 faces), so odd rows load (i0 + 1, i0 + 2) and take face i0
+    // from the western lane.  Clamped indices keep lanes and rows outside the grid in bounds.
+    const bool lane_ok = i0 < n;
 #pragma unroll
-  for (int r = 0; r < RPW; ++r) {
-    const int j = j0 + r;
+    for (int r = 0; r < RPW; ++r) {
+      const int j = j0 + r;
+      const bool ok = j < n && lane_ok;
+      // rows outside the grid read a row of the same parity (the pair stays 8-byte aligned)
+      const int jc = j < n ? j : ((r & 1) ? n - 1 : n - 2), ic = lane_ok ? i0 : 0;
+      const float2 X2 = *reinterpret_cast<const float2*>(sfm + (int64_t)jc * (n + 1) + ic + (r & 1));
+      const float2 Y2 = *reinterpret_cast<const float2*>(sfm + gnx + (int64_t)jc * n + ic);
+      const float e0 = (r & 1) ? from_west(X2.y) : X2.x;   // face west of column i0
+      const float e1 = (r & 1) ? X2.x : X2.y;              // face between i0 and i0 + 1
+      EW[r][0] = (ok && i0 >= 1) ? -e0 : 0.f;
+      EW[r][1] = (ok && i0 + 1 <= n - 1) ? -e1 : 0.f;
+      NS[r][0] = (ok && j >= 1) ? -Y2.x : 0.f;
+      NS[r][1] = (ok && j >= 1) ? -Y2.y : 0.f;
+    }
+  } else {
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
-      const int col = i0 + t;
-      EW[r][t] = (j < n && col >= 1 && col <= n - 1) ? -sfm[(int64_t)j * (n + 1) + col] : 0.f;
-      NS[r][t] = (col < n && j >= 1 && j <= n - 1) ? -sfm[gnx + (int64_t)j * n + col] : 0.f;
+    for (int r = 0; r < RPW; ++r) {
+      const int j = j0 + r;
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const int col = i0 + t;
+        EW[r][t] = (j < n && col >= 1 && col <= n - 1) ? -sfm[(int64_t)j * (n + 1) + col] : 0.f;
+        NS[r][t] = (col < n && j >= 1 && j <= n - 1) ? -sfm[gnx + (int64_t)j * n + col] : 0.f;
+      }
     }
   }
   // right-hand side b split by colour, then the reduced right-hand side R = b_e - N_eo b_o
