@@ -106,8 +106,9 @@ struct Grid2 {
 };
 
 // D^{-1/2} of M = I + c h^2 A (c = tau / h^2): d_p = 1 + c * (sum of the face coefficients of p)
+// dinvf (nullable) receives the same values rounded to float32.
 __global__ void dinv_kernel(const double* __restrict__ a, int n, double c, int64_t M,
-                            double* __restrict__ dinv) {
+                            double* __restrict__ dinv, float* __restrict__ dinvf) {
   int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t m = blockIdx.y;
   int64_t Nx = (int64_t)n * n;
@@ -116,7 +117,9 @@ __global__ void dinv_kernel(const double* __restrict__ a, int n, double c, int64
   int i = (int)(p % n), j = (int)(p / n);
   const double* af = a + m * 2 * g.nx;
   double d = 1.0 + c * (af[g.fW(i, j)] + af[g.fE(i, j)] + af[g.fS(i, j)] + af[g.fN(i, j)]);
-  dinv[m * Nx + p] = 1.0 / sqrt(d);
+  const double v = 1.0 / sqrt(d);
+  dinv[m * Nx + p] = v;
+  if (dinvf) dinvf[m * Nx + p] = (float)v;
 }
 
 // float32 coefficients of the symmetrically Jacobi-scaled operator D^{-1/2} M D^{-1/2}:
@@ -626,6 +629,7 @@ __device__ __attribute__((noinline)) RbPassOut rb_pass(lds_float* xs_l, float fi
 template <int NW, int CPL, int RPW, bool RB = false>
 __global__ __launch_bounds__(64 * NW) void fine2d_resident_kernel(
     const double* __restrict__ a, const float* __restrict__ sf, const double* __restrict__ dinv,
+    const float* __restrict__ dinvf,
     int n, double c, double tauf, int J, double tol, float pcg_rtol, int maxit, StartRef sr,
     double* __restrict__ out, double* __restrict__ incbuf, int64_t M, int N, int skip_first, const uint8_t* __restrict__ active, int* __restrict__ flag,
     unsigned long long* __restrict__ cnt) {
@@ -653,6 +657,7 @@ __global__ __launch_bounds__(64 * NW) void fine2d_resident_kernel(
   const double* af = a + m * Fc;
   const float* sfm = sf + m * Fc;
   const double* dv = dinv + m * Nx;
+  const float* dvf = dinvf + m * Nx;   // the same, float32: scaling of float32 quantities
   double* w = out + sys * Nx;
   double* inc = incbuf + sys * Nx;   // increment w_{j+1} - w_j of the current step
   double* incp = incbuf + ((int64_t)gridDim.x + sys) * Nx;   // the previous step's increment
@@ -736,7 +741,8 @@ __global__ __launch_bounds__(64 * NW) void fine2d_resident_kernel(
         const bool hn = ok && jc < n - 1;
         const int64_t pn = hn ? p + n : p;
         const double2 Wl = ld2(w + pn), Il = ld2(inc + pn);
-        const double2 D = ld2(dv + p);
+        const float2 Df = *reinterpret_cast<const float2*>(dvf + p);
+        const double2 D = make_double2(Df.x, Df.y);
         const double2 FN = ld2(af + g.fN(ic, jc));
         // x-faces i0, i0 + 1, i0 + 2 of the row: the aligned pair is (i0, i0 + 1) on even
         // rows and (i0 + 1, i0 + 2) on odd ones (rows hold n + 1 faces)
@@ -806,7 +812,7 @@ __global__ __launch_bounds__(64 * NW) void fine2d_resident_kernel(
         const double au = af[g.fW(ic, jc)] * dW + af[g.fE(ic, jc)] * dE + af[g.fS(ic, jc)] * dS +
                           af[g.fN(ic, jc)] * dN;
         const double rv = tauf - c * au - ip;
-        const double dp = dv[p];
+        const double dp = dvf[p];
         rhs[u] = (float)(dp * rv);
         pp[u] = p;
         okk[u] = ok;
@@ -919,23 +925,23 @@ __global__ __launch_bounds__(64 * NW) void fine2d_resident_kernel(
       if (pairs) {
 #pragma unroll 1
         for (int r0 = 0; r0 < RPW; r0 += KR) {   // KR rows' loads in flight, then the stores
-          double2 I[KR], D[KR];
-          float2 Xv[KR];
+          double2 I[KR];
+          float2 D[KR], Xv[KR];
 #pragma unroll
           for (int u = 0; u < KR && r0 + u < RPW; ++u) {
             const int j = j0 + r0 + u;
             const bool ok = j < n && i0 < n;
             const int64_t p = ok ? (int64_t)j * n + i0 : 0;
             I[u] = ld2(inc + p);
-            D[u] = ld2(dv + p);
+            D[u] = *reinterpret_cast<const float2*>(dvf + p);
             Xv[u] = *reinterpret_cast<const float2*>(xs + (ok ? j * n + i0 : n * n));
           }
 #pragma unroll
           for (int u = 0; u < KR && r0 + u < RPW; ++u) {
             const int j = j0 + r0 + u;
             if (j < n && i0 < n)
-              st2(inc + (int64_t)j * n + i0, I[u].x + sig * D[u].x * (double)Xv[u].x,
-                  I[u].y + sig * D[u].y * (double)Xv[u].y);
+              st2(inc + (int64_t)j * n + i0, I[u].x + sig * (double)D[u].x * (double)Xv[u].x,
+                  I[u].y + sig * (double)D[u].y * (double)Xv[u].y);
           }
         }
       } else
@@ -950,7 +956,7 @@ __global__ __launch_bounds__(64 * NW) void fine2d_resident_kernel(
           const int j = j0 + k / CPL, i = i0 + k % CPL;
           const bool ok = j < n && i < n;
           const int64_t p = ok ? (int64_t)j * n + i : 0;
-          v[u] = inc[p] + sig * dv[p] * (double)xs[p];
+          v[u] = inc[p] + sig * (double)dvf[p] * (double)xs[p];
           pp[u] = p;
           okk[u] = ok;
         }
@@ -1238,12 +1244,12 @@ __global__ __launch_bounds__(64 * NW, WPE) void fine2d_mg_kernel(
 
 template <int NW, int CPL, int RPW, bool RB = false>
 void launch_resident(hipStream_t st, int64_t nsys, const double* a, const float* sf,
-                     const double* dinv, int n, double c, double tauf, int J, double tol,
+                     const double* dinv, const float* dinvf, int n, double c, double tauf, int J, double tol,
                      float pcg_rtol, int maxit, StartRef sr, double* out, double* incbuf, int64_t M, int N,
                      int skip_first, const uint8_t* active, int* flag, unsigned long long* cnt) {
   size_t lds = sizeof(float) * ((size_t)n * n + 2);   // n^2 tile + a spare word pair
   fine2d_resident_kernel<NW, CPL, RPW, RB><<<dim3((unsigned)nsys), dim3(64 * NW), lds, st>>>(
-      a, sf, dinv, n, c, tauf, J, tol, pcg_rtol, maxit, sr, out, incbuf, M, N, skip_first, active,
+      a, sf, dinv, dinvf, n, c, tauf, J, tol, pcg_rtol, maxit, sr, out, incbuf, M, N, skip_first, active,
       flag, cnt);
   KC_LAUNCH_CHECK();
 }
@@ -1251,11 +1257,11 @@ void launch_resident(hipStream_t st, int64_t nsys, const double* a, const float*
 }  // namespace
 
 // 2D system tables (float64 D^{-1/2} and float32 scaled coefficients) for tau.
-void build_tables_2d(hipStream_t st, const double* a, int n, double c, int64_t M, double* dinv,
+void build_tables_2d(hipStream_t st, const double* a, int n, double c, int64_t M, double* dinv, float* dinvf,
                      float* sf) {
   int64_t Nx = (int64_t)n * n;
   dim3 b(256);
-  dinv_kernel<<<dim3((unsigned)((Nx + 255) / 256), (unsigned)M), b, 0, st>>>(a, n, c, M, dinv);
+  dinv_kernel<<<dim3((unsigned)((Nx + 255) / 256), (unsigned)M), b, 0, st>>>(a, n, c, M, dinv, dinvf);
   KC_LAUNCH_CHECK();
   if (sf) {
     int64_t Fc = 2LL * n * (n + 1);
@@ -1295,13 +1301,17 @@ int propagate_impl(klecgc_ctx* ctx, const klecgc_problem& p, const FineArgs& fa,
   const int64_t Fc = 2LL * n * (n + 1);
   const double tol = p.inner_rtol > 0 ? p.inner_rtol : 1e-13;
   const int maxit = p.inner_max_iter > 0 ? p.inner_max_iter : 4000;
-  double* dinv = (double*)ctx->ws.get(WS_DINV, sizeof(double) * Nx * M);
+  // float64 D^{-1/2} [M][Nx], then its float32 copy [M][Nx] (the resident kernels scale the
+  // float32 right-hand sides and corrections with it: a consistent scaling, not an accuracy
+  // question, since the float64 residuals alone decide convergence)
+  double* dinv = (double*)ctx->ws.get(WS_DINV, (sizeof(double) + sizeof(float)) * Nx * M);
+  float* dinvf = (float*)(dinv + Nx * M);
   const KcTuning tu = tuning_for(ctx, n);
   const int variant = p.precision == KC_PREC_F32_REFINED ? fine_variant_for(n, tu.fine_variant) : KC_FINE_STREAM64;
   const bool resident = variant != KC_FINE_STREAM64 && variant != KC_FINE_MG;
   const bool scaled = variant != KC_FINE_STREAM64;
   float* sf = scaled ? (float*)ctx->ws.get(WS_FSCALED, sizeof(float) * Fc * M) : nullptr;
-  build_tables_2d(st, fa.a, n, c, M, dinv, sf);
+  build_tables_2d(st, fa.a, n, c, M, dinv, dinvf, sf);
   // increments of the current and the previous step per system ([2][nsys][Nx])
   double* incbuf = resident ? (double*)ctx->ws.get(WS_FINE_INC, 2 * sizeof(double) * Nx * nsys) : nullptr;
   double* scr = variant == KC_FINE_STREAM64 ? (double*)ctx->ws.get(WS_KRYLOV, sizeof(double) * 3 * Nx * nsys)
@@ -1310,24 +1320,24 @@ int propagate_impl(klecgc_ctx* ctx, const klecgc_problem& p, const FineArgs& fa,
   timed(ctx, KT_FINE, [&] {
     switch (variant) {
       case KC_FINE_RES16:
-        launch_resident<8, 1, 2>(st, nsys, fa.a, sf, dinv, n, c, tauf, J, tol, pcg_rtol, maxit, sr, fa.out, incbuf,
+        launch_resident<8, 1, 2>(st, nsys, fa.a, sf, dinv, dinvf, n, c, tauf, J, tol, pcg_rtol, maxit, sr, fa.out, incbuf,
                                  M, N, fa.skip_first, fa.active, flag, cnt);
         break;
       case KC_FINE_RES32:
-        launch_resident<8, 1, 4>(st, nsys, fa.a, sf, dinv, n, c, tauf, J, tol, pcg_rtol, maxit, sr, fa.out, incbuf,
+        launch_resident<8, 1, 4>(st, nsys, fa.a, sf, dinv, dinvf, n, c, tauf, J, tol, pcg_rtol, maxit, sr, fa.out, incbuf,
                                  M, N, fa.skip_first, fa.active, flag, cnt);
         break;
       case KC_FINE_RES64:
-        launch_resident<8, 1, 8>(st, nsys, fa.a, sf, dinv, n, c, tauf, J, tol, pcg_rtol, maxit, sr, fa.out, incbuf,
+        launch_resident<8, 1, 8>(st, nsys, fa.a, sf, dinv, dinvf, n, c, tauf, J, tol, pcg_rtol, maxit, sr, fa.out, incbuf,
                                  M, N, fa.skip_first, fa.active, flag, cnt);
         break;
       case KC_FINE_RES128:
-        launch_resident<KC_RES128_NW, 2, 128 / KC_RES128_NW>(st, nsys, fa.a, sf, dinv, n, c, tauf, J, tol, pcg_rtol,
+        launch_resident<KC_RES128_NW, 2, 128 / KC_RES128_NW>(st, nsys, fa.a, sf, dinv, dinvf, n, c, tauf, J, tol, pcg_rtol,
                                                              maxit, sr, fa.out, incbuf, M, N, fa.skip_first,
                                                              fa.active, flag, cnt);
         break;
       case KC_FINE_RB128:
-        launch_resident<KC_RES128_NW, 2, 128 / KC_RES128_NW, true>(st, nsys, fa.a, sf, dinv, n, c, tauf, J, tol, pcg_rtol,
+        launch_resident<KC_RES128_NW, 2, 128 / KC_RES128_NW, true>(st, nsys, fa.a, sf, dinv, dinvf, n, c, tauf, J, tol, pcg_rtol,
                                                              maxit, sr, fa.out, incbuf, M, N, fa.skip_first,
                                                              fa.active, flag, cnt);
         break;
