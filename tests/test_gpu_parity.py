@@ -80,6 +80,16 @@ def test_fine_2d_f32_refined(ctx, n):
     assert _fine_case(ctx, w, 2, 11, dict(precision=1, inner_rtol=1e-14)) < 1e-11
 
 
+@pytest.mark.parametrize("n,J", [(72, 1), (72, 2), (72, 3), (13, 2), (13, 3), (101, 3), (200, 3)])
+def test_fine_2d_f32_refined_few_steps(ctx, n, J):
+    # the start of step j is 0 (j = 0), inc_0 (j = 1), then 2 inc_{j-1} - inc_{j-2}: slices of
+    # one to three steps cover each rule and the switch between them (resident red-black at 72
+    # and 101, full-system resident at 13, multigrid at 200)
+    log(f"fine 2D f32-refined n={n} J={J}")
+    w = W.small_2d(n=n, N=4, J=J)
+    assert _fine_case(ctx, w, 2, 13, dict(precision=1, inner_rtol=1e-14)) < 1e-11
+
+
 # ---------------------------------------------------------------- coarse correction
 @pytest.mark.parametrize("dim,n,N,alpha", [(1, 31, 8, 1e-2), (1, 127, 16, 1e-2), (1, 5, 2, 0.5),
                                            (2, 12, 8, 1e-2), (2, 20, 16, 1e-4), (2, 1, 4, 0.3)])
