@@ -1081,6 +1081,7 @@ __global__ __launch_bounds__(64 * NW, WPE) void fine2d_mg_kernel(
   double* w = out + sys * Nx;
   double* res = resbuf + (int64_t)blockIdx.x * Nx;
   double* inc = incbuf + (int64_t)blockIdx.x * Nx;
+  double* incp = incbuf + ((int64_t)gridDim.x + blockIdx.x) * Nx;   // the previous step's increment
   float* base = scr + (int64_t)blockIdx.x * h.per_sys;
   float* X = base;
   float* R = X + Nx;
@@ -1108,7 +1109,15 @@ __global__ __launch_bounds__(64 * NW, WPE) void fine2d_mg_kernel(
 
   for (int step = 0; step < J; ++step) {
     if (step > 0) {
-      for (int64_t p = threadIdx.x; p < Nx; p += blockDim.x) w[p] += inc[p];
+      // start from w_j + g with the increment extrapolated from the earlier ones:
+      // g = 2 inc_{j-1} - inc_{j-2} (inc_0 itself at the second step of a slice)
+      for (int64_t p = threadIdx.x; p < Nx; p += blockDim.x) {
+        const double i1 = inc[p];
+        const double gp = step > 1 ? 2.0 * i1 - incp[p] : i1;
+        w[p] += gp;
+        incp[p] = i1;
+        inc[p] = gp;
+      }
       __syncthreads();
     }
     // float64 residual at the start w_j + inc:  tau f - tau A (w_j + inc) - inc
@@ -1345,12 +1354,13 @@ int propagate_impl(klecgc_ctx* ctx, const klecgc_problem& p, const FineArgs& fa,
         // 16 waves per system (the node loops are latency-bound); scratch for at most
         // `chunk` systems at a time, and never fewer than the device keeps in flight
         const MgLevels h = mg_levels(n, 1, 4 * Nx, tu.mg_sweeps, tu.mg_smoother);
-        const int64_t per_sys = (int64_t)sizeof(float) * h.per_sys + 2 * (int64_t)sizeof(double) * Nx;
+        const int64_t per_sys = (int64_t)sizeof(float) * h.per_sys + 3 * (int64_t)sizeof(double) * Nx;
         const int64_t cap_bytes = (int64_t)16 << 30;
         const int64_t chunk = std::min<int64_t>(nsys, std::max<int64_t>(4LL * ctx->num_cus, cap_bytes / per_sys));
         float* scr = (float*)ctx->ws.get(WS_FINE_AUX, sizeof(float) * h.per_sys * chunk);
         double* rb = (double*)ctx->ws.get(WS_KRYLOV, sizeof(double) * Nx * chunk);
-        double* ib = (double*)ctx->ws.get(WS_FINE_INC, sizeof(double) * Nx * chunk);
+        // increments of the current and the previous step per system of a chunk
+        double* ib = (double*)ctx->ws.get(WS_FINE_INC, 2 * sizeof(double) * Nx * chunk);
         for (int64_t s0 = 0; s0 < nsys; s0 += chunk) {
           const int64_t cnt_sys = std::min<int64_t>(chunk, nsys - s0);
           fine2d_mg_kernel<16, 4><<<dim3((unsigned)cnt_sys), dim3(1024), 0, st>>>(
