@@ -16,10 +16,12 @@
 //  * 2D, multigrid-preconditioned: one work-group per system streams float32 vectors and
 //    the V-cycle levels through device memory, for grids too large to stay on the CU.
 #include <cmath>
+#include <type_traits>
 
 #include "common.h"
 #include "mg.h"
 #include "reduce.h"
+#include "xcd.h"
 
 namespace kc {
 
@@ -31,6 +33,9 @@ constexpr int kMaxRefinePasses = 12;
 // margin (the 2-norm reduction that CG measures bounds the max-norm one only loosely; a
 // pass that falls short is followed by another), and never beyond the tuned factor.
 constexpr double kPassMargin = 0.1;
+// what the resident kernels' float64 residual sweep also does (column pairs): nothing, the
+// update that closes the previous step, or the update by the last float32 pass
+constexpr int kSweepPlain = 0, kSweepStart = 1, kSweepCorrect = 2;
 #ifndef KC_RES128_NW
 #define KC_RES128_NW 16
 #endif
@@ -178,7 +183,9 @@ __global__ __launch_bounds__(kStreamThreads) void fine2d_pcg64_kernel(
     unsigned long long* __restrict__ cnt) {
   __shared__ double slots[3 * (kStreamThreads / 64)];
   unsigned long long tot_it = 0, max_it = 0, missed = 0;
-  const int64_t sys = blockIdx.x;
+  // the slices of a sample share its coefficients (and scaled forms): XCD-major order
+  // keeps them under one L2
+  const int64_t sys = xcd_major(blockIdx.x, gridDim.x);
   const int64_t m = sys / N;
   const int s = (int)(sys % N);
   if (active && !active[m]) return;
@@ -646,7 +653,9 @@ __global__ __launch_bounds__(64 * NW) void fine2d_resident_kernel(
   unsigned long long tot_it = 0, tot_pass = 0, max_it = 0, missed = 0;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int64_t sys = blockIdx.x;
+  // the slices of a sample share its coefficients (and scaled forms): XCD-major order
+  // keeps them under one L2
+  const int64_t sys = xcd_major(blockIdx.x, gridDim.x);
   const int64_t m = sys / N;
   const int s = (int)(sys % N);
   if (active && !active[m]) return;
@@ -704,7 +713,17 @@ __global__ __launch_bounds__(64 * NW) void fine2d_resident_kernel(
   // w_j + inc:  tau f - tau A (w_j + inc) - inc, for the nodes this thread owns; it also
   // writes the unnormalised float32 right-hand side D^{-1/2} r of the next pass to xs.
   // acc: max |r|, max |w_j + inc|, max D^{-1/2} |r| over the work-group.
-  auto residual = [&](double (&acc)[3]) {
+  // With column pairs the sweep can also finish the update that precedes it, on each row
+  // as it is read (the state is then read once instead of twice):
+  //  * MODE kSweepStart, the sweep that opens step j >= 1: memory holds w_{j-1}, its
+  //    final increment and the one before; a row becomes w_j = w_{j-1} + inc and the
+  //    starting increment ka inc + kb inc_prev, written back with inc as the new previous
+  //    increment;
+  //  * MODE kSweepCorrect, the sweep after a float32 pass: inc += ka D^{-1/2} x, with the
+  //    pass's solution x in xs.
+  auto residual = [&](double (&acc)[3], auto mode, double ka, double kb) {
+    constexpr int MODE = decltype(mode)::value;
+    constexpr bool FUSED = MODE != kSweepPlain;
     acc[0] = acc[1] = acc[2] = 0.0;
     const bool mx[3] = {true, true, true};
     if (pairs) {
@@ -718,16 +737,59 @@ __global__ __launch_bounds__(64 * NW) void fine2d_resident_kernel(
       const double2 zero2 = make_double2(0.0, 0.0);
       // rows are walked upwards with a window of three rows of w and inc (south, current,
       // north) and the south y-faces carried over, so each row loads only its north row
+      // FUSED: the update of the pair at q (in the grid); Iold: the increment it held
+      auto advance = [&](int64_t q, double2& Wv, double2& Iv, double2& Iold) {
+        const double2 w0 = ld2(w + q), i1 = ld2(inc + q);
+        if constexpr (MODE == kSweepStart) {
+          const double2 i2 = ld2(incp + q);
+          Wv = make_double2(w0.x + i1.x, w0.y + i1.y);
+          Iv = make_double2(ka * i1.x + kb * i2.x, ka * i1.y + kb * i2.y);
+        } else {
+          const float2 Df = *reinterpret_cast<const float2*>(dvf + q);
+          const float2 Xv = *reinterpret_cast<const float2*>(xs + q);
+          Wv = w0;
+          Iv = make_double2(i1.x + ka * (double)Df.x * (double)Xv.x, i1.y + ka * (double)Df.y * (double)Xv.y);
+        }
+        Iold = i1;
+      };
+      // FUSED: the updated pair at q written back
+      auto write_back = [&](int64_t q, const double2& Wv, const double2& Iv, const double2& Iold) {
+        if constexpr (MODE == kSweepStart) {
+          st2(w + q, Wv.x, Wv.y);
+          st2(incp + q, Iold.x, Iold.y);
+        }
+        st2(inc + q, Iv.x, Iv.y);
+      };
       double2 Ws, Is, Wc, Ic, FSc;
+      double2 Wh, Ih;   // FUSED: the first row of the next wave (north halo of the last row)
       {
         const bool ok0 = j0 < n && lane_ok;
         const int jc = ok0 ? j0 : 0;
         const int64_t p = (int64_t)jc * n + ic;
         const bool hs = ok0 && jc > 0;
         const int64_t ps = hs ? p - n : p;
-        Wc = ld2(w + p);
-        Ic = ld2(inc + p);
-        const double2 ws = ld2(w + ps), is = ld2(inc + ps);
+        double2 ws, is;
+        if constexpr (FUSED) {
+          // offsets re-formed at every sweep (opaque to loop-invariant hoisting, whose
+          // nine 64-bit addresses would live in scratch)
+          int64_t q0 = p, qs = ps, qh = j0 + RPW < n && lane_ok ? (int64_t)(j0 + RPW) * n + ic : p;
+          asm volatile("" : "+v"(q0), "+v"(qs), "+v"(qh));
+          double2 I0, Ix;
+          advance(q0, Wc, Ic, I0);
+          advance(qs, ws, is, Ix);
+          advance(qh, Wh, Ih, Ix);
+          // the rows a wave shares with its neighbours (its first and last, their south
+          // and north halos; in xs too) are all read, and the loads complete, before any
+          // is written
+          __builtin_amdgcn_s_waitcnt(0);
+          __syncthreads();
+          if (ok0) write_back(q0, Wc, Ic, I0);
+        } else {
+          Wc = ld2(w + p);
+          Ic = ld2(inc + p);
+          ws = ld2(w + ps);
+          is = ld2(inc + ps);
+        }
         FSc = ld2(af + g.fS(ic, jc));
         Ws = hs ? ws : zero2;
         Is = hs ? is : zero2;
@@ -740,7 +802,20 @@ __global__ __launch_bounds__(64 * NW) void fine2d_resident_kernel(
         const int64_t p = (int64_t)jc * n + ic;
         const bool hn = ok && jc < n - 1;
         const int64_t pn = hn ? p + n : p;
-        const double2 Wl = ld2(w + pn), Il = ld2(inc + pn);
+        double2 Wl, Il;
+        if constexpr (FUSED) {
+          if (r + 1 < RPW) {   // an own row: updated, written back, kept as the window's next
+            double2 Iold;
+            advance(pn, Wl, Il, Iold);
+            if (hn) write_back(pn, Wl, Il, Iold);
+          } else {
+            Wl = Wh;
+            Il = Ih;
+          }
+        } else {
+          Wl = ld2(w + pn);
+          Il = ld2(inc + pn);
+        }
         const float2 Df = *reinterpret_cast<const float2*>(dvf + p);
         const double2 D = make_double2(Df.x, Df.y);
         const double2 FN = ld2(af + g.fN(ic, jc));
@@ -783,6 +858,7 @@ __global__ __launch_bounds__(64 * NW) void fine2d_resident_kernel(
       block_reduce<3>(acc, mx, dslots);
       return;
     }
+    if constexpr (!FUSED) {   // odd n: updates run in their own passes
 #pragma unroll 1
     for (int k0 = 0; k0 < RPW * CPL; k0 += KG) {
       float rhs[KG];
@@ -824,6 +900,7 @@ __global__ __launch_bounds__(64 * NW) void fine2d_resident_kernel(
       for (int u = 0; u < KG; ++u)
         if (okk[u]) xs[pp[u]] = rhs[u];
     }
+    }
     block_reduce<3>(acc, mx, dslots);
   };
 
@@ -836,7 +913,10 @@ __global__ __launch_bounds__(64 * NW) void fine2d_resident_kernel(
     // increment at the first step of a slice, inc_0 at the second).  Each pass recomputes
     // the true float64 residual from w_j and inc; only inc changes during the step.
     double acc[3];
-    residual(acc);
+    if (pairs && step > 0)   // closes step j - 1: w_j, and the start 2 inc_{j-1} - inc_{j-2}
+      residual(acc, std::integral_constant<int, kSweepStart>{}, step > 1 ? 2.0 : 1.0, step > 1 ? -1.0 : 0.0);
+    else
+      residual(acc, std::integral_constant<int, kSweepPlain>{}, 0.0, 0.0);
     double rmax = acc[0];
     double sig = acc[2];   // float32 right-hand sides are normalised by their max
     // The rounding allowance scales with the largest |w_j + inc| the step has reached: a
@@ -923,49 +1003,33 @@ __global__ __launch_bounds__(64 * NW) void fine2d_resident_kernel(
         max_it = po.it > (int)max_it ? po.it : max_it;
       }
       if (pairs) {
+        // the sweep adds sig D^{-1/2} x to inc row by row; it reads the x of its
+        // neighbours' rows, which the pass has just written
+        __syncthreads();
+        residual(acc, std::integral_constant<int, kSweepCorrect>{}, sig, 0.0);
+      } else {
 #pragma unroll 1
-        for (int r0 = 0; r0 < RPW; r0 += KR) {   // KR rows' loads in flight, then the stores
-          double2 I[KR];
-          float2 D[KR], Xv[KR];
+        for (int k0 = 0; k0 < RPW * CPL; k0 += KU) {
+          double v[KU];
+          int64_t pp[KU];
+          bool okk[KU];
 #pragma unroll
-          for (int u = 0; u < KR && r0 + u < RPW; ++u) {
-            const int j = j0 + r0 + u;
-            const bool ok = j < n && i0 < n;
-            const int64_t p = ok ? (int64_t)j * n + i0 : 0;
-            I[u] = ld2(inc + p);
-            D[u] = *reinterpret_cast<const float2*>(dvf + p);
-            Xv[u] = *reinterpret_cast<const float2*>(xs + (ok ? j * n + i0 : n * n));
+          for (int u = 0; u < KU; ++u) {   // branch-free loads (clamped), guarded stores
+            const int k = k0 + u;
+            const int j = j0 + k / CPL, i = i0 + k % CPL;
+            const bool ok = j < n && i < n;
+            const int64_t p = ok ? (int64_t)j * n + i : 0;
+            v[u] = inc[p] + sig * (double)dvf[p] * (double)xs[p];
+            pp[u] = p;
+            okk[u] = ok;
           }
 #pragma unroll
-          for (int u = 0; u < KR && r0 + u < RPW; ++u) {
-            const int j = j0 + r0 + u;
-            if (j < n && i0 < n)
-              st2(inc + (int64_t)j * n + i0, I[u].x + sig * (double)D[u].x * (double)Xv[u].x,
-                  I[u].y + sig * (double)D[u].y * (double)Xv[u].y);
-          }
+          for (int u = 0; u < KU; ++u)
+            if (okk[u]) inc[pp[u]] = v[u];
         }
-      } else
-#pragma unroll 1
-      for (int k0 = 0; k0 < RPW * CPL; k0 += KU) {
-        double v[KU];
-        int64_t pp[KU];
-        bool okk[KU];
-#pragma unroll
-        for (int u = 0; u < KU; ++u) {   // branch-free loads (clamped), guarded stores
-          const int k = k0 + u;
-          const int j = j0 + k / CPL, i = i0 + k % CPL;
-          const bool ok = j < n && i < n;
-          const int64_t p = ok ? (int64_t)j * n + i : 0;
-          v[u] = inc[p] + sig * (double)dvf[p] * (double)xs[p];
-          pp[u] = p;
-          okk[u] = ok;
-        }
-#pragma unroll
-        for (int u = 0; u < KU; ++u)
-          if (okk[u]) inc[pp[u]] = v[u];
+        __syncthreads();   // the residual sweep reads neighbours' inc
+        residual(acc, std::integral_constant<int, kSweepPlain>{}, 0.0, 0.0);
       }
-      __syncthreads();   // the residual sweep reads neighbours' inc
-      residual(acc);
       rmax = acc[0];
       sig = acc[2];
       wref = fmax(wref, acc[1]);
@@ -977,6 +1041,8 @@ __global__ __launch_bounds__(64 * NW) void fine2d_resident_kernel(
       fail = true;
       ++missed;
     }
+    // with column pairs the next step's first sweep closes this one
+    if (pairs && step + 1 < J) continue;
     // w_{j+1} = w_j + inc, and the next step's starting increment: extrapolated linearly
     // in the increments, 2 inc_j - inc_{j-1} (inc_j itself after the first step of a slice)
     const double ka = step > 0 ? 2.0 : 1.0, kb = step > 0 ? -1.0 : 0.0;
