@@ -509,13 +509,15 @@ struct RbPassOut {
   long long cycles;  // shader clocks inside the Krylov loop
 };
 
-// One float32 correction pass of the red-black reduced solve (see RedBlack), outlined from the
-// resident kernel so that its registers are allocated apart from the float64 refinement
-// around it: the caller's live values are saved once per pass instead of spilling into the
-// Krylov loop.  In: the pass's right-hand side D^{-1/2} r / sig in xs (scaled by fis here).
-// Out: the correction of every owned node in xs.  Called by every thread of the work-group.
+// One float32 correction pass of the red-black reduced solve (see RedBlack).  In: the pass's
+// right-hand side D^{-1/2} r / sig in xs (scaled by fis here).  Out: the correction of every
+// owned node in xs.  Called by every thread of the work-group.  Inlined: as a call it would
+// save and restore the ~40 callee-saved VGPRs it uses (v40-47, v56-63, ...) on every pass,
+// some 10 KB of scratch traffic per wave; inlined, its lane and row indices are re-formed at
+// each pass (opaque below), so no address arithmetic is hoisted out of the caller's loops
+// into scratch across the Krylov loop.
 template <int NW, int RPW>
-__device__ __attribute__((noinline)) RbPassOut rb_pass(lds_float* xs_l, float fis, const float* __restrict__ sfm,
+__device__ __forceinline__ RbPassOut rb_pass(lds_float* xs_l, float fis, const float* __restrict__ sfm,
                                                      int n, int64_t gnx, float rel, int maxit, lds_float* hr_top_l,
                                                      lds_float* hp_top_l, lds_float* hr_bot_l, lds_float* hp_bot_l,
                                                      lds_float* ht_top_l, lds_float* ht_bot_l, lds_float* fs0_l,
@@ -524,8 +526,9 @@ __device__ __attribute__((noinline)) RbPassOut rb_pass(lds_float* xs_l, float fi
   float* xs = (float*)xs_l;
   float *hr_top = (float*)hr_top_l, *hp_top = (float*)hp_top_l, *hr_bot = (float*)hr_bot_l, *hp_bot = (float*)hp_bot_l;
   float *ht_top = (float*)ht_top_l, *ht_bot = (float*)ht_bot_l, *fs0 = (float*)fs0_l, *fs1 = (float*)fs1_l;
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  int lane = threadIdx.x & 63;
+  int wave = threadIdx.x >> 6;
+  asm volatile("" : "+v"(lane), "+v"(wave));
   const int j0 = wave * RPW, i0 = lane * 2;
   // negated scaled couplings (0 on boundary faces and outside the grid)
   float EW[RPW][2], NS[RPW][2];
