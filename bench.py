@@ -45,16 +45,29 @@ BYTES_PER_FP64_RESIDUAL_EVAL = 48.0
 BYTES_PER_COCG_UNKNOWN_IT = 128.0      # complex128 vectors streamed per COCG iteration
 
 
+def code_sha256(path: str) -> str:
+    """sha256 of a C++ source with its // comments, trailing blanks and empty lines removed:
+    it changes with the code, not with the comments (the sources hold no string literal
+    containing //)."""
+    import hashlib
+    import re
+    lines = []
+    for line in open(path, encoding="utf-8"):
+        line = re.sub(r"//.*", "", line).rstrip()
+        if line:
+            lines.append(line)
+    return hashlib.sha256("\n".join(lines).encode()).hexdigest()
+
+
 def profiled_traffic(kernel_src: str, profile_json: str):
     """HBM bytes per launch from the committed rocprofv3 counter passes, or None if the
-    kernel source has changed since the counters were taken."""
-    import hashlib
+    kernel source's code has changed since the counters were taken."""
     try:
         prof = json.load(open(os.path.join(ROOT, "profiles", profile_json)))
-        sha = hashlib.sha256(open(os.path.join(ROOT, "paper_2510_26180_amd", "csrc", kernel_src), "rb").read()).hexdigest()
+        sha = code_sha256(os.path.join(ROOT, "paper_2510_26180_amd", "csrc", kernel_src))
     except OSError:
         return None
-    if prof.get("fine_hip_sha256") != sha:
+    if prof.get("fine_hip_code_sha256") != sha:
         return None
     return (prof["fetch_bytes_per_launch"] + prof["write_bytes_per_launch"]) / 1e9
 

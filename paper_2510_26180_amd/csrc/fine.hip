@@ -6,13 +6,15 @@
 //    factorisation tables built once per sample (the matrix is the same for every slice).
 //  * 2D, float64: Jacobi-PCG, one work-group per system streaming its vectors.
 //  * 2D, float32-refined: one work-group of up to 16 waves per system keeps the whole
-//    system on the CU.  The float32 Jacobi-PCG state (x, r, p, q) and the float32 scaled
-//    stencil coefficients live in registers; neighbours cross lanes with DPP shifts and
-//    cross waves through LDS halo rows.  Each step is solved for its increment and
-//    refined in float64: every pass forms the true residual of the step equation in
-//    float64 with float64 coefficients from the state and the increment, float32 PCG
-//    solves for a correction and the increment takes it in float64, until the residual
-//    meets inner_rtol * (|w|_inf + tau |f|) (plus the float64 rounding floor).
+//    system on the CU.  The float32 Krylov state (Jacobi-PCG on the full system, or CG on
+//    the red-black reduced system) and the float32 scaled stencil coefficients live in
+//    registers; neighbours cross lanes with DPP shifts and cross waves through LDS halo
+//    rows.  Each step is solved for its increment and refined in float64: every pass forms
+//    the true residual of the step equation in float64 with float64 coefficients from the
+//    state and the increment, the float32 solve gives a correction and the increment takes
+//    it in float64, until the residual meets inner_rtol * (|w|_inf + tau |f|) (plus the
+//    float64 rounding floor).  With even n each residual sweep also applies the update
+//    that precedes it (the close of the previous step, or the last pass's correction).
 //  * 2D, multigrid-preconditioned: one work-group per system streams float32 vectors and
 //    the V-cycle levels through device memory, for grids too large to stay on the CU.
 #include <cmath>
