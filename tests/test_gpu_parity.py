@@ -1,7 +1,7 @@
 """GPU parity: every C-ABI entry point against the CPU oracle, element by element.
 
 Inputs are seeded and synthetic (workloads); expected values come only from the
-oracle.  Tolerances: 1e-10 relative for float64 paths (the spec bar), with
+oracle.  Tolerances: 1e-10 relative for float64 paths (the stated float64 bar), with
 the coarse correction's bound scaled by the alpha-circulant round-off growth
 alpha^{-(N-1)/N} where stated; iteration counts must be equal.
 """
