@@ -90,6 +90,17 @@ def test_fine_2d_f32_refined_few_steps(ctx, n, J):
     assert _fine_case(ctx, w, 2, 13, dict(precision=1, inner_rtol=1e-14)) < 1e-11
 
 
+@pytest.mark.parametrize("prec,M,N", [(1, 3, 4), (1, 5, 4), (1, 21, 4), (1, 11, 2), (0, 3, 4)])
+def test_fine_2d_work_group_counts(ctx, prec, M, N):
+    # systems are numbered XCD-major: with G = M N work-groups not a multiple of 8 (12, 20,
+    # 84, 22) the first G mod 8 XCDs take one system more; every (sample, slice) result is still
+    # checked against its own start (red-black resident kernel at 72, or float64 PCG)
+    log(f"fine 2D prec={prec} n=72 M={M} N={N}")
+    w = W.small_2d(n=72, N=N, J=4)
+    kw = dict(precision=1, inner_rtol=1e-14) if prec else dict(precision=0, inner_rtol=1e-14)
+    assert _fine_case(ctx, w, M, 17, kw) < 1e-11
+
+
 # ---------------------------------------------------------------- coarse correction
 @pytest.mark.parametrize("dim,n,N,alpha", [(1, 31, 8, 1e-2), (1, 127, 16, 1e-2), (1, 5, 2, 0.5),
                                            (2, 12, 8, 1e-2), (2, 20, 16, 1e-4), (2, 1, 4, 0.3)])
