@@ -110,3 +110,24 @@ def test_transfer_exact_on_piecewise_linear_and_second_order():
         Fc = (np.sin(np.pi * Xc) * np.sin(2 * np.pi * Yc)).ravel()
         errs.append(np.abs(mlp.restrict(F, n, 32) - Fc).max())
     assert errs[0] / errs[1] > 3.0 and errs[1] / errs[2] > 3.0
+
+
+def test_zscore_hand_computed():
+    # three rows: column 0 = (1, 2, 6): mean 3, population variance ((-2)^2 + (-1)^2 + 3^2)/3 = 14/3;
+    # column 1 is constant (deviation 0 -> replaced by 1, z = 0); column 2 = (-1, 0, 1): mean 0,
+    # population std sqrt(2/3) (a sample std, ddof 1, would be 1)
+    Y = np.array([[1.0, 5.0, -1.0], [2.0, 5.0, 0.0], [6.0, 5.0, 1.0]])
+    mu, sd, Z = mlp.zscore(Y)
+    assert np.allclose(mu, [3.0, 5.0, 0.0], rtol=0, atol=1e-15)
+    assert np.allclose(sd, [math.sqrt(14.0 / 3.0), 1.0, math.sqrt(2.0 / 3.0)], rtol=1e-15)
+    assert np.allclose(Z[:, 0], np.array([-2.0, -1.0, 3.0]) / math.sqrt(14.0 / 3.0), rtol=1e-15)
+    assert np.all(Z[:, 1] == 0.0)
+    assert np.allclose(Z[:, 2], np.array([-1.0, 0.0, 1.0]) / math.sqrt(2.0 / 3.0), rtol=1e-15)
+    # invariants: every non-constant column of Z has mean 0 and population variance 1
+    assert np.allclose(Z.mean(0), 0.0, atol=1e-15)
+    assert np.allclose((Z[:, [0, 2]] ** 2).mean(0), 1.0, rtol=1e-14)
+
+
+def test_zscore_single_row_is_constant():
+    mu, sd, Z = mlp.zscore(np.array([[3.0, -4.0]]))
+    assert np.all(mu == [3.0, -4.0]) and np.all(sd == 1.0) and np.all(Z == 0.0)

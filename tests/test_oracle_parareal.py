@@ -94,3 +94,27 @@ def test_alg2_converges_to_serial_fine(dim, n):
     # increments decay geometrically with a rate below the classical bound
     d = np.array(h.deltas)
     assert np.all(d[3:] / d[2:-1] < 0.35)
+
+
+def test_expected_iterations_on_a_geometric_sequence():
+    # an error that shrinks by exactly rho per iteration reaches eps after log(eps/e0)/log(rho)
+    # iterations (Section 3.3 estimate): e0 = 1, rho = 1/2, eps = 2^-10 gives 10
+    assert theory.expected_iterations(2.0 ** -10, 1.0, 0.5) == pytest.approx(10.0, rel=1e-14)
+    assert theory.expected_iterations(1e-8, 1e-2, 0.1) == pytest.approx(6.0, rel=1e-14)
+
+
+def test_expected_iterations_bounds_the_scalar_error_recursion():
+    # Lemma 4.1 on the scalar model problem: |e^k|_inf <= |E|_inf^k |e^0|_inf, so the error meets
+    # eps no later than the estimate taken with rho = |E|_inf
+    N, J, alpha, eps = 16, 32, 1e-2, 1e-10
+    for z in (0.3, 3.0, 30.0):
+        E = theory.error_operator(z, N, J, alpha)
+        rho = np.abs(E).sum(1).max()
+        assert rho < 1
+        e = np.random.default_rng(3).random(N)
+        e0 = np.abs(e).max()
+        k = 0
+        while np.abs(e).max() > eps:
+            e = E @ e
+            k += 1
+        assert k <= int(np.ceil(theory.expected_iterations(eps, e0, rho)))

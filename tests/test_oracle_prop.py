@@ -88,3 +88,34 @@ def test_serial_fine_is_composition():
     P = prop.Propagators(1, 7, a, 1.0, 3, 4, 1.0)
     ref = prop.serial_fine(P, np.zeros(7), 3)
     assert np.allclose(ref[2], P.F(P.F(P.F(np.zeros(7)))), rtol=0, atol=1e-16)
+
+
+@pytest.mark.parametrize("dim,n", [(1, 6), (2, 3)])
+def test_coarse_sweep_closed_form(dim, n):
+    # N backward-Euler steps of size dT from u0: U_s = w* + R_G^s (u0 - w*), R_G = (I + dT A)^{-1},
+    # A w* = g (dense matrix powers; independent of the banded solves and of the loop over slices)
+    rng = np.random.default_rng(11)
+    F = n + 1 if dim == 1 else 2 * n * (n + 1)
+    a = np.exp(0.4 * rng.standard_normal(F))
+    T, N, J, f = 0.7, 5, 3, 1.7
+    P = prop.Propagators(dim, n, a, T, N, J, f)
+    A = op.assemble(dim, n, a).toarray()
+    Nx = A.shape[0]
+    RG = np.linalg.inv(np.eye(Nx) + (T / N) * A)
+    wstar = np.linalg.solve(A, f * np.ones(Nx))
+    u0 = rng.standard_normal(Nx)
+    got = prop.coarse_sweep(P, u0, N)
+    assert got.shape == (N, Nx)
+    for s in range(N):
+        want = wstar + np.linalg.matrix_power(RG, s + 1) @ (u0 - wstar)
+        assert np.abs(got[s] - want).max() <= 1e-13 * np.abs(want).max()
+
+
+def test_coarse_sweep_steady_state_is_fixed():
+    # the steady state A w* = g is a fixed point of every coarse step
+    rng = np.random.default_rng(12)
+    a = np.exp(rng.standard_normal(10))
+    P = prop.Propagators(1, 9, a, 1.0, 4, 2, 2.0)
+    wstar = np.linalg.solve(op.assemble(1, 9, a).toarray(), 2.0 * np.ones(9))
+    got = prop.coarse_sweep(P, wstar, 4)
+    assert np.abs(got - wstar[None, :]).max() <= 1e-13 * np.abs(wstar).max()
