@@ -70,22 +70,46 @@ class ShiftedSolver:
         return spla.splu(Ms.tocsc()).solve(p)
 
 
+class DiagSolver:
+    """Steps (a)-(c) for one sample and one (dT, alpha, N); the N shifted matrices of
+    step (b) do not change between parareal iterations of a linear problem, so each is
+    factorised once, when first needed, and reused (the same solves, not repeated)."""
+
+    def __init__(self, dim: int, n: int, a: np.ndarray, dT: float, alpha: float, N: int):
+        self.N = N
+        self.FN = dft_matrix(N)
+        self.Lam = scaling(N, alpha)
+        self.lam = eigenvalues(N, alpha)
+        self.shifted = ShiftedSolver(dim, n, a, dT)
+        self.lu = [None] * N
+
+    def _solve_k(self, k: int, p: np.ndarray) -> np.ndarray:
+        S = self.shifted
+        if S.dim == 1:
+            return S.solve(self.lam[k], p)
+        if self.lu[k] is None:
+            Ms = self.lam[k] * sp.identity(S.Nx, dtype=np.complex128, format="csr") + S.dT * S.A
+            self.lu[k] = spla.splu(Ms.tocsc())
+        return self.lu[k].solve(p)
+
+    def solve(self, r: np.ndarray) -> np.ndarray:
+        """Solve (C_alpha (x) I + dT I (x) A) u = r; r is [N, Nx] real.  Returns the real
+        part; the imaginary part is checked to vanish (r real)."""
+        assert r.shape[0] == self.N
+        p = self.FN.conj().T @ (self.Lam[:, None] * r)                        # step (a)
+        q = np.stack([self._solve_k(k, p[k]) for k in range(self.N)])         # step (b)
+        u = (1.0 / self.Lam)[:, None] * (self.FN @ q)                           # step (c)
+        scale = max(np.abs(u.real).max(), 1e-300)
+        assert np.abs(u.imag).max() <= 1e-8 * scale, "diagonalised CGC lost conjugate symmetry"
+        return u.real
+
+
 def diag_solve(dim: int, n: int, a: np.ndarray, dT: float, alpha: float, r: np.ndarray) -> np.ndarray:
     """Steps (a)-(c): solve (C_alpha (x) I + dT I (x) A) u = r; r is [N, Nx] real.
 
     Returns the real part; the imaginary part is checked to vanish (r real).
     """
-    N = r.shape[0]
-    FN = dft_matrix(N)
-    Lam = scaling(N, alpha)
-    lam = eigenvalues(N, alpha)
-    p = FN.conj().T @ (Lam[:, None] * r)                     # step (a)
-    S = ShiftedSolver(dim, n, a, dT)
-    q = np.stack([S.solve(lam[k], p[k]) for k in range(N)])   # step (b)
-    u = (1.0 / Lam)[:, None] * (FN @ q)                        # step (c)
-    scale = max(np.abs(u.real).max(), 1e-300)
-    assert np.abs(u.imag).max() <= 1e-8 * scale, "diagonalised CGC lost conjugate symmetry"
-    return u.real
+    return DiagSolver(dim, n, a, dT, alpha, r.shape[0]).solve(r)
 
 
 def all_at_once_matrix(dim: int, n: int, a: np.ndarray, dT: float, alpha: float, N: int) -> sp.csr_matrix:

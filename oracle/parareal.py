@@ -79,11 +79,12 @@ def parareal_diag(props: Propagators, alpha: float, u0: np.ndarray, U0: np.ndarr
     converged = False
     k = 0
     n_max = fixed_iters if fixed_iters is not None else max_iter
+    solver = cgc.DiagSolver(props.dim, props.n, props.a, props.dT, alpha, N)
     while k < n_max:
         starts = [u0] + [U[j - 1] for j in range(1, N)]
         Fv = np.stack([props.F(s) for s in starts])
         r = cgc_rhs(props, alpha, U, Fv)
-        Unew = cgc.diag_solve(props.dim, props.n, props.a, props.dT, alpha, r)
+        Unew = solver.solve(r)
         delta = increment(Unew, U)
         deltas.append(delta)
         U = Unew
