@@ -20,6 +20,8 @@ Modules
   gpc       Hermite gPC basis and least-squares fit (Section 2.2)
   theory    scalar model problem: stability functions and contraction factors
   mlp       learned initial guess (MLP) forward/backward/Adam in FP64
+  guess     random initial guess (counter-based SplitMix64), continuity defect and the
+            learned-guess / gPC fallback rule
 
 Parity status: every function is pinned by a closed form, an invariant or a
 brute-force computation in tests/test_oracle_*.py.  Where the paper is silent
