@@ -7,7 +7,8 @@ first parareal residual is larger: the residual is read as the continuity defect
 guess after the fine sweep of iteration 0,
     d(U^0) = max_n |F(U^0_{n-1}) - U^0_n|_inf / max_n |U^0_n|_inf,   U^0_0 := u0,
 (the jumps the fine propagator leaves between consecutive slices; 1 replaces a zero
-denominator), and the guess with the smaller defect is kept (ties keep the learned guess).
+denominator), and the guess with the smaller defect is kept (ties keep the learned guess; a
+non-finite learned defect counts as larger than any finite fallback defect).
 
 Random numbers: one counter-based generator, SplitMix64 (Steele, Lea and Flood, "Fast
 splittable pseudorandom number generators", OOPSLA 2014): entry i of a guess drawn with seed s
@@ -51,18 +52,19 @@ def random_guess(seed: int, M: int, N: int, Nx: int) -> np.ndarray:
 def continuity_defect(props: Propagators, u0: np.ndarray, U0: np.ndarray) -> float:
     """max_n |F(U^0_{n-1}) - U^0_n|_inf / max_n |U^0_n|_inf for one sample's guess [N][Nx]."""
     N = U0.shape[0]
-    num = 0.0
-    for n in range(N):
-        start = u0 if n == 0 else U0[n - 1]
-        num = max(num, float(np.abs(props.F(start) - U0[n]).max()))
+    if not (np.all(np.isfinite(U0)) and np.all(np.isfinite(u0))):
+        return float("nan")               # F of a non-finite start is not finite
+    jumps = [np.abs(props.F(u0 if n == 0 else U0[n - 1]) - U0[n]).max() for n in range(N)]
+    num = float(np.max(jumps))            # NaN propagates
     den = float(np.abs(U0).max())
     return num / (den if den > 0 else 1.0)
 
 
 def choose_guess(props: Propagators, u0: np.ndarray, U_learned: np.ndarray, U_fallback: np.ndarray):
-    """Keep the learned guess unless the fallback's continuity defect is strictly smaller.
+    """Keep the learned guess unless the fallback's continuity defect is strictly smaller
+    (or the learned one is NaN and the fallback's is not).
     Returns (guess, used_fallback, defect_learned, defect_fallback)."""
     d_l = continuity_defect(props, u0, U_learned)
     d_f = continuity_defect(props, u0, U_fallback)
-    use_f = d_f < d_l
+    use_f = bool(d_f < d_l or (np.isnan(d_l) and not np.isnan(d_f)))
     return (U_fallback if use_f else U_learned), use_f, d_l, d_f

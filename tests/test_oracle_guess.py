@@ -83,3 +83,14 @@ def test_chooser_keeps_the_smaller_defect():
     assert not used_f and g is ref and dl < df
     g, used_f, dl, df = guess.choose_guess(P, u0, bad, bad.copy())
     assert not used_f and dl == df            # ties keep the learned guess
+
+
+def test_chooser_falls_back_from_a_non_finite_learned_guess():
+    rng = np.random.default_rng(24)
+    P = prop.Propagators(1, 9, np.exp(rng.standard_normal(10)), 1.0, 4, 4, 1.0)
+    u0 = np.zeros(9)
+    ref = prop.serial_fine(P, u0, 4)
+    nan_guess = ref.copy()
+    nan_guess[2, 3] = np.nan
+    g, used_f, dl, df = guess.choose_guess(P, u0, nan_guess, ref + 1.0)
+    assert used_f and np.isnan(dl) and np.isfinite(df)
