@@ -59,15 +59,19 @@ def code_sha256(path: str) -> str:
     return hashlib.sha256("\n".join(lines).encode()).hexdigest()
 
 
-def profiled_traffic(kernel_src: str, profile_json: str):
+def profiled_traffic(kernel_src: str, profile_json: str, shape: dict = None):
     """HBM bytes per launch from the committed rocprofv3 counter passes, or None if the
-    kernel source's code has changed since the counters were taken."""
+    kernel source's code has changed since the counters were taken, or if the launch shape
+    (grid size, slices, fine steps, samples, kernel variant, launches) differs from the
+    profiled one."""
     try:
         prof = json.load(open(os.path.join(ROOT, "profiles", profile_json)))
         sha = code_sha256(os.path.join(ROOT, "paper_2510_26180_amd", "csrc", kernel_src))
     except OSError:
         return None
     if prof.get("fine_hip_code_sha256") != sha:
+        return None
+    if shape is not None and prof.get("shape") != shape:
         return None
     return (prof["fetch_bytes_per_launch"] + prof["write_bytes_per_launch"]) / 1e9
 
@@ -76,21 +80,92 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(w, xi_row, iters_mean):
-    """The oracle, single-threaded: one parareal iteration on one sample, scaled."""
-    os.environ.setdefault("OMP_NUM_THREADS", "1")
-    import numpy as np
-    from oracle import field, parareal as opar, prop
+# ---------------------------------------------------------------- CPU leg: the oracle
+# Worker processes are forked before this process touches the GPU, each limited to one BLAS
+# thread; they import the oracle themselves.
+def oracle_workers() -> int:
+    """Single-threaded oracle workers: the host cores this process may use, at most 16 (the
+    CPU share of one GPU), one left for driving the GPU."""
+    return max(1, min(len(os.sched_getaffinity(0)), 16) - 1)
+
+
+def _oracle_init():
+    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[k] = "1"
+
+
+def _oracle_faces(w, xi_row):
+    from oracle import field
     lam, Phi = field.kl_modes(w.dim, w.n, w.d, w.corr_len, w.sigma)
-    a = field.synthesize(lam, Phi, xi_row[None, :])[0]
+    return field.synthesize(lam, Phi, xi_row[None, :])[0]
+
+
+def _oracle_serial_fine(job):
+    """The oracle's FP64 serial fine solution of one sample, and its time."""
+    w, xi_row = job
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    from oracle import prop
+    with threadpool_limits(1):
+        a = _oracle_faces(w, xi_row)
+        t0 = time.perf_counter()
+        P = prop.Propagators(w.dim, w.n, a, w.T, w.N, w.J, w.forcing)
+        ref = prop.serial_fine(P, np.zeros(w.Nx), w.N)
+        return ref, time.perf_counter() - t0
+
+
+def _oracle_two_iterations(job):
+    """Two parareal iterations (Algorithm 2, diagonalised CGC) of the oracle on one sample:
+    the seconds of the first (which also factorises the shifted systems) and of the second."""
+    w, xi_row = job
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    from oracle import parareal as opar, prop
+    with threadpool_limits(1):
+        a = _oracle_faces(w, xi_row)
+        t0 = time.perf_counter()
+        P = prop.Propagators(w.dim, w.n, a, w.T, w.N, w.J, w.forcing)
+        opar.parareal_diag(P, w.alpha, np.zeros(w.Nx), np.zeros((w.N, w.Nx)), w.tol, 1, fixed_iters=1)
+        t1 = time.perf_counter() - t0
+        opar.parareal_diag(P, w.alpha, np.zeros(w.Nx), np.zeros((w.N, w.Nx)), w.tol, 2, fixed_iters=2)
+        t2 = time.perf_counter() - t0 - t1
+        return t1, max(t2 - t1, 0.0)
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(pool, P, w, xi, subset, iters_mean):
+    """The oracle on the host cores: (i) its FP64 serial fine solution of the seeded subset
+    of evaluation samples (the accuracy reference of those samples), (ii) two parareal
+    iterations on each of P samples, one per worker.  Oracle solves/s = P / (first iteration +
+    (mean GPU iteration count - 1) x later iteration), the whole pool busy."""
     t0 = time.perf_counter()
-    P = prop.Propagators(w.dim, w.n, a, w.T, w.N, w.J, w.forcing)
-    opar.parareal_diag(P, w.alpha, np.zeros(w.Nx), np.zeros((w.N, w.Nx)), w.tol, 1, fixed_iters=1)
-    t_iter = time.perf_counter() - t0
-    t_solve = t_iter * iters_mean
-    return {"value": 1.0 / t_solve, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": f"1 sample x 1 parareal iteration ({w.N} slices x {w.J} BE steps + diagonalised CGC)"
-                      f" = {t_iter:.1f} s, scaled by the measured mean iteration count {iters_mean:.2f}"}
+    refs = pool.map(_oracle_serial_fine, [(w, xi[m]) for m in subset], chunksize=1)
+    t_ref = time.perf_counter() - t0
+    log(f"oracle serial fine on {len(subset)} samples: {t_ref:.1f} s with {P} workers")
+    rows = [xi[int(m) % len(xi)] for m in range(P)]
+    t0 = time.perf_counter()
+    its = pool.map(_oracle_two_iterations, [(w, r) for r in rows], chunksize=1)
+    t_its = time.perf_counter() - t0
+    t_first = sum(t for t, _ in its) / len(its)
+    t_next = sum(t for _, t in its) / len(its)
+    t_solve = t_first + max(iters_mean - 1.0, 0.0) * t_next
+    log(f"oracle parareal: first iteration {t_first:.1f} s, later {t_next:.1f} s per sample ({t_its:.1f} s wall)")
+    base = {"value": P / t_solve, "unit": "solves/s", "cores": P, "kind": "oracle", "cpu": cpu_model(),
+            "sample": f"{P} samples x 2 parareal iterations ({w.N} slices x {w.J} BE steps + diagonalised CGC), "
+                      f"one per single-threaded worker: first {t_first:.1f} s, later {t_next:.1f} s per iteration; "
+                      f"a solve = first + ({iters_mean:.2f} - 1) later iterations (mean GPU count)",
+            "serial_fine_solves_per_s": len(subset) / t_ref, "serial_fine_sample": f"{len(subset)} samples, "
+            f"{t_ref:.1f} s wall on {P} workers (the accuracy reference of the oracle subset)"}
+    return base, [r for r, _ in refs]
 
 
 def run_ragged(args):
@@ -143,7 +218,7 @@ def run_ragged(args):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         its, st, lat, total, rc = ctx.parareal_solve_batch(base, tasks, a_d, U, init=K.KC_INIT_COARSE, graph=graph,
-                                                           allow_noconv=True)
+                                                           allow_noconv=True, progress=True)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         runs[graph] = dict(its=its, st=st, lat=lat, total=total, wall=wall, rc=rc)
@@ -203,9 +278,13 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="keep the built-in kernel choices")
     ap.add_argument("--grids", default="", help="ragged batch: comma-separated grid sizes (default 64,128,256)")
     ap.add_argument("--compare-eager", action="store_true", help="ragged batch: also run without the HIP graph")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-oracle-check", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the oracle leg (CPU baseline and the oracle accuracy subset)")
+    ap.add_argument("--no-oracle-check", action="store_true", help="same as --no-cpu-baseline")
+    ap.add_argument("--oracle-subset", type=int, default=16, help="evaluation samples checked against the oracle")
+    ap.add_argument("--oracle-workers", type=int, default=0, help="oracle worker processes (0 = host cores, <= 15)")
     args = ap.parse_args()
+    args.no_cpu_baseline = args.no_cpu_baseline or args.no_oracle_check
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; sharding the batch over "
                                    "several GPUs is not built"}))
@@ -214,6 +293,12 @@ def main():
     if args.config == "c3_ragged":
         run_ragged(args)
         return
+
+    pool, P = None, 0
+    if not args.no_cpu_baseline:
+        import multiprocessing as mp
+        P = args.oracle_workers or oracle_workers()
+        pool = mp.get_context("fork").Pool(P, initializer=_oracle_init)   # before any GPU call
 
     import numpy as np
     import torch
@@ -311,6 +396,8 @@ def main():
             return ctx.parareal_solve(prob, a_eval, U, init=K.KC_INIT_GIVEN, init_U=U, allow_noconv=True)
         return ctx.parareal_solve(prob, a_eval, U, init=K.KC_INIT_GPC, gpc=gpc, xi=xi_eval, allow_noconv=True)
 
+    # the seeded subset of evaluation samples checked against the oracle's serial fine solution
+    subset = W.draw_subset(w.M, min(args.oracle_subset, w.M), w.seed_eval + 7)
     # accuracy reference: batched GPU serial fine for every evaluation sample
     ref = torch.empty_like(U)
     torch.cuda.synchronize()
@@ -341,24 +428,11 @@ def main():
         stats = ctx.last_stats()
         err = ((U - ref).abs().amax(dim=(1, 2)) / refmax).cpu().numpy()
         results[kind] = dict(ms_per_step=1e3 * t_steps / args.steps, its=its, err=err, ktimes=ktimes, e0=e0,
-                             stats=stats, U0=U[0].cpu().numpy() if kind == inits[0] else None)
+                             stats=stats, U_sub=U[subset].cpu().numpy() if kind == inits[0] else None)
     primary = results[inits[0]]
     ms_per_step, its, err, ktimes, stats = (primary[k] for k in ("ms_per_step", "its", "err", "ktimes", "stats"))
     n_ok = int((err <= 1e-8).sum())
     value = n_ok / (ms_per_step / 1e3)
-    oracle_check = None
-    if not args.no_oracle_check:
-        from oracle import field, prop
-        lam, Phi = field.kl_modes(w.dim, w.n, w.d, w.corr_len, w.sigma)
-        a0 = field.synthesize(lam, Phi, xi_eval_np[:1])[0]
-        P = prop.Propagators(w.dim, w.n, a0, w.T, w.N, w.J, w.forcing)
-        ref_o = prop.serial_fine(P, np.zeros(w.Nx), w.N)
-        U0 = primary["U0"]
-        R0 = ref[0].cpu().numpy()
-        oracle_check = {"sample": 0,
-                        "parareal_vs_oracle_serial_fine": float(np.abs(U0 - ref_o).max() / np.abs(ref_o).max()),
-                        "gpu_serial_fine_vs_oracle": float(np.abs(R0 - ref_o).max() / np.abs(ref_o).max())}
-        log(f"oracle check: {oracle_check}")
 
     # ---- roofline of the dominant kernel (HIP-event time of the last timed step)
     dom = max(ktimes, key=lambda k: ktimes[k][0])
@@ -372,7 +446,8 @@ def main():
         evals = stats["fine_passes"] + stats["fine_solves"]   # float64 residual evaluations
         byts = BYTES_PER_FP64_RESIDUAL_EVAL * w.Nx * evals
         secs = dom_ms / 1e3
-        traffic = profiled_traffic("fine.hip", "fine2d_resident_c2_traffic.json")
+        shape = {"n": w.n, "N": w.N, "J": w.J, "M": w.M, "variant": fv, "launches": dom_n}
+        traffic = profiled_traffic("fine.hip", "fine2d_resident_c2_traffic.json", shape)
         ms_launch = dom_ms / max(dom_n, 1)
         fine_hbm = None if traffic is None else {
             "GB_per_s": traffic / (ms_launch / 1e3), "frac_of_peak": traffic / (ms_launch / 1e3) / PEAK_HBM_GBS,
@@ -409,8 +484,8 @@ def main():
                    "samples": w.M, "grid": w.n, "slices": w.N, "fine_steps": w.J},
         "iters": {"mean": float(its.mean()), "max": int(its.max()), "min": int(its.min()),
                   "hist": {int(k): int(v) for k, v in zip(*np.unique(its, return_counts=True))}},
-        "accuracy": {"n_within_1e-8": n_ok, "max_rel_err_vs_serial_fine": float(err.max()),
-                     "median_rel_err": float(np.median(err)), "oracle_check": oracle_check},
+        "accuracy": {"n_within_1e-8": n_ok, "reference": "batched GPU serial fine (float64 residuals to 1e-13)",
+                     "max_rel_err_vs_serial_fine": float(err.max()), "median_rel_err": float(np.median(err))},
         "serial_fine_gpu": {"solves_per_s": w.M / t_serial, "ms": 1e3 * t_serial},
         "offline_s": t_offline,
         "offline": offline,
@@ -431,9 +506,20 @@ def main():
                                "max_rel_err": float(r["err"].max()),
                                "init_err_median": float(np.median(r["e0"])), "init_err_max": float(r["e0"].max())}
                            for k, r in results.items()}
-    if not args.no_cpu_baseline:
-        log("timing the CPU oracle on a bounded sample")
-        line["cpu_baseline"] = cpu_baseline(w, xi_eval_np[0], float(its.mean()))
+    if pool is not None:
+        log(f"oracle leg: serial fine on {len(subset)} evaluation samples and the CPU baseline, {P} workers")
+        base, refs = cpu_baseline(pool, P, w, xi_eval_np, subset, float(its.mean()))
+        pool.close()
+        line["cpu_baseline"] = base
+        Ug = primary["U_sub"]
+        Rg = ref[subset].cpu().numpy()
+        e_par = [float(np.abs(Ug[j] - r).max() / np.abs(r).max()) for j, r in enumerate(refs)]
+        e_ser = [float(np.abs(Rg[j] - r).max() / np.abs(r).max()) for j, r in enumerate(refs)]
+        line["accuracy"]["oracle_subset"] = {
+            "samples": [int(m) for m in subset], "n_within_1e-8": int(sum(e <= 1e-8 for e in e_par)),
+            "max_rel_err_parareal_vs_oracle_serial_fine": max(e_par),
+            "max_rel_err_gpu_serial_fine_vs_oracle": max(e_ser)}
+        log(f"oracle subset: {line['accuracy']['oracle_subset']}")
     print(json.dumps(line), flush=True)
     ctx.close()
 

@@ -52,7 +52,9 @@ enum {
 
 enum { KC_PREC_F64 = 0, KC_PREC_F32_REFINED = 1 };
 enum { KC_KLE_FIELD_EXP = 0, KC_KLE_SNAPSHOT = 1 };
-enum { KC_INIT_GIVEN = 0, KC_INIT_ZERO = 1, KC_INIT_COARSE = 2, KC_INIT_GPC = 3 };
+/* initial guess of parareal_solve (Algorithm 3 step 6 and the comparators of Section 5) */
+enum { KC_INIT_GIVEN = 0, KC_INIT_ZERO = 1, KC_INIT_COARSE = 2, KC_INIT_GPC = 3, KC_INIT_RANDOM = 4,
+       KC_INIT_MLP = 5, KC_INIT_MLP_GPC_FALLBACK = 6 };
 /* per-sample status written by parareal_solve */
 enum { KC_SAMPLE_CONVERGED = 0, KC_SAMPLE_MAXITER = 1, KC_SAMPLE_NONFINITE = 2 };
 
@@ -180,9 +182,10 @@ const char* klecgc_version(void);
 int kle_build(klecgc_ctx* ctx, const klecgc_kle_desc* desc, const double* S_dev, int64_t n_t,
               klecgc_kle** out, int32_t* n_modes);
 /* kle_synthesize: a[m][f] = exp(sum_k sqrt(lam_k) phi_k(face f) xi[m][k]) for a
- * FIELD_EXP handle.  xi_dev [M][d] float64, a_dev [M][Fc] float64. */
+ * FIELD_EXP handle.  xi_dev [M][d] float64, a_dev [M][Fc] float64; a32_dev [M][Fc]
+ * float32 (nullable) receives the same values rounded to nearest float32. */
 int kle_synthesize(klecgc_ctx* ctx, const klecgc_kle* field, const double* xi_dev, int64_t M,
-                   double* a_dev);
+                   double* a_dev, float* a32_dev);
 /* Copy a SNAPSHOT handle's mean [L] and scaled basis W = diag(sqrt(lam)) G
  * [M_Q][L] (row k = sqrt(lam_k) g_k) and eigenvalues [M_Q] to caller device memory
  * (any pointer may be NULL). */
@@ -208,13 +211,15 @@ int gpc_predict(klecgc_ctx* ctx, const klecgc_gpc* gpc, const double* xi_dev, in
  * slice s, J backward-Euler steps of size dt = T/(N J) from start[m][s]:
  *     (I + dt A_m) w_{j+1} = w_j + dt f,   end[m][s] = w_J.
  * a_dev [M][Fc], start_dev and end_dev [M][N][Nx] float64 (may not alias).
+ * active_dev [M] (nullable = all samples): samples with active_dev[m] == 0 are skipped
+ * and their rows of end_dev are left untouched.
  * 1D: direct tridiagonal (Thomas) solves in float64.
  * 2D: precision F64 -> float64 Jacobi-PCG to inner_rtol; F32_REFINED ->
- * float32 Jacobi-PCG corrections with float64 residuals and coefficients
+ * float32 Krylov corrections with float64 residuals and coefficients
  * until the float64 residual meets inner_rtol.  Returns KC_ENOCONV if a
  * solve hits inner_max_iter (results are still written). */
 int fine_propagate(klecgc_ctx* ctx, const klecgc_problem* prob, const double* a_dev,
-                   const double* start_dev, int64_t M, double* end_dev);
+                   const double* start_dev, int64_t M, double* end_dev, const uint8_t* active_dev);
 /* cgc_diag_solve (Section 3.2, eq. matrix_NT and eq. three-steps): solves
  *     (C_alpha (x) I + dT I (x) A_m) u_m = r_m   for every sample m,
  * C_alpha the alpha-circulant time matrix, by (a) p = F_N^* Lambda r (real FFT
@@ -239,12 +244,31 @@ int serial_fine_propagate(klecgc_ctx* ctx, const klecgc_problem* prob, const dou
 /* ---- driver (Algorithms 2 and 3) ----------------------------------------- */
 /* parareal_solve: parareal with diagonalised CGC for M samples.
  *   u0_dev [M][Nx] or NULL (zero initial condition);
- *   init: KC_INIT_GIVEN (init_dev [M][N][Nx]), KC_INIT_ZERO, KC_INIT_COARSE
- *         (one sequential G sweep), KC_INIT_GPC (gpc + xi_dev [M][d]);
+ *   init (the initial guess U^0 [M][N][Nx]):
+ *     KC_INIT_GIVEN   init_dev [M][N][Nx];
+ *     KC_INIT_ZERO    U^0 = 0;
+ *     KC_INIT_COARSE  one sequential G sweep from u0 (Section 3.1);
+ *     KC_INIT_GPC     the gPC surrogate at xi_dev [M][d] (Algorithm 3 step 6; gpc required);
+ *     KC_INIT_RANDOM  the random guess of the comparators of Section 5: entry i of U^0
+ *                     (row-major over [M][N][Nx]) is the SplitMix64 output (Steele, Lea
+ *                     and Flood, OOPSLA 2014) of the state seed + (i+1) 0x9E3779B97F4A7C15
+ *                     (mod 2^64), its top 53 bits times 2^-53, i.i.d. U(0,1);
+ *     KC_INIT_MLP     the learned guess of mlp_initial_guess at xi_dev [M][n_in] (mlp
+ *                     required; its n_out must be N nc^2, nc the restricted grid);
+ *     KC_INIT_MLP_GPC_FALLBACK  both the learned and the gPC guess (mlp, gpc, xi_dev
+ *                     required); iteration 0's fine sweep runs on each, and a sample keeps
+ *                     the gPC guess when its continuity defect
+ *                         max_s |F(U^0_{s-1}) - U^0_s|_inf / max_s |U^0_s|_inf  (U^0_{-1} = u0)
+ *                     is strictly smaller than the learned guess's, or when the learned
+ *                     one's is NaN and the gPC one's is not (one fine sweep more than
+ *                     KC_INIT_MLP; the sweep of the kept guess is iteration 0's);
+ *   seed: KC_INIT_RANDOM only;
  *   U_dev [M][N][Nx] receives U^k at each sample's stop;
  *   iters_host [M], status_host [M] (KC_SAMPLE_*) host arrays;
  *   delta_hist_host [M][max_iter] (nullable) receives the increments
- *   (unused entries set to 0).
+ *   (unused entries set to 0);
+ *   guess_host [M] (nullable) receives the guess each sample started from: init, or
+ *   KC_INIT_GPC for a sample that KC_INIT_MLP_GPC_FALLBACK moved to the gPC guess.
  * Each iteration: fine sweep over all active (sample, slice) pairs (the first
  * slice's F(u0) is computed once), defect d_s = (I + dT A)(F_s - U_s), one
  * cgc_diag_solve, U += correction; a sample stops when its increment
@@ -253,8 +277,9 @@ int serial_fine_propagate(klecgc_ctx* ctx, const klecgc_problem* prob, const dou
  * all-at-once system for U^{k+1} - U^k). */
 int parareal_solve(klecgc_ctx* ctx, const klecgc_problem* prob, const double* a_dev,
                    const double* u0_dev, int64_t M, int32_t init, const double* init_dev,
-                   const klecgc_gpc* gpc, const double* xi_dev, double* U_dev,
-                   int32_t* iters_host, int32_t* status_host, double* delta_hist_host);
+                   const klecgc_gpc* gpc, klecgc_mlp* mlp, const double* xi_dev, uint64_t seed,
+                   double* U_dev, int32_t* iters_host, int32_t* status_host,
+                   double* delta_hist_host, int32_t* guess_host);
 
 /* ---- ragged batches ------------------------------------------------------------
  * Samples of one problem family that differ in grid size n and slice count N, solved
@@ -280,7 +305,9 @@ typedef struct {
   int64_t face_off;   /* element offset of the sample's faces in a_dev */
   int64_t state_off;  /* element offset of the sample's N * n^dim states in U_dev */
 } klecgc_task;
-enum { KC_BATCH_GRAPH = 1 };
+/* flags: KC_BATCH_GRAPH as above; KC_BATCH_PROGRESS prints one line per iteration to stderr
+ * (iteration index, samples still active, elapsed seconds) so a long call is never silent */
+enum { KC_BATCH_GRAPH = 1, KC_BATCH_PROGRESS = 2 };
 int parareal_solve_batch(klecgc_ctx* ctx, const klecgc_problem* base, const klecgc_task* tasks,
                          int64_t M, const double* a_dev, int32_t init, double* U_dev, int32_t flags,
                          int32_t* iters_host, int32_t* status_host, double* latency_ms_host,

@@ -15,6 +15,7 @@ ERRORS = {
 KC_PREC_F64, KC_PREC_F32_REFINED = 0, 1
 KC_KLE_FIELD_EXP, KC_KLE_SNAPSHOT = 0, 1
 KC_INIT_GIVEN, KC_INIT_ZERO, KC_INIT_COARSE, KC_INIT_GPC = 0, 1, 2, 3
+KC_INIT_RANDOM, KC_INIT_MLP, KC_INIT_MLP_GPC_FALLBACK = 4, 5, 6
 KC_SAMPLE_CONVERGED, KC_SAMPLE_MAXITER, KC_SAMPLE_NONFINITE = 0, 1, 2
 
 
@@ -43,7 +44,7 @@ class Task(ctypes.Structure):
                 ("state_off", ctypes.c_int64)]
 
 
-KC_BATCH_GRAPH = 1
+KC_BATCH_GRAPH, KC_BATCH_PROGRESS = 1, 2
 KC_FINE_STREAM64, KC_FINE_RES16, KC_FINE_RES32, KC_FINE_RES64, KC_FINE_RES128, KC_FINE_MG, KC_FINE_RB128 = 0, 1, 2, 3, 4, 5, 6
 KC_CGC_STREAM64, KC_CGC_RES16, KC_CGC_RES32, KC_CGC_RES64, KC_CGC_STREAM32, KC_CGC_MG32 = 0, 1, 2, 3, 4, 5
 
@@ -74,15 +75,16 @@ SIGNATURES = {
     "klecgc_autotune": (ctypes.c_int, [_vp, _P(Problem), _vp, _i64, _P(Tuning), _P(ctypes.c_double)]),
     "serial_fine_propagate": (ctypes.c_int, [_vp, _P(Problem), _vp, _vp, _i64, _vp]),
     "kle_build": (ctypes.c_int, [_vp, _P(KleDesc), _vp, _i64, _P(_vp), _P(_i32)]),
-    "kle_synthesize": (ctypes.c_int, [_vp, _vp, _vp, _i64, _vp]),
+    "kle_synthesize": (ctypes.c_int, [_vp, _vp, _vp, _i64, _vp, _vp]),
     "kle_export": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "gpc_fit": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, _i32, _P(_vp), _P(_i32)]),
     "gpc_predict": (ctypes.c_int, [_vp, _vp, _vp, _i64, _vp]),
-    "fine_propagate": (ctypes.c_int, [_vp, _P(Problem), _vp, _vp, _i64, _vp]),
+    "fine_propagate": (ctypes.c_int, [_vp, _P(Problem), _vp, _vp, _i64, _vp, _vp]),
     "cgc_diag_solve": (ctypes.c_int, [_vp, _P(Problem), _vp, _vp, _i64, _vp]),
     "coarse_propagate": (ctypes.c_int, [_vp, _P(Problem), _vp, _vp, _i64, _vp]),
     "parareal_solve": (ctypes.c_int, [_vp, _P(Problem), _vp, _vp, _i64, _i32, _vp, _vp, _vp, _vp,
-                                      _P(_i32), _P(_i32), _P(ctypes.c_double)]),
+                                      ctypes.c_uint64, _vp, _P(_i32), _P(_i32), _P(ctypes.c_double),
+                                      _P(_i32)]),
     "parareal_solve_batch": (ctypes.c_int, [_vp, _P(Problem), _P(Task), _i64, _vp, _i32, _vp, _i32,
                                             _P(_i32), _P(_i32), _P(ctypes.c_double), _P(ctypes.c_double)]),
     "mlp_create": (ctypes.c_int, [_vp, _i32, _i32, _i64, _P(_vp), _P(_i64)]),

@@ -179,8 +179,8 @@ class Context:
         self._check(self.lib.kle_build(self.h, ctypes.byref(desc), _ptr(S), n_t, ctypes.byref(out), ctypes.byref(nm)))
         return Handle(out.value, self.lib.klecgc_kle_free, n_modes=nm.value, L=Lrow, n_t=n_t)
 
-    def kle_synthesize(self, field: Handle, xi, a):
-        self._check(self.lib.kle_synthesize(self.h, field.ptr, _ptr(xi), xi.shape[0], _ptr(a)))
+    def kle_synthesize(self, field: Handle, xi, a, a32=None):
+        self._check(self.lib.kle_synthesize(self.h, field.ptr, _ptr(xi), xi.shape[0], _ptr(a), _ptr(a32)))
         return a
 
     def kle_export(self, snap: Handle, mean=None, W=None, lam=None):
@@ -198,9 +198,10 @@ class Context:
         return U0
 
     # ---- parareal pieces
-    def fine_propagate(self, prob: ProblemSpec, a, start, end, allow_noconv=False) -> int:
+    def fine_propagate(self, prob: ProblemSpec, a, start, end, allow_noconv=False, active=None) -> int:
         pc = prob.c()
-        return self._check(self.lib.fine_propagate(self.h, ctypes.byref(pc), _ptr(a), _ptr(start), start.shape[0], _ptr(end)),
+        return self._check(self.lib.fine_propagate(self.h, ctypes.byref(pc), _ptr(a), _ptr(start), start.shape[0],
+                                                   _ptr(end), _ptr(active)),
                            allow=(-5,) if allow_noconv else ())
 
     def cgc_diag_solve(self, prob: ProblemSpec, a, r, u, allow_noconv=False) -> int:
@@ -218,20 +219,27 @@ class Context:
         return self._check(self.lib.coarse_propagate(self.h, ctypes.byref(pc), _ptr(a), _ptr(u0), U.shape[0], _ptr(U)))
 
     def parareal_solve(self, prob: ProblemSpec, a, U, u0=None, init: int = L.KC_INIT_ZERO, init_U=None,
-                       gpc: Optional[Handle] = None, xi=None, allow_noconv=False):
+                       gpc: Optional[Handle] = None, xi=None, allow_noconv=False, mlp: Optional[Handle] = None,
+                       seed: int = 0, guess_out: Optional[np.ndarray] = None):
+        """Returns (iters, status, increment history, rc); guess_out [M] int32 (optional)
+        receives the guess each sample started from."""
         M = U.shape[0]
         iters = (ctypes.c_int32 * M)()
         status = (ctypes.c_int32 * M)()
         hist = (ctypes.c_double * (M * prob.max_iter))()
+        guess = (ctypes.c_int32 * M)()
         pc = prob.c()
         rc = self.lib.parareal_solve(self.h, ctypes.byref(pc), _ptr(a), _ptr(u0), M, init, _ptr(init_U),
-                                     gpc.ptr if gpc is not None else None, _ptr(xi), _ptr(U), iters, status, hist)
+                                     gpc.ptr if gpc is not None else None, mlp.ptr if mlp is not None else None,
+                                     _ptr(xi), ctypes.c_uint64(seed), _ptr(U), iters, status, hist, guess)
         self._check(rc, allow=(-5,) if allow_noconv else ())
+        if guess_out is not None:
+            guess_out[:] = np.frombuffer(guess, dtype=np.int32)
         return (np.frombuffer(iters, dtype=np.int32).copy(), np.frombuffer(status, dtype=np.int32).copy(),
                 np.frombuffer(hist, dtype=np.float64).reshape(M, prob.max_iter).copy(), rc)
 
     def parareal_solve_batch(self, base: ProblemSpec, tasks, a, U, init: int = L.KC_INIT_ZERO, graph: bool = True,
-                             allow_noconv=False):
+                             allow_noconv=False, progress: bool = False):
         """tasks: sequence of (n, N, face_off, state_off); a, U: flat float64 device buffers."""
         M = len(tasks)
         arr = (L.Task * M)(*[L.Task(int(n), int(N), int(fo), int(so)) for n, N, fo, so in tasks])
@@ -241,7 +249,8 @@ class Context:
         total = ctypes.c_double()
         pc = base.c()
         rc = self.lib.parareal_solve_batch(self.h, ctypes.byref(pc), arr, M, _ptr(a), init, _ptr(U),
-                                           L.KC_BATCH_GRAPH if graph else 0, iters, status, lat,
+                                           (L.KC_BATCH_GRAPH if graph else 0) |
+                                           (L.KC_BATCH_PROGRESS if progress else 0), iters, status, lat,
                                            ctypes.byref(total))
         self._check(rc, allow=(-5,) if allow_noconv else ())
         return (np.frombuffer(iters, dtype=np.int32).copy(), np.frombuffer(status, dtype=np.int32).copy(),

@@ -392,12 +392,13 @@ int kle_build(klecgc_ctx* ctx, const klecgc_kle_desc* desc, const double* S_dev,
   });
 }
 
-int kle_synthesize(klecgc_ctx* ctx, const klecgc_kle* f, const double* xi_dev, int64_t M, double* a_dev) {
+int kle_synthesize(klecgc_ctx* ctx, const klecgc_kle* f, const double* xi_dev, int64_t M, double* a_dev,
+                   float* a32_dev) {
   return guarded(ctx, [&] {
     KC_REQUIRE(f && xi_dev && a_dev, KC_EINVAL, "null argument");
     KC_REQUIRE(f->kind == KC_KLE_FIELD_EXP, KC_EINVAL, "handle is not a FIELD_EXP KL");
     KC_REQUIRE(M >= 1, KC_EINVAL, "M must be >= 1");
-    launch_field_synth(ctx->stream, f->phi, f->sqrt_lam, f->d, f->nfaces, xi_dev, M, a_dev);
+    launch_field_synth(ctx->stream, f->phi, f->sqrt_lam, f->d, f->nfaces, xi_dev, M, a_dev, a32_dev);
     return KC_OK;
   });
 }
@@ -471,13 +472,13 @@ int gpc_predict(klecgc_ctx* ctx, const klecgc_gpc* g, const double* xi_dev, int6
 }
 
 int fine_propagate(klecgc_ctx* ctx, const klecgc_problem* prob, const double* a_dev,
-                   const double* start_dev, int64_t M, double* end_dev) {
+                   const double* start_dev, int64_t M, double* end_dev, const uint8_t* active_dev) {
   return guarded(ctx, [&] {
     KC_REQUIRE(prob && a_dev && start_dev && end_dev, KC_EINVAL, "null argument");
     KC_REQUIRE(M >= 1, KC_EINVAL, "M must be >= 1");
     validate_problem(*prob);
     KC_REQUIRE(start_dev != end_dev, KC_EINVAL, "start_dev and end_dev may not alias");
-    FineArgs fa{a_dev, start_dev, nullptr, false, 0, nullptr, end_dev, M};
+    FineArgs fa{a_dev, start_dev, nullptr, false, 0, active_dev, end_dev, M};
     return fine_propagate_impl(ctx, *prob, fa);
   });
 }
@@ -524,22 +525,23 @@ int parareal_solve_batch(klecgc_ctx* ctx, const klecgc_problem* base, const klec
   return guarded(ctx, [&] {
     KC_REQUIRE(base && tasks && a_dev && U_dev && iters_host && status_host, KC_EINVAL, "null argument");
     KC_REQUIRE(M >= 1, KC_EINVAL, "M must be >= 1");
-    KC_REQUIRE((flags & ~KC_BATCH_GRAPH) == 0, KC_EINVAL, "unknown flags");
+    KC_REQUIRE((flags & ~(KC_BATCH_GRAPH | KC_BATCH_PROGRESS)) == 0, KC_EINVAL, "unknown flags");
     return parareal_batch_impl(ctx, *base, tasks, M, a_dev, init, U_dev, flags, iters_host, status_host,
                                latency_ms_host, total_ms_host);
   });
 }
 
 int parareal_solve(klecgc_ctx* ctx, const klecgc_problem* prob, const double* a_dev, const double* u0_dev,
-                   int64_t M, int32_t init, const double* init_dev, const klecgc_gpc* gpc,
-                   const double* xi_dev, double* U_dev, int32_t* iters_host, int32_t* status_host,
-                   double* delta_hist_host) {
+                   int64_t M, int32_t init, const double* init_dev, const klecgc_gpc* gpc, klecgc_mlp* mlp,
+                   const double* xi_dev, uint64_t seed, double* U_dev, int32_t* iters_host, int32_t* status_host,
+                   double* delta_hist_host, int32_t* guess_host) {
   return guarded(ctx, [&] {
     KC_REQUIRE(prob && a_dev && U_dev && iters_host && status_host, KC_EINVAL, "null argument");
     KC_REQUIRE(M >= 1, KC_EINVAL, "M must be >= 1");
     validate_problem(*prob);
-    return parareal_impl(ctx, *prob, a_dev, u0_dev, M, init, init_dev, gpc, xi_dev, U_dev, iters_host,
-                         status_host, delta_hist_host);
+    GuessArgs g{init, init_dev, gpc, mlp, xi_dev, seed};
+    return parareal_impl(ctx, *prob, a_dev, u0_dev, M, g, U_dev, iters_host, status_host, delta_hist_host,
+                         guess_host);
   });
 }
 

@@ -14,7 +14,9 @@
 // classes of equal (n, N); each class is gathered into contiguous buffers, run on its own
 // context and stream, and scattered back.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -22,6 +24,7 @@
 #include <vector>
 
 #include "common.h"
+#include "reduce.h"
 
 namespace kc {
 
@@ -97,6 +100,74 @@ __global__ void scatter_rows_kernel(const double* __restrict__ src, const int64_
     d[i] = s[i];
 }
 
+// The random initial guess: entry i is the SplitMix64 output (Steele, Lea and Flood, OOPSLA
+// 2014) of the state seed + (i + 1) * golden (mod 2^64), its top 53 bits scaled by 2^-53.
+__global__ void random_guess_kernel(unsigned long long seed, int64_t n, double* __restrict__ U) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    unsigned long long z = seed + (unsigned long long)(i + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    U[i] = (double)(z >> 11) * 0x1.0p-53;
+  }
+}
+
+// Continuity defects of two guesses after a fine sweep on each: for sample m,
+// mx[4m + 0] = max |F_l - U_l|, mx[4m + 1] = max |U_l|, mx[4m + 2], mx[4m + 3] the same for the
+// second guess (F_g - U_g, U_g), as ordered bit patterns of non-negative doubles (NaN wins).
+__global__ __launch_bounds__(256) void guess_defect_kernel(const double* __restrict__ Fl, const double* __restrict__ Ul,
+                                                           const double* __restrict__ Fg, const double* __restrict__ Ug,
+                                                           int64_t S, unsigned long long* __restrict__ mx) {
+  const int64_t m = blockIdx.y;
+  const int64_t o = m * S;
+  double jl = 0.0, ul = 0.0, jg = 0.0, ug = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < S; i += (int64_t)gridDim.x * blockDim.x) {
+    const double u = Ul[o + i], v = Ug[o + i];
+    jl = nanmax(jl, fabs(Fl[o + i] - u));
+    ul = nanmax(ul, fabs(u));
+    jg = nanmax(jg, fabs(Fg[o + i] - v));
+    ug = nanmax(ug, fabs(v));
+  }
+  jl = wave_nanmax(jl);
+  ul = wave_nanmax(ul);
+  jg = wave_nanmax(jg);
+  ug = wave_nanmax(ug);
+  if ((threadIdx.x & 63) == 0) {
+    atomicMax(&mx[4 * m + 0], (unsigned long long)__double_as_longlong(jl));
+    atomicMax(&mx[4 * m + 1], (unsigned long long)__double_as_longlong(ul));
+    atomicMax(&mx[4 * m + 2], (unsigned long long)__double_as_longlong(jg));
+    atomicMax(&mx[4 * m + 3], (unsigned long long)__double_as_longlong(ug));
+  }
+}
+
+// The fallback rule: keep the learned guess unless the fallback's defect is strictly
+// smaller, or the learned one's is NaN and the fallback's is not.  A zero maximum of |U|
+// divides by 1.  use[m] = 1 selects the fallback.
+__global__ void guess_choose_kernel(const unsigned long long* __restrict__ mx, int64_t M, int32_t* __restrict__ use) {
+  for (int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; m < M; m += (int64_t)gridDim.x * blockDim.x) {
+    const double jl = __longlong_as_double((long long)mx[4 * m + 0]);
+    const double ul = __longlong_as_double((long long)mx[4 * m + 1]);
+    const double jg = __longlong_as_double((long long)mx[4 * m + 2]);
+    const double ug = __longlong_as_double((long long)mx[4 * m + 3]);
+    const double dl = jl / (ul > 0 ? ul : 1.0);
+    const double dg = jg / (ug > 0 ? ug : 1.0);
+    use[m] = (dg < dl || (isnan(dl) && !isnan(dg))) ? 1 : 0;
+  }
+}
+
+// U[m] = Ug[m] and F[m] = Fg[m] for the samples with use[m] != 0
+__global__ void guess_take_kernel(const int32_t* __restrict__ use, const double* __restrict__ Ug,
+                                  const double* __restrict__ Fg, int64_t S, double* __restrict__ U,
+                                  double* __restrict__ F) {
+  const int64_t m = blockIdx.y;
+  if (!use[m]) return;
+  const int64_t o = m * S;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < S; i += (int64_t)gridDim.x * blockDim.x) {
+    U[o + i] = Ug[o + i];
+    F[o + i] = Fg[o + i];
+  }
+}
+
 __global__ void zero_kernel(double* __restrict__ x, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     x[i] = 0.0;
@@ -170,6 +241,7 @@ struct ParaClass {
   double* U = nullptr;
   ClassState st;
   int index = 1;            // slot in the device counter array (0 = all classes)
+  bool fine_ready = false;  // the F buffer already holds iteration 0's fine sweep
 };
 
 static void enqueue_iteration(ParaClass& pc, int k, int* counts, int& rc) {
@@ -182,9 +254,12 @@ static void enqueue_iteration(ParaClass& pc, int k, int* counts, int& rc) {
   double* Fv = (double*)c->ws.get(WS_FINE, sizeof(double) * pc.M * S);
   double* D = (double*)c->ws.get(WS_DEFECT, sizeof(double) * pc.M * S);
   double* spec = (double*)c->ws.get(WS_SPEC, sizeof(double) * 2 * pc.M * K * Nx);
-  FineArgs fa{pc.a, pc.U, pc.u0, true, k > 0 ? 1 : 0, pc.st.active, Fv, pc.M};
-  int r = fine_propagate_impl(c, p, fa);
-  if (r != KC_OK) rc = r;
+  if (!(k == 0 && pc.fine_ready)) {
+    FineArgs fa{pc.a, pc.U, pc.u0, true, k > 0 ? 1 : 0, pc.st.active, Fv, pc.M};
+    const int r = fine_propagate_impl(c, p, fa);
+    if (r != KC_OK) rc = r;
+  }
+  int r;
   timed(c, KT_DEFECT, [&] { launch_defect(s, p, pc.a, Fv, pc.U, pc.st.active, pc.M, D); });
   timed(c, KT_FFT_FWD, [&] { launch_fft_forward(s, p, D, pc.st.active, pc.M, spec); });
   r = shifted_solve_impl(c, pc.pb, pc.a, pc.st.active, pc.M, spec);
@@ -208,7 +283,14 @@ struct DriverOut {
 // whole run (the caller's); with use_graph the classes' iterations after the first are
 // replayed from one captured graph.
 static int run_classes(klecgc_ctx* ctx, std::vector<ParaClass*>& cls, bool use_graph, bool want_hist,
-                       DriverOut& out) {
+                       DriverOut& out, bool progress = false) {
+  const auto t_start = std::chrono::steady_clock::now();
+  auto report = [&](int k, int active) {
+    if (!progress) return;
+    const double s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+    std::fprintf(stderr, "[klecgc] parareal iteration %d: %d samples active, %.1f s\n", k, active, s);
+    std::fflush(stderr);
+  };
   hipStream_t main = ctx->stream;
   const int C = (int)cls.size();
   int max_iter = 1;
@@ -288,6 +370,7 @@ static int run_classes(klecgc_ctx* ctx, std::vector<ParaClass*>& cls, bool use_g
     join_all();
     read_counts();
     ++k;
+    report(k, hc[0]);
     if (hc[0] == 0 || use_graph) break;
   }
   const bool replay = use_graph && hc[0] > 0 && k < max_iter;
@@ -349,6 +432,7 @@ static int run_classes(klecgc_ctx* ctx, std::vector<ParaClass*>& cls, bool use_g
         KC_TRY_HIP(hipGraphLaunch(exec, order));
         read_counts();
         ++k;
+        report(k, hc[0]);
       }
     } catch (...) {
       (void)hipGraphExecDestroy(exec);
@@ -408,17 +492,42 @@ static int run_classes(klecgc_ctx* ctx, std::vector<ParaClass*>& cls, bool use_g
 }
 
 // ---------------------------------------------------------------- uniform batch
+namespace {
+// the restricted grid nc of a network whose n_out is N nc^2 (0 if there is none)
+int mlp_coarse_grid(const klecgc_mlp* h, int N) {
+  const int64_t per = mlp_out_count(h) / N;
+  if (per * N != mlp_out_count(h)) return 0;
+  int nc = (int)std::llround(std::sqrt((double)per));
+  return (int64_t)nc * nc == per ? nc : 0;
+}
+}  // namespace
+
 int parareal_impl(klecgc_ctx* ctx, const klecgc_problem& p, const double* a, const double* u0, int64_t M,
-                  int32_t init, const double* init_dev, const klecgc_gpc* gpc, const double* xi, double* U,
-                  int32_t* iters, int32_t* status, double* hist) {
+                  const GuessArgs& g, double* U, int32_t* iters, int32_t* status, double* hist, int32_t* guess) {
   hipStream_t st = ctx->stream;
-  const int64_t S = (int64_t)p.N * n_unknowns(p);
+  const int64_t Nx = n_unknowns(p);
+  const int64_t S = (int64_t)p.N * Nx;
+  const int K = p.N / 2 + 1;
   int rc = KC_OK;
-  switch (init) {
+  bool fine_ready = false;
+  std::vector<int32_t> used(M, g.init);
+  auto need_gpc = [&] {
+    KC_REQUIRE(g.gpc && g.xi, KC_EINVAL, "gpc handle and xi_dev required for the gPC guess");
+    KC_REQUIRE(g.gpc->L == S, KC_EINVAL, "gpc surrogate state length differs from N*Nx");
+  };
+  auto mlp_guess = [&](double* out) {
+    KC_REQUIRE(g.mlp && g.xi, KC_EINVAL, "mlp handle and xi_dev required for the learned guess");
+    KC_REQUIRE(p.dim == 2, KC_EUNSUPPORTED, "the learned guess restricts 2D states");
+    const int nc = mlp_coarse_grid(g.mlp, p.N);
+    KC_REQUIRE(nc > 0, KC_EINVAL, "MLP output size must be N nc^2");
+    const int r = mlp_initial_guess_impl(ctx, g.mlp, p.n, nc, p.N, g.xi, M, out);
+    if (r != KC_OK) rc = r;
+  };
+  switch (g.init) {
     case KC_INIT_GIVEN:
-      KC_REQUIRE(init_dev, KC_EINVAL, "init_dev required for KC_INIT_GIVEN");
-      if (init_dev != U)
-        KC_TRY_HIP(hipMemcpyAsync(U, init_dev, sizeof(double) * M * S, hipMemcpyDeviceToDevice, st));
+      KC_REQUIRE(g.given, KC_EINVAL, "init_dev required for KC_INIT_GIVEN");
+      if (g.given != U)
+        KC_TRY_HIP(hipMemcpyAsync(U, g.given, sizeof(double) * M * S, hipMemcpyDeviceToDevice, st));
       break;
     case KC_INIT_ZERO:
       KC_TRY_HIP(hipMemsetAsync(U, 0, sizeof(double) * M * S, st));
@@ -429,10 +538,56 @@ int parareal_impl(klecgc_ctx* ctx, const klecgc_problem& p, const double* a, con
       break;
     }
     case KC_INIT_GPC:
-      KC_REQUIRE(gpc && xi, KC_EINVAL, "gpc handle and xi_dev required for KC_INIT_GPC");
-      KC_REQUIRE(gpc->L == S, KC_EINVAL, "gpc surrogate state length differs from N*Nx");
-      gpc_predict_impl(ctx, gpc, xi, M, U);
+      need_gpc();
+      gpc_predict_impl(ctx, g.gpc, g.xi, M, U);
       break;
+    case KC_INIT_RANDOM:
+      random_guess_kernel<<<blocks_of(M * S, 16384), 256, 0, st>>>((unsigned long long)g.seed, M * S, U);
+      KC_LAUNCH_CHECK();
+      break;
+    case KC_INIT_MLP:
+      mlp_guess(U);
+      break;
+    case KC_INIT_MLP_GPC_FALLBACK: {
+      need_gpc();
+      mlp_guess(U);
+      // the gPC guess and its fine sweep live in the defect and spectrum buffers of the
+      // iteration (sized as the iteration asks for them), free until iteration 0's defect
+      double* Fv = (double*)ctx->ws.get(WS_FINE, sizeof(double) * M * S);
+      double* Ug = (double*)ctx->ws.get(WS_DEFECT, sizeof(double) * M * S);
+      double* Fg = (double*)ctx->ws.get(WS_SPEC, sizeof(double) * 2 * M * K * Nx);
+      gpc_predict_impl(ctx, g.gpc, g.xi, M, Ug);
+      for (int which = 0; which < 2; ++which) {
+        FineArgs fa{a, which ? Ug : U, u0, true, 0, nullptr, which ? Fg : Fv, M};
+        const int r = fine_propagate_impl(ctx, p, fa);
+        if (r != KC_OK) rc = r;
+      }
+      char* gb = (char*)ctx->ws.get(WS_GUESS, sizeof(unsigned long long) * 4 * M + sizeof(int32_t) * M);
+      unsigned long long* mx = (unsigned long long*)gb;
+      int32_t* use = (int32_t*)(gb + sizeof(unsigned long long) * 4 * M);
+      KC_TRY_HIP(hipMemsetAsync(mx, 0, sizeof(unsigned long long) * 4 * M, st));
+      for (int64_t m0 = 0; m0 < M; m0 += 65535) {
+        const int64_t Mc = std::min<int64_t>(65535, M - m0);
+        guess_defect_kernel<<<dim3(blocks_of(S, 64), (unsigned)Mc), 256, 0, st>>>(
+            Fv + m0 * S, U + m0 * S, Fg + m0 * S, Ug + m0 * S, S, mx + 4 * m0);
+        KC_LAUNCH_CHECK();
+      }
+      guess_choose_kernel<<<blocks_of(M), 256, 0, st>>>(mx, M, use);
+      KC_LAUNCH_CHECK();
+      for (int64_t m0 = 0; m0 < M; m0 += 65535) {
+        const int64_t Mc = std::min<int64_t>(65535, M - m0);
+        guess_take_kernel<<<dim3(blocks_of(S, 64), (unsigned)Mc), 256, 0, st>>>(use + m0, Ug + m0 * S,
+                                                                                Fg + m0 * S, S, U + m0 * S,
+                                                                                Fv + m0 * S);
+        KC_LAUNCH_CHECK();
+      }
+      std::vector<int32_t> hu(M);
+      KC_TRY_HIP(hipMemcpyAsync(hu.data(), use, sizeof(int32_t) * M, hipMemcpyDeviceToHost, st));
+      KC_TRY_HIP(hipStreamSynchronize(st));
+      for (int64_t m = 0; m < M; ++m) used[m] = hu[m] ? KC_INIT_GPC : KC_INIT_MLP;
+      fine_ready = true;
+      break;
+    }
     default:
       throw Error{KC_EINVAL, "unknown init mode"};
   }
@@ -449,6 +604,7 @@ int parareal_impl(klecgc_ctx* ctx, const klecgc_problem& p, const double* a, con
   pc.a = a;
   pc.u0 = u0;
   pc.U = U;
+  pc.fine_ready = fine_ready;
   std::vector<ParaClass*> cls{&pc};
   DriverOut out;
   int r = run_classes(ctx, cls, false, hist != nullptr, out);
@@ -456,6 +612,7 @@ int parareal_impl(klecgc_ctx* ctx, const klecgc_problem& p, const double* a, con
   std::memcpy(iters, out.its.data(), sizeof(int32_t) * M);
   std::memcpy(status, out.status.data(), sizeof(int32_t) * M);
   if (hist) std::memcpy(hist, out.hist.data(), sizeof(double) * M * p.max_iter);
+  if (guess) std::memcpy(guess, used.data(), sizeof(int32_t) * M);
   return rc;
 }
 
@@ -586,7 +743,7 @@ int parareal_batch_impl(klecgc_ctx* ctx, const klecgc_problem& base, const klecg
     KC_TRY_HIP(hipStreamSynchronize(pc->c->stream));
   }
   DriverOut out;
-  int r = run_classes(ctx, cls, (flags & KC_BATCH_GRAPH) != 0, false, out);
+  int r = run_classes(ctx, cls, (flags & KC_BATCH_GRAPH) != 0, false, out, (flags & KC_BATCH_PROGRESS) != 0);
   if (r != KC_OK) rc = r;
   // scatter the iterates back
   for (int i = 0; i < C; ++i) {

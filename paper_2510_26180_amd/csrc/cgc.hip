@@ -189,8 +189,15 @@ __global__ __launch_bounds__(COLS) void fft_inverse_kernel(const double* __restr
     if (COLS >= 64) {
       cmax = wave_nanmax(cmax);
       umax = wave_nanmax(umax);
+    } else {
+      // a work-group of COLS < 64 threads is one partial wave: reduce over its lanes only
+#pragma unroll
+      for (int off = COLS / 2; off >= 1; off >>= 1) {
+        cmax = nanmax(cmax, __shfl_xor(cmax, off, COLS));
+        umax = nanmax(umax, __shfl_xor(umax, off, COLS));
+      }
     }
-    if (COLS < 64 || (t & 63) == 0) {
+    if ((t & 63) == 0) {
       atomicMax(&maxima[2 * m], (unsigned long long)__double_as_longlong(cmax));
       atomicMax(&maxima[2 * m + 1], (unsigned long long)__double_as_longlong(umax));
     }

@@ -59,6 +59,7 @@ enum WsSlot {
   WS_FINE_AUX,      // float32 correction tiles of the shifted solves
   WS_MLP,           // MLP predictions before prolongation
   WS_FINE_INC,      // fine propagator: per-system increment of the current step
+  WS_GUESS,         // parareal: per-sample guess choice (flags, defect maxima)
   WS_COUNT
 };
 
@@ -177,7 +178,7 @@ void validate_problem(const klecgc_problem& p);
 // ---- kernels' host launchers -------------------------------------------------
 // field
 void launch_field_synth(hipStream_t s, const double* phi, const double* sqrt_lam, int d,
-                        int64_t nfaces, const double* xi, int64_t M, double* a);
+                        int64_t nfaces, const double* xi, int64_t M, double* a, float* a32);
 // fine propagator
 // start rows: if start_shift, the start of (m, s) is u0[m] (or 0) for s == 0 and
 // U[m][s-1] otherwise (the parareal layout); else start[m][s].
@@ -225,9 +226,17 @@ void launch_col_mean_center(hipStream_t s, const double* S, int64_t n_t, int64_t
 // gPC prediction U0 = mean + Psi(xi) H W (abi.cpp)
 int gpc_predict_impl(klecgc_ctx* ctx, const klecgc_gpc* g, const double* xi, int64_t M, double* U0);
 // parareal drivers (batch.hip)
+// the initial guess of parareal_solve (KC_INIT_*) and what it reads
+struct GuessArgs {
+  int32_t init;
+  const double* given;      // KC_INIT_GIVEN
+  const klecgc_gpc* gpc;    // KC_INIT_GPC, KC_INIT_MLP_GPC_FALLBACK
+  klecgc_mlp* mlp;          // KC_INIT_MLP, KC_INIT_MLP_GPC_FALLBACK
+  const double* xi;         // [M][d] for the surrogates
+  uint64_t seed;            // KC_INIT_RANDOM
+};
 int parareal_impl(klecgc_ctx* ctx, const klecgc_problem& p, const double* a, const double* u0, int64_t M,
-                  int32_t init, const double* init_dev, const klecgc_gpc* gpc, const double* xi, double* U,
-                  int32_t* iters, int32_t* status, double* hist);
+                  const GuessArgs& g, double* U, int32_t* iters, int32_t* status, double* hist, int32_t* guess);
 int parareal_batch_impl(klecgc_ctx* ctx, const klecgc_problem& base, const klecgc_task* tasks, int64_t M,
                         const double* a, int32_t init, double* U, int32_t flags, int32_t* iters, int32_t* status,
                         double* latency_ms, double* total_ms);

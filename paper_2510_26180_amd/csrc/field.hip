@@ -67,14 +67,16 @@ inline double eval_mode(const Mode1D& m, double x) {
 
 __global__ void field_synth_kernel(const double* __restrict__ phi, const double* __restrict__ sl,
                                    int d, int64_t nf, const double* __restrict__ xi, int64_t M,
-                                   double* __restrict__ a) {
+                                   double* __restrict__ a, float* __restrict__ a32) {
   int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t m = blockIdx.y;
   if (f >= nf || m >= M) return;
   const double* x = xi + m * d;
   double s = 0.0;
   for (int k = 0; k < d; ++k) s += (sl[k] * x[k]) * phi[(int64_t)k * nf + f];
-  a[m * nf + f] = exp(s);
+  const double v = exp(s);
+  a[m * nf + f] = v;
+  if (a32) a32[m * nf + f] = (float)v;   // round to nearest
 }
 
 }  // namespace
@@ -116,11 +118,14 @@ void field_kl_host(int dim, int n, int d, double corr_len, double sigma, std::ve
 }
 
 void launch_field_synth(hipStream_t s, const double* phi, const double* sqrt_lam, int d,
-                        int64_t nfaces, const double* xi, int64_t M, double* a) {
-  dim3 block(256);
-  dim3 grid((unsigned)((nfaces + 255) / 256), (unsigned)M);
-  field_synth_kernel<<<grid, block, 0, s>>>(phi, sqrt_lam, d, nfaces, xi, M, a);
-  KC_LAUNCH_CHECK();
+                        int64_t nfaces, const double* xi, int64_t M, double* a, float* a32) {
+  for (int64_t m0 = 0; m0 < M; m0 += 65535) {
+    const int64_t Mc = std::min<int64_t>(65535, M - m0);
+    dim3 grid((unsigned)((nfaces + 255) / 256), (unsigned)Mc);
+    field_synth_kernel<<<grid, dim3(256), 0, s>>>(phi, sqrt_lam, d, nfaces, xi + m0 * d, Mc, a + m0 * nfaces,
+                                                  a32 ? a32 + m0 * nfaces : nullptr);
+    KC_LAUNCH_CHECK();
+  }
 }
 
 }  // namespace kc

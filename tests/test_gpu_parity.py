@@ -102,8 +102,14 @@ def test_fine_2d_work_group_counts(ctx, prec, M, N):
 
 
 # ---------------------------------------------------------------- coarse correction
+# N = 64, 128 and 256 run their own slice-FFT instances (32, 16 and 8 columns per
+# work-group, whose per-sample maxima reduce inside a partial wave); alpha = 1e-4 at large N
+# gives the smallest shifts (1 - alpha^{1/N} = 0.035 at N = 256), where step (b) is hardest
 @pytest.mark.parametrize("dim,n,N,alpha", [(1, 31, 8, 1e-2), (1, 127, 16, 1e-2), (1, 5, 2, 0.5),
-                                           (2, 12, 8, 1e-2), (2, 20, 16, 1e-4), (2, 1, 4, 0.3)])
+                                           (2, 12, 8, 1e-2), (2, 20, 16, 1e-4), (2, 1, 4, 0.3),
+                                           (1, 31, 64, 1e-4), (1, 9, 256, 1e-2), (2, 12, 32, 1e-4),
+                                           (2, 12, 64, 1e-4), (2, 12, 128, 1e-4), (2, 12, 256, 1e-4),
+                                           (2, 72, 64, 1e-4)])
 def test_cgc_diag_solve(ctx, dim, n, N, alpha):
     log(f"cgc dim={dim} n={n} N={N} alpha={alpha}")
     w = (W.small_1d if dim == 1 else W.small_2d)(n=n, N=N, alpha=alpha)
@@ -122,9 +128,11 @@ def test_cgc_diag_solve(ctx, dim, n, N, alpha):
 
 
 @pytest.mark.parametrize("n,N,alpha", [(12, 8, 1e-2), (20, 16, 1e-4), (33, 8, 1e-4), (64, 16, 1e-4), (1, 4, 0.3),
-                                     (65, 4, 1e-2), (100, 8, 1e-4)])
+                                     (65, 4, 1e-2), (100, 8, 1e-4), (12, 64, 1e-4), (12, 128, 1e-4),
+                                     (12, 256, 1e-4), (72, 64, 1e-4), (128, 64, 1e-4)])
 def test_cgc_diag_solve_resident(ctx, n, N, alpha):
-    # float32 complex COCG with float64 residual refinement (CU-resident, n <= 64)
+    # float32 complex COCG with float64 residual refinement: CU-resident for n <= 64, the
+    # multigrid-preconditioned streaming kernel above (n = 128, N = 64 is the c2 shape)
     log(f"cgc resident n={n} N={N} alpha={alpha}")
     w = W.small_2d(n=n, N=N, alpha=alpha)
     M = 2
@@ -190,17 +198,55 @@ def test_parareal_1d_c1(ctx, init):
         assert np.allclose(hg, ho, rtol=1e-5, atol=1e-13)
 
 
-@pytest.mark.parametrize("prec,n", [(0, 12), (1, 12), (1, 72), (1, 130)])
+def iterations_agree(it_gpu: int, it_or: int, deltas_or, tol: float) -> bool:
+    """Equal iteration counts, or one apart when the oracle's increment at the deciding
+    iteration lies within 1% of tol (both sides then stop on a rounding-level difference)."""
+    if it_gpu == it_or:
+        return True
+    if it_gpu == it_or - 1 and it_or >= 2:
+        return deltas_or[it_or - 2] <= 1.01 * tol
+    if it_gpu == it_or + 1:
+        return deltas_or[it_or - 1] >= 0.99 * tol
+    return False
+
+
+@pytest.mark.parametrize("prec,n", [(0, 12), (0, 33), (1, 12), (1, 72), (1, 130)])
 def test_parareal_2d_small(ctx, prec, n):
-    # n = 72: resident fine kernel + multigrid COCG; n = 130: multigrid fine kernel too
+    # n = 72: resident fine kernel + multigrid COCG; n = 130: multigrid fine kernel too.
+    # float64 (prec 0): equal iteration counts and the oracle's Alg. 2 iterate to 1e-10;
+    # float32-refined: iterates to 1e-8 (the float32 Krylov passes stop at their own
+    # residual targets, so the paths agree to the refinement tolerance, not to round-off)
     w = W.small_2d(n=n, N=8 if n < 100 else 4, J=6 if n < 100 else 3, alpha=1e-2)
     log(f"parareal 2D small prec={prec} n={n}")
     for it_gpu, it_or, e_or, e_ref, st, hg, ho in _parareal_case(
             ctx, w, 3 if n < 100 else 1, "zero", dict(precision=prec, inner_rtol=1e-14, cgc_rtol=1e-14)):
         assert st == 0
-        assert abs(it_gpu - it_or) <= 1
+        assert e_ref < 1e-8
+        if prec == 0:
+            assert it_gpu == it_or
+            assert e_or < 1e-10
+            assert np.allclose(hg, ho, rtol=1e-6, atol=1e-13)
+        else:
+            assert iterations_agree(it_gpu, it_or, ho, w.tol)
+            assert e_or < 1e-8
+
+
+@pytest.mark.parametrize("J,M", [(2, 1), (4, 1)])
+def test_parareal_c2_shape(ctx, J, M):
+    # the c2 grid, slice count and twist (128^2, N = 64, alpha = 1e-4, float32-refined fine
+    # path on the red-black resident kernel, multigrid COCG, 32-column slice FFTs) with a
+    # shorter slice (J fine steps) so the oracle finishes in seconds
+    w = W.get("c2_2d_n128").replace(J=J)
+    log(f"parareal c2 shape n=128 N=64 J={J} M={M}")
+    for it_gpu, it_or, e_or, e_ref, st, hg, ho in _parareal_case(
+            ctx, w, M, "zero", dict(inner_rtol=1e-14, cgc_rtol=1e-14)):
+        log(f"  iterations gpu {it_gpu} oracle {it_or}; vs oracle iterate {e_or:.2e}, vs serial fine {e_ref:.2e}")
+        assert st == 0
+        assert iterations_agree(it_gpu, it_or, ho, w.tol)
         assert e_ref < 1e-8
         assert e_or < 1e-8
+        k = min(it_gpu, it_or)
+        assert np.allclose(hg[:k], ho[:k], rtol=1e-4, atol=1e-13)
 
 
 # ---------------------------------------------------------------- KL / gPC
@@ -238,7 +284,7 @@ def test_snapshot_kl_and_gpc_prediction(ctx):
     xi_e = W.draw_xi(6, w.d, 42)
     U0 = torch.empty((6, S.shape[1]), dtype=torch.float64, device="cuda")
     ctx.gpc_predict(g, dev(xi_e), U0)
-    assert rel(host(U0), ogpc.predict(g_o, xi_e)) < 1e-9
+    assert rel(host(U0), ogpc.predict(g_o, xi_e)) < 1e-10
 
 
 def test_snapshot_gram_spectrum(ctx):

@@ -147,6 +147,12 @@ def draw_ragged(M: int, seed: int, grids=(64, 128, 256), slices=(32, 64, 128)):
     return np.asarray(grids)[g], np.asarray(slices)[s]
 
 
+def draw_subset(M: int, k: int, seed: int) -> np.ndarray:
+    """k distinct sample indices out of M, ascending (the seeded accuracy subset)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return np.sort(rng.choice(M, size=k, replace=False))
+
+
 def draw_normal(shape, seed: int, scale: float = 1.0) -> np.ndarray:
     rng = np.random.Generator(np.random.PCG64(seed))
     return scale * rng.standard_normal(shape)
