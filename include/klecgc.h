@@ -220,6 +220,19 @@ int gpc_predict(klecgc_ctx* ctx, const klecgc_gpc* gpc, const double* xi_dev, in
  * solve hits inner_max_iter (results are still written). */
 int fine_propagate(klecgc_ctx* ctx, const klecgc_problem* prob, const double* a_dev,
                    const double* start_dev, int64_t M, double* end_dev, const uint8_t* active_dev);
+/* fine_propagate_noalloc: fine_propagate (same arguments, kernels and results) for callers
+ * that cannot allocate device memory (code under graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  It allocates nothing: its workspace (solver tables,
+ * per-system increments, multigrid levels and Krylov vectors, the status block) comes from
+ * a 64 MiB device array that the library holds on each GPU until the process ends.
+ * Returns KC_EINVAL, before any output is written, if the call needs more than that
+ * (roughly: 2D n <= 128 float32-refined needs 16 N Nx M bytes of increments plus 12 Nx M +
+ * 8 n (n+1) M; 1D 24 n M; float64 PCG 24 N Nx M; n > 128 runs its multigrid systems in
+ * chunks of what fits).  All calls on one GPU share the array: calls that overlap on one
+ * GPU (several host threads or streams) race. */
+int fine_propagate_noalloc(klecgc_ctx* ctx, const klecgc_problem* prob, const double* a_dev,
+                           const double* start_dev, int64_t M, double* end_dev,
+                           const uint8_t* active_dev);
 /* cgc_diag_solve (Section 3.2, eq. matrix_NT and eq. three-steps): solves
  *     (C_alpha (x) I + dT I (x) A_m) u_m = r_m   for every sample m,
  * C_alpha the alpha-circulant time matrix, by (a) p = F_N^* Lambda r (real FFT

@@ -80,6 +80,7 @@ SIGNATURES = {
     "gpc_fit": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, _i32, _P(_vp), _P(_i32)]),
     "gpc_predict": (ctypes.c_int, [_vp, _vp, _vp, _i64, _vp]),
     "fine_propagate": (ctypes.c_int, [_vp, _P(Problem), _vp, _vp, _i64, _vp, _vp]),
+    "fine_propagate_noalloc": (ctypes.c_int, [_vp, _P(Problem), _vp, _vp, _i64, _vp, _vp]),
     "cgc_diag_solve": (ctypes.c_int, [_vp, _P(Problem), _vp, _vp, _i64, _vp]),
     "coarse_propagate": (ctypes.c_int, [_vp, _P(Problem), _vp, _vp, _i64, _vp]),
     "parareal_solve": (ctypes.c_int, [_vp, _P(Problem), _vp, _vp, _i64, _i32, _vp, _vp, _vp, _vp,

@@ -204,6 +204,12 @@ class Context:
                                                    _ptr(end), _ptr(active)),
                            allow=(-5,) if allow_noconv else ())
 
+    def fine_propagate_noalloc(self, prob: ProblemSpec, a, start, end, allow_noconv=False, active=None) -> int:
+        pc = prob.c()
+        return self._check(self.lib.fine_propagate_noalloc(self.h, ctypes.byref(pc), _ptr(a), _ptr(start),
+                                                           start.shape[0], _ptr(end), _ptr(active)),
+                           allow=(-5,) if allow_noconv else ())
+
     def cgc_diag_solve(self, prob: ProblemSpec, a, r, u, allow_noconv=False) -> int:
         pc = prob.c()
         return self._check(self.lib.cgc_diag_solve(self.h, ctypes.byref(pc), _ptr(a), _ptr(r), r.shape[0], _ptr(u)),

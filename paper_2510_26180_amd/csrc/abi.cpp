@@ -24,6 +24,18 @@ void* Workspace::get(int slot, size_t bytes) {
     cap.resize(WS_COUNT, 0);
   }
   if (bytes == 0) bytes = 1;
+  if (arena) {
+    if (cap[slot] >= bytes) return ptr[slot];
+    const size_t need = (bytes + 255) & ~(size_t)255;
+    if (need > arena_left())
+      throw Error{KC_EINVAL, "allocation-free call: its workspace exceeds the " + std::to_string(arena_bytes) +
+                                 "-byte device scratch array (" + std::to_string(arena_used) +
+                                 " bytes taken, " + std::to_string(bytes) + " more requested)"};
+    ptr[slot] = arena + arena_used;
+    cap[slot] = bytes;
+    arena_used += need;
+    return ptr[slot];
+  }
   if (cap[slot] < bytes) {
     if (ptr[slot]) {
       KC_TRY_HIP(hipDeviceSynchronize());
@@ -44,6 +56,7 @@ void* Workspace::get(int slot, size_t bytes) {
 }
 
 void Workspace::release() {
+  if (arena) return;   // the arena is not the workspace's
   for (auto& p : ptr)
     if (p) {
       (void)hipFree(p);
@@ -59,7 +72,7 @@ DevStatus status_block(klecgc_ctx* ctx, int slot) {
 
 void status_reset(klecgc_ctx* ctx, const DevStatus& st) {
   if (ctx->capturing) return;
-  KC_TRY_HIP(hipMemsetAsync(st.flag, 0, kStatusBytes, ctx->stream));
+  launch_zero_bytes(ctx->stream, st.flag, kStatusBytes);
 }
 
 int status_collect(klecgc_ctx* ctx, const DevStatus& st, int base) {
@@ -197,6 +210,12 @@ int klecgc_create(klecgc_ctx** out, int device, void* hip_stream) {
   if (hipEventCreate(&c->ev[0]) != hipSuccess || hipEventCreate(&c->ev[1]) != hipSuccess) {
     delete c;
     return KC_EHIP;
+  }
+  // the device's copy of the allocation-free scratch array (resolved once per device); a
+  // failure leaves it unset and only the allocation-free entry point reports it
+  if (kc::scratch_resolve(device, &c->scratch) != hipSuccess) {
+    (void)hipGetLastError();
+    c->scratch = nullptr;
   }
   *out = c;
   return KC_OK;
@@ -478,6 +497,31 @@ int fine_propagate(klecgc_ctx* ctx, const klecgc_problem* prob, const double* a_
     KC_REQUIRE(M >= 1, KC_EINVAL, "M must be >= 1");
     validate_problem(*prob);
     KC_REQUIRE(start_dev != end_dev, KC_EINVAL, "start_dev and end_dev may not alias");
+    FineArgs fa{a_dev, start_dev, nullptr, false, 0, active_dev, end_dev, M};
+    return fine_propagate_impl(ctx, *prob, fa);
+  });
+}
+
+int fine_propagate_noalloc(klecgc_ctx* ctx, const klecgc_problem* prob, const double* a_dev,
+                           const double* start_dev, int64_t M, double* end_dev, const uint8_t* active_dev) {
+  return guarded(ctx, [&] {
+    KC_REQUIRE(prob && a_dev && start_dev && end_dev, KC_EINVAL, "null argument");
+    KC_REQUIRE(M >= 1, KC_EINVAL, "M must be >= 1");
+    validate_problem(*prob);
+    KC_REQUIRE(start_dev != end_dev, KC_EINVAL, "start_dev and end_dev may not alias");
+    KC_REQUIRE(ctx->scratch, KC_EHIP, "the device scratch array could not be resolved on this device");
+    // the context's own workspace is set aside for the call; every slot comes from the scratch array
+    struct ArenaScope {
+      klecgc_ctx* c;
+      Workspace saved;
+      ArenaScope(klecgc_ctx* c_, void* base, size_t bytes) : c(c_) {
+        saved = std::move(c->ws);
+        c->ws = Workspace{};
+        c->ws.arena = (char*)base;
+        c->ws.arena_bytes = bytes;
+      }
+      ~ArenaScope() { c->ws = std::move(saved); }
+    } scope(ctx, ctx->scratch, scratch_bytes());
     FineArgs fa{a_dev, start_dev, nullptr, false, 0, active_dev, end_dev, M};
     return fine_propagate_impl(ctx, *prob, fa);
   });

@@ -34,11 +34,16 @@ struct Error {
 #define KC_LAUNCH_CHECK() KC_TRY_HIP(hipGetLastError())
 
 // ---- device workspace ---------------------------------------------------------
-// Grow-only device buffers keyed by slot; freed when the context is destroyed.
+// Grow-only device buffers keyed by slot; freed when the context is destroyed.  In arena
+// mode (`arena` set) slots are carved in request order from a fixed region the workspace
+// does not own, nothing is allocated or freed, and a request beyond the region throws.
 struct Workspace {
   std::vector<void*> ptr;
   std::vector<size_t> cap;
+  char* arena = nullptr;
+  size_t arena_bytes = 0, arena_used = 0;
   void* get(int slot, size_t bytes);
+  size_t arena_left() const { return arena_bytes - arena_used; }
   void release();
 };
 
@@ -96,6 +101,7 @@ struct klecgc_ctx {
   // no status resets or read-backs (the parareal loop does them around the captured region)
   bool capturing = false;
   std::map<int, KcTuning> tuning;   // by grid size n
+  void* scratch = nullptr;          // this device's copy of the allocation-free scratch array
 };
 
 struct klecgc_kle {
@@ -261,6 +267,12 @@ int mlp_train_impl(klecgc_ctx* ctx, klecgc_mlp* h, const double* xi, const float
 int grid_restrict_impl(klecgc_ctx* ctx, int n, int nc, const double* U, int64_t R, float* Yc);
 int mlp_initial_guess_impl(klecgc_ctx* ctx, klecgc_mlp* h, int n, int nc, int N, const double* xi, int64_t M,
                            double* U0);
+
+// the allocation-free scratch array (noalloc.hip): resolves this device's copy (the device
+// must be current), its size, and a fill kernel that clears device memory without a memset
+hipError_t scratch_resolve(int device, void** out);
+size_t scratch_bytes();
+void launch_zero_bytes(hipStream_t s, void* p, size_t bytes);
 
 // host linear algebra
 // Gram eigen-decomposition on the device (eig.cpp): Cd [n][n] symmetric (overwritten) ->

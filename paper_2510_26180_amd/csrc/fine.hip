@@ -1426,8 +1426,13 @@ int propagate_impl(klecgc_ctx* ctx, const klecgc_problem& p, const FineArgs& fa,
         // `chunk` systems at a time, and never fewer than the device keeps in flight
         const MgLevels h = mg_levels(n, 1, 4 * Nx, tu.mg_sweeps, tu.mg_smoother);
         const int64_t per_sys = (int64_t)sizeof(float) * h.per_sys + 3 * (int64_t)sizeof(double) * Nx;
-        const int64_t cap_bytes = (int64_t)16 << 30;
-        const int64_t chunk = std::min<int64_t>(nsys, std::max<int64_t>(4LL * ctx->num_cus, cap_bytes / per_sys));
+        // a fixed workspace (allocation-free call) takes as many systems per chunk as it holds
+        const bool fixed = ctx->ws.arena != nullptr;
+        const int64_t cap_bytes = fixed ? (int64_t)ctx->ws.arena_left() - 3 * 256 : (int64_t)16 << 30;
+        const int64_t chunk = std::min<int64_t>(nsys, fixed ? cap_bytes / per_sys
+                                                            : std::max<int64_t>(4LL * ctx->num_cus, cap_bytes / per_sys));
+        KC_REQUIRE(chunk >= 1, KC_EINVAL, "allocation-free call: one multigrid system needs " +
+                                              std::to_string(per_sys) + " bytes, more than the device scratch array has left");
         float* scr = (float*)ctx->ws.get(WS_FINE_AUX, sizeof(float) * h.per_sys * chunk);
         double* rb = (double*)ctx->ws.get(WS_KRYLOV, sizeof(double) * Nx * chunk);
         // increments of the current and the previous step per system of a chunk
