@@ -270,6 +270,12 @@ static void enqueue_iteration(ParaClass& pc, int k, int* counts, int& rc) {
   KC_LAUNCH_CHECK();
 }
 
+// an iteration of the class is a fixed sequence of launches (no host decisions inside)
+static bool iteration_capturable(const ParaClass& pc) {
+  if (pc.p.dim == 1 || pc.p.precision != KC_PREC_F32_REFINED) return true;
+  return fine_variant_for(pc.p.n, tuning_for(pc.c, pc.p.n).fine_variant) != KC_FINE_MG;
+}
+
 struct DriverOut {
   std::vector<int32_t> its, status;   // per class, concatenated in class order
   std::vector<double> hist;
@@ -362,6 +368,15 @@ static int run_classes(klecgc_ctx* ctx, std::vector<ParaClass*>& cls, bool use_g
     KC_TRY_HIP(hipMemcpyAsync(hc.data(), counts, sizeof(int) * (C + 1), hipMemcpyDeviceToHost, order));
     KC_TRY_HIP(hipStreamSynchronize(order));
   };
+  // Classes whose iteration is a fixed sequence of launches are captured; a class whose fine
+  // sweep steers its own loops from the host (the streamed multigrid path) runs eagerly on
+  // its stream beside each replay.
+  std::vector<char> in_graph(C, 0);
+  int n_graph = 0;
+  for (int i = 0; i < C; ++i) {
+    in_graph[i] = iteration_capturable(*cls[i]);
+    n_graph += in_graph[i];
+  }
   // eager iterations (all of them without a graph; the first one with a graph)
   while (k < max_iter) {
     fork_all();
@@ -371,15 +386,16 @@ static int run_classes(klecgc_ctx* ctx, std::vector<ParaClass*>& cls, bool use_g
     read_counts();
     ++k;
     report(k, hc[0]);
-    if (hc[0] == 0 || use_graph) break;
+    if (hc[0] == 0 || (use_graph && n_graph > 0)) break;
   }
-  const bool replay = use_graph && hc[0] > 0 && k < max_iter;
+  const bool replay = use_graph && hc[0] > 0 && k < max_iter && n_graph > 0;
   if (replay) {
     // the replays accumulate solver counters into status blocks cleared here
-    for (auto* pc : cls) {
-      status_reset(pc->c, status_block(pc->c, WS_STATUS));
-      status_reset(pc->c, status_block(pc->c, WS_STATUS_CGC));
-    }
+    for (int i = 0; i < C; ++i)
+      if (in_graph[i]) {
+        status_reset(cls[i]->c, status_block(cls[i]->c, WS_STATUS));
+        status_reset(cls[i]->c, status_block(cls[i]->c, WS_STATUS_CGC));
+      }
     for (auto* pc : cls)
       if (pc->c->stream != main) KC_TRY_HIP(hipStreamSynchronize(pc->c->stream));
   }
@@ -407,11 +423,18 @@ static int run_classes(klecgc_ctx* ctx, std::vector<ParaClass*>& cls, bool use_g
     KC_TRY_HIP(hipStreamWaitEvent(cs.s, g0, 0));
     order = cs.s;
     KC_TRY_HIP(hipStreamBeginCapture(order, hipStreamCaptureModeRelaxed));
-    for (auto* pc : cls) pc->c->capturing = true;
+    for (int i = 0; i < C; ++i) cls[i]->c->capturing = in_graph[i] != 0;
     try {
-      fork_all();
-      for (int i = 0; i < C; ++i) enqueue_iteration(*cls[i], 1, counts, rc);
-      join_all();
+      KC_TRY_HIP(hipEventRecord(fork, order));
+      for (int i = 0; i < C; ++i)
+        if (in_graph[i]) {
+          if (cls[i]->c->stream != order) KC_TRY_HIP(hipStreamWaitEvent(cls[i]->c->stream, fork, 0));
+          enqueue_iteration(*cls[i], 1, counts, rc);
+          if (cls[i]->c->stream != order) {
+            KC_TRY_HIP(hipEventRecord(join[i], cls[i]->c->stream));
+            KC_TRY_HIP(hipStreamWaitEvent(order, join[i], 0));
+          }
+        }
     } catch (...) {
       for (auto* pc : cls) pc->c->capturing = false;
       hipGraph_t g = nullptr;
@@ -430,6 +453,12 @@ static int run_classes(klecgc_ctx* ctx, std::vector<ParaClass*>& cls, bool use_g
     try {
       while (k < max_iter && hc[0] > 0) {
         KC_TRY_HIP(hipGraphLaunch(exec, order));
+        for (int i = 0; i < C; ++i)   // the eager classes beside the replay, each on its stream
+          if (!in_graph[i] && hc[i + 1] > 0) {
+            enqueue_iteration(*cls[i], k, counts, rc);
+            KC_TRY_HIP(hipEventRecord(join[i], cls[i]->c->stream));
+            KC_TRY_HIP(hipStreamWaitEvent(order, join[i], 0));
+          }
         read_counts();
         ++k;
         report(k, hc[0]);
@@ -451,7 +480,9 @@ static int run_classes(klecgc_ctx* ctx, std::vector<ParaClass*>& cls, bool use_g
   }
   out.iterations = k;
   if (replay)
-    for (auto* pc : cls) {
+    for (int i = 0; i < C; ++i) {   // eager classes collected their counters call by call
+      if (!in_graph[i]) continue;
+      ParaClass* pc = cls[i];
       if (status_collect(pc->c, status_block(pc->c, WS_STATUS), 0)) rc = KC_ENOCONV;
       if (pc->p.dim == 2 && status_collect(pc->c, status_block(pc->c, WS_STATUS_CGC), 4)) rc = KC_ENOCONV;
     }

@@ -65,6 +65,8 @@ enum WsSlot {
   WS_MLP,           // MLP predictions before prolongation
   WS_FINE_INC,      // fine propagator: per-system increment of the current step
   WS_GUESS,         // parareal: per-sample guess choice (flags, defect maxima)
+  WS_MG_COEF,       // streamed multigrid: per-sample coarse operators
+  WS_MG_SMALL,      // streamed multigrid: band partials, per-system state, counters
   WS_COUNT
 };
 
@@ -199,6 +201,10 @@ struct FineArgs {
   int64_t M;
 };
 int fine_propagate_impl(klecgc_ctx* ctx, const klecgc_problem& p, const FineArgs& fa);
+// multigrid-preconditioned fine propagation streamed pass by pass (fine_mg.hip); dinv and the
+// scaled float32 couplings sf of every sample are built by the caller
+int fine_mg_streamed(klecgc_ctx* ctx, const klecgc_problem& p, const FineArgs& fa, double tau, int J, int N,
+                     const double* dinv, const float* sf, int* flag, unsigned long long* cnt);
 
 // coarse grid correction pieces
 void launch_defect(hipStream_t s, const klecgc_problem& p, const double* a, const double* Fv,

@@ -21,6 +21,7 @@
 #include <type_traits>
 
 #include "common.h"
+#include "fine_common.h"
 #include "mg.h"
 #include "reduce.h"
 #include "xcd.h"
@@ -30,11 +31,6 @@ namespace kc {
 namespace {
 
 constexpr int kStreamThreads = 256;
-constexpr int kMaxRefinePasses = 12;
-// A float32 pass reduces its residual only as far as the float64 target needs, times this
-// margin (the 2-norm reduction that CG measures bounds the max-norm one only loosely; a
-// pass that falls short is followed by another), and never beyond the tuned factor.
-constexpr double kPassMargin = 0.1;
 // what the resident kernels' float64 residual sweep also does (column pairs): nothing, the
 // update that closes the previous step, or the update by the last float32 pass
 constexpr int kSweepPlain = 0, kSweepStart = 1, kSweepCorrect = 2;
@@ -42,16 +38,6 @@ constexpr int kSweepPlain = 0, kSweepStart = 1, kSweepCorrect = 2;
 #define KC_RES128_NW 16
 #endif
 
-struct StartRef {
-  const double* start;
-  const double* u0;
-  bool shift;
-  __device__ __forceinline__ const double* row(int64_t m, int s, int N, int64_t Nx) const {
-    if (!shift) return start + ((int64_t)m * N + s) * Nx;
-    if (s == 0) return u0 ? u0 + m * Nx : nullptr;
-    return start + ((int64_t)m * N + (s - 1)) * Nx;
-  }
-};
 
 // ------------------------------------------------------------------------- 1D
 __global__ void tri_factor_kernel(const double* __restrict__ a, int n, double c, int64_t M,
@@ -103,14 +89,6 @@ __global__ void fine1d_kernel(const double* __restrict__ tab, int n, int J, doub
 }
 
 // --------------------------------------------------------------- 2D helpers
-struct Grid2 {
-  int n;
-  int64_t nx;   // number of x-faces, n(n+1)
-  __device__ __forceinline__ int64_t fW(int i, int j) const { return (int64_t)j * (n + 1) + i; }
-  __device__ __forceinline__ int64_t fE(int i, int j) const { return (int64_t)j * (n + 1) + i + 1; }
-  __device__ __forceinline__ int64_t fS(int i, int j) const { return nx + (int64_t)j * n + i; }
-  __device__ __forceinline__ int64_t fN(int i, int j) const { return nx + (int64_t)(j + 1) * n + i; }
-};
 
 // D^{-1/2} of M = I + c h^2 A (c = tau / h^2): d_p = 1 + c * (sum of the face coefficients of p)
 // dinvf (nullable) receives the same values rounded to float32.
@@ -154,26 +132,7 @@ __global__ void scaled_faces_kernel(const double* __restrict__ a, const double* 
   sf[m * Fc + f] = out;
 }
 
-// Stopping target for the float64 residual of one implicit step: tol relative to the
-// state size, but never below the rounding floor of forming that residual in float64,
-// about eps * max_p d_p * |w|_inf (d_p the diagonal of I + tau A).
-__device__ __forceinline__ double residual_target(double tol, double wmax, double tauf, double dmax) {
-  return tol * (wmax + fabs(tauf)) + 8.0 * 2.220446049250313e-16 * dmax * wmax;
-}
 
-// (M v)_p - v_p = c * sum_faces a_f (v_p - v_q), float64, v read from global memory.
-__device__ __forceinline__ double stencil64(const double* __restrict__ af, const double* __restrict__ v,
-                                            const Grid2& g, int i, int j) {
-  const int n = g.n;
-  int64_t p = (int64_t)j * n + i;
-  double vp = v[p];
-  double vw = i > 0 ? v[p - 1] : 0.0;
-  double ve = i < n - 1 ? v[p + 1] : 0.0;
-  double vs = j > 0 ? v[p - n] : 0.0;
-  double vn = j < n - 1 ? v[p + n] : 0.0;
-  return af[g.fW(i, j)] * (vp - vw) + af[g.fE(i, j)] * (vp - ve) + af[g.fS(i, j)] * (vp - vs) +
-         af[g.fN(i, j)] * (vp - vn);
-}
 
 // --------------------------------------------------- 2D streaming float64 PCG
 // One work-group per (sample, slice) system; x is the state row of `out`, r/p/q live
@@ -1114,214 +1073,6 @@ __global__ __launch_bounds__(64 * NW) void fine2d_resident_kernel(
   }
 }
 
-// Streaming fine propagator for grids too large for one CU's registers: one work-group per
-// (sample, slice) system for all J steps, with the float32 Krylov vectors and the
-// aggregation-multigrid levels of the scaled step operator I + tau A (mg.h; the same
-// levels serve every step) in per-system scratch.  Each implicit step is refined in
-// float64 exactly as in the resident kernel: float64 residual with float64 couplings,
-// start from the previous increment, float32 multigrid-preconditioned CG for the
-// correction, until the float64 residual meets its target.  Systems run in chunks of
-// `chunk` work-groups (sys0 = first system of the launch); scratch, residual and increment
-// buffers are indexed by the work-group.
-template <int NW, int WPE>
-__global__ __launch_bounds__(64 * NW, WPE) void fine2d_mg_kernel(
-    const double* __restrict__ a, const float* __restrict__ sf, const double* __restrict__ dinv, int n, double c,
-    double tauf, int J, double tol, float pcg_rtol, int maxit, StartRef sr, double* __restrict__ out,
-    double* __restrict__ resbuf, double* __restrict__ incbuf, float* __restrict__ scr, MgLevels h, int64_t sys0,
-    int64_t M, int N, int skip_first, const uint8_t* __restrict__ active, int* __restrict__ flag,
-    unsigned long long* __restrict__ cnt) {
-  __shared__ float fslots[2][4 * NW];
-  __shared__ double dslots[4 * NW];
-  const long long t_start = clock64();
-  long long t_cg = 0;
-  unsigned long long tot_it = 0, tot_pass = 0, max_it = 0, missed = 0;
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int64_t sys = sys0 + blockIdx.x;
-  const int64_t m = sys / N;
-  const int s = (int)(sys % N);
-  if (m >= M) return;
-  if (active && !active[m]) return;
-  if (skip_first && s == 0) return;
-  const int64_t Nx = (int64_t)n * n;
-  const Grid2 g{n, (int64_t)n * (n + 1)};
-  const int64_t Fc = 2 * g.nx;
-  const double* af = a + m * Fc;
-  const float* sfm = sf + m * Fc;
-  const double* dv = dinv + m * Nx;
-  double* w = out + sys * Nx;
-  double* res = resbuf + (int64_t)blockIdx.x * Nx;
-  double* inc = incbuf + (int64_t)blockIdx.x * Nx;
-  double* incp = incbuf + ((int64_t)gridDim.x + blockIdx.x) * Nx;   // the previous step's increment
-  float* base = scr + (int64_t)blockIdx.x * h.per_sys;
-  float* X = base;
-  float* R = X + Nx;
-  float* P = R + Nx;
-  float* Q = P + Nx;
-  const MgLv<float> v0 = mg_lv<float>(base, h, 0);
-
-  const double* src = sr.row(m, s, N, Nx);
-  double dmx[1] = {0.0};
-  const bool mxd[1] = {true};
-  for (int64_t p = threadIdx.x; p < Nx; p += blockDim.x) {
-    const int i = (int)(p % n), j = (int)(p / n);
-    w[p] = src ? src[p] : 0.0;
-    inc[p] = 0.0;
-    dmx[0] = nanmax(dmx[0], 1.0 / (dv[p] * dv[p]));
-    v0.cw[p] = i >= 1 ? sfm[(int64_t)j * (n + 1) + i] : 0.f;
-    v0.cs[p] = j >= 1 ? sfm[g.nx + (int64_t)j * n + i] : 0.f;
-    v0.dg[p] = 1.f;
-    v0.di[p] = 1.f;
-  }
-  block_reduce<1>(dmx, mxd, dslots);   // its barriers publish the copy and level 0
-  const double dmax = dmx[0];
-  mg_build_coarse<float>(base, h);
-  bool fail = false;
-
-  for (int step = 0; step < J; ++step) {
-    if (step > 0) {
-      // start from w_j + g with the increment extrapolated from the earlier ones:
-      // g = 2 inc_{j-1} - inc_{j-2} (inc_0 itself at the second step of a slice)
-      for (int64_t p = threadIdx.x; p < Nx; p += blockDim.x) {
-        const double i1 = inc[p];
-        const double gp = step > 1 ? 2.0 * i1 - incp[p] : i1;
-        w[p] += gp;
-        incp[p] = i1;
-        inc[p] = gp;
-      }
-      __syncthreads();
-    }
-    // float64 residual at the start w_j + inc:  tau f - tau A (w_j + inc) - inc
-    double acc[3] = {0.0, 0.0, 0.0};
-    const bool mx[3] = {true, true, true};
-    for (int64_t p = threadIdx.x; p < Nx; p += blockDim.x) {
-      const int i = (int)(p % n), j = (int)(p / n);
-      const double rv = tauf - c * stencil64(af, w, g, i, j) - inc[p];
-      res[p] = rv;
-      acc[0] = nanmax(acc[0], fabs(rv));
-      acc[1] = nanmax(acc[1], fabs(w[p]));
-      acc[2] = nanmax(acc[2], dv[p] * fabs(rv));
-    }
-    block_reduce<3>(acc, mx, dslots);
-    double rmax = acc[0];
-    double sig = acc[2];
-    const double target = residual_target(tol, acc[1], tauf, dmax);
-    int pass = 0;
-    while (rmax > target && sig > 0.0 && pass < kMaxRefinePasses) {
-      // float32 right-hand side D^{-1/2} res / sig
-      const double isig = 1.0 / sig;
-      float r0 = 0.f;
-      for (int64_t p = threadIdx.x; p < Nx; p += blockDim.x) {
-        const float v = (float)(isig * dv[p] * res[p]);
-        R[p] = v;
-        X[p] = 0.f;
-        r0 = fmaf(v, v, r0);
-      }
-      r0 = block_sum_f<NW>(r0, fslots[1], lane, wave);   // its barrier also publishes R
-      const long long t0 = clock64();
-      float* Z = mg_vcycle<float>(base, h, R);
-      float rz = 0.f;
-      for (int64_t p = threadIdx.x; p < Nx; p += blockDim.x) {
-        const float zv = Z[p];
-        P[p] = zv;
-        rz = fmaf(R[p], zv, rz);
-      }
-      // one-barrier sums alternate between the two slot arrays: this one and the p.q sum
-      // that follows with no barrier in between use different slots
-      rz = block_sum_f<NW>(rz, fslots[1], lane, wave);
-      const float stop = pcg_rtol * pcg_rtol * r0;
-      float rr = r0;
-      int it = 0;
-      bool bad = false;
-      const int cap = maxit < 400 ? maxit : 400;
-      while (rr > stop && it < cap) {
-        float pq = 0.f;
-        for (int64_t p = threadIdx.x; p < Nx; p += blockDim.x) {
-          const int i = (int)(p % n), j = (int)(p / n);
-          const float qv = mg_apply<float>(v0, p, i, j, [&](int64_t q, int, int) { return P[q]; });
-          Q[p] = qv;
-          pq = fmaf(P[p], qv, pq);
-        }
-        pq = block_sum_f<NW>(pq, fslots[0], lane, wave);
-        const float al = rz / pq;
-        float rn = 0.f;
-        for (int64_t p = threadIdx.x; p < Nx; p += blockDim.x) {
-          X[p] = fmaf(al, P[p], X[p]);
-          const float rv = fmaf(-al, Q[p], R[p]);
-          R[p] = rv;
-          rn = fmaf(rv, rv, rn);
-        }
-        rn = block_sum_f<NW>(rn, fslots[1], lane, wave);   // its barrier also publishes R
-        rr = rn;
-        ++it;
-        if (!(rr < 3.0e38f)) {
-          bad = true;
-          break;
-        }
-        if (rr <= stop) break;
-        float rzn = 0.f;
-        if (h.smoother == kMgGaussSeidel) {   // r.z accumulated by the V-cycle's last sweeps
-          Z = mg_vcycle_gs<float>(base, h, R, &rzn);
-        } else {
-          Z = mg_vcycle<float>(base, h, R);
-          for (int64_t p = threadIdx.x; p < Nx; p += blockDim.x) rzn = fmaf(R[p], Z[p], rzn);
-        }
-        rzn = block_sum_f<NW>(rzn, fslots[0], lane, wave);
-        const float be = rzn / rz;
-        rz = rzn;
-        for (int64_t p = threadIdx.x; p < Nx; p += blockDim.x) P[p] = fmaf(be, P[p], Z[p]);
-        __syncthreads();
-      }
-      t_cg += clock64() - t0;
-      tot_it += it;
-      max_it = it > (int)max_it ? it : max_it;
-      if (bad) {   // a non-finite float32 pass is discarded; the step reports failure
-        fail = true;
-        break;
-      }
-      __syncthreads();   // X complete before neighbours are read below
-      // float64 update with the correction e = sig D^{-1/2} X:  res -= M e,  w += e
-      double emax[2] = {0.0, 0.0};
-      const bool mx1[2] = {true, true};
-      for (int64_t p = threadIdx.x; p < Nx; p += blockDim.x) {
-        const int i = (int)(p % n), j = (int)(p / n);
-        const double ep = sig * dv[p] * (double)X[p];
-        const double ew = i > 0 ? sig * dv[p - 1] * (double)X[p - 1] : 0.0;
-        const double ee = i < n - 1 ? sig * dv[p + 1] * (double)X[p + 1] : 0.0;
-        const double es = j > 0 ? sig * dv[p - n] * (double)X[p - n] : 0.0;
-        const double en = j < n - 1 ? sig * dv[p + n] * (double)X[p + n] : 0.0;
-        const double Me = ep + c * (af[g.fW(i, j)] * (ep - ew) + af[g.fE(i, j)] * (ep - ee) +
-                                    af[g.fS(i, j)] * (ep - es) + af[g.fN(i, j)] * (ep - en));
-        const double rv = res[p] - Me;
-        res[p] = rv;
-        w[p] += ep;
-        inc[p] += ep;
-        emax[0] = nanmax(emax[0], fabs(rv));
-        emax[1] = nanmax(emax[1], dv[p] * fabs(rv));
-      }
-      block_reduce<2>(emax, mx1, dslots);
-      rmax = emax[0];
-      sig = emax[1];
-      ++pass;
-    }
-    tot_pass += pass;
-    if (rmax > target) {
-      fail = true;
-      ++missed;
-    }
-  }
-  if (threadIdx.x == 0) {
-    if (fail) atomicOr(flag, 1);
-    atomicAdd(&cnt[0], tot_it);
-    atomicAdd(&cnt[1], tot_pass);
-    atomicAdd(&cnt[2], (unsigned long long)J);
-    atomicMax(&cnt[3], max_it);
-    atomicAdd(&cnt[5], missed);
-    atomicAdd(&cnt[8], (unsigned long long)(clock64() - t_start));
-    atomicAdd(&cnt[9], (unsigned long long)t_cg);
-  }
-}
-
 template <int NW, int CPL, int RPW, bool RB = false>
 void launch_resident(hipStream_t st, int64_t nsys, const double* a, const float* sf,
                      const double* dinv, const float* dinvf, int n, double c, double tauf, int J, double tol,
@@ -1422,28 +1173,8 @@ int propagate_impl(klecgc_ctx* ctx, const klecgc_problem& p, const FineArgs& fa,
                                                              fa.active, flag, cnt);
         break;
       case KC_FINE_MG: {
-        // 16 waves per system (the node loops are latency-bound); scratch for at most
-        // `chunk` systems at a time, and never fewer than the device keeps in flight
-        const MgLevels h = mg_levels(n, 1, 4 * Nx, tu.mg_sweeps, tu.mg_smoother);
-        const int64_t per_sys = (int64_t)sizeof(float) * h.per_sys + 3 * (int64_t)sizeof(double) * Nx;
-        // a fixed workspace (allocation-free call) takes as many systems per chunk as it holds
-        const bool fixed = ctx->ws.arena != nullptr;
-        const int64_t cap_bytes = fixed ? (int64_t)ctx->ws.arena_left() - 3 * 256 : (int64_t)16 << 30;
-        const int64_t chunk = std::min<int64_t>(nsys, fixed ? cap_bytes / per_sys
-                                                            : std::max<int64_t>(4LL * ctx->num_cus, cap_bytes / per_sys));
-        KC_REQUIRE(chunk >= 1, KC_EINVAL, "allocation-free call: one multigrid system needs " +
-                                              std::to_string(per_sys) + " bytes, more than the device scratch array has left");
-        float* scr = (float*)ctx->ws.get(WS_FINE_AUX, sizeof(float) * h.per_sys * chunk);
-        double* rb = (double*)ctx->ws.get(WS_KRYLOV, sizeof(double) * Nx * chunk);
-        // increments of the current and the previous step per system of a chunk
-        double* ib = (double*)ctx->ws.get(WS_FINE_INC, 2 * sizeof(double) * Nx * chunk);
-        for (int64_t s0 = 0; s0 < nsys; s0 += chunk) {
-          const int64_t cnt_sys = std::min<int64_t>(chunk, nsys - s0);
-          fine2d_mg_kernel<16, 4><<<dim3((unsigned)cnt_sys), dim3(1024), 0, st>>>(
-              fa.a, sf, dinv, n, c, tauf, J, tol, pcg_rtol, maxit, sr, fa.out, rb, ib, scr, h, s0, M, N,
-              fa.skip_first, fa.active, flag, cnt);
-          KC_LAUNCH_CHECK();
-        }
+        const int r = fine_mg_streamed(ctx, p, fa, tau, J, N, dinv, sf, flag, cnt);
+        if (r != KC_OK) throw Error{r, "multigrid fine propagation failed"};
         break;
       }
       default:
