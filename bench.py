@@ -43,6 +43,13 @@ KC_FINE_RB128 = 6
 # increment, two face-coefficient arrays and D^{-1/2} read, the increment written
 BYTES_PER_FP64_RESIDUAL_EVAL = 48.0
 BYTES_PER_COCG_UNKNOWN_IT = 128.0      # complex128 vectors streamed per COCG iteration
+# streamed multigrid fine path (grids above 128^2), per unknown, one smoothing sweep, float32
+# vectors and scaled couplings counted per pass and system (a pass reads a neighbour once):
+#  CG iteration: level-0 V-cycle 67 B (first sweep 16, restriction 17, two post-smoothing half
+#  sweeps 17 each) + coarser streamed levels ~28 B + P update 12 + matvec 16 + X/R update 24
+#  = 147 B; each implicit step: start 48 B + float64 residual 48 B = 96 B; each float64
+#  refinement pass: float32 right-hand side 24 B + float64 update 76 B = 100 B
+MG_BYTES_PER_CG_IT, MG_BYTES_PER_STEP, MG_BYTES_PER_PASS = 147.0, 96.0, 100.0
 
 
 def code_sha256(path: str) -> str:
@@ -264,6 +271,68 @@ def run_ragged(args):
     ctx.close()
 
 
+def run_iterations(args):
+    """The large configuration (2D 512^2, KL d = 20, N = 256, J = 128, M = 64): a bounded
+    number of parareal iterations from the coarse-sweep guess, timed; a full solve (about ten
+    iterations) takes over an hour on one GPU, so the line reports the iteration rate."""
+    import numpy as np
+    import torch
+
+    import paper_2510_26180_amd as K
+    import workloads as W
+    w = W.get(args.config)
+    M = args.M or w.M
+    iters = max(1, args.iters)
+    dev = torch.device("cuda:0")
+    ctx = K.Context(0)
+    prob = K.ProblemSpec.from_workload(w, max_iter=iters)
+    # one smoothing sweep per level (faster per solve than two at this grid, measured)
+    ctx.set_tuning(w.n, fine_variant=5, fine_pcg_rtol=1e-6, cgc_variant=5, cgc_inner_rtol=1e-4, mg_sweeps=1)
+    log(f"workload {w.name}: n={w.n} N={w.N} J={w.J} M={M} d={w.d}, {iters} parareal iteration(s)")
+    fh = ctx.kle_build_field(2, w.n, w.d, w.corr_len, w.sigma)
+    xi = torch.as_tensor(W.draw_xi(M, w.d, w.seed_eval)).to(dev)
+    a = torch.empty((M, w.n_faces), dtype=torch.float64, device=dev)
+    ctx.kle_synthesize(fh, xi, a)
+    U = torch.empty((M, w.N, w.Nx), dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.coarse_propagate(prob, a, None, U)
+    torch.cuda.synchronize()
+    t_init = time.perf_counter() - t0
+    log(f"coarse-sweep guess: {t_init:.1f} s")
+    t0 = time.perf_counter()
+    its, st, hist, rc = ctx.parareal_solve(prob, a, U, init=K.KC_INIT_GIVEN, init_U=U, allow_noconv=True)
+    torch.cuda.synchronize()
+    t_it = time.perf_counter() - t0
+    kt = ctx.last_times()
+    stats = ctx.last_stats()
+    fine_ms, fine_n = kt["fine"]
+    byts = w.Nx * (MG_BYTES_PER_CG_IT * stats["fine_krylov_its"] + MG_BYTES_PER_STEP * stats["fine_solves"] +
+                   MG_BYTES_PER_PASS * stats["fine_passes"])
+    achieved = byts / (fine_ms / 1e3) / 1e9
+    deltas = hist[:, :iters]
+    line = {
+        "metric": "parareal iteration rate, large configuration (not converged: bounded run)",
+        "value": M * iters / t_it, "unit": "sample-iterations/s", "n_gpus": 1, "steps": iters, "warmup": 0,
+        "ms_per_step": 1e3 * t_it / iters, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64+f32", "data": "synthetic",
+        "config": {"workload": f"{w.name}: 2D diffusion {w.n}x{w.n}, KL d={w.d} (corr {w.corr_len}, sigma {w.sigma}), "
+                               f"N={w.N}, J={w.J}, alpha={w.alpha}, M={M}, coarse-sweep guess, {iters} iteration(s)",
+                   "samples": M, "grid": w.n, "slices": w.N, "fine_steps": w.J},
+        "init_s": t_init, "iteration_s": t_it / iters,
+        "increment_after_iteration": {"median": float(np.median(deltas[:, -1])), "max": float(deltas[:, -1].max())},
+        "kernel_ms": {k: v[0] for k, v in kt.items()}, "solver_stats": stats,
+        "roofline": {"kernel": "fine multigrid (streamed passes)", "bound": "hbm", "achieved": achieved,
+                     "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+                     "algorithmic_gb_per_launch": byts / 1e9 / max(fine_n, 1), "launches": fine_n,
+                     "ms_per_launch": fine_ms / max(fine_n, 1),
+                     "algorithmic_unit": "147 B per unknown per CG iteration + 96 B per implicit step + 100 B per "
+                                         "float64 pass"},
+    }
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -271,6 +340,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="c2_2d_n128")
     ap.add_argument("--M", type=int, default=0, help="override the batch size (0 = config)")
+    ap.add_argument("--iters", type=int, default=1, help="large configuration: parareal iterations timed")
     ap.add_argument("--n-train", type=int, default=0)
     ap.add_argument("--init", choices=["gpc", "mlp", "both"], default=None,
                     help="initial guess (default: gpc; both for the MLP workload)")
@@ -290,8 +360,13 @@ def main():
                                    "several GPUs is not built"}))
         sys.exit(2)
 
+    if args.config in ("c3_ragged", "c5_2d_n512"):
+        os.environ.setdefault("KLECGC_PROGRESS", "1")   # long calls report from inside the library
     if args.config == "c3_ragged":
         run_ragged(args)
+        return
+    if args.config == "c5_2d_n512":
+        run_iterations(args)
         return
 
     pool, P = None, 0

@@ -1,7 +1,11 @@
 // C ABI entry points: argument validation, stream/device binding, error capture, and
 // the host-side orchestration of the KL / gPC stages and of the parareal iteration.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <functional>
 #include <vector>
@@ -17,6 +21,37 @@ int propagate_impl(klecgc_ctx* ctx, const klecgc_problem& p, const FineArgs& fa,
 void launch_dgemm_nt(hipStream_t s, int64_t Mr, int64_t Nc, int64_t K, const double* A,
                      int64_t lda, const double* B, int64_t ldb, double* C, int64_t ldc,
                      double alpha);
+
+bool progress_enabled() {
+  static const bool on = [] {
+    const char* v = std::getenv("KLECGC_PROGRESS");
+    return v && v[0] && v[0] != '0';
+  }();
+  return on;
+}
+
+static double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+bool progress_due(double& last_s) {
+  if (!progress_enabled()) return false;
+  const double t = now_s();
+  if (t - last_s < 10.0) return false;
+  last_s = t;
+  return true;
+}
+
+void progress_line(const char* fmt, ...) {
+  if (!progress_enabled()) return;
+  std::va_list ap;
+  va_start(ap, fmt);
+  std::fputs("[klecgc] ", stderr);
+  std::vfprintf(stderr, fmt, ap);
+  std::fputc('\n', stderr);
+  std::fflush(stderr);
+  va_end(ap);
+}
 
 void* Workspace::get(int slot, size_t bytes) {
   if ((int)ptr.size() < WS_COUNT) {

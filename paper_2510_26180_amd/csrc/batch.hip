@@ -292,7 +292,7 @@ static int run_classes(klecgc_ctx* ctx, std::vector<ParaClass*>& cls, bool use_g
                        DriverOut& out, bool progress = false) {
   const auto t_start = std::chrono::steady_clock::now();
   auto report = [&](int k, int active) {
-    if (!progress) return;
+    if (!progress && !progress_enabled()) return;
     const double s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
     std::fprintf(stderr, "[klecgc] parareal iteration %d: %d samples active, %.1f s\n", k, active, s);
     std::fflush(stderr);

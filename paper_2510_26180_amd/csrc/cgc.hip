@@ -80,102 +80,105 @@ __global__ void defect_kernel(const double* __restrict__ a, int dim, int n, doub
 }
 
 // ---------------------------------------------------------------- FFTs
-// One thread per column (m, x); COLS consecutive x per work-group; the column's N
-// values live in LDS as [N][COLS] complex so that a wave touches contiguous words.
-template <int COLS>
-__device__ void fft_inplace(cd* buf, const cd* tw, int N, int logn, int t) {
+// A work-group transforms C consecutive columns (m, x .. x + C - 1) along the slice axis:
+// their N values live in LDS as [N][C] complex, thread t serves column t % C and takes
+// every T-th butterfly of each radix-2 stage (T = threads per column), with a barrier
+// between stages.  Consecutive threads hold consecutive columns, so every load and store
+// of a slice row is one contiguous segment.
+template <int C, int T>
+__device__ __forceinline__ void fft_stages(cd* buf, const cd* tw, int N, int c, int r) {
   for (int len = 2; len <= N; len <<= 1) {
     const int half = len >> 1;
     const int stride = N / len;
-    for (int start = 0; start < N; start += len) {
-      for (int k = 0; k < half; ++k) {
-        cd w = tw[k * stride];
-        cd u = buf[(start + k) * COLS + t];
-        cd v = buf[(start + k + half) * COLS + t] * w;
-        buf[(start + k) * COLS + t] = u + v;
-        buf[(start + k + half) * COLS + t] = u - v;
-      }
+    for (int b = r; b < N / 2; b += T) {
+      const int k = b & (half - 1);
+      const int i0 = (b - k) * 2 + k;            // start of the block + k
+      const cd w = tw[k * stride];
+      const cd u = buf[i0 * C + c];
+      const cd v = buf[(i0 + half) * C + c] * w;
+      buf[i0 * C + c] = u + v;
+      buf[(i0 + half) * C + c] = u - v;
     }
+    __syncthreads();
   }
 }
 
-template <int COLS>
-__global__ __launch_bounds__(COLS) void fft_forward_kernel(const double* __restrict__ r, int64_t Nx,
-                                                           int N, int logn, double alpha,
-                                                           const uint8_t* __restrict__ active,
-                                                           double* __restrict__ spec) {
+template <int C, int T>
+__global__ __launch_bounds__(C * T) void fft_forward_kernel(const double* __restrict__ r, int64_t Nx,
+                                                            int N, int logn, double alpha,
+                                                            const uint8_t* __restrict__ active,
+                                                            double* __restrict__ spec) {
   extern __shared__ cd lds[];
-  cd* buf = lds;                 // [N][COLS]
-  cd* tw = lds + N * COLS;       // [N/2] e^{-2 pi i k / N}
-  const int t = threadIdx.x;
+  cd* buf = lds;                 // [N][C]
+  cd* tw = lds + N * C;          // [N/2] e^{-2 pi i k / N}
+  const int c = threadIdx.x % C, rr = threadIdx.x / C;
   const int64_t m = blockIdx.y;
   if (active && !active[m]) return;
-  for (int k = t; k < N / 2; k += COLS) {
+  for (int k = threadIdx.x; k < N / 2; k += C * T) {
     double sv, cv;
     sincospi(-2.0 * k / N, &sv, &cv);
     tw[k] = {cv, sv};
   }
-  const int64_t x = (int64_t)blockIdx.x * COLS + t;
-  const double invsq = 1.0 / sqrt((double)N);
+  const int64_t x = (int64_t)blockIdx.x * C + c;
+  const bool ok = x < Nx;
   const double la = log(alpha) / N;
-  if (x < Nx) {
-    const double* col = r + m * N * Nx + x;
-    for (int s = 0; s < N; ++s) {
-      double sc = exp(la * s);   // alpha^{s/N}
-      buf[bitrev(s, logn) * COLS + t] = {sc * col[(int64_t)s * Nx], 0.0};
-    }
+  const double* col = r + m * N * Nx + x;
+  for (int s = rr; s < N; s += T) {
+    const double sc = exp(la * s);   // alpha^{s/N}
+    buf[bitrev(s, logn) * C + c] = {ok ? sc * col[(int64_t)s * Nx] : 0.0, 0.0};
   }
   __syncthreads();
-  if (x < Nx) {
-    fft_inplace<COLS>(buf, tw, N, logn, t);
+  fft_stages<C, T>(buf, tw, N, c, rr);
+  if (ok) {
+    const double invsq = 1.0 / sqrt((double)N);
     const int K = N / 2 + 1;
     cd* out = (cd*)spec + m * K * Nx + x;
-    for (int k = 0; k < K; ++k) out[(int64_t)k * Nx] = invsq * buf[k * COLS + t];
+    for (int k = rr; k < K; k += T) out[(int64_t)k * Nx] = invsq * buf[k * C + c];
   }
 }
 
 // u_s = alpha^{-s/N} Re( N^{-1/2} sum_k e^{+2 pi i k s/N} Q_k ), Q_{N-k} = conj(Q_k).
 // accumulate: u += result; maxima[m] = {max |result|, max |u_new|} as ordered bit patterns.
-template <int COLS>
-__global__ __launch_bounds__(COLS) void fft_inverse_kernel(const double* __restrict__ spec,
-                                                           int64_t Nx, int N, int logn,
-                                                           double alpha,
-                                                           const uint8_t* __restrict__ active,
-                                                           double* __restrict__ u, int accumulate,
-                                                           unsigned long long* __restrict__ maxima) {
+template <int C, int T>
+__global__ __launch_bounds__(C * T) void fft_inverse_kernel(const double* __restrict__ spec,
+                                                            int64_t Nx, int N, int logn,
+                                                            double alpha,
+                                                            const uint8_t* __restrict__ active,
+                                                            double* __restrict__ u, int accumulate,
+                                                            unsigned long long* __restrict__ maxima) {
   extern __shared__ cd lds[];
   cd* buf = lds;
-  cd* tw = lds + N * COLS;       // e^{+2 pi i k / N}
-  const int t = threadIdx.x;
+  cd* tw = lds + N * C;          // e^{+2 pi i k / N}
+  __shared__ double red[2][C * T / 64];
+  const int c = threadIdx.x % C, rr = threadIdx.x / C;
   const int64_t m = blockIdx.y;
   if (active && !active[m]) return;
-  for (int k = t; k < N / 2; k += COLS) {
+  for (int k = threadIdx.x; k < N / 2; k += C * T) {
     double sv, cv;
     sincospi(2.0 * k / N, &sv, &cv);
     tw[k] = {cv, sv};
   }
-  const int64_t x = (int64_t)blockIdx.x * COLS + t;
+  const int64_t x = (int64_t)blockIdx.x * C + c;
+  const bool ok = x < Nx;
   const int K = N / 2 + 1;
-  if (x < Nx) {
-    const cd* in = (const cd*)spec + m * K * Nx + x;
-    for (int k = 0; k < K; ++k) {
-      cd q = in[(int64_t)k * Nx];
-      buf[bitrev(k, logn) * COLS + t] = q;
-      if (k > 0 && k < N - k) buf[bitrev(N - k, logn) * COLS + t] = conj(q);
-    }
+  const cd* in = (const cd*)spec + m * K * Nx + x;
+  for (int k = rr; k < K; k += T) {
+    const cd q = ok ? in[(int64_t)k * Nx] : cd{0.0, 0.0};
+    buf[bitrev(k, logn) * C + c] = q;
+    if (k > 0 && k < N - k) buf[bitrev(N - k, logn) * C + c] = conj(q);
   }
   __syncthreads();
+  fft_stages<C, T>(buf, tw, N, c, rr);
   double cmax = 0.0, umax = 0.0;
-  if (x < Nx) {
-    fft_inplace<COLS>(buf, tw, N, logn, t);
+  if (ok) {
     const double invsq = 1.0 / sqrt((double)N);
     const double la = -log(alpha) / N;
     double* col = u + m * N * Nx + x;
-    for (int s = 0; s < N; ++s) {
-      double v = exp(la * s) * invsq * buf[s * COLS + t].x;
+    for (int s = rr; s < N; s += T) {
+      const double v = exp(la * s) * invsq * buf[s * C + c].x;
       double* dst = col + (int64_t)s * Nx;
       if (accumulate) {
-        double nu = *dst + v;
+        const double nu = *dst + v;
         *dst = nu;
         cmax = nanmax(cmax, fabs(v));
         umax = nanmax(umax, fabs(nu));
@@ -185,19 +188,20 @@ __global__ __launch_bounds__(COLS) void fft_inverse_kernel(const double* __restr
     }
   }
   if (maxima) {
-    // non-negative doubles order like their bit patterns
-    if (COLS >= 64) {
-      cmax = wave_nanmax(cmax);
-      umax = wave_nanmax(umax);
-    } else {
-      // a work-group of COLS < 64 threads is one partial wave: reduce over its lanes only
-#pragma unroll
-      for (int off = COLS / 2; off >= 1; off >>= 1) {
-        cmax = nanmax(cmax, __shfl_xor(cmax, off, COLS));
-        umax = nanmax(umax, __shfl_xor(umax, off, COLS));
-      }
+    // non-negative doubles order like their bit patterns; one atomic per work-group
+    cmax = wave_nanmax(cmax);
+    umax = wave_nanmax(umax);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+      red[0][w] = cmax;
+      red[1][w] = umax;
     }
-    if ((t & 63) == 0) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      for (int q = 1; q < C * T / 64; ++q) {
+        cmax = nanmax(cmax, red[0][q]);
+        umax = nanmax(umax, red[1][q]);
+      }
       atomicMax(&maxima[2 * m], (unsigned long long)__double_as_longlong(cmax));
       atomicMax(&maxima[2 * m + 1], (unsigned long long)__double_as_longlong(umax));
     }
@@ -366,12 +370,14 @@ __global__ __launch_bounds__(kCocgThreads) void cocg_kernel(const double* __rest
 // registers, the correction accumulated in an LDS tile), adds it to q in float64 and
 // updates the residual, until |res|_2 <= rtol |p|_2.
 
+// D_r^{-1/2} of the shifted systems mk0 .. mk0 + gridDim.y - 1, stored from dr (row of system
+// mk0 first)
 __global__ void shift_dinv_kernel(const double* __restrict__ a, int n, double cT, int N, double alpha,
-                                  int64_t M, double* __restrict__ dr) {
+                                  int64_t M, double* __restrict__ dr, int64_t mk0 = 0) {
   const int K = N / 2 + 1;
   const int64_t Nx = (int64_t)n * n;
   int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int64_t mk = blockIdx.y;
+  int64_t mk = mk0 + blockIdx.y;
   if (p >= Nx || mk >= M * K) return;
   int64_t m = mk / K;
   int k = (int)(mk % K);
@@ -383,7 +389,7 @@ __global__ void shift_dinv_kernel(const double* __restrict__ a, int n, double cT
   int i = (int)(p % n), j = (int)(p / n);
   double sa = af[(int64_t)j * (n + 1) + i] + af[(int64_t)j * (n + 1) + i + 1] + af[nx + (int64_t)j * n + i] +
               af[nx + (int64_t)(j + 1) * n + i];
-  dr[mk * Nx + p] = 1.0 / sqrt(lre + cT * sa);
+  dr[(mk - mk0) * Nx + p] = 1.0 / sqrt(lre + cT * sa);
 }
 
 template <int CTRL>
@@ -905,23 +911,24 @@ __global__ __launch_bounds__(64 * NW, WPE) void cocg_mg_kernel(
     const double* __restrict__ a, const double* __restrict__ dinvr, int n, double cT, int N, double alpha,
     double rtol, float inner_rtol, int maxit, const uint8_t* __restrict__ active, double* __restrict__ spec,
     double* __restrict__ resbuf, float* __restrict__ scr, MgLevels h, int* __restrict__ flag,
-    unsigned long long* __restrict__ cnt) {
+    unsigned long long* __restrict__ cnt, int64_t sys0) {
   __shared__ float fsl[2][3 * NW];
   __shared__ double dsl[4 * NW];
   const int K = N / 2 + 1;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int64_t sys = blockIdx.x;
+  // system sys0 + b of the launch; its D_r^{-1/2}, residual and scratch rows are the b-th
+  const int64_t sys = sys0 + blockIdx.x;
   const int64_t m = sys / K;
   const int k = (int)(sys % K);
   if (active && !active[m]) return;
   const int64_t Nx = (int64_t)n * n;
   const int64_t nx = (int64_t)n * (n + 1);
   const double* af = a + m * 2 * nx;
-  const double* dr = dinvr + sys * Nx;
+  const double* dr = dinvr + (int64_t)blockIdx.x * Nx;
   double2* q = (double2*)spec + sys * Nx;
-  double2* res = (double2*)resbuf + sys * Nx;
-  float* base = scr + sys * h.per_sys;
+  double2* res = (double2*)resbuf + (int64_t)blockIdx.x * Nx;
+  float* base = scr + (int64_t)blockIdx.x * h.per_sys;
   float2* X = (float2*)base;
   float2* R = X + Nx;
   float2* P = R + Nx;
@@ -1121,9 +1128,9 @@ void launch_cocg_resident(hipStream_t st, int64_t nsys, const double* a, const d
   KC_LAUNCH_CHECK();
 }
 
-template <int COLS>
+template <int C>
 size_t fft_lds(int N) {
-  return sizeof(cd) * ((size_t)N * COLS + N / 2);
+  return sizeof(cd) * ((size_t)N * C + N / 2);
 }
 
 }  // namespace
@@ -1144,23 +1151,24 @@ static int ilog2(int N) {
   return l;
 }
 
-// Columns per work-group: the [N][COLS] complex LDS tile stays at 32 KB (N >= 32).
+// Columns per work-group C and threads per column T (C T = 256): the [N][C] complex LDS
+// tile stays at 32 KB for N >= 32; for N <= 4 the columns take one thread each.
+#define KC_FFT_LAUNCH(KERNEL, C_, T_, ...)                                                      \
+  KERNEL<C_, T_><<<dim3((unsigned)((Nx_ + (C_) - 1) / (C_)), (unsigned)M), dim3((C_) * (T_)), fft_lds<C_>(p.N), s>>>( \
+      __VA_ARGS__)
 #define KC_FFT_DISPATCH(KERNEL, ...)                                                            \
   do {                                                                                          \
     const int64_t Nx_ = n_unknowns(p);                                                          \
-    if (p.N <= 32) {                                                                            \
-      constexpr int C = 64;                                                                     \
-      KERNEL<C><<<dim3((unsigned)((Nx_ + C - 1) / C), (unsigned)M), dim3(C), fft_lds<C>(p.N), s>>>(__VA_ARGS__); \
-    } else if (p.N == 64) {                                                                     \
-      constexpr int C = 32;                                                                     \
-      KERNEL<C><<<dim3((unsigned)((Nx_ + C - 1) / C), (unsigned)M), dim3(C), fft_lds<C>(p.N), s>>>(__VA_ARGS__); \
-    } else if (p.N == 128) {                                                                    \
-      constexpr int C = 16;                                                                     \
-      KERNEL<C><<<dim3((unsigned)((Nx_ + C - 1) / C), (unsigned)M), dim3(C), fft_lds<C>(p.N), s>>>(__VA_ARGS__); \
-    } else {                                                                                    \
-      constexpr int C = 8;                                                                      \
-      KERNEL<C><<<dim3((unsigned)((Nx_ + C - 1) / C), (unsigned)M), dim3(C), fft_lds<C>(p.N), s>>>(__VA_ARGS__); \
-    }                                                                                           \
+    if (p.N <= 4)                                                                               \
+      KC_FFT_LAUNCH(KERNEL, 256, 1, __VA_ARGS__);                                               \
+    else if (p.N <= 32)                                                                         \
+      KC_FFT_LAUNCH(KERNEL, 64, 4, __VA_ARGS__);                                                \
+    else if (p.N == 64)                                                                         \
+      KC_FFT_LAUNCH(KERNEL, 32, 8, __VA_ARGS__);                                                \
+    else if (p.N == 128)                                                                        \
+      KC_FFT_LAUNCH(KERNEL, 16, 16, __VA_ARGS__);                                               \
+    else                                                                                        \
+      KC_FFT_LAUNCH(KERNEL, 8, 32, __VA_ARGS__);                                                \
     KC_LAUNCH_CHECK();                                                                          \
   } while (0)
 
@@ -1205,18 +1213,24 @@ int shifted_solve_impl(klecgc_ctx* ctx, const klecgc_problem& p, const double* a
   const float inner = tu.cgc_inner_rtol;
   if (variant == KC_CGC_MG32) {
     const MgLevels h = mg_levels(p.n, 2, 8LL * Nx, tu.mg_sweeps, tu.mg_smoother);
-    double* dr = (double*)ctx->ws.get(WS_DINV, sizeof(double) * Nx * nsys);
-    double* resb = (double*)ctx->ws.get(WS_KRYLOV, sizeof(double) * 2 * Nx * nsys);
-    float* scr = (float*)ctx->ws.get(WS_FINE_AUX, sizeof(float) * h.per_sys * nsys);
-    shift_dinv_kernel<<<dim3((unsigned)((Nx + 255) / 256), (unsigned)nsys), dim3(256), 0, st>>>(
-        a, p.n, cT, p.N, p.alpha, M, dr);
-    KC_LAUNCH_CHECK();
+    // systems run in chunks whose D_r^{-1/2}, residuals and scratch take at most 16 GiB
+    const int64_t per_sys = (int64_t)sizeof(double) * 3 * Nx + (int64_t)sizeof(float) * h.per_sys;
+    const int64_t chunk = std::min<int64_t>(nsys, std::max<int64_t>(4LL * ctx->num_cus, ((int64_t)16 << 30) / per_sys));
+    double* dr = (double*)ctx->ws.get(WS_DINV, sizeof(double) * Nx * chunk);
+    double* resb = (double*)ctx->ws.get(WS_KRYLOV, sizeof(double) * 2 * Nx * chunk);
+    float* scr = (float*)ctx->ws.get(WS_FINE_AUX, sizeof(float) * h.per_sys * chunk);
     timed(ctx, KT_SHIFTED, [&] {
-      // 16 waves per system, one work-group per CU: the node loops are latency-bound and
-      // gain most from the waves one system can keep in flight
-      cocg_mg_kernel<16, 4><<<dim3((unsigned)nsys), dim3(1024), 0, st>>>(
-          a, dr, p.n, cT, p.N, p.alpha, rtol, inner, maxit, active, spec, resb, scr, h, ds.flag, ds.cnt);
-      KC_LAUNCH_CHECK();
+      for (int64_t s0 = 0; s0 < nsys; s0 += chunk) {
+        const int64_t cs = std::min<int64_t>(chunk, nsys - s0);
+        shift_dinv_kernel<<<dim3((unsigned)((Nx + 255) / 256), (unsigned)cs), dim3(256), 0, st>>>(
+            a, p.n, cT, p.N, p.alpha, M, dr, s0);
+        KC_LAUNCH_CHECK();
+        // 16 waves per system, one work-group per CU: the node loops are latency-bound and
+        // gain most from the waves one system can keep in flight
+        cocg_mg_kernel<16, 4><<<dim3((unsigned)cs), dim3(1024), 0, st>>>(
+            a, dr, p.n, cT, p.N, p.alpha, rtol, inner, maxit, active, spec, resb, scr, h, ds.flag, ds.cnt, s0);
+        KC_LAUNCH_CHECK();
+      }
     });
     return status_collect(ctx, ds, 4) ? KC_ENOCONV : KC_OK;
   }

@@ -274,6 +274,12 @@ int grid_restrict_impl(klecgc_ctx* ctx, int n, int nc, const double* U, int64_t 
 int mlp_initial_guess_impl(klecgc_ctx* ctx, klecgc_mlp* h, int n, int nc, int N, const double* xi, int64_t M,
                            double* U0);
 
+// Progress lines on stderr from long-running loops, enabled by the environment variable
+// KLECGC_PROGRESS=1 (read once); `progress_due` rate-limits a loop to one line per 10 s.
+bool progress_enabled();
+bool progress_due(double& last_s);
+void progress_line(const char* fmt, ...);
+
 // the allocation-free scratch array (noalloc.hip): resolves this device's copy (the device
 // must be current), its size, and a fill kernel that clears device memory without a memset
 hipError_t scratch_resolve(int device, void** out);

@@ -872,6 +872,9 @@ int fine_mg_streamed(klecgc_ctx* ctx, const klecgc_problem& p, const FineArgs& f
     oc.coef_off[l] = y.coef_off[l];
   }
 
+  double last_line = 0.0;
+  progress_line("multigrid fine propagation: %lld systems of %dx%d, %d steps, chunks of %lld", (long long)nsys, n, n,
+                J, (long long)chunk);
   F64 f{fa.a, dinv, c, tau * p.forcing, fa.out, res, incb, n, y.rb[0]};
   StartRef sr{fa.start, fa.u0, fa.start_shift};
   const int sw = y.sweeps;
@@ -981,6 +984,9 @@ int fine_mg_streamed(klecgc_ctx* ctx, const klecgc_problem& p, const FineArgs& f
       }
       k_decide<<<(unsigned)S, 64, 0, st>>>(ch, part, nb0, PH_END, k0);
       KC_LAUNCH_CHECK();
+      if (progress_due(last_line))
+        progress_line("multigrid fine propagation: systems %lld..%lld of %lld, step %d of %d", (long long)s0,
+                      (long long)(s0 + S), (long long)nsys, step + 1, J);
     }
     k_stats<<<grid1(S), 256, 0, st>>>(sysst, S, J, flag, cnt);
     KC_LAUNCH_CHECK();
