@@ -18,9 +18,13 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <exception>
+#include <functional>
 #include <map>
+#include <mutex>
 #include <memory>
 #include <numeric>
+#include <thread>
 #include <vector>
 
 #include "common.h"
@@ -522,6 +526,142 @@ static int run_classes(klecgc_ctx* ctx, std::vector<ParaClass*>& cls, bool use_g
   return rc;
 }
 
+// Ragged batches: the classes advance independently, each on its own host thread and
+// stream.  A class whose iteration is a fixed launch sequence runs its first iteration
+// eagerly, then captures one iteration into a graph of its own and replays it; a class whose
+// fine sweep steers its loops from the host runs every iteration eagerly.  A class stops as
+// soon as all its samples have retired, so the samples of fast classes leave early instead of
+// waiting for the slowest class at every iteration.  init_class puts the class's initial
+// guess into its U (on the class's stream).
+static int run_classes_threads(klecgc_ctx* ctx, std::vector<ParaClass*>& cls, bool use_graph, bool progress,
+                               const std::function<int(ParaClass&)>& init_class, DriverOut& out) {
+  hipStream_t main = ctx->stream;
+  const int C = (int)cls.size();
+  char* cbuf = (char*)ctx->ws.get(WS_SMALL, 256 + sizeof(int) * (C + 1));
+  unsigned long long* t0dev = (unsigned long long*)cbuf;
+  int* counts = (int*)(cbuf + 256);
+  std::vector<int> hc(C + 1);
+  hc[0] = 0;
+  for (int i = 0; i < C; ++i) {
+    hc[i + 1] = (int)cls[i]->M;
+    hc[0] += hc[i + 1];
+  }
+  KC_TRY_HIP(hipMemcpyAsync(counts, hc.data(), sizeof(int) * (C + 1), hipMemcpyHostToDevice, main));
+  stamp_kernel<<<1, 64, 0, main>>>(t0dev);
+  KC_LAUNCH_CHECK();
+  hipEvent_t fork = nullptr;
+  KC_TRY_HIP(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+  struct EvGuard {
+    hipEvent_t e;
+    ~EvGuard() {
+      if (e) (void)hipEventDestroy(e);
+    }
+  } fg{fork};
+  KC_TRY_HIP(hipEventRecord(fork, main));
+  std::vector<int> rcs(C, KC_OK), iters(C, 0);
+  std::vector<std::exception_ptr> errs(C);
+  std::mutex capture_mu;   // one capture at a time
+  auto work = [&](int i) {
+    ParaClass& pc = *cls[i];
+    klecgc_ctx* c = pc.c;
+    hipStream_t s = c->stream;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    try {
+      KC_TRY_HIP(hipSetDevice(ctx->device));
+      KC_TRY_HIP(hipStreamWaitEvent(s, fork, 0));
+      pc.index = i + 1;
+      pc.st.alloc(pc.M, pc.p.max_iter, false);
+      class_init_kernel<<<blocks_of(pc.M), 256, 0, s>>>(pc.M, pc.st.active, pc.st.its, pc.st.status, pc.st.maxima);
+      KC_LAUNCH_CHECK();
+      int r = init_class(pc);
+      if (r != KC_OK) rcs[i] = r;
+      const bool capture = use_graph && iteration_capturable(pc);
+      int left = (int)pc.M, k = 0;
+      double last_line = 0.0;
+      while (k < pc.p.max_iter && left > 0) {
+        if (capture && k == 1) {
+          // replays accumulate the solver counters into status blocks cleared here
+          status_reset(c, status_block(c, WS_STATUS));
+          status_reset(c, status_block(c, WS_STATUS_CGC));
+          std::lock_guard<std::mutex> lock(capture_mu);
+          KC_TRY_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
+          c->capturing = true;
+          try {
+            enqueue_iteration(pc, 1, counts, rcs[i]);
+          } catch (...) {
+            c->capturing = false;
+            hipGraph_t g = nullptr;
+            (void)hipStreamEndCapture(s, &g);
+            if (g) (void)hipGraphDestroy(g);
+            throw;
+          }
+          c->capturing = false;
+          KC_TRY_HIP(hipStreamEndCapture(s, &graph));
+          const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+          if (ie != hipSuccess) throw Error{KC_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie)};
+        }
+        if (exec)
+          KC_TRY_HIP(hipGraphLaunch(exec, s));
+        else
+          enqueue_iteration(pc, k, counts, rcs[i]);
+        int hv = 0;
+        KC_TRY_HIP(hipMemcpyAsync(&hv, counts + i + 1, sizeof(int), hipMemcpyDeviceToHost, s));
+        KC_TRY_HIP(hipStreamSynchronize(s));
+        left = hv;
+        ++k;
+        if (progress || progress_due(last_line))   // every iteration when asked, else one line per 10 s
+          std::fprintf(stderr, "[klecgc] class %dx%d N=%d (%lld samples): iteration %d, %d active\n", pc.p.n, pc.p.n,
+                       pc.p.N, (long long)pc.M, k, left),
+              std::fflush(stderr);
+      }
+      if (exec) {
+        if (status_collect(c, status_block(c, WS_STATUS), 0)) rcs[i] = KC_ENOCONV;
+        if (pc.p.dim == 2 && status_collect(c, status_block(c, WS_STATUS_CGC), 4)) rcs[i] = KC_ENOCONV;
+      }
+      iters[i] = k;
+    } catch (...) {
+      errs[i] = std::current_exception();
+    }
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+  };
+  {
+    std::vector<std::thread> threads;
+    for (int i = 0; i < C; ++i) threads.emplace_back(work, i);
+    for (auto& t : threads) t.join();
+  }
+  for (auto& e : errs)
+    if (e) std::rethrow_exception(e);
+  int rc = KC_OK;
+  for (int r : rcs)
+    if (r != KC_OK) rc = r;
+  out.iterations = *std::max_element(iters.begin(), iters.end());
+  for (auto* pc : cls) {
+    for (int i = 0; i < 16; ++i) ctx->stats[i] += pc->c->stats[i];
+    for (int i = 0; i < 8; ++i) {
+      ctx->ktime[i] += pc->c->ktime[i];
+      ctx->kcount[i] += pc->c->kcount[i];
+    }
+  }
+  out.its.clear();
+  out.status.clear();
+  out.tconv.clear();
+  for (auto* pc : cls) {
+    const size_t o = out.its.size();
+    out.its.resize(o + pc->M);
+    out.status.resize(o + pc->M);
+    out.tconv.resize(o + pc->M);
+    KC_TRY_HIP(hipMemcpyAsync(&out.its[o], pc->st.its, sizeof(int32_t) * pc->M, hipMemcpyDeviceToHost, main));
+    KC_TRY_HIP(hipMemcpyAsync(&out.status[o], pc->st.status, sizeof(int32_t) * pc->M, hipMemcpyDeviceToHost, main));
+    KC_TRY_HIP(hipMemcpyAsync(&out.tconv[o], pc->st.tconv, sizeof(unsigned long long) * pc->M,
+                              hipMemcpyDeviceToHost, main));
+  }
+  KC_TRY_HIP(hipMemcpyAsync(&out.t0, t0dev, sizeof(unsigned long long), hipMemcpyDeviceToHost, main));
+  KC_TRY_HIP(hipStreamSynchronize(main));
+  return rc;
+}
+
 // ---------------------------------------------------------------- uniform batch
 namespace {
 // the restricted grid nc of a network whose n_out is N nc^2 (0 if there is none)
@@ -758,23 +898,20 @@ int parareal_batch_impl(klecgc_ctx* ctx, const klecgc_problem& base, const klecg
   }
   KC_TRY_HIP(hipStreamSynchronize(main));
   std::vector<ParaClass*> cls;
-  for (auto& pc : pcs) {
-    cls.push_back(pc.get());
+  for (auto& pc : pcs) cls.push_back(pc.get());
+  auto init_class = [&](ParaClass& pc) -> int {
     if (init == KC_INIT_ZERO) {
-      zero_kernel<<<blocks_of(pc->M * pc->p.N * n_unknowns(pc->p)), 256, 0, pc->c->stream>>>(
-          pc->U, pc->M * pc->p.N * n_unknowns(pc->p));
+      zero_kernel<<<blocks_of(pc.M * pc.p.N * n_unknowns(pc.p)), 256, 0, pc.c->stream>>>(
+          pc.U, pc.M * pc.p.N * n_unknowns(pc.p));
       KC_LAUNCH_CHECK();
     } else if (init == KC_INIT_COARSE) {
-      int r = coarse_sweep_impl(pc->c, pc->p, pc->a, nullptr, pc->M, pc->U);
-      if (r != KC_OK) rc = r;
+      return coarse_sweep_impl(pc.c, pc.p, pc.a, nullptr, pc.M, pc.U);
     }
-    // status blocks are reset once: replays of a captured iteration accumulate into them
-    status_reset(pc->c, status_block(pc->c, WS_STATUS));
-    status_reset(pc->c, status_block(pc->c, WS_STATUS_CGC));
-    KC_TRY_HIP(hipStreamSynchronize(pc->c->stream));
-  }
+    return KC_OK;
+  };
   DriverOut out;
-  int r = run_classes(ctx, cls, (flags & KC_BATCH_GRAPH) != 0, false, out, (flags & KC_BATCH_PROGRESS) != 0);
+  int r = run_classes_threads(ctx, cls, (flags & KC_BATCH_GRAPH) != 0, (flags & KC_BATCH_PROGRESS) != 0, init_class,
+                              out);
   if (r != KC_OK) rc = r;
   // scatter the iterates back
   for (int i = 0; i < C; ++i) {
