@@ -294,6 +294,20 @@ int parareal_solve(klecgc_ctx* ctx, const klecgc_problem* prob, const double* a_
                    double* U_dev, int32_t* iters_host, int32_t* status_host,
                    double* delta_hist_host, int32_t* guess_host);
 
+/* parareal_solve_sequential (Section 3.1, Algorithm 1, eq. pred_correc): parareal with the
+ * sequential coarse grid correction, the comparator of Section 5 ("standard parareal"):
+ *     U^{k+1}_1 = F(u0),  U^{k+1}_s = G(U^{k+1}_{s-1}) + F(U^k_{s-1}) - G(U^k_{s-1}),
+ * G one backward-Euler step of dT = T/N.  The fine sweep and the coarse steps of the old
+ * starts run over all slices at once; the correction sweeps the N slices in order (one
+ * batched coarse step per slice).  alpha is not used.  Arguments as parareal_solve, with
+ * init any mode but KC_INIT_MLP_GPC_FALLBACK (KC_EUNSUPPORTED); the stop rule is the same
+ * increment test.  In exact arithmetic U^N is the serial fine solution (finite termination). */
+int parareal_solve_sequential(klecgc_ctx* ctx, const klecgc_problem* prob, const double* a_dev,
+                              const double* u0_dev, int64_t M, int32_t init, const double* init_dev,
+                              const klecgc_gpc* gpc, klecgc_mlp* mlp, const double* xi_dev, uint64_t seed,
+                              double* U_dev, int32_t* iters_host, int32_t* status_host,
+                              double* delta_hist_host);
+
 /* ---- ragged batches ------------------------------------------------------------
  * Samples of one problem family that differ in grid size n and slice count N, solved
  * together by the iteration of parareal_solve (Algorithm 2 with the diagonalised CGC of

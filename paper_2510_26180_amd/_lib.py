@@ -86,6 +86,8 @@ SIGNATURES = {
     "parareal_solve": (ctypes.c_int, [_vp, _P(Problem), _vp, _vp, _i64, _i32, _vp, _vp, _vp, _vp,
                                       ctypes.c_uint64, _vp, _P(_i32), _P(_i32), _P(ctypes.c_double),
                                       _P(_i32)]),
+    "parareal_solve_sequential": (ctypes.c_int, [_vp, _P(Problem), _vp, _vp, _i64, _i32, _vp, _vp, _vp, _vp,
+                                                 ctypes.c_uint64, _vp, _P(_i32), _P(_i32), _P(ctypes.c_double)]),
     "parareal_solve_batch": (ctypes.c_int, [_vp, _P(Problem), _P(Task), _i64, _vp, _i32, _vp, _i32,
                                             _P(_i32), _P(_i32), _P(ctypes.c_double), _P(ctypes.c_double)]),
     "mlp_create": (ctypes.c_int, [_vp, _i32, _i32, _i64, _P(_vp), _P(_i64)]),

@@ -244,6 +244,23 @@ class Context:
         return (np.frombuffer(iters, dtype=np.int32).copy(), np.frombuffer(status, dtype=np.int32).copy(),
                 np.frombuffer(hist, dtype=np.float64).reshape(M, prob.max_iter).copy(), rc)
 
+    def parareal_solve_sequential(self, prob: ProblemSpec, a, U, u0=None, init: int = L.KC_INIT_ZERO, init_U=None,
+                                  gpc: Optional[Handle] = None, xi=None, mlp: Optional[Handle] = None, seed: int = 0,
+                                  allow_noconv=False):
+        """Algorithm 1 (sequential coarse grid correction); returns (iters, status, increments, rc)."""
+        M = U.shape[0]
+        iters = (ctypes.c_int32 * M)()
+        status = (ctypes.c_int32 * M)()
+        hist = (ctypes.c_double * (M * prob.max_iter))()
+        pc = prob.c()
+        rc = self.lib.parareal_solve_sequential(self.h, ctypes.byref(pc), _ptr(a), _ptr(u0), M, init, _ptr(init_U),
+                                                gpc.ptr if gpc is not None else None,
+                                                mlp.ptr if mlp is not None else None, _ptr(xi),
+                                                ctypes.c_uint64(seed), _ptr(U), iters, status, hist)
+        self._check(rc, allow=(-5,) if allow_noconv else ())
+        return (np.frombuffer(iters, dtype=np.int32).copy(), np.frombuffer(status, dtype=np.int32).copy(),
+                np.frombuffer(hist, dtype=np.float64).reshape(M, prob.max_iter).copy(), rc)
+
     def parareal_solve_batch(self, base: ProblemSpec, tasks, a, U, init: int = L.KC_INIT_ZERO, graph: bool = True,
                              allow_noconv=False, progress: bool = False):
         """tasks: sequence of (n, N, face_off, state_off); a, U: flat float64 device buffers."""

@@ -16,8 +16,6 @@ namespace kc {
 
 void field_kl_host(int dim, int n, int d, double corr_len, double sigma, std::vector<double>& lam,
                    std::vector<double>& phi);
-int propagate_impl(klecgc_ctx* ctx, const klecgc_problem& p, const FineArgs& fa, double tau, int J,
-                   int N);
 void launch_dgemm_nt(hipStream_t s, int64_t Mr, int64_t Nc, int64_t K, const double* A,
                      int64_t lda, const double* B, int64_t ldb, double* C, int64_t ldc,
                      double alpha);
@@ -621,6 +619,19 @@ int parareal_solve(klecgc_ctx* ctx, const klecgc_problem* prob, const double* a_
     GuessArgs g{init, init_dev, gpc, mlp, xi_dev, seed};
     return parareal_impl(ctx, *prob, a_dev, u0_dev, M, g, U_dev, iters_host, status_host, delta_hist_host,
                          guess_host);
+  });
+}
+
+int parareal_solve_sequential(klecgc_ctx* ctx, const klecgc_problem* prob, const double* a_dev,
+                              const double* u0_dev, int64_t M, int32_t init, const double* init_dev,
+                              const klecgc_gpc* gpc, klecgc_mlp* mlp, const double* xi_dev, uint64_t seed,
+                              double* U_dev, int32_t* iters_host, int32_t* status_host, double* delta_hist_host) {
+  return guarded(ctx, [&] {
+    KC_REQUIRE(prob && a_dev && U_dev && iters_host && status_host, KC_EINVAL, "null argument");
+    KC_REQUIRE(M >= 1, KC_EINVAL, "M must be >= 1");
+    validate_problem(*prob);
+    GuessArgs g{init, init_dev, gpc, mlp, xi_dev, seed};
+    return parareal_seq_impl(ctx, *prob, a_dev, u0_dev, M, g, U_dev, iters_host, status_host, delta_hist_host);
   });
 }
 

@@ -673,15 +673,18 @@ int mlp_coarse_grid(const klecgc_mlp* h, int N) {
 }
 }  // namespace
 
-int parareal_impl(klecgc_ctx* ctx, const klecgc_problem& p, const double* a, const double* u0, int64_t M,
-                  const GuessArgs& g, double* U, int32_t* iters, int32_t* status, double* hist, int32_t* guess) {
+// The initial guess U^0 of init mode g.init into U; `used` receives the guess each sample
+// started from.  With KC_INIT_MLP_GPC_FALLBACK the fine sweep of iteration 0 is left in the
+// WS_FINE buffer and fine_ready is set.
+static int initial_guess(klecgc_ctx* ctx, const klecgc_problem& p, const double* a, const double* u0, int64_t M,
+                         const GuessArgs& g, double* U, std::vector<int32_t>& used, bool& fine_ready) {
   hipStream_t st = ctx->stream;
   const int64_t Nx = n_unknowns(p);
   const int64_t S = (int64_t)p.N * Nx;
   const int K = p.N / 2 + 1;
   int rc = KC_OK;
-  bool fine_ready = false;
-  std::vector<int32_t> used(M, g.init);
+  fine_ready = false;
+  used.assign(M, g.init);
   auto need_gpc = [&] {
     KC_REQUIRE(g.gpc && g.xi, KC_EINVAL, "gpc handle and xi_dev required for the gPC guess");
     KC_REQUIRE(g.gpc->L == S, KC_EINVAL, "gpc surrogate state length differs from N*Nx");
@@ -762,6 +765,14 @@ int parareal_impl(klecgc_ctx* ctx, const klecgc_problem& p, const double* a, con
     default:
       throw Error{KC_EINVAL, "unknown init mode"};
   }
+  return rc;
+}
+
+int parareal_impl(klecgc_ctx* ctx, const klecgc_problem& p, const double* a, const double* u0, int64_t M,
+                  const GuessArgs& g, double* U, int32_t* iters, int32_t* status, double* hist, int32_t* guess) {
+  bool fine_ready = false;
+  std::vector<int32_t> used;
+  int rc = initial_guess(ctx, p, a, u0, M, g, U, used, fine_ready);
   ParaClass pc;
   pc.c = ctx;
   pc.p = p;
@@ -784,6 +795,120 @@ int parareal_impl(klecgc_ctx* ctx, const klecgc_problem& p, const double* a, con
   std::memcpy(status, out.status.data(), sizeof(int32_t) * M);
   if (hist) std::memcpy(hist, out.hist.data(), sizeof(double) * M * p.max_iter);
   if (guess) std::memcpy(guess, used.data(), sizeof(int32_t) * M);
+  return rc;
+}
+
+// ---------------------------------------------------------------- Algorithm 1
+namespace {
+// D = F - G of the old starts; Unew[m][0] = F[m][0] (G(u0) cancels)
+// (Gv and D may be the same buffer: each element is read before it is written)
+__global__ void seq_diff_kernel(const double* __restrict__ Fv, const double* Gv,
+                                const uint8_t* __restrict__ active, int64_t S, int64_t Nx, double* D,
+                                double* __restrict__ Unew) {
+  const int64_t m = blockIdx.y;
+  if (!active[m]) return;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < S; i += (int64_t)gridDim.x * blockDim.x) {
+    const double f = Fv[m * S + i];
+    D[m * S + i] = f - Gv[m * S + i];
+    if (i < Nx) Unew[m * S + i] = f;
+  }
+}
+
+// Unew[m][s] = G(Unew[m][s-1]) + D[m][s] with the coarse step's result g [M][Nx]
+__global__ void seq_correct_kernel(const double* __restrict__ g, const double* __restrict__ D,
+                                   const uint8_t* __restrict__ active, int64_t S, int64_t Nx, int s,
+                                   double* __restrict__ Unew) {
+  const int64_t m = blockIdx.y;
+  if (!active[m]) return;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < Nx; i += (int64_t)gridDim.x * blockDim.x)
+    Unew[m * S + (int64_t)s * Nx + i] = g[m * Nx + i] + D[m * S + (int64_t)s * Nx + i];
+}
+
+// maxima[2m] = max |Unew - U|, maxima[2m+1] = max |Unew| (ordered bit patterns); U = Unew
+__global__ __launch_bounds__(256) void seq_increment_kernel(const double* __restrict__ Unew,
+                                                            const uint8_t* __restrict__ active, int64_t S,
+                                                            double* __restrict__ U,
+                                                            unsigned long long* __restrict__ maxima) {
+  const int64_t m = blockIdx.y;
+  if (!active[m]) return;
+  double c = 0.0, u = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < S; i += (int64_t)gridDim.x * blockDim.x) {
+    const double nv = Unew[m * S + i];
+    c = nanmax(c, fabs(nv - U[m * S + i]));
+    u = nanmax(u, fabs(nv));
+    U[m * S + i] = nv;
+  }
+  c = wave_nanmax(c);
+  u = wave_nanmax(u);
+  if ((threadIdx.x & 63) == 0) {
+    atomicMax(&maxima[2 * m], (unsigned long long)__double_as_longlong(c));
+    atomicMax(&maxima[2 * m + 1], (unsigned long long)__double_as_longlong(u));
+  }
+}
+}  // namespace
+
+int parareal_seq_impl(klecgc_ctx* ctx, const klecgc_problem& p, const double* a, const double* u0, int64_t M,
+                      const GuessArgs& g, double* U, int32_t* iters, int32_t* status, double* hist) {
+  KC_REQUIRE(g.init != KC_INIT_MLP_GPC_FALLBACK, KC_EUNSUPPORTED,
+             "the sequential coarse grid correction takes a single initial guess");
+  hipStream_t st = ctx->stream;
+  const int64_t Nx = n_unknowns(p);
+  const int64_t S = (int64_t)p.N * Nx;
+  bool fine_ready = false;
+  std::vector<int32_t> used;
+  int rc = initial_guess(ctx, p, a, u0, M, g, U, used, fine_ready);
+  double* Fv = (double*)ctx->ws.get(WS_FINE, sizeof(double) * M * S);
+  double* D = (double*)ctx->ws.get(WS_DEFECT, sizeof(double) * M * S);
+  double* Un = (double*)ctx->ws.get(WS_SPEC, sizeof(double) * M * S);
+  double* stage = (double*)ctx->ws.get(WS_START, sizeof(double) * Nx * M);
+  double* gout = (double*)ctx->ws.get(WS_GEMM_A, sizeof(double) * Nx * M);
+  int* counts = (int*)ctx->ws.get(WS_SMALL, sizeof(int) * 2);
+  ClassState cs;
+  cs.alloc(M, p.max_iter, hist != nullptr);
+  class_init_kernel<<<blocks_of(M), 256, 0, st>>>(M, cs.active, cs.its, cs.status, cs.maxima);
+  KC_LAUNCH_CHECK();
+  if (cs.hist) {
+    zero_kernel<<<blocks_of(M * p.max_iter), 256, 0, st>>>(cs.hist, M * p.max_iter);
+    KC_LAUNCH_CHECK();
+  }
+  int hc[2] = {(int)M, (int)M};
+  KC_TRY_HIP(hipMemcpyAsync(counts, hc, sizeof(hc), hipMemcpyHostToDevice, st));
+  const double dT = p.T / p.N;
+  const dim3 gs(blocks_of(S, 64), (unsigned)M);
+  const dim3 gx(blocks_of(Nx, 64), (unsigned)M);
+  for (int k = 0; k < p.max_iter; ++k) {
+    // F and G of the old starts u0, U_0 .. U_{N-2}, all slices at once (F(u0) once)
+    FineArgs ff{a, U, u0, true, k > 0 ? 1 : 0, cs.active, Fv, M};
+    int r = fine_propagate_impl(ctx, p, ff);
+    if (r != KC_OK) rc = r;
+    FineArgs fg{a, U, u0, true, 0, cs.active, D, M};
+    r = propagate_impl(ctx, p, fg, dT, 1, p.N);   // G of the old starts, into D
+    if (r != KC_OK) rc = r;
+    seq_diff_kernel<<<gs, 256, 0, st>>>(Fv, D, cs.active, S, Nx, D, Un);
+    KC_LAUNCH_CHECK();
+    // the correction sweeps the slices: U^{k+1}_s = G(U^{k+1}_{s-1}) + F_s - G_s
+    for (int s = 1; s < p.N; ++s) {
+      KC_TRY_HIP(hipMemcpy2DAsync(stage, sizeof(double) * Nx, Un + (int64_t)(s - 1) * Nx, sizeof(double) * S,
+                                  sizeof(double) * Nx, M, hipMemcpyDeviceToDevice, st));
+      FineArgs fc{a, stage, nullptr, false, 0, cs.active, gout, M};
+      r = propagate_impl(ctx, p, fc, dT, 1, 1);
+      if (r != KC_OK) rc = r;
+      seq_correct_kernel<<<gx, 256, 0, st>>>(gout, D, cs.active, S, Nx, s, Un);
+      KC_LAUNCH_CHECK();
+    }
+    seq_increment_kernel<<<gs, 256, 0, st>>>(Un, cs.active, S, U, cs.maxima);
+    KC_LAUNCH_CHECK();
+    converge_kernel<<<blocks_of(M), 256, 0, st>>>(M, p.max_iter, p.tol, cs.maxima, cs.active, cs.its, cs.status,
+                                                  cs.hist, nullptr, counts, 1);
+    KC_LAUNCH_CHECK();
+    KC_TRY_HIP(hipMemcpyAsync(hc, counts, sizeof(hc), hipMemcpyDeviceToHost, st));
+    KC_TRY_HIP(hipStreamSynchronize(st));
+    if (hc[0] == 0) break;
+  }
+  KC_TRY_HIP(hipMemcpyAsync(iters, cs.its, sizeof(int32_t) * M, hipMemcpyDeviceToHost, st));
+  KC_TRY_HIP(hipMemcpyAsync(status, cs.status, sizeof(int32_t) * M, hipMemcpyDeviceToHost, st));
+  if (hist) KC_TRY_HIP(hipMemcpyAsync(hist, cs.hist, sizeof(double) * M * p.max_iter, hipMemcpyDeviceToHost, st));
+  KC_TRY_HIP(hipStreamSynchronize(st));
   return rc;
 }
 

@@ -249,6 +249,11 @@ struct GuessArgs {
 };
 int parareal_impl(klecgc_ctx* ctx, const klecgc_problem& p, const double* a, const double* u0, int64_t M,
                   const GuessArgs& g, double* U, int32_t* iters, int32_t* status, double* hist, int32_t* guess);
+int parareal_seq_impl(klecgc_ctx* ctx, const klecgc_problem& p, const double* a, const double* u0, int64_t M,
+                      const GuessArgs& g, double* U, int32_t* iters, int32_t* status, double* hist);
+// J steps of size tau over N slices per sample (fine propagation with tau = dT/J; one coarse
+// step with tau = dT, J = 1)
+int propagate_impl(klecgc_ctx* ctx, const klecgc_problem& p, const FineArgs& fa, double tau, int J, int N);
 int parareal_batch_impl(klecgc_ctx* ctx, const klecgc_problem& base, const klecgc_task* tasks, int64_t M,
                         const double* a, int32_t init, double* U, int32_t flags, int32_t* iters, int32_t* status,
                         double* latency_ms, double* total_ms);

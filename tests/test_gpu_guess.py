@@ -313,3 +313,70 @@ def test_fine_propagate_active_mask(ctx, dim, n, prec):
         P = prop.Propagators(dim, n, a[m], w.T, w.N, w.J, w.forcing)
         for s in range(w.N):
             assert rel(got[m, s], P.F(starts[m, s])) < 1e-11
+
+
+# ---------------------------------------------------------------- Algorithm 1 and the alpha sweep
+@pytest.mark.parametrize("dim,n,N,J,init", [(1, 31, 8, 8, "zero"), (1, 127, 16, 32, "random"), (2, 12, 4, 4, "zero"),
+                                            (2, 20, 8, 3, "random")])
+def test_sequential_cgc_iterates(ctx, dim, n, N, J, init):
+    """Algorithm 1 (sequential CGC) for exactly K iterations against the oracle's iterates,
+    K = 1, 2 and N; at K = N the iterate is the serial fine solution (finite termination)."""
+    import paper_2510_26180_amd as K_
+    w = (W.small_1d if dim == 1 else W.small_2d)(n=n, N=N, J=J)
+    M, seed = 2, 77
+    xi = W.draw_xi(M, w.d, 63)
+    a = oracle_faces(w, xi)
+    mode = K_.KC_INIT_ZERO if init == "zero" else K_.KC_INIT_RANDOM
+    U0 = np.zeros((M, N, w.Nx)) if init == "zero" else oguess.random_guess(seed, M, N, w.Nx)
+    ref = [opar.parareal_sequential(prop.Propagators(dim, n, a[m], w.T, N, J, w.forcing), np.zeros(w.Nx), U0[m], N)
+           for m in range(M)]
+    for Kit in (1, 2, N):
+        log(f"sequential CGC dim={dim} n={n} N={N} J={J} init={init} K={Kit}")
+        prob = spec_of(w, max_iter=Kit, tol=1e-300, inner_rtol=1e-14)
+        U = torch.empty((M, N, w.Nx), dtype=torch.float64, device="cuda")
+        iters, status, hist, _ = ctx.parareal_solve_sequential(prob, dev(a), U, init=mode, seed=seed)
+        got = host(U)
+        for m in range(M):
+            assert iters[m] == Kit
+            assert rel(got[m], ref[m][Kit]) < 1e-11
+            # both iterates agree with the oracle's to ~1e-12 relative, so their increment to ~1e-11
+            inc = opar.increment(ref[m][Kit], ref[m][Kit - 1])
+            assert abs(hist[m, Kit - 1] - inc) <= 1e-10
+        if Kit == N:
+            for m in range(M):
+                P = prop.Propagators(dim, n, a[m], w.T, N, J, w.forcing)
+                assert rel(got[m], prop.serial_fine(P, np.zeros(w.Nx), N)) < 1e-12
+
+
+def test_alpha_sweep_c1(ctx):
+    """The twist parameter at the 1D configuration: for alpha = 1e-1, 1e-2, 1e-4 the
+    diagonalised CGC (Algorithm 2) stops after the oracle's iteration count; Algorithm 1
+    (alpha = 0, sequential CGC) likewise.  Smaller alpha moves Algorithm 2 towards
+    Algorithm 1's convergence."""
+    import paper_2510_26180_amd as K_
+    w = W.get("c1_1d_n127")
+    M = 4
+    xi = W.draw_xi(M, w.d, w.seed_eval)
+    a = oracle_faces(w, xi)
+    counts = {}
+    for alpha in (1e-1, 1e-2, 1e-4):
+        log(f"alpha sweep c1: alpha={alpha}")
+        U = torch.empty((M, w.N, w.Nx), dtype=torch.float64, device="cuda")
+        its, st, _, _ = ctx.parareal_solve(spec_of(w, alpha=alpha), dev(a), U, init=K_.KC_INIT_ZERO)
+        want = []
+        for m in range(M):
+            P = prop.Propagators(1, w.n, a[m], w.T, w.N, w.J, w.forcing)
+            h = opar.parareal_diag(P, alpha, np.zeros(w.Nx), np.zeros((w.N, w.Nx)), w.tol, w.max_iter)
+            want.append(h.iters)
+            assert iterations_agree(int(its[m]), h.iters, h.deltas, w.tol)
+        counts[alpha] = (its.tolist(), want)
+    U = torch.empty((M, w.N, w.Nx), dtype=torch.float64, device="cuda")
+    its, st, hist, _ = ctx.parareal_solve_sequential(spec_of(w), dev(a), U, init=K_.KC_INIT_ZERO)
+    for m in range(M):
+        P = prop.Propagators(1, w.n, a[m], w.T, w.N, w.J, w.forcing)
+        seq = opar.parareal_sequential(P, np.zeros(w.Nx), np.zeros((w.N, w.Nx)), w.N)
+        deltas = [opar.increment(seq[k], seq[k - 1]) for k in range(1, w.N + 1)]
+        k_or = next(k for k, d in enumerate(deltas, 1) if d <= w.tol)
+        assert iterations_agree(int(its[m]), k_or, deltas, w.tol)
+    counts[0.0] = its.tolist()
+    log(f"  iterations by alpha (gpu, oracle): {counts}")
