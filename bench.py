@@ -345,6 +345,7 @@ def main():
     ap.add_argument("--init", choices=["gpc", "mlp", "both"], default=None,
                     help="initial guess (default: gpc; both for the MLP workload)")
     ap.add_argument("--epochs", type=int, default=0, help="override the MLP epochs (0 = spec)")
+    ap.add_argument("--batch", type=int, default=0, help="override the MLP mini-batch (0 = spec)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the built-in kernel choices")
     ap.add_argument("--grids", default="", help="ragged batch: comma-separated grid sizes (default 64,128,256)")
     ap.add_argument("--compare-eager", action="store_true", help="ragged batch: also run without the HIP graph")
@@ -407,6 +408,8 @@ def main():
     spec = W.MLP_C4
     if args.epochs:
         spec = W.MlpSpec(**{**spec.__dict__, "epochs": args.epochs})
+    if args.batch:
+        spec = W.MlpSpec(**{**spec.__dict__, "batch": args.batch})
 
     # ---- offline stage (untimed): autotuning, training solutions, snapshot KL + gPC fit, MLP training
     torch.cuda.synchronize()

@@ -158,7 +158,8 @@ typedef struct {
  * the defaults (-1, 1e-6, -1, 1e-5, 0, 0) for an n never tuned. */
 int klecgc_set_tuning(klecgc_ctx* ctx, int32_t n, const klecgc_tuning* t);
 int klecgc_get_tuning(const klecgc_ctx* ctx, int32_t n, klecgc_tuning* t);
-/* Autotuner: times every fitting fine variant x per-pass reduction {1e-5, 3e-6, 1e-6,
+/* Autotuner: times every fitting fine variant (KC_FINE_MG only above n = 128, where no
+ * resident variant fits) x per-pass reduction {1e-5, 3e-6, 1e-6,
  * 3e-7} (the faster of two timings each) on the first min(M, 16) samples of a_dev (fine
  * sweep over all N slices from the
  * coarse-propagator states), then every fitting shifted-solve variant x {1e-4, 3e-5,

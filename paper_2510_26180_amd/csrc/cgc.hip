@@ -942,9 +942,10 @@ __global__ __launch_bounds__(64 * NW, WPE) void cocg_mg_kernel(
   const MgLv<float2> v0 = mg_lv<float2>(base, h, 0);
   double bn[2] = {0.0, 0.0};
   const bool sm[2] = {false, true};
-  for_nodes(n, [&](int p, int i, int j) {
-    v0.cw[p] = i >= 1 ? (float)(cT * af[j * (n + 1) + i] * dr[p - 1] * dr[p]) : 0.f;
-    v0.cs[p] = j >= 1 ? (float)(cT * af[nx + j * n + i] * dr[p - n] * dr[p]) : 0.f;
+  for (int64_t p = threadIdx.x; p < Nx; p += blockDim.x) {
+    const int i = (int)(p % n), j = (int)(p / n);
+    v0.cw[p] = i >= 1 ? (float)(cT * af[(int64_t)j * (n + 1) + i] * dr[p - 1] * dr[p]) : 0.f;
+    v0.cs[p] = j >= 1 ? (float)(cT * af[nx + (int64_t)j * n + i] * dr[p - n] * dr[p]) : 0.f;
     const float th = (float)(lim * dr[p] * dr[p]);
     v0.dg[p] = make_float2(1.f, th);
     const float den = 1.f + th * th;
@@ -954,7 +955,7 @@ __global__ __launch_bounds__(64 * NW, WPE) void cocg_mg_kernel(
     q[p] = make_double2(0.0, 0.0);
     bn[0] += vv.x * vv.x + vv.y * vv.y;
     bn[1] = nanmax(bn[1], dr[p] * fmax(fabs(vv.x), fabs(vv.y)));
-  });
+  }
   block_reduce<2>(bn, sm, dsl);   // its barriers also publish level 0
   mg_build_coarse<float2>(base, h);
   const double stop2 = rtol * rtol * bn[0];
@@ -996,13 +997,14 @@ __global__ __launch_bounds__(64 * NW, WPE) void cocg_mg_kernel(
     bool bad = false;
     while (rr > stop_in && it < cap) {
       float pq2[2] = {0.f, 0.f};
-      for_nodes(n, [&](int p, int i, int j) {
-        const float2 qv = mg_apply<float2>(v0, p, i, j, [&](int s, int, int) { return P[s]; });
+      for (int64_t p = threadIdx.x; p < Nx; p += blockDim.x) {
+        const int i = (int)(p % n), j = (int)(p / n);
+        const float2 qv = mg_apply<float2>(v0, p, i, j, [&](int64_t s, int, int) { return P[s]; });
         Q[p] = qv;
         const float2 pv = P[p];
         pq2[0] += pv.x * qv.x - pv.y * qv.y;
         pq2[1] += pv.x * qv.y + pv.y * qv.x;
-      });
+      }
       block_sum_fk<NW, 2>(pq2, fsl[0], lane, wave);
       const cf al = cf_div(rz, cf{pq2[0], pq2[1]});
       float racc[1] = {0.f};
@@ -1061,12 +1063,13 @@ __global__ __launch_bounds__(64 * NW, WPE) void cocg_mg_kernel(
     }
     __syncthreads();   // X complete before neighbours are read below
     double acc[2] = {0.0, 0.0};
-    for_nodes(n, [&](int p, int i, int j) {
+    for (int64_t p = threadIdx.x; p < Nx; p += blockDim.x) {
+      const int i = (int)(p % n), j = (int)(p / n);
       const float2 xp = X[p];
       const double ex = sig * dr[p] * xp.x, ey = sig * dr[p] * xp.y;
       double sx = 0.0, sy = 0.0;
-      const double aW = af[j * (n + 1) + i], aE = af[j * (n + 1) + i + 1];
-      const double aS = af[nx + j * n + i], aN = af[nx + (j + 1) * n + i];
+      const double aW = af[(int64_t)j * (n + 1) + i], aE = af[(int64_t)j * (n + 1) + i + 1];
+      const double aS = af[nx + (int64_t)j * n + i], aN = af[nx + (int64_t)(j + 1) * n + i];
       double nxv = 0.0, nyv = 0.0;
       if (i > 0) { const float2 t = X[p - 1]; nxv = sig * dr[p - 1] * t.x; nyv = sig * dr[p - 1] * t.y; }
       sx += aW * (ex - nxv); sy += aW * (ey - nyv);
@@ -1091,7 +1094,7 @@ __global__ __launch_bounds__(64 * NW, WPE) void cocg_mg_kernel(
       q[p] = qv;
       acc[0] += rv.x * rv.x + rv.y * rv.y;
       acc[1] = nanmax(acc[1], dr[p] * fmax(fabs(rv.x), fabs(rv.y)));
-    });
+    }
     block_reduce<2>(acc, sm, dsl);
     rn2 = acc[0];
     sig = acc[1];

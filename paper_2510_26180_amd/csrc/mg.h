@@ -31,29 +31,14 @@ constexpr float kMgScale = 1.8f;
 constexpr int kMgSweeps = 2;   // default smoothing sweeps per level and direction
 constexpr int kMgGaussSeidel = 0, kMgJacobi = 1;
 
-// The level table is a handful of scalars (a kernel argument held in scalar registers):
-// level l's grid size and the float offset of its block are recomputed from them where
-// needed (a few scalar operations per level), rather than kept as per-level arrays.
 struct MgLevels {
-  int L;                       // levels (level 0 = the n x n grid)
+  int L;
   int sweeps;                  // smoothing sweeps per level and direction (>= 1)
   int smoother;                // kMgGaussSeidel or kMgJacobi
-  int n;                       // level-0 grid size
-  int words;                   // floats per value of type T (1 real, 2 complex)
-  int64_t head;                // floats of Krylov vectors before level 0 in a system's scratch
+  int m[kMgMaxLevels];
+  int64_t off[kMgMaxLevels];   // float offset of each level's block in a system's scratch
   int64_t per_sys;             // floats of scratch per system
 };
-
-// grid size and block offset (floats from the start of a system's scratch) of level l
-__host__ __device__ __forceinline__ void mg_level_at(const MgLevels& h, int l, int& m, int64_t& off) {
-  m = h.n;
-  off = h.head;
-  for (int k = 0; k < l; ++k) {
-    off += (2 + 5 * (int64_t)h.words) * m * m;
-    off = (off + 1) / 2 * 2;   // keep float2 blocks 8-byte aligned
-    m = (m + 1) / 2;
-  }
-}
 
 template <class T>
 struct MgT;
@@ -97,17 +82,19 @@ inline MgLevels mg_levels(int n, int words, int64_t head, int sweeps, int smooth
   MgLevels h{};
   h.sweeps = sweeps >= 1 ? sweeps : kMgSweeps;
   h.smoother = smoother == kMgJacobi ? kMgJacobi : kMgGaussSeidel;
-  h.n = n;
-  h.words = words;
-  h.head = head;
-  int m = n, L = 1;
-  while (m > 2 && L < kMgMaxLevels) {
-    m = (m + 1) / 2;
+  int m = n, L = 0;
+  int64_t off = head;
+  while (true) {
+    h.m[L] = m;
+    h.off[L] = off;
+    off += (2 + 5 * (int64_t)words) * m * m;
+    off = (off + 1) / 2 * 2;   // keep float2 blocks 8-byte aligned
     ++L;
+    if (m <= 2 || L == kMgMaxLevels) break;
+    m = (m + 1) / 2;
   }
   h.L = L;
-  int mL;
-  mg_level_at(h, L, mL, h.per_sys);   // the end of the last level's block
+  h.per_sys = off;
   return h;
 }
 
@@ -121,10 +108,9 @@ struct MgLv {
 template <class T>
 __device__ __forceinline__ MgLv<T> mg_lv(float* base, const MgLevels& h, int l) {
   MgLv<T> v;
-  int64_t off;
-  mg_level_at(h, l, v.m, off);
+  v.m = h.m[l];
   const int64_t mm = (int64_t)v.m * v.m;
-  float* p = base + off;
+  float* p = base + h.off[l];
   v.cw = p;
   v.cs = p + mm;
   v.dg = (T*)(p + 2 * mm);
@@ -135,32 +121,9 @@ __device__ __forceinline__ MgLv<T> mg_lv(float* base, const MgLevels& h, int l) 
   return v;
 }
 
-// Node loops without integer division: wave w of the work-group takes rows w, w + nw, ...
-// and its lanes the columns of a row in steps of 64 (coalesced), so a node's (i, j) and
-// index come from additions only.  f(p, i, j) with p = j m + i.
-template <class F>
-__device__ __forceinline__ void for_nodes(int m, F&& f) {
-  const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
-  for (int j = threadIdx.x >> 6; j < m; j += nw) {
-    const int row = j * m;
-    for (int i = lane; i < m; i += 64) f(row + i, i, j);
-  }
-}
-
-// The nodes of colour col ((i + j) mod 2 == col) of an m x m grid: row j holds them at
-// i = 2k + ((col + j) & 1).
-template <class F>
-__device__ __forceinline__ void for_colour(int m, int col, F&& f) {
-  const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
-  for (int j = threadIdx.x >> 6; j < m; j += nw) {
-    const int row = j * m;
-    for (int i = 2 * lane + ((col + j) & 1); i < m; i += 128) f(row + i, i, j);
-  }
-}
-
 // (L x)_p on a level; X(q, i, j) yields x at node q = j m + i
 template <class T, class XF>
-__device__ __forceinline__ T mg_apply(const MgLv<T>& v, int p, int i, int j, XF X) {
+__device__ __forceinline__ T mg_apply(const MgLv<T>& v, int64_t p, int i, int j, XF X) {
   using O = MgT<T>;
   const int m = v.m;
   T acc = O::mul(v.dg[p], X(p, i, j));
@@ -179,14 +142,15 @@ __device__ void mg_build_coarse(float* base, const MgLevels& h) {
     const MgLv<T> f = mg_lv<T>(base, h, l - 1);
     const MgLv<T> c = mg_lv<T>(base, h, l);
     const int mf = f.m, mc = c.m;
-    for_nodes(mc, [&](int Pn, int I, int J) {
+    for (int64_t Pn = threadIdx.x; Pn < (int64_t)mc * mc; Pn += blockDim.x) {
+      const int I = (int)(Pn % mc), J = (int)(Pn / mc);
       const int i0 = 2 * I, j0 = 2 * J;
       const bool two_i = i0 + 1 < mf, two_j = j0 + 1 < mf;
       T dg = O::zero();
       float cwc = 0.f, csc = 0.f, inner = 0.f;
       for (int dj = 0; dj < (two_j ? 2 : 1); ++dj)
         for (int di = 0; di < (two_i ? 2 : 1); ++di) {
-          const int p = (j0 + dj) * mf + (i0 + di);
+          const int64_t p = (int64_t)(j0 + dj) * mf + (i0 + di);
           dg = O::add(dg, f.dg[p]);
           if (di == 1) inner += f.cw[p];            // coupling inside the block (x)
           if (dj == 1) inner += f.cs[p];            // coupling inside the block (y)
@@ -198,7 +162,7 @@ __device__ void mg_build_coarse(float* base, const MgLevels& h) {
       c.di[Pn] = O::recip(dg);
       c.cw[Pn] = cwc;
       c.cs[Pn] = csc;
-    });
+    }
     __syncthreads();
   }
 }
@@ -211,8 +175,12 @@ __device__ void mg_build_coarse(float* base, const MgLevels& h) {
 template <class T, bool DOT = false>
 __device__ __forceinline__ void mg_gs_half(const MgLv<T>& v, const T* b, T* x, int col, T* dot = nullptr) {
   using O = MgT<T>;
-  const int m = v.m;
-  for_colour(m, col, [&](int p, int i, int j) {
+  const int m = v.m, hw = (m + 1) / 2;
+  for (int64_t q = threadIdx.x; q < (int64_t)m * hw; q += blockDim.x) {
+    const int j = (int)(q / hw);
+    const int i = 2 * (int)(q % hw) + ((col + j) & 1);
+    if (i < m) {
+      const int64_t p = (int64_t)j * m + i;
       // the diagonal's reciprocal from the diagonal mg_apply reads anyway (the kernel is
       // bound by memory traffic, not by the few extra operations)
       const T dgp = v.dg[p];
@@ -226,7 +194,8 @@ __device__ __forceinline__ void mg_gs_half(const MgLv<T>& v, const T* b, T* x, i
       const T xn = O::add(xp, O::mul(O::recip(dgp), O::sub(bp, acc)));
       x[p] = xn;
       if constexpr (DOT) *dot = O::add(*dot, O::mul(bp, xn));
-  });
+    }
+  }
   __syncthreads();
 }
 
@@ -236,14 +205,17 @@ __device__ __forceinline__ void mg_gs_half(const MgLv<T>& v, const T* b, T* x, i
 template <class T>
 __device__ T* mg_vcycle_gs(float* base, const MgLevels& h, const T* rhs0, T* dot = nullptr) {
   using O = MgT<T>;
+  const int tid = threadIdx.x, nt = blockDim.x;
   for (int l = 0; l < h.L; ++l) {
     const MgLv<T> v = mg_lv<T>(base, h, l);
     const T* b = l == 0 ? rhs0 : v.b;
     const int m = v.m;
+    const int64_t mm = (int64_t)m * m;
     // first sweep from x = 0: the red half is x_r = di_r b_r, the black nodes start at 0
-    for_nodes(m, [&](int p, int i, int j) {
+    for (int64_t p = tid; p < mm; p += nt) {
+      const int i = (int)(p % m), j = (int)(p / m);
       v.xa[p] = ((i + j) & 1) == 0 ? O::mul(O::recip(v.dg[p]), b[p]) : O::zero();
-    });
+    }
     __syncthreads();
     mg_gs_half<T>(v, b, v.xa, 1);
     for (int s = 1; s < h.sweeps; ++s) {
@@ -254,19 +226,20 @@ __device__ T* mg_vcycle_gs(float* base, const MgLevels& h, const T* rhs0, T* dot
       const MgLv<T> c = mg_lv<T>(base, h, l + 1);
       const int mc = c.m;
       const T* xc = v.xa;
-      for_nodes(mc, [&](int P, int I, int J) {
+      for (int64_t P = tid; P < (int64_t)mc * mc; P += nt) {
+        const int I = (int)(P % mc), J = (int)(P / mc);
         T sum = O::zero();
         for (int dj = 0; dj < 2; ++dj)
           for (int di = 0; di < 2; ++di) {
             const int i = 2 * I + di, j = 2 * J + dj;
             if (i < m && j < m) {
-              const int p = j * m + i;
-              const T lx = mg_apply<T>(v, p, i, j, [&](int q, int, int) { return xc[q]; });
+              const int64_t p = (int64_t)j * m + i;
+              const T lx = mg_apply<T>(v, p, i, j, [&](int64_t q, int, int) { return xc[q]; });
               sum = O::add(sum, O::sub(b[p], lx));
             }
           }
         c.b[P] = sum;
-      });
+      }
       __syncthreads();
     } else {             // coarsest level: the transposed sweeps complete its smoothing
       for (int s = 0; s < h.sweeps; ++s) {
@@ -285,9 +258,11 @@ __device__ T* mg_vcycle_gs(float* base, const MgLevels& h, const T* rhs0, T* dot
     const MgLv<T> c = mg_lv<T>(base, h, l + 1);
     const T* b = l == 0 ? rhs0 : v.b;
     const int m = v.m, mc = c.m;
-    for_nodes(m, [&](int p, int i, int j) {   // x += s P e
-      v.xa[p] = O::axpy(kMgScale, c.xa[(j >> 1) * mc + (i >> 1)], v.xa[p]);
-    });
+    const int64_t mm = (int64_t)m * m;
+    for (int64_t p = tid; p < mm; p += nt) {   // x += s P e
+      const int i = (int)(p % m), j = (int)(p / m);
+      v.xa[p] = O::axpy(kMgScale, c.xa[(int64_t)(j >> 1) * mc + (i >> 1)], v.xa[p]);
+    }
     __syncthreads();
     for (int s = 0; s < h.sweeps; ++s) {
       if (l == 0 && dot && s == h.sweeps - 1) {
@@ -309,19 +284,22 @@ __device__ T* mg_vcycle(float* base, const MgLevels& h, const T* rhs0) {
   if (h.smoother == kMgGaussSeidel) return mg_vcycle_gs<T>(base, h, rhs0);
   using O = MgT<T>;
   int cur[kMgMaxLevels];
+  const int tid = threadIdx.x, nt = blockDim.x;
   for (int l = 0; l < h.L; ++l) {
     const MgLv<T> v = mg_lv<T>(base, h, l);
     const T* b = l == 0 ? rhs0 : v.b;
     const int m = v.m;
-    for_nodes(m, [&](int p, int, int) { v.xa[p] = O::scale(kMgOmega, O::mul(v.di[p], b[p])); });
+    const int64_t mm = (int64_t)m * m;
+    for (int64_t p = tid; p < mm; p += nt) v.xa[p] = O::scale(kMgOmega, O::mul(v.di[p], b[p]));
     __syncthreads();
     T* xc = v.xa;
     T* xn = v.xb;
     for (int s = 1; s < h.sweeps; ++s) {
-      for_nodes(m, [&](int p, int i, int j) {
-        const T lx = mg_apply<T>(v, p, i, j, [&](int q, int, int) { return xc[q]; });
+      for (int64_t p = tid; p < mm; p += nt) {
+        const int i = (int)(p % m), j = (int)(p / m);
+        const T lx = mg_apply<T>(v, p, i, j, [&](int64_t q, int, int) { return xc[q]; });
         xn[p] = O::add(xc[p], O::scale(kMgOmega, O::mul(v.di[p], O::sub(b[p], lx))));
-      });
+      }
       __syncthreads();
       T* tmp = xc;
       xc = xn;
@@ -331,19 +309,20 @@ __device__ T* mg_vcycle(float* base, const MgLevels& h, const T* rhs0) {
     if (l + 1 < h.L) {   // restrict the residual: b_{l+1}[I,J] = sum over the block of (b - L x)
       const MgLv<T> c = mg_lv<T>(base, h, l + 1);
       const int mc = c.m;
-      for_nodes(mc, [&](int P, int I, int J) {
+      for (int64_t P = tid; P < (int64_t)mc * mc; P += nt) {
+        const int I = (int)(P % mc), J = (int)(P / mc);
         T sum = O::zero();
         for (int dj = 0; dj < 2; ++dj)
           for (int di = 0; di < 2; ++di) {
             const int i = 2 * I + di, j = 2 * J + dj;
             if (i < m && j < m) {
-              const int p = j * m + i;
-              const T lx = mg_apply<T>(v, p, i, j, [&](int q, int, int) { return xc[q]; });
+              const int64_t p = (int64_t)j * m + i;
+              const T lx = mg_apply<T>(v, p, i, j, [&](int64_t q, int, int) { return xc[q]; });
               sum = O::add(sum, O::sub(b[p], lx));
             }
           }
         c.b[P] = sum;
-      });
+      }
       __syncthreads();
     }
   }
@@ -353,25 +332,28 @@ __device__ T* mg_vcycle(float* base, const MgLevels& h, const T* rhs0) {
     const T* ec = cur[l + 1] ? c.xb : c.xa;
     const T* b = l == 0 ? rhs0 : v.b;
     const int m = v.m, mc = c.m;
+    const int64_t mm = (int64_t)m * m;
     T* xc = cur[l] ? v.xb : v.xa;
     T* xn = cur[l] ? v.xa : v.xb;
     // first post-smoothing sweep on x + s P e (the prolongated correction folded in)
-    auto xp = [&](int q, int qi, int qj) {
-      return O::axpy(kMgScale, ec[(qj >> 1) * mc + (qi >> 1)], xc[q]);
+    auto xp = [&](int64_t q, int qi, int qj) {
+      return O::axpy(kMgScale, ec[(int64_t)(qj >> 1) * mc + (qi >> 1)], xc[q]);
     };
-    for_nodes(m, [&](int p, int i, int j) {
+    for (int64_t p = tid; p < mm; p += nt) {
+      const int i = (int)(p % m), j = (int)(p / m);
       const T lx = mg_apply<T>(v, p, i, j, xp);
       xn[p] = O::add(xp(p, i, j), O::scale(kMgOmega, O::mul(v.di[p], O::sub(b[p], lx))));
-    });
+    }
     __syncthreads();
     T* tmp = xc;
     xc = xn;
     xn = tmp;
     for (int s = 1; s < h.sweeps; ++s) {
-      for_nodes(m, [&](int p, int i, int j) {
-        const T lx = mg_apply<T>(v, p, i, j, [&](int q, int, int) { return xc[q]; });
+      for (int64_t p = tid; p < mm; p += nt) {
+        const int i = (int)(p % m), j = (int)(p / m);
+        const T lx = mg_apply<T>(v, p, i, j, [&](int64_t q, int, int) { return xc[q]; });
         xn[p] = O::add(xc[p], O::scale(kMgOmega, O::mul(v.di[p], O::sub(b[p], lx))));
-      });
+      }
       __syncthreads();
       tmp = xc;
       xc = xn;

@@ -63,6 +63,9 @@ int autotune_impl(klecgc_ctx* ctx, const klecgc_problem& p, const double* a, int
     // ---- fine propagator
     for (int v : {KC_FINE_RES16, KC_FINE_RES32, KC_FINE_RES64, KC_FINE_RES128, KC_FINE_RB128, KC_FINE_MG}) {
       if (!fine_variant_fits(v, n)) continue;
+      // up to 128^2 a system fits one CU and the resident kernels beat the streamed multigrid
+      // path several times over (9x at 128^2, measured); it is timed only above
+      if (v == KC_FINE_MG && n <= 128) continue;
       bool warmed = false;
       for (float r : fine_rtols) {
         KcTuning t = saved;
