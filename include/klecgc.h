@@ -194,14 +194,19 @@ int kle_export(klecgc_ctx* ctx, const klecgc_kle* snap, double* mean_dev, double
                double* lam_dev);
 
 /* ---- gPC (Section 2.2; Algorithm 3 steps 3, 5, 6) ------------------------- */
-/* gpc_fit: orthonormal probabilists' Hermite tensor basis of total degree <= p
+/* univariate families of the Wiener-Askey table (Section 2.2): Gaussian inputs ~ N(0,1) take
+ * orthonormal probabilists' Hermite polynomials, uniform inputs on [-1, 1] orthonormal
+ * Legendre polynomials sqrt(2m+1) P_m (inputs uniform on [lo, hi] are mapped to [-1, 1] by
+ * the caller) */
+enum { KC_GPC_HERMITE = 0, KC_GPC_LEGENDRE = 1 };
+/* gpc_fit: orthonormal tensor basis of the family `basis` of total degree <= p
  * in d variables (P = C(p+d, p) terms, degree-graded lexicographic order),
  * B[j][i] = psi_i(xi_j), D = zeta(xi_j) of the training snapshots of `snap`,
  * h = argmin |B h - D|_2 by Householder QR on the host.  xi_train_dev [n_t][d]
  * float64 must be the parameters of the rows of S given to kle_build.
  * Returns KC_ERANK if n_t < P or B is rank-deficient.  *P receives P. */
 int gpc_fit(klecgc_ctx* ctx, const klecgc_kle* snap, const double* xi_train_dev, int64_t n_t,
-            int32_t d, int32_t p, klecgc_gpc** out, int32_t* P);
+            int32_t d, int32_t p, int32_t basis, klecgc_gpc** out, int32_t* P);
 /* gpc_predict: U0[m] = u_bar + sum_i sqrt(lam_i) (sum_j h_{j,i} psi_j(xi_m)) g_i
  * (Algorithm 3 step 6).  xi_dev [M][d], U0_dev [M][L] float64. */
 int gpc_predict(klecgc_ctx* ctx, const klecgc_gpc* gpc, const double* xi_dev, int64_t M,
@@ -340,6 +345,78 @@ int parareal_solve_batch(klecgc_ctx* ctx, const klecgc_problem* base, const klec
                          int64_t M, const double* a_dev, int32_t init, double* U_dev, int32_t flags,
                          int32_t* iters_host, int32_t* status_host, double* latency_ms_host,
                          double* total_ms_host);
+
+/* ---- the model problems of Section 5 ------------------------------------------------
+ * Batches of one of the paper's example problems, each sample with its own scalar parameter
+ * c_dev[m] (float64 [M]):
+ *   KC_MODEL_ADE_P1 (Section 5.1): u_t - div(a grad u) + b . grad u = f on (0,1)^2, zero
+ *     Dirichlet data, a = c[m] (the paper's 0.5 (2 + cos(pi xi)^2)), b = beta (x2, x1),
+ *     f = exp(-t) (g0 + a g1) with g1 = pi^2 sin(pi x1) sin(2 pi x2),
+ *     g0 = -sin(pi x1) sin(2 pi x2) + beta pi (x2 cos(pi x1) sin(2 pi x2) / 2 + x1 sin(pi x1)
+ *     cos(2 pi x2)), u(0) = sin(pi x1) sin(2 pi x2).  P1 elements on the uniform grid of n x n
+ *     interior nodes (h = 1/(n+1)), each cell cut by its diagonal from (x_i, y_j) to
+ *     (x_{i+1}, y_{j+1}); mass, stiffness and advection integrated exactly; load = the
+ *     consistent mass matrix times the nodal interpolant of f (boundary nodes included).
+ *     Unknown of interior node (i, j) (0-based) is j*n + i.  One backward-Euler step of size
+ *     tau ending at t: (M + tau (a K + B)) w' = M w + tau F(t).  n <= 31.
+ *   KC_MODEL_BURGERS and KC_MODEL_ALLEN_CAHN (Sections 5.2, 5.3; see model_cgc_solve).
+ * States are [M][N][Nx] float64 (Nx = n^2 for the 2D model, n in 1D).  The coarse problem
+ * of Algorithm 2 couples U_0 = alpha U_N; with the mass matrix its all-at-once system is
+ * (C_alpha (x) M + dT I (x) L) u = r (Section 3.2 with M in front of the time derivative). */
+enum { KC_MODEL_ADE_P1 = 1, KC_MODEL_BURGERS = 2, KC_MODEL_ALLEN_CAHN = 3 };
+typedef struct {
+  int32_t model;           /* KC_MODEL_* */
+  int32_t n;               /* interior nodes per dimension */
+  double  T;               /* horizon, > 0 */
+  int32_t N;               /* coarse slices, 2 <= N <= 64 (any N: the slice transforms are dense) */
+  int32_t J;               /* fine steps per slice, >= 1 */
+  double  alpha;           /* twist parameter, 0 < alpha < 1 */
+  double  tol;             /* parareal stop on the increment (as parareal_solve); 0 runs max_iter */
+  int32_t max_iter;        /* iteration cap, 1 <= max_iter <= 1000 */
+  double  beta;            /* KC_MODEL_ADE_P1: advection scale (b = beta (x2, x1)) */
+  double  newton_tol;      /* nonlinear models: Newton stop, |increment|_inf <= newton_tol |u|_inf;
+                              0 selects 1e-13 */
+  int32_t newton_max_iter; /* nonlinear models: Newton cap per solve; 0 selects 50 */
+} klecgc_model;
+/* model_fine_propagate: end[m][s] = F(start[m][s]) over slice s (J backward-Euler steps of
+ * dt = T/(N J), the time-dependent load of slice s).  start_dev, end_dev [M][N][Nx] (may
+ * not alias).  KC_ENONFINITE if a sample's step matrix has a zero or non-finite pivot. */
+int model_fine_propagate(klecgc_ctx* ctx, const klecgc_model* mp, const double* c_dev,
+                         const double* start_dev, int64_t M, double* end_dev);
+/* model_coarse_propagate / model_serial_fine: U[m][s] = G(U[m][s-1]) (one step of dT) or
+ * F(U[m][s-1]) sequentially from u0_dev [M][Nx] (NULL = the model's initial value). */
+int model_coarse_propagate(klecgc_ctx* ctx, const klecgc_model* mp, const double* c_dev,
+                           const double* u0_dev, int64_t M, double* U_dev);
+int model_serial_fine(klecgc_ctx* ctx, const klecgc_model* mp, const double* c_dev,
+                      const double* u0_dev, int64_t M, double* U_dev);
+/* model_cgc_solve (Algorithm 2 step 2, Section 3.2): from the iterate Uk_dev and the fine
+ * results F_dev (F_dev[m][0] = F(u0), F_dev[m][s] = F(Uk[m][s-1])), both [M][N][Nx], the new
+ * iterate Unew_dev [M][N][Nx] (may alias Uk_dev).  The linear model solves the all-at-once
+ * system once by the three steps of eq. three-steps (dense transforms over the N slices,
+ * banded LU of the N/2+1 shifted systems (lambda_k M + dT L)); the nonlinear models run the
+ * simplified Newton iteration of eq. Newton2 with the averaged Jacobian of eq. Jac, each
+ * Newton step by the same three steps; newton_its_host [M] (nullable) receives its counts. */
+int model_cgc_solve(klecgc_ctx* ctx, const klecgc_model* mp, const double* c_dev, const double* Uk_dev,
+                    const double* F_dev, int64_t M, double* Unew_dev, int32_t* newton_its_host);
+/* model_parareal_solve (Algorithms 2 and 3) and model_parareal_solve_sequential
+ * (Algorithm 1): arguments as parareal_solve, with
+ *   init KC_INIT_GIVEN | ZERO | COARSE | GPC | RANDOM (the gPC surrogate's L must be N Nx);
+ *   u0_dev [M][Nx] or NULL (the model's initial value);
+ *   ref_dev [M][N][Nx] (nullable): a reference solution (the serial fine solution of
+ *   Section 5) for the error history err_hist_host [M][max_iter+1][N] (nullable; needs
+ *   ref_dev): entry [m][k][s] = max_p |U^k[m][s][p] - ref[m][s][p]|, k = 0 the guess;
+ *   rows after a sample's stop repeat its last iterate's errors.
+ * With tol = 0 every sample runs exactly max_iter iterations (status KC_SAMPLE_MAXITER). */
+int model_parareal_solve(klecgc_ctx* ctx, const klecgc_model* mp, const double* c_dev,
+                         const double* u0_dev, int64_t M, int32_t init, const double* init_dev,
+                         const klecgc_gpc* gpc, const double* xi_dev, uint64_t seed,
+                         const double* ref_dev, double* U_dev, int32_t* iters_host, int32_t* status_host,
+                         double* delta_hist_host, double* err_hist_host);
+int model_parareal_solve_sequential(klecgc_ctx* ctx, const klecgc_model* mp, const double* c_dev,
+                                    const double* u0_dev, int64_t M, int32_t init, const double* init_dev,
+                                    const klecgc_gpc* gpc, const double* xi_dev, uint64_t seed,
+                                    const double* ref_dev, double* U_dev, int32_t* iters_host,
+                                    int32_t* status_host, double* delta_hist_host, double* err_hist_host);
 
 /* ---- learned initial guess (replaces the gPC map of Algorithm 3 step 6) ------
  * A multilayer perceptron maps xi [d] to the states of all N slices restricted to an

@@ -17,6 +17,8 @@ KC_KLE_FIELD_EXP, KC_KLE_SNAPSHOT = 0, 1
 KC_INIT_GIVEN, KC_INIT_ZERO, KC_INIT_COARSE, KC_INIT_GPC = 0, 1, 2, 3
 KC_INIT_RANDOM, KC_INIT_MLP, KC_INIT_MLP_GPC_FALLBACK = 4, 5, 6
 KC_SAMPLE_CONVERGED, KC_SAMPLE_MAXITER, KC_SAMPLE_NONFINITE = 0, 1, 2
+KC_GPC_HERMITE, KC_GPC_LEGENDRE = 0, 1
+KC_MODEL_ADE_P1, KC_MODEL_BURGERS, KC_MODEL_ALLEN_CAHN = 1, 2, 3
 
 
 class Problem(ctypes.Structure):
@@ -28,6 +30,15 @@ class Problem(ctypes.Structure):
         ("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
         ("inner_rtol", ctypes.c_double), ("inner_max_iter", ctypes.c_int32),
         ("cgc_rtol", ctypes.c_double), ("cgc_max_iter", ctypes.c_int32),
+    ]
+
+
+class Model(ctypes.Structure):
+    _fields_ = [
+        ("model", ctypes.c_int32), ("n", ctypes.c_int32),
+        ("T", ctypes.c_double), ("N", ctypes.c_int32), ("J", ctypes.c_int32),
+        ("alpha", ctypes.c_double), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
+        ("beta", ctypes.c_double), ("newton_tol", ctypes.c_double), ("newton_max_iter", ctypes.c_int32),
     ]
 
 
@@ -77,7 +88,7 @@ SIGNATURES = {
     "kle_build": (ctypes.c_int, [_vp, _P(KleDesc), _vp, _i64, _P(_vp), _P(_i32)]),
     "kle_synthesize": (ctypes.c_int, [_vp, _vp, _vp, _i64, _vp, _vp]),
     "kle_export": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
-    "gpc_fit": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, _i32, _P(_vp), _P(_i32)]),
+    "gpc_fit": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, _i32, _i32, _P(_vp), _P(_i32)]),
     "gpc_predict": (ctypes.c_int, [_vp, _vp, _vp, _i64, _vp]),
     "fine_propagate": (ctypes.c_int, [_vp, _P(Problem), _vp, _vp, _i64, _vp, _vp]),
     "fine_propagate_noalloc": (ctypes.c_int, [_vp, _P(Problem), _vp, _vp, _i64, _vp, _vp]),
@@ -90,6 +101,16 @@ SIGNATURES = {
                                                  ctypes.c_uint64, _vp, _P(_i32), _P(_i32), _P(ctypes.c_double)]),
     "parareal_solve_batch": (ctypes.c_int, [_vp, _P(Problem), _P(Task), _i64, _vp, _i32, _vp, _i32,
                                             _P(_i32), _P(_i32), _P(ctypes.c_double), _P(ctypes.c_double)]),
+    "model_fine_propagate": (ctypes.c_int, [_vp, _P(Model), _vp, _vp, _i64, _vp]),
+    "model_coarse_propagate": (ctypes.c_int, [_vp, _P(Model), _vp, _vp, _i64, _vp]),
+    "model_serial_fine": (ctypes.c_int, [_vp, _P(Model), _vp, _vp, _i64, _vp]),
+    "model_cgc_solve": (ctypes.c_int, [_vp, _P(Model), _vp, _vp, _vp, _i64, _vp, _P(_i32)]),
+    "model_parareal_solve": (ctypes.c_int, [_vp, _P(Model), _vp, _vp, _i64, _i32, _vp, _vp, _vp, ctypes.c_uint64,
+                                            _vp, _vp, _P(_i32), _P(_i32), _P(ctypes.c_double),
+                                            _P(ctypes.c_double)]),
+    "model_parareal_solve_sequential": (ctypes.c_int, [_vp, _P(Model), _vp, _vp, _i64, _i32, _vp, _vp, _vp,
+                                                       ctypes.c_uint64, _vp, _vp, _P(_i32), _P(_i32),
+                                                       _P(ctypes.c_double), _P(ctypes.c_double)]),
     "mlp_create": (ctypes.c_int, [_vp, _i32, _i32, _i64, _P(_vp), _P(_i64)]),
     "mlp_set_params": (ctypes.c_int, [_vp, _vp, _vp]),
     "mlp_get_params": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),

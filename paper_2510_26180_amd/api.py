@@ -78,6 +78,30 @@ class ProblemSpec:
         return ProblemSpec(**args)
 
 
+@dataclass
+class ModelSpec:
+    """One of the Section 5 model problems (klecgc_model)."""
+    model: int
+    n: int
+    T: float
+    N: int
+    J: int
+    alpha: float
+    tol: float = 0.0
+    max_iter: int = 30
+    beta: float = 0.1
+    newton_tol: float = 0.0
+    newton_max_iter: int = 0
+
+    @property
+    def Nx(self) -> int:
+        return self.n * self.n if self.model == L.KC_MODEL_ADE_P1 else self.n
+
+    def c(self) -> L.Model:
+        return L.Model(self.model, self.n, self.T, self.N, self.J, self.alpha, self.tol, self.max_iter,
+                       self.beta, self.newton_tol, self.newton_max_iter)
+
+
 class Handle:
     def __init__(self, ptr: int, free, **meta):
         self.ptr = ptr
@@ -186,11 +210,12 @@ class Context:
     def kle_export(self, snap: Handle, mean=None, W=None, lam=None):
         self._check(self.lib.kle_export(self.h, snap.ptr, _ptr(mean), _ptr(W), _ptr(lam)))
 
-    def gpc_fit(self, snap: Handle, xi_train, p: int) -> Handle:
+    def gpc_fit(self, snap: Handle, xi_train, p: int, basis: int = L.KC_GPC_HERMITE) -> Handle:
         n_t, d = xi_train.shape
         out = ctypes.c_void_p()
         P = ctypes.c_int32()
-        self._check(self.lib.gpc_fit(self.h, snap.ptr, _ptr(xi_train), n_t, d, p, ctypes.byref(out), ctypes.byref(P)))
+        self._check(self.lib.gpc_fit(self.h, snap.ptr, _ptr(xi_train), n_t, d, p, basis, ctypes.byref(out),
+                                     ctypes.byref(P)))
         return Handle(out.value, self.lib.klecgc_gpc_free, P=P.value, d=d, p=p, snap=snap)
 
     def gpc_predict(self, gpc: Handle, xi, U0):
@@ -260,6 +285,49 @@ class Context:
         self._check(rc, allow=(-5,) if allow_noconv else ())
         return (np.frombuffer(iters, dtype=np.int32).copy(), np.frombuffer(status, dtype=np.int32).copy(),
                 np.frombuffer(hist, dtype=np.float64).reshape(M, prob.max_iter).copy(), rc)
+
+    # ---- Section 5 model problems ------------------------------------------------------
+    def model_fine_propagate(self, mp: ModelSpec, c, start, end):
+        pc = mp.c()
+        return self._check(self.lib.model_fine_propagate(self.h, ctypes.byref(pc), _ptr(c), _ptr(start),
+                                                         start.shape[0], _ptr(end)))
+
+    def model_coarse_propagate(self, mp: ModelSpec, c, U, u0=None):
+        pc = mp.c()
+        return self._check(self.lib.model_coarse_propagate(self.h, ctypes.byref(pc), _ptr(c), _ptr(u0), U.shape[0],
+                                                           _ptr(U)))
+
+    def model_serial_fine(self, mp: ModelSpec, c, U, u0=None):
+        pc = mp.c()
+        return self._check(self.lib.model_serial_fine(self.h, ctypes.byref(pc), _ptr(c), _ptr(u0), U.shape[0],
+                                                      _ptr(U)))
+
+    def model_cgc_solve(self, mp: ModelSpec, c, Uk, F, Unew):
+        M = Uk.shape[0]
+        its = (ctypes.c_int32 * M)()
+        pc = mp.c()
+        self._check(self.lib.model_cgc_solve(self.h, ctypes.byref(pc), _ptr(c), _ptr(Uk), _ptr(F), M, _ptr(Unew), its))
+        return np.frombuffer(its, dtype=np.int32).copy()
+
+    def model_parareal_solve(self, mp: ModelSpec, c, U, u0=None, init: int = L.KC_INIT_ZERO, init_U=None,
+                             gpc: Optional[Handle] = None, xi=None, seed: int = 0, ref=None,
+                             sequential: bool = False):
+        """Algorithms 2/3 (or Algorithm 1 with sequential=True) for a model problem; returns
+        (iters, status, increments [M][max_iter], errors [M][max_iter+1][N] or None)."""
+        M = U.shape[0]
+        iters = (ctypes.c_int32 * M)()
+        status = (ctypes.c_int32 * M)()
+        hist = (ctypes.c_double * (M * mp.max_iter))()
+        err = (ctypes.c_double * (M * (mp.max_iter + 1) * mp.N))() if ref is not None else None
+        pc = mp.c()
+        fn = self.lib.model_parareal_solve_sequential if sequential else self.lib.model_parareal_solve
+        self._check(fn(self.h, ctypes.byref(pc), _ptr(c), _ptr(u0), M, init, _ptr(init_U),
+                       gpc.ptr if gpc is not None else None, _ptr(xi), ctypes.c_uint64(seed), _ptr(ref), _ptr(U),
+                       iters, status, hist, err))
+        errs = (np.frombuffer(err, dtype=np.float64).reshape(M, mp.max_iter + 1, mp.N).copy()
+                if err is not None else None)
+        return (np.frombuffer(iters, dtype=np.int32).copy(), np.frombuffer(status, dtype=np.int32).copy(),
+                np.frombuffer(hist, dtype=np.float64).reshape(M, mp.max_iter).copy(), errs)
 
     def parareal_solve_batch(self, base: ProblemSpec, tasks, a, U, init: int = L.KC_INIT_ZERO, graph: bool = True,
                              allow_noconv=False, progress: bool = False):

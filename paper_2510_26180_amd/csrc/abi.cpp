@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "common.h"
+#include "models.h"
 
 namespace kc {
 
@@ -175,7 +176,7 @@ int gpc_predict_impl(klecgc_ctx* ctx, const klecgc_gpc* g, const double* xi, int
   hipStream_t st = ctx->stream;
   double* Psi = (double*)ctx->ws.get(WS_GEMM_A, sizeof(double) * M * g->P);
   double* Z = (double*)ctx->ws.get(WS_GEMM_B, sizeof(double) * M * g->n_modes);
-  launch_hermite(st, xi, M, g->d, g->idx, g->P, g->p, Psi);
+  launch_gpc_basis(st, xi, M, g->d, g->idx, g->P, g->basis, Psi);
   launch_dgemm(st, M, g->n_modes, g->P, Psi, g->P, g->H, g->n_modes, Z, g->n_modes, nullptr, 1.0);
   timed(ctx, KT_GEMM, [&] { launch_dgemm(st, M, g->L, g->n_modes, Z, g->n_modes, g->W, g->L, U0, g->L, g->mean, 1.0); });
   return KC_OK;
@@ -468,12 +469,13 @@ int kle_export(klecgc_ctx* ctx, const klecgc_kle* h, double* mean_dev, double* W
 }
 
 int gpc_fit(klecgc_ctx* ctx, const klecgc_kle* snap, const double* xi_train_dev, int64_t n_t,
-            int32_t d, int32_t p, klecgc_gpc** out, int32_t* P) {
+            int32_t d, int32_t p, int32_t basis, klecgc_gpc** out, int32_t* P) {
   return guarded(ctx, [&] {
     KC_REQUIRE(snap && xi_train_dev && out, KC_EINVAL, "null argument");
     KC_REQUIRE(snap->kind == KC_KLE_SNAPSHOT, KC_EINVAL, "handle is not a SNAPSHOT KL");
     KC_REQUIRE(n_t == snap->n_t, KC_EINVAL, "n_t differs from the snapshot count");
     KC_REQUIRE(d >= 1 && p >= 0 && p <= 16, KC_EINVAL, "bad d or p");
+    KC_REQUIRE(basis == KC_GPC_HERMITE || basis == KC_GPC_LEGENDRE, KC_EINVAL, "unknown gPC basis");
     *out = nullptr;
     hipStream_t st = ctx->stream;
     auto idx = index_set(d, p);
@@ -484,6 +486,7 @@ int gpc_fit(klecgc_ctx* ctx, const klecgc_kle* snap, const double* xi_train_dev,
     try {
       g->d = d;
       g->p = p;
+      g->basis = basis;
       g->P = Pn;
       g->n_modes = snap->n_modes;
       g->L = snap->L;
@@ -496,7 +499,7 @@ int gpc_fit(klecgc_ctx* ctx, const klecgc_kle* snap, const double* xi_train_dev,
       KC_TRY_HIP(hipMalloc(&g->idx, sizeof(int32_t) * flat.size()));
       KC_TRY_HIP(hipMemcpyAsync(g->idx, flat.data(), sizeof(int32_t) * flat.size(), hipMemcpyHostToDevice, st));
       double* Bd = (double*)ctx->ws.get(WS_GEMM_A, sizeof(double) * n_t * Pn);
-      launch_hermite(st, xi_train_dev, n_t, d, g->idx, Pn, p, Bd);
+      launch_gpc_basis(st, xi_train_dev, n_t, d, g->idx, Pn, basis, Bd);
       std::vector<double> B((size_t)n_t * Pn);
       KC_TRY_HIP(hipMemcpyAsync(B.data(), Bd, sizeof(double) * B.size(), hipMemcpyDeviceToHost, st));
       KC_TRY_HIP(hipStreamSynchronize(st));
@@ -633,6 +636,82 @@ int parareal_solve_sequential(klecgc_ctx* ctx, const klecgc_problem* prob, const
     GuessArgs g{init, init_dev, gpc, mlp, xi_dev, seed};
     return parareal_seq_impl(ctx, *prob, a_dev, u0_dev, M, g, U_dev, iters_host, status_host, delta_hist_host);
   });
+}
+
+int model_fine_propagate(klecgc_ctx* ctx, const klecgc_model* mp, const double* c_dev, const double* start_dev,
+                         int64_t M, double* end_dev) {
+  return guarded(ctx, [&] {
+    KC_REQUIRE(mp && c_dev && start_dev && end_dev, KC_EINVAL, "null argument");
+    KC_REQUIRE(M >= 1, KC_EINVAL, "M must be >= 1");
+    validate_model(*mp);
+    KC_REQUIRE(start_dev != end_dev, KC_EINVAL, "start_dev and end_dev may not alias");
+    return model_fine_impl(ctx, *mp, c_dev, start_dev, M, end_dev);
+  });
+}
+
+int model_coarse_propagate(klecgc_ctx* ctx, const klecgc_model* mp, const double* c_dev, const double* u0_dev,
+                           int64_t M, double* U_dev) {
+  return guarded(ctx, [&] {
+    KC_REQUIRE(mp && c_dev && U_dev, KC_EINVAL, "null argument");
+    KC_REQUIRE(M >= 1, KC_EINVAL, "M must be >= 1");
+    validate_model(*mp);
+    return model_coarse_impl(ctx, *mp, c_dev, u0_dev, M, U_dev);
+  });
+}
+
+int model_serial_fine(klecgc_ctx* ctx, const klecgc_model* mp, const double* c_dev, const double* u0_dev, int64_t M,
+                      double* U_dev) {
+  return guarded(ctx, [&] {
+    KC_REQUIRE(mp && c_dev && U_dev, KC_EINVAL, "null argument");
+    KC_REQUIRE(M >= 1, KC_EINVAL, "M must be >= 1");
+    validate_model(*mp);
+    return model_serial_fine_impl(ctx, *mp, c_dev, u0_dev, M, U_dev);
+  });
+}
+
+int model_cgc_solve(klecgc_ctx* ctx, const klecgc_model* mp, const double* c_dev, const double* Uk_dev,
+                    const double* F_dev, int64_t M, double* Unew_dev, int32_t* newton_its_host) {
+  return guarded(ctx, [&] {
+    KC_REQUIRE(mp && c_dev && Uk_dev && F_dev && Unew_dev, KC_EINVAL, "null argument");
+    KC_REQUIRE(M >= 1, KC_EINVAL, "M must be >= 1");
+    validate_model(*mp);
+    KC_REQUIRE(F_dev != Unew_dev, KC_EINVAL, "F_dev and Unew_dev may not alias");
+    return model_cgc_impl(ctx, *mp, c_dev, Uk_dev, F_dev, M, Unew_dev, newton_its_host);
+  });
+}
+
+static int model_solve_common(klecgc_ctx* ctx, const klecgc_model* mp, const double* c_dev, const double* u0_dev,
+                              int64_t M, int32_t init, const double* init_dev, const klecgc_gpc* gpc,
+                              const double* xi_dev, uint64_t seed, const double* ref_dev, double* U_dev,
+                              int32_t* iters_host, int32_t* status_host, double* delta_hist_host,
+                              double* err_hist_host, bool sequential) {
+  return guarded(ctx, [&] {
+    KC_REQUIRE(mp && c_dev && U_dev && iters_host && status_host, KC_EINVAL, "null argument");
+    KC_REQUIRE(M >= 1, KC_EINVAL, "M must be >= 1");
+    validate_model(*mp);
+    KC_REQUIRE(!err_hist_host || ref_dev, KC_EINVAL, "err_hist_host needs ref_dev");
+    KC_REQUIRE(init != KC_INIT_GIVEN || init_dev, KC_EINVAL, "KC_INIT_GIVEN needs init_dev");
+    ModelSolveArgs a{c_dev, u0_dev, M, GuessArgs{init, init_dev, gpc, nullptr, xi_dev, seed}, ref_dev, U_dev,
+                     iters_host, status_host, delta_hist_host, err_hist_host, sequential};
+    return model_parareal_impl(ctx, *mp, a);
+  });
+}
+
+int model_parareal_solve(klecgc_ctx* ctx, const klecgc_model* mp, const double* c_dev, const double* u0_dev,
+                         int64_t M, int32_t init, const double* init_dev, const klecgc_gpc* gpc, const double* xi_dev,
+                         uint64_t seed, const double* ref_dev, double* U_dev, int32_t* iters_host,
+                         int32_t* status_host, double* delta_hist_host, double* err_hist_host) {
+  return model_solve_common(ctx, mp, c_dev, u0_dev, M, init, init_dev, gpc, xi_dev, seed, ref_dev, U_dev, iters_host,
+                            status_host, delta_hist_host, err_hist_host, false);
+}
+
+int model_parareal_solve_sequential(klecgc_ctx* ctx, const klecgc_model* mp, const double* c_dev,
+                                    const double* u0_dev, int64_t M, int32_t init, const double* init_dev,
+                                    const klecgc_gpc* gpc, const double* xi_dev, uint64_t seed,
+                                    const double* ref_dev, double* U_dev, int32_t* iters_host,
+                                    int32_t* status_host, double* delta_hist_host, double* err_hist_host) {
+  return model_solve_common(ctx, mp, c_dev, u0_dev, M, init, init_dev, gpc, xi_dev, seed, ref_dev, U_dev, iters_host,
+                            status_host, delta_hist_host, err_hist_host, true);
 }
 
 int mlp_create(klecgc_ctx* ctx, int32_t n_in, int32_t hidden, int64_t n_out, klecgc_mlp** out, int64_t* n_params) {

@@ -28,6 +28,7 @@
 #include <vector>
 
 #include "common.h"
+#include "models.h"
 #include "reduce.h"
 
 namespace kc {
@@ -766,6 +767,11 @@ static int initial_guess(klecgc_ctx* ctx, const klecgc_problem& p, const double*
       throw Error{KC_EINVAL, "unknown init mode"};
   }
   return rc;
+}
+
+void launch_random_guess(hipStream_t st, uint64_t seed, int64_t n, double* U) {
+  random_guess_kernel<<<blocks_of(n, 16384), 256, 0, st>>>((unsigned long long)seed, n, U);
+  KC_LAUNCH_CHECK();
 }
 
 int parareal_impl(klecgc_ctx* ctx, const klecgc_problem& p, const double* a, const double* u0, int64_t M,

@@ -67,6 +67,13 @@ enum WsSlot {
   WS_GUESS,         // parareal: per-sample guess choice (flags, defect maxima)
   WS_MG_COEF,       // streamed multigrid: per-sample coarse operators
   WS_MG_SMALL,      // streamed multigrid: band partials, per-system state, counters
+  WS_MODEL_FAC,     // model problems: real step-matrix factors
+  WS_MODEL_CFAC,    // model problems: complex shifted-system factors
+  WS_MODEL_WORK,    // model problems: per-lane work vectors of the fine sweep
+  WS_MODEL_STATE,   // model problems: fine results, defects
+  WS_MODEL_SPEC,    // model problems: slice spectra
+  WS_MODEL_SMALL,   // model problems: tables, lists, maxima, initial values
+  WS_MODEL_AUX,     // model problems: second state buffer (Algorithm 1, Newton)
   WS_COUNT
 };
 
@@ -125,6 +132,7 @@ struct klecgc_kle {
 
 struct klecgc_gpc {
   int32_t d = 0, p = 0, P = 0, n_modes = 0;
+  int32_t basis = KC_GPC_HERMITE;
   int64_t L = 0;
   int32_t* idx = nullptr;     // [P][d] device multi-indices
   double* H = nullptr;        // [P][M_Q] device
@@ -230,8 +238,8 @@ void launch_dgemm(hipStream_t s, int64_t Mr, int64_t Nc, int64_t K, const double
 void launch_dgemm_tn(hipStream_t s, int64_t Mr, int64_t Nc, int64_t K, const double* A,
                      int64_t lda, const double* B, int64_t ldb, double* C, int64_t ldc,
                      double alpha);
-void launch_hermite(hipStream_t s, const double* xi, int64_t M, int d, const int32_t* idx, int P,
-                    int pmax, double* Psi);
+void launch_gpc_basis(hipStream_t s, const double* xi, int64_t M, int d, const int32_t* idx, int P,
+                      int basis, double* Psi);
 void launch_col_mean_center(hipStream_t s, const double* S, int64_t n_t, int64_t L, double* mean,
                             double* Sc);
 

@@ -1,6 +1,6 @@
 // Dense float64 GEMM on the CDNA matrix cores (v_mfma_f64_16x16x4f64), plus the small
 // kernels of the KL / gPC stages (Section 2.1, Section 2.2, Algorithm 3):
-//   * Hermite tensor basis Psi[m][i] = prod_l psi_{k_il}(xi_ml)
+//   * gPC tensor basis (Hermite or Legendre) Psi[m][i] = prod_l psi_{k_il}(xi_ml)
 //   * column mean of the snapshot matrix and its centred copy
 //   * C = bias + alpha * op(A) op(B) used for the Gram matrix S~ S~^T, the basis
 //     E^T S~ and the prediction Psi H W.
@@ -104,9 +104,9 @@ __global__ __launch_bounds__(256) void dgemm_kernel(int64_t Mr, int64_t Nc, int6
       }
 }
 
-__global__ void hermite_kernel(const double* __restrict__ xi, int64_t M, int d,
-                               const int32_t* __restrict__ idx, int P, int pmax,
-                               double* __restrict__ Psi) {
+__global__ void gpc_basis_kernel(const double* __restrict__ xi, int64_t M, int d,
+                                 const int32_t* __restrict__ idx, int P, int basis,
+                                 double* __restrict__ Psi) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= M * P) return;
   int64_t m = t / P;
@@ -116,16 +116,25 @@ __global__ void hermite_kernel(const double* __restrict__ xi, int64_t M, int d,
     int k = idx[i * d + l];
     if (k == 0) continue;
     double x = xi[m * d + l];
-    // orthonormal probabilists' Hermite: psi_{j+1} = (x psi_j - sqrt(j) psi_{j-1}) / sqrt(j+1)
     double pm1 = 1.0, pj = x;
-    for (int j = 1; j < k; ++j) {
-      double nx = (x * pj - sqrt((double)j) * pm1) / sqrt((double)(j + 1));
-      pm1 = pj;
-      pj = nx;
+    if (basis == KC_GPC_LEGENDRE) {
+      // Bonnet: (j+1) P_{j+1} = (2j+1) x P_j - j P_{j-1}; orthonormal under U(-1,1): sqrt(2k+1) P_k
+      for (int j = 1; j < k; ++j) {
+        double nx = ((2.0 * j + 1.0) * x * pj - (double)j * pm1) / (double)(j + 1);
+        pm1 = pj;
+        pj = nx;
+      }
+      pj *= sqrt(2.0 * k + 1.0);
+    } else {
+      // orthonormal probabilists' Hermite: psi_{j+1} = (x psi_j - sqrt(j) psi_{j-1}) / sqrt(j+1)
+      for (int j = 1; j < k; ++j) {
+        double nx = (x * pj - sqrt((double)j) * pm1) / sqrt((double)(j + 1));
+        pm1 = pj;
+        pj = nx;
+      }
     }
     prod *= pj;
   }
-  (void)pmax;
   Psi[m * P + i] = prod;
 }
 
@@ -170,10 +179,10 @@ void launch_dgemm_tn(hipStream_t s, int64_t Mr, int64_t Nc, int64_t K, const dou
   KC_LAUNCH_CHECK();
 }
 
-void launch_hermite(hipStream_t s, const double* xi, int64_t M, int d, const int32_t* idx, int P,
-                    int pmax, double* Psi) {
+void launch_gpc_basis(hipStream_t s, const double* xi, int64_t M, int d, const int32_t* idx, int P,
+                      int basis, double* Psi) {
   int64_t tot = M * P;
-  hermite_kernel<<<dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s>>>(xi, M, d, idx, P, pmax, Psi);
+  gpc_basis_kernel<<<dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s>>>(xi, M, d, idx, P, basis, Psi);
   KC_LAUNCH_CHECK();
 }
 

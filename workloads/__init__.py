@@ -20,7 +20,7 @@ from typing import Optional
 
 import numpy as np
 
-__all__ = ["Workload", "CONFIGS", "MlpSpec", "MLP_C4", "RaggedSpec", "C3_RAGGED", "draw_xi", "draw_mlp_init", "draw_perms", "get",
+__all__ = ["Workload", "CONFIGS", "ModelWorkload", "MODELS", "draw_model_params", "MlpSpec", "MLP_C4", "RaggedSpec", "C3_RAGGED", "draw_xi", "draw_mlp_init", "draw_perms", "get",
            "small_1d", "small_2d"]
 
 
@@ -107,6 +107,67 @@ C3_RAGGED = RaggedSpec(Workload("c3_ragged", 2, 0, 1.0, 0, 32, 1e-4, 1.0, 10, 0.
 
 
 MLP_C4 = MlpSpec(hidden=256, nc=32, epochs=1000, batch=64, lr=1e-3, lr_final=1e-5, seed_init=3004, seed_perm=4004)
+
+
+@dataclasses.dataclass(frozen=True)
+class ModelWorkload:
+    """One of the Section 5 examples: a scalar random parameter per sample.
+
+    The parameter xi is drawn from `dist` and handed to the solver as the coefficient
+    c = coef(xi) (the problem's own parameterisation, part of the input recipe):
+      model 1 (advection-diffusion, Section 5.1): xi ~ U[2, 6], c = a = 0.5 (2 + cos(pi xi)^2);
+      model 2 (Burgers, Section 5.2): eps ~ U[1, 3], c = eps (viscosity eps / 50);
+      model 3 (Allen-Cahn, Section 5.3): eps ~ N(0.53, 0.15^2) truncated to [0.06, 1], c = eps.
+    The gPC variable z is xi mapped to [-1, 1] for the uniform laws (Legendre basis) and
+    standardised, (eps - 0.53) / 0.15, for the truncated normal (Hermite basis)."""
+    name: str
+    model: int               # klecgc_model code: 1 ADE_P1, 2 BURGERS, 3 ALLEN_CAHN
+    n: int
+    T: float
+    N: int
+    J: int
+    alpha: float
+    beta: float              # advection scale (model 1)
+    M: int                   # evaluation samples
+    n_train: int             # training-set size of the snapshot KL (Section 5)
+    gpc_degree: int
+    eps_kl: float
+    err_tol: float           # the error threshold of Section 5 (mean error vs the serial fine solution)
+    max_iter: int
+    seed_train: int
+    seed_eval: int
+
+    @property
+    def Nx(self) -> int:
+        return self.n * self.n if self.model == 1 else self.n
+
+    def replace(self, **kw) -> "ModelWorkload":
+        return dataclasses.replace(self, **kw)
+
+
+MODELS = {
+    # Section 5.1: P1 FEM h = 1/20 (19^2 unknowns), T = 1, dT = 1/24, dt = dT/50, alpha = 0.1,
+    # n_t = 10, eps_KL = 1e-10, 1000 samples, beta = 0.1 sin(pi/2).
+    "f3_ade_s51": ModelWorkload("f3_ade_s51", 1, 19, 1.0, 24, 50, 0.1, 0.1, 1000, 10, 3, 1e-10, 1e-10, 25,
+                                1051, 2051),
+}
+
+
+def draw_model_params(w: ModelWorkload, M: int, seed: int):
+    """(xi [M], coefficient c [M], gPC variable z [M, 1]) for a Section 5 example."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    if w.model == 1:
+        xi = rng.uniform(2.0, 6.0, size=M)
+        return xi, 0.5 * (2.0 + np.cos(np.pi * xi) ** 2), ((xi - 4.0) / 2.0)[:, None]
+    if w.model == 2:
+        eps = rng.uniform(1.0, 3.0, size=M)
+        return eps, eps.copy(), (eps - 2.0)[:, None]
+    out = np.empty(0)
+    while out.size < M:
+        e = 0.53 + 0.15 * rng.standard_normal(2 * M)
+        out = np.concatenate([out, e[(e >= 0.06) & (e <= 1.0)]])
+    eps = out[:M]
+    return eps, eps.copy(), ((eps - 0.53) / 0.15)[:, None]
 
 
 def get(name: str) -> Workload:
