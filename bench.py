@@ -50,6 +50,16 @@ BYTES_PER_COCG_UNKNOWN_IT = 128.0      # complex128 vectors streamed per COCG it
 #  = 147 B; each implicit step: start 48 B + float64 residual 48 B = 96 B; each float64
 #  refinement pass: float32 right-hand side 24 B + float64 update 76 B = 100 B
 MG_BYTES_PER_CG_IT, MG_BYTES_PER_STEP, MG_BYTES_PER_PASS = 147.0, 96.0, 100.0
+PEAK_FP64_TFLOPS = 78.6
+# P1 advection-diffusion fine sweep (banded LU of half-bandwidth W), per unknown and
+# backward-Euler step of one slice: mass stencil 7 FMA (14), load 3, forward substitution
+# W FMA (2W), back substitution W FMA + 1 scaling (2W + 1) -> 4W + 18 flops; the lane's
+# state is read and written once by each substitution -> 32 B
+def ade_flops_per_row(W: int) -> float:
+    return 4.0 * W + 18.0
+
+
+ADE_BYTES_PER_ROW = 32.0
 
 
 def code_sha256(path: str) -> str:
@@ -333,6 +343,162 @@ def run_iterations(args):
     ctx.close()
 
 
+def _oracle_model_run(job):
+    """The oracle on one Section 5 sample: serial fine solution and k parareal iterations
+    (Algorithm 2 from the zero guess); returns (reference, seconds of the parareal run)."""
+    w, c, k = job
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    from oracle import ade, fem
+    with threadpool_limits(1):
+        P = ade.ADEPropagators(fem.Discretisation(w.n, w.beta), c, w.T, w.N, w.J)
+        ref = ade.serial_fine(P, P.disc.u0)
+        t0 = time.perf_counter()
+        ade.parareal_diag(P, w.alpha, P.disc.u0, np.zeros((w.N, w.Nx)), 0.0, k)
+        return ref, time.perf_counter() - t0
+
+
+def iterations_to(curve, tol):
+    """First k with max over slices of the mean error <= tol (None if never)."""
+    for k, e in enumerate(curve):
+        if e <= tol:
+            return k
+    return None
+
+
+def run_model(args):
+    """A Section 5 example: the replication runs (standard parareal and diagonalised CGC from the
+    random guess, KLE-PCGC from the KL/gPC guess; mean error against the serial fine solution
+    per iteration) and the timed KLE-PCGC batch."""
+    import workloads as W
+    w = W.MODELS[args.config]
+    if args.M:
+        w = w.replace(M=args.M)
+    pool, P = None, 0
+    if not args.no_cpu_baseline:
+        import multiprocessing as mp
+        P = args.oracle_workers or oracle_workers()
+        pool = mp.get_context("fork").Pool(P, initializer=_oracle_init)   # before any GPU call
+    import numpy as np
+    import torch
+    import paper_2510_26180_amd as K
+    dev = torch.device("cuda:0")
+    ctx = K.Context(0)
+    ms = K.ModelSpec(w.model, w.n, w.T, w.N, w.J, w.alpha, tol=0.0, max_iter=w.max_iter, beta=w.beta)
+    log(f"model {w.name}: n={w.n} N={w.N} J={w.J} alpha={w.alpha} M={w.M} n_t={w.n_train}")
+    _, c_tr, z_tr = W.draw_model_params(w, w.n_train, w.seed_train)
+    _, c_ev, z_ev = W.draw_model_params(w, w.M, w.seed_eval)
+    c_tr, z_tr = torch.as_tensor(c_tr).to(dev), torch.as_tensor(z_tr).to(dev)
+    c_ev_np = c_ev
+    c_ev, z_ev = torch.as_tensor(c_ev).to(dev), torch.as_tensor(z_ev).to(dev)
+    basis = K.KC_GPC_HERMITE if w.model == K.KC_MODEL_ALLEN_CAHN else K.KC_GPC_LEGENDRE
+    # offline: training solutions, snapshot KL, gPC fit
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    S = torch.empty((w.n_train, w.N, w.Nx), dtype=torch.float64, device=dev)
+    ctx.model_serial_fine(ms, c_tr, S)
+    kl = ctx.kle_build(S.view(w.n_train, -1), w.eps_kl)
+    gpc = ctx.gpc_fit(kl, z_tr, w.gpc_degree, basis=basis)
+    torch.cuda.synchronize()
+    t_off = time.perf_counter() - t0
+    log(f"offline: {w.n_train} training solutions, KL modes {kl.n_modes}, gPC P={gpc.P}: {t_off:.2f} s")
+    # reference: the serial fine solution of every evaluation sample (also the time-serial baseline)
+    ref = torch.empty((w.M, w.N, w.Nx), dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.model_serial_fine(ms, c_ev, ref)
+    torch.cuda.synchronize()
+    t_serial = time.perf_counter() - t0
+    U = torch.empty_like(ref)
+    runs = {}
+    for name, kw in (("parareal_random", dict(init=K.KC_INIT_RANDOM, seed=w.seed_eval, sequential=True)),
+                     ("diag_cgc_random", dict(init=K.KC_INIT_RANDOM, seed=w.seed_eval)),
+                     ("kle_pcgc", dict(init=K.KC_INIT_GPC, gpc=gpc, xi=z_ev))):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        its, st, hist, errs = ctx.model_parareal_solve(ms, c_ev, U, ref=ref, **kw)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        mean_err = errs.mean(axis=0).max(axis=1)          # max over slices of the sample mean
+        k_star = iterations_to(mean_err, w.err_tol)
+        runs[name] = {"iterations_to_tol": k_star, "mean_error_by_iteration": [float(e) for e in mean_err],
+                      "seconds_for_max_iter": dt}
+        log(f"{name}: mean error below {w.err_tol:g} at k = {k_star} ({w.max_iter} iterations in {dt:.2f} s)")
+    k_kle = runs["kle_pcgc"]["iterations_to_tol"] or w.max_iter
+    # timed: KLE-PCGC, every sample k_kle iterations (the Section 5 stop: mean error <= err_tol)
+    mt = K.ModelSpec(w.model, w.n, w.T, w.N, w.J, w.alpha, tol=0.0, max_iter=k_kle, beta=w.beta)
+    for i in range(args.warmup):
+        ctx.model_parareal_solve(mt, c_ev, U, init=K.KC_INIT_GPC, gpc=gpc, xi=z_ev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        its, st, hist, _ = ctx.model_parareal_solve(mt, c_ev, U, init=K.KC_INIT_GPC, gpc=gpc, xi=z_ev)
+        log(f"step {i}: {k_kle} iterations on {w.M} samples")
+    torch.cuda.synchronize()
+    t_steps = time.perf_counter() - t0
+    ms_per_step = 1e3 * t_steps / args.steps
+    ktimes = ctx.last_times()
+    err = (U - ref).abs().amax(dim=2)                     # [M][N]
+    mean_err = float(err.mean(dim=0).max())
+    per_sample = err.amax(dim=1).cpu().numpy()
+    value = w.M / (ms_per_step / 1e3)
+    # roofline of the fine sweep (the dominant kernel)
+    Wb = ((w.n + 1) + 3) // 4 * 4
+    fine_ms, fine_n = ktimes["fine"]
+    systems = w.M * (1 + k_kle * (w.N - 1))
+    flops = systems * w.J * w.Nx * ade_flops_per_row(Wb)
+    byts = systems * w.J * w.Nx * ADE_BYTES_PER_ROW
+    secs = fine_ms / 1e3
+    roof = {"kernel": "ade_sweep_kernel", "bound": "alu", "achieved": flops / secs / 1e12,
+            "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": flops / secs / 1e12 / PEAK_FP64_TFLOPS,
+            "traffic": None, "launches": fine_n, "ms_per_launch": fine_ms / max(fine_n, 1),
+            "algorithmic_tflop_per_launch": flops / 1e12 / max(fine_n, 1),
+            "algorithmic_unit": f"(4W + 18) flops per unknown, step and slice, W = {Wb}",
+            "state_bytes": {"achieved_GB_s": byts / secs / 1e9, "unit": "32 B per unknown, step and slice"},
+            "active_lanes": f"{w.N - 1} of 64 (one wavefront per sample, lane = slice)"}
+    line = {
+        "metric": "parareal solves/s at the Section 5 error threshold vs serial fine",
+        "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{w.name}: P1-FEM advection-diffusion {w.n}x{w.n}, N={w.N}, J={w.J}, "
+                               f"alpha={w.alpha}, M={w.M}, Legendre gPC p={w.gpc_degree} (n_t={w.n_train})",
+                   "samples": w.M, "grid": w.n, "slices": w.N, "fine_steps": w.J},
+        "replication": {"criterion": f"max over slices of the mean (over samples) max-norm error <= {w.err_tol:g}",
+                        "paper": {"kle_pcgc": 10, "parareal_random": 18, "diag_cgc_random": 18}, **runs},
+        "iterations": k_kle,
+        "accuracy": {"mean_error_max_over_slices": mean_err, "max_sample_error": float(per_sample.max()),
+                     "n_samples_below_threshold": int((per_sample <= w.err_tol).sum())},
+        "serial_fine_gpu": {"solves_per_s": w.M / t_serial, "ms": 1e3 * t_serial},
+        "offline_s": t_off,
+        "kernel_ms": {k: v[0] for k, v in ktimes.items()},
+        "roofline": roof,
+    }
+    if pool is not None:
+        nsub = min(args.oracle_subset, w.M)
+        subset = W.draw_subset(w.M, nsub, w.seed_eval + 7)
+        jobs = [(w, float(c_ev_np[m]), k_kle) for m in subset]
+        t0 = time.perf_counter()
+        res = pool.map(_oracle_model_run, jobs, chunksize=1)
+        wall = time.perf_counter() - t0
+        pool.close()
+        t_solve = sum(t for _, t in res) / len(res)
+        Rg = ref[subset].cpu().numpy()
+        e_ser = [float(np.abs(Rg[j] - r).max() / np.abs(r).max()) for j, (r, _) in enumerate(res)]
+        Ug = U[subset].cpu().numpy()
+        e_par = [float(np.abs(Ug[j] - r).max()) for j, (r, _) in enumerate(res)]
+        line["cpu_baseline"] = {"value": P / t_solve, "unit": "solves/s", "cores": P, "kind": "oracle",
+                                "cpu": cpu_model(),
+                                "sample": f"{nsub} samples x {k_kle} parareal iterations (Algorithm 2), one per "
+                                          f"single-threaded worker, {t_solve:.2f} s each ({wall:.1f} s wall)"}
+        line["accuracy"]["oracle_subset"] = {"samples": [int(m) for m in subset],
+                                             "max_rel_err_gpu_serial_fine_vs_oracle": max(e_ser),
+                                             "max_abs_err_kle_pcgc_vs_oracle_serial_fine": max(e_par)}
+        log(f"oracle subset: {line['accuracy']['oracle_subset']}")
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -361,6 +527,9 @@ def main():
                                    "several GPUs is not built"}))
         sys.exit(2)
 
+    if args.config.startswith("f"):
+        run_model(args)
+        return
     if args.config in ("c3_ragged", "c5_2d_n512"):
         os.environ.setdefault("KLECGC_PROGRESS", "1")   # long calls report from inside the library
     if args.config == "c3_ragged":
