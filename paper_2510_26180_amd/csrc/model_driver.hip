@@ -63,17 +63,74 @@ double bits_to_double(unsigned long long b) {
   return d;
 }
 
-struct AdeHolder {
-  AdeState* s = nullptr;
-  ~AdeHolder() {
-    if (s) ade_release(s);
+// The operations the drivers need from a model: F or G on a range of slices, one coarse
+// grid correction of the listed samples, the model's initial value, and the samples a
+// solver flagged (unusable pivots, Newton iterations that hit their cap).
+struct Ops {
+  virtual ~Ops() = default;
+  virtual void sweep(const int32_t* list, int64_t nlist, const double* base, const double* u0, bool shift,
+                     int s_lo, int nsl, bool coarse, double* out) = 0;
+  virtual void correct(const int32_t* list, const std::vector<int32_t>& hlist, const double* Fv, double* U,
+                       unsigned long long* maxima) = 0;
+  virtual void initial_value(int64_t M, double* u0) = 0;
+  virtual int flagged(std::vector<uint8_t>& bad) = 0;
+  virtual int64_t newton_its(int64_t m) const { return 1; }
+  virtual int flagged_code() const { return KC_ENONFINITE; }
+  // counters for klecgc_last_stats: [4] Newton steps of the corrections summed over samples,
+  // [7] the most Newton steps one correction of one sample took
+  virtual void report(int64_t* stats) const {}
+};
+
+struct AdeOps : Ops {
+  klecgc_ctx* ctx;
+  klecgc_model mp;
+  AdeState* s;
+  AdeOps(klecgc_ctx* c, const klecgc_model& m, const double* coef, int64_t M, bool coarse, bool cgc)
+      : ctx(c), mp(m), s(ade_prepare(c, m, coef, M, coarse, cgc)) {}
+  ~AdeOps() override { ade_release(s); }
+  void sweep(const int32_t* list, int64_t nlist, const double* base, const double* u0, bool shift, int s_lo, int nsl,
+             bool coarse, double* out) override {
+    ade_sweep(ctx, s, list, nlist, AdeSweep{base, u0, shift, s_lo, nsl, coarse, out});
+  }
+  void correct(const int32_t* list, const std::vector<int32_t>& hlist, const double* Fv, double* U,
+               unsigned long long* maxima) override {
+    ade_correct(ctx, s, list, (int64_t)hlist.size(), Fv, U, maxima);
+  }
+  void initial_value(int64_t M, double* u0) override { ade_initial_value(ctx, mp, M, u0); }
+  int flagged(std::vector<uint8_t>& bad) override { return ade_bad_samples(ctx, s, bad); }
+};
+
+struct NLOps : Ops {
+  klecgc_ctx* ctx;
+  klecgc_model mp;
+  NLState* s;
+  int32_t* newton_list;
+  NLOps(klecgc_ctx* c, const klecgc_model& m, const double* coef, int64_t M, bool cgc, int32_t* scratch_list)
+      : ctx(c), mp(m), s(nl_prepare(c, m, coef, M, cgc)), newton_list(scratch_list) {}
+  ~NLOps() override { nl_release(s); }
+  void sweep(const int32_t* list, int64_t nlist, const double* base, const double* u0, bool shift, int s_lo, int nsl,
+             bool coarse, double* out) override {
+    nl_sweep(ctx, s, list, nlist, base, u0, shift ? 1 : 0, s_lo, nsl, coarse, out);
+  }
+  void correct(const int32_t* list, const std::vector<int32_t>& hlist, const double* Fv, double* U,
+               unsigned long long* maxima) override {
+    nl_correct(ctx, s, list, hlist, newton_list, Fv, U, maxima);
+  }
+  void initial_value(int64_t M, double* u0) override { nl_initial_value(ctx, mp, M, u0); }
+  int flagged(std::vector<uint8_t>& bad) override { return nl_failed_samples(ctx, s, bad); }
+  int64_t newton_its(int64_t m) const override { return nl_newton_counts(s)[m]; }
+  int flagged_code() const override { return KC_ENOCONV; }
+  void report(int64_t* stats) const override {
+    stats[4] = nl_newton_total(s);
+    stats[7] = nl_newton_max(s);
   }
 };
 
-// device scratch of the drivers: u0 [M][Nx], list [M], maxima [2M], err [M][N], two states
+// device scratch of the drivers: u0 [M][Nx], two lists [M], maxima [2M], err [M][N], states
 struct DriverBufs {
   double* u0 = nullptr;
   int32_t* list = nullptr;
+  int32_t* list2 = nullptr;
   unsigned long long* maxima = nullptr;
   unsigned long long* err = nullptr;
   double* A = nullptr;
@@ -87,11 +144,13 @@ DriverBufs driver_bufs(klecgc_ctx* ctx, int64_t M, int N, int64_t Nx, int n_stat
   const size_t mx_b = sizeof(unsigned long long) * 2 * (size_t)M;
   const size_t err_b = (sizeof(unsigned long long) * (size_t)M * N + 255) / 256 * 256;
   const size_t st_b = sizeof(double) * (size_t)M * N * Nx;
-  char* p = (char*)ctx->ws.get(WS_MODEL_AUX, u0_b + list_b + mx_b + err_b + st_b * n_states + 1024);
+  char* p = (char*)ctx->ws.get(WS_MODEL_AUX, u0_b + 2 * list_b + mx_b + err_b + st_b * n_states + 1024);
   DriverBufs b;
   b.u0 = (double*)p;
   p += (u0_b + 255) / 256 * 256;
   b.list = (int32_t*)p;
+  p += list_b;
+  b.list2 = (int32_t*)p;
   p += list_b;
   b.maxima = (unsigned long long*)p;
   p += (mx_b + 255) / 256 * 256;
@@ -101,6 +160,12 @@ DriverBufs driver_bufs(klecgc_ctx* ctx, int64_t M, int N, int64_t Nx, int n_stat
   if (n_states > 1) b.B = (double*)(p + st_b);
   if (n_states > 2) b.C = (double*)(p + 2 * st_b);
   return b;
+}
+
+std::unique_ptr<Ops> make_ops(klecgc_ctx* ctx, const klecgc_model& mp, const double* c, int64_t M, bool coarse,
+                              bool cgc, const DriverBufs& b) {
+  if (mp.model == KC_MODEL_ADE_P1) return std::unique_ptr<Ops>(new AdeOps(ctx, mp, c, M, coarse, cgc));
+  return std::unique_ptr<Ops>(new NLOps(ctx, mp, c, M, cgc, b.list2));
 }
 
 }  // namespace
@@ -120,32 +185,31 @@ void validate_model(const klecgc_model& mp) {
     KC_REQUIRE(mp.n <= 31, KC_EUNSUPPORTED, "the banded finite-element solver takes n <= 31");
     KC_REQUIRE(std::isfinite(mp.beta), KC_EINVAL, "beta must be finite");
   } else {
-    KC_REQUIRE(false, KC_EUNSUPPORTED, "nonlinear models are not available in this build");
+    KC_REQUIRE(mp.n >= 2, KC_EINVAL, "n must be >= 2");
+    KC_REQUIRE(mp.n <= 512, KC_EUNSUPPORTED, "the nonlinear models take n <= 512");
   }
 }
 
 int model_fine_impl(klecgc_ctx* ctx, const klecgc_model& mp, const double* c, const double* start, int64_t M,
                     double* end) {
-  AdeHolder h;
-  h.s = ade_prepare(ctx, mp, c, M, false, false);
-  ade_sweep(ctx, h.s, nullptr, M, AdeSweep{start, nullptr, false, 0, mp.N, false, end});
+  DriverBufs b = driver_bufs(ctx, M, mp.N, model_nx(mp), 0);
+  auto ops = make_ops(ctx, mp, c, M, false, false, b);
+  ops->sweep(nullptr, M, start, nullptr, false, 0, mp.N, false, end);
   std::vector<uint8_t> bad;
-  return ade_bad_samples(ctx, h.s, bad) ? KC_ENONFINITE : KC_OK;
+  return ops->flagged(bad) ? ops->flagged_code() : KC_OK;
 }
 
 static int sequential_sweep(klecgc_ctx* ctx, const klecgc_model& mp, const double* c, const double* u0, int64_t M,
                             double* U, bool coarse) {
-  const int64_t Nx = model_nx(mp);
-  AdeHolder h;
-  h.s = ade_prepare(ctx, mp, c, M, coarse, false);
-  DriverBufs b = driver_bufs(ctx, M, mp.N, Nx, 0);
+  DriverBufs b = driver_bufs(ctx, M, mp.N, model_nx(mp), 0);
+  auto ops = make_ops(ctx, mp, c, M, coarse, false, b);
   if (!u0) {
-    ade_initial_value(ctx, mp, M, b.u0);
+    ops->initial_value(M, b.u0);
     u0 = b.u0;
   }
-  for (int s = 0; s < mp.N; ++s) ade_sweep(ctx, h.s, nullptr, M, AdeSweep{U, u0, true, s, 1, coarse, U});
+  for (int s = 0; s < mp.N; ++s) ops->sweep(nullptr, M, U, u0, true, s, 1, coarse, U);
   std::vector<uint8_t> bad;
-  return ade_bad_samples(ctx, h.s, bad) ? KC_ENONFINITE : KC_OK;
+  return ops->flagged(bad) ? ops->flagged_code() : KC_OK;
 }
 
 int model_coarse_impl(klecgc_ctx* ctx, const klecgc_model& mp, const double* c, const double* u0, int64_t M,
@@ -161,16 +225,19 @@ int model_serial_fine_impl(klecgc_ctx* ctx, const klecgc_model& mp, const double
 int model_cgc_impl(klecgc_ctx* ctx, const klecgc_model& mp, const double* c, const double* Uk, const double* Fv,
                    int64_t M, double* Unew, int32_t* newton_its) {
   const int64_t Nx = model_nx(mp);
-  AdeHolder h;
-  h.s = ade_prepare(ctx, mp, c, M, false, true);
+  DriverBufs b = driver_bufs(ctx, M, mp.N, Nx, 0);
+  auto ops = make_ops(ctx, mp, c, M, false, true, b);
   if (Unew != Uk)
     KC_TRY_HIP(hipMemcpyAsync(Unew, Uk, sizeof(double) * (size_t)M * mp.N * Nx, hipMemcpyDeviceToDevice, ctx->stream));
-  ade_correct(ctx, h.s, nullptr, M, Fv, Unew, nullptr);
+  std::vector<int32_t> all((size_t)M);
+  for (int64_t m = 0; m < M; ++m) all[m] = (int32_t)m;
+  KC_TRY_HIP(hipMemcpyAsync(b.list, all.data(), sizeof(int32_t) * M, hipMemcpyHostToDevice, ctx->stream));
+  ops->correct(b.list, all, Fv, Unew, nullptr);
+  KC_TRY_HIP(hipStreamSynchronize(ctx->stream));
   if (newton_its)
-    for (int64_t m = 0; m < M; ++m) newton_its[m] = 1;
+    for (int64_t m = 0; m < M; ++m) newton_its[m] = (int32_t)ops->newton_its(m);
   std::vector<uint8_t> bad;
-  const int any = ade_bad_samples(ctx, h.s, bad);
-  return any ? KC_ENONFINITE : KC_OK;
+  return ops->flagged(bad) ? ops->flagged_code() : KC_OK;
 }
 
 int model_parareal_impl(klecgc_ctx* ctx, const klecgc_model& mp, const ModelSolveArgs& a) {
@@ -181,14 +248,13 @@ int model_parareal_impl(klecgc_ctx* ctx, const klecgc_model& mp, const ModelSolv
   const int64_t S = (int64_t)N * Nx;
   const GuessArgs& g = a.guess;
   const bool seq = a.sequential;
-  AdeHolder h;
-  h.s = ade_prepare(ctx, mp, a.c, M, seq || g.init == KC_INIT_COARSE, !seq);
   // states: Fbuf; Algorithm 1 also Gold and Unew
   DriverBufs b = driver_bufs(ctx, M, N, Nx, seq ? 3 : 1);
+  auto ops = make_ops(ctx, mp, a.c, M, seq || g.init == KC_INIT_COARSE, !seq, b);
   double* Fbuf = b.A;
   const double* u0 = a.u0;
   if (!u0) {
-    ade_initial_value(ctx, mp, M, b.u0);
+    ops->initial_value(M, b.u0);
     u0 = b.u0;
   }
   double* U = a.U;
@@ -203,7 +269,7 @@ int model_parareal_impl(klecgc_ctx* ctx, const klecgc_model& mp, const ModelSolv
       launch_random_guess(st, g.seed, M * S, U);
       break;
     case KC_INIT_COARSE:
-      for (int s = 0; s < N; ++s) ade_sweep(ctx, h.s, nullptr, M, AdeSweep{U, u0, true, s, 1, true, U});
+      for (int s = 0; s < N; ++s) ops->sweep(nullptr, M, U, u0, true, s, 1, true, U);
       break;
     case KC_INIT_GPC:
       KC_REQUIRE(g.gpc && g.xi, KC_EINVAL, "KC_INIT_GPC needs a gPC surrogate and xi");
@@ -214,7 +280,7 @@ int model_parareal_impl(klecgc_ctx* ctx, const klecgc_model& mp, const ModelSolv
       throw Error{KC_EUNSUPPORTED, "initial guess mode not available for the model problems"};
   }
   std::vector<uint8_t> bad;
-  ade_bad_samples(ctx, h.s, bad);
+  ops->flagged(bad);
   std::vector<int32_t> list;
   for (int64_t m = 0; m < M; ++m) {
     a.iters[m] = 0;
@@ -241,7 +307,7 @@ int model_parareal_impl(klecgc_ctx* ctx, const klecgc_model& mp, const ModelSolv
   if (!list.empty()) {
     KC_TRY_HIP(hipMemcpyAsync(b.list, list.data(), sizeof(int32_t) * list.size(), hipMemcpyHostToDevice, st));
     record_errors(0, b.list, (int64_t)list.size());
-    ade_sweep(ctx, h.s, b.list, (int64_t)list.size(), AdeSweep{U, u0, true, 0, 1, false, Fbuf});
+    ops->sweep(b.list, (int64_t)list.size(), U, u0, true, 0, 1, false, Fbuf);
   }
   std::vector<unsigned long long> mx;
   for (int it = 0; it < mp.max_iter && !list.empty(); ++it) {
@@ -249,17 +315,17 @@ int model_parareal_impl(klecgc_ctx* ctx, const klecgc_model& mp, const ModelSolv
     KC_TRY_HIP(hipMemcpyAsync(b.list, list.data(), sizeof(int32_t) * nl, hipMemcpyHostToDevice, st));
     KC_TRY_HIP(hipMemsetAsync(b.maxima, 0, sizeof(unsigned long long) * 2 * M, st));
     // step 1: fine propagation of slices 1..N-1 from the current iterate
-    ade_sweep(ctx, h.s, b.list, nl, AdeSweep{U, u0, true, 1, N - 1, false, Fbuf});
+    ops->sweep(b.list, nl, U, u0, true, 1, N - 1, false, Fbuf);
     if (!seq) {
-      // step 2 (Algorithms 2/3): diagonalised CGC in correction form
-      ade_correct(ctx, h.s, b.list, nl, Fbuf, U, b.maxima);
+      // step 2 (Algorithms 2/3): the diagonalised CGC (one linear solve, or the Newton iteration)
+      ops->correct(b.list, list, Fbuf, U, b.maxima);
     } else {
       // step 2 (Algorithm 1): Gold = G(U^k_{s-1}) on all slices, then the sequential sweep
       double* Gold = b.B;
       double* Unew = b.C;
-      ade_sweep(ctx, h.s, b.list, nl, AdeSweep{U, u0, true, 0, N, true, Gold});
+      ops->sweep(b.list, nl, U, u0, true, 0, N, true, Gold);
       for (int s = 0; s < N; ++s) {
-        ade_sweep(ctx, h.s, b.list, nl, AdeSweep{Unew, u0, true, s, 1, true, Unew});
+        ops->sweep(b.list, nl, Unew, u0, true, s, 1, true, Unew);
         seq_combine_kernel<<<grid1(nl * Nx), 256, 0, st>>>(b.list, nl, N, Nx, s, Unew, Fbuf, Gold, Unew);
         KC_LAUNCH_CHECK();
       }
@@ -288,6 +354,7 @@ int model_parareal_impl(klecgc_ctx* ctx, const klecgc_model& mp, const ModelSolv
     }
     list.swap(keep);
   }
+  ops->report(ctx->stats);
   // rows of the error history after a sample's stop repeat its last iterate's errors
   if (a.err_hist && a.ref)
     for (int64_t m = 0; m < M; ++m)
@@ -295,7 +362,9 @@ int model_parareal_impl(klecgc_ctx* ctx, const klecgc_model& mp, const ModelSolv
         for (int s = 0; s < N; ++s)
           a.err_hist[((size_t)m * (mp.max_iter + 1) + k) * N + s] =
               a.err_hist[((size_t)m * (mp.max_iter + 1) + a.iters[m]) * N + s];
-  return KC_OK;
+  // a Newton iteration of a backward-Euler step that hit its cap (nonlinear models)
+  std::vector<uint8_t> fl;
+  return (mp.model != KC_MODEL_ADE_P1 && ops->flagged(fl)) ? ops->flagged_code() : KC_OK;
 }
 
 }  // namespace kc

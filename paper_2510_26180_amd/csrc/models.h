@@ -91,4 +91,21 @@ void ade_correct(klecgc_ctx* ctx, AdeState* s, const int32_t* list, int64_t nlis
                  unsigned long long* maxima);
 int ade_bad_samples(klecgc_ctx* ctx, AdeState* s, std::vector<uint8_t>& bad);
 
+// ---- the nonlinear models (nonlinear.hip) -------------------------------------------------
+struct NLState;   // per-call parameters, Newton bookkeeping and the correction's buffers
+NLState* nl_prepare(klecgc_ctx* ctx, const klecgc_model& mp, const double* c, int64_t M, bool need_cgc);
+void nl_release(NLState* s);
+void nl_initial_value(klecgc_ctx* ctx, const klecgc_model& mp, int64_t M, double* u0);
+// mode 0: start base[m][s]; 1: s == 0 ? u0[m] : base[m][s-1]; 2: s == 0 ? alpha base[m][N-1] : base[m][s-1]
+void nl_sweep(klecgc_ctx* ctx, NLState* s, const int32_t* list, int64_t nlist, const double* base, const double* u0,
+              int mode, int s_lo, int nsl, bool coarse, double* out);
+// Newton coarse grid correction of the listed samples (list on the device and on the host;
+// dev_newton_list: device scratch of M int32); maxima as ade_correct
+void nl_correct(klecgc_ctx* ctx, NLState* s, const int32_t* list, const std::vector<int32_t>& hlist,
+                int32_t* dev_newton_list, const double* Fv, double* U, unsigned long long* maxima);
+int nl_failed_samples(klecgc_ctx* ctx, NLState* s, std::vector<uint8_t>& bad);
+const std::vector<int64_t>& nl_newton_counts(const NLState* s);
+int64_t nl_newton_total(const NLState* s);
+int nl_newton_max(const NLState* s);
+
 }  // namespace kc

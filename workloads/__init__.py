@@ -150,6 +150,14 @@ MODELS = {
     # n_t = 10, eps_KL = 1e-10, 1000 samples, beta = 0.1 sin(pi/2).
     "f3_ade_s51": ModelWorkload("f3_ade_s51", 1, 19, 1.0, 24, 50, 0.1, 0.1, 1000, 10, 3, 1e-10, 1e-10, 25,
                                 1051, 2051),
+    # Section 5.2: Burgers, dx = 1/100 (99 unknowns), T = 2, dT = 2/25, dt = dT/40, n_t = 36,
+    # 1000 samples; alpha is not given for the nonlinear examples (reading: 0.1 as in 5.1).
+    "f1_burgers_s52": ModelWorkload("f1_burgers_s52", 2, 99, 2.0, 25, 40, 0.1, 0.0, 1000, 36, 4, 1e-10, 1e-10,
+                                    25, 1052, 2052),
+    # Section 5.3: Allen-Cahn on (-1, 1), dx = 1/128 (255 unknowns), T = 30, dT = 1, dt = dT/48,
+    # n_t = 10, 1000 samples, alpha = 0.1 (reading).
+    "f1_allen_cahn_s53": ModelWorkload("f1_allen_cahn_s53", 3, 255, 30.0, 30, 48, 0.1, 0.0, 1000, 10, 3, 1e-10,
+                                       1e-10, 25, 1053, 2053),
 }
 
 
