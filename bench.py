@@ -62,6 +62,15 @@ def ade_flops_per_row(W: int) -> float:
 ADE_BYTES_PER_ROW = 32.0
 
 
+# nonlinear sweep (one work-group per system, parallel cyclic reduction over P = 2^q >= n rows),
+# per unknown and Newton step: f and its Jacobian row ~20, the Newton row and the update ~10,
+# each of the q reduction steps 2 divisions + 6 multiplications + 6 additions (+ the final
+# division) -> 30 + 14 q flops
+def nl_flops_per_row(n: int) -> float:
+    q = max(6, math.ceil(math.log2(n)))
+    return 30.0 + 14.0 * q
+
+
 def code_sha256(path: str) -> str:
     """sha256 of a C++ source with its // comments, trailing blanks and empty lines removed:
     it changes with the code, not with the comments (the sources hold no string literal
@@ -349,13 +358,25 @@ def _oracle_model_run(job):
     w, c, k = job
     import numpy as np
     from threadpoolctl import threadpool_limits
-    from oracle import ade, fem
+    from oracle import ade, fem, nonlinear as onl
     with threadpool_limits(1):
-        P = ade.ADEPropagators(fem.Discretisation(w.n, w.beta), c, w.T, w.N, w.J)
-        ref = ade.serial_fine(P, P.disc.u0)
-        t0 = time.perf_counter()
-        ade.parareal_diag(P, w.alpha, P.disc.u0, np.zeros((w.N, w.Nx)), 0.0, k)
+        if w.model == 1:
+            P = ade.ADEPropagators(fem.Discretisation(w.n, w.beta), c, w.T, w.N, w.J)
+            ref = ade.serial_fine(P, P.disc.u0)
+            t0 = time.perf_counter()
+            ade.parareal_diag(P, w.alpha, P.disc.u0, np.zeros((w.N, w.Nx)), 0.0, k)
+        else:
+            P = onl.NLPropagators(w.model, w.n, c, w.T, w.N, w.J)
+            u0 = P.prob.initial_value()
+            ref = onl.serial_fine(P, u0)
+            t0 = time.perf_counter()
+            onl.parareal_diag(P, w.alpha, u0, np.zeros((w.N, w.Nx)), 0.0, k)
         return ref, time.perf_counter() - t0
+
+
+MODEL_NAMES = {1: "P1-FEM advection-diffusion", 2: "Burgers (upwind)", 3: "Allen-Cahn"}
+# iteration counts Section 5 prints (Section 5.1 only; 5.2 and 5.3 show curves)
+PAPER_COUNTS = {1: {"kle_pcgc": 10, "parareal_random": 18, "diag_cgc_random": 18}}
 
 
 def iterations_to(curve, tol):
@@ -443,29 +464,46 @@ def run_model(args):
     per_sample = err.amax(dim=1).cpu().numpy()
     value = w.M / (ms_per_step / 1e3)
     # roofline of the fine sweep (the dominant kernel)
-    Wb = ((w.n + 1) + 3) // 4 * 4
+    stats = ctx.last_stats()
     fine_ms, fine_n = ktimes["fine"]
-    systems = w.M * (1 + k_kle * (w.N - 1))
-    flops = systems * w.J * w.Nx * ade_flops_per_row(Wb)
-    byts = systems * w.J * w.Nx * ADE_BYTES_PER_ROW
     secs = fine_ms / 1e3
-    roof = {"kernel": "ade_sweep_kernel", "bound": "alu", "achieved": flops / secs / 1e12,
-            "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": flops / secs / 1e12 / PEAK_FP64_TFLOPS,
-            "traffic": None, "launches": fine_n, "ms_per_launch": fine_ms / max(fine_n, 1),
-            "algorithmic_tflop_per_launch": flops / 1e12 / max(fine_n, 1),
-            "algorithmic_unit": f"(4W + 18) flops per unknown, step and slice, W = {Wb}",
-            "state_bytes": {"achieved_GB_s": byts / secs / 1e9, "unit": "32 B per unknown, step and slice"},
-            "active_lanes": f"{w.N - 1} of 64 (one wavefront per sample, lane = slice)"}
+    if w.model == 1:
+        Wb = ((w.n + 1) + 3) // 4 * 4
+        systems = w.M * (1 + k_kle * (w.N - 1))
+        flops = systems * w.J * w.Nx * ade_flops_per_row(Wb)
+        byts = systems * w.J * w.Nx * ADE_BYTES_PER_ROW
+        roof = {"kernel": "ade_sweep_kernel", "bound": "alu", "achieved": flops / secs / 1e12,
+                "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": flops / secs / 1e12 / PEAK_FP64_TFLOPS,
+                "traffic": None, "launches": fine_n, "ms_per_launch": fine_ms / max(fine_n, 1),
+                "algorithmic_tflop_per_launch": flops / 1e12 / max(fine_n, 1),
+                "algorithmic_unit": f"(4W + 18) flops per unknown, step and slice, W = {Wb}",
+                "state_bytes": {"achieved_GB_s": byts / secs / 1e9, "unit": "32 B per unknown, step and slice"},
+                "active_lanes": f"{w.N - 1} of 64 (one wavefront per sample, lane = slice)"}
+    else:
+        newton = stats["fine_krylov_its"]          # Newton steps of all backward-Euler steps
+        flops = newton * w.n * nl_flops_per_row(w.n)
+        roof = {"kernel": "nl_sweep_kernel", "bound": "alu", "achieved": flops / secs / 1e12,
+                "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": flops / secs / 1e12 / PEAK_FP64_TFLOPS,
+                "traffic": None, "launches": fine_n, "ms_per_launch": fine_ms / max(fine_n, 1),
+                "algorithmic_tflop_per_launch": flops / 1e12 / max(fine_n, 1),
+                "algorithmic_unit": f"(30 + 14 q) flops per unknown and Newton step, q = {max(6, math.ceil(math.log2(w.n)))} "
+                                    "reduction steps",
+                "newton_steps": int(newton), "backward_euler_steps": int(stats["fine_solves"]),
+                "newton_per_step": newton / max(stats["fine_solves"], 1),
+                "cgc_newton_steps_per_correction": stats["cgc_krylov_its"] / max(w.M * k_kle, 1),
+                "cgc_newton_max": int(stats["cgc_max_its"]),
+                "backward_euler_steps_at_newton_cap": int(stats["fine_missed"])}
     line = {
         "metric": "parareal solves/s at the Section 5 error threshold vs serial fine",
         "value": value, "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"{w.name}: P1-FEM advection-diffusion {w.n}x{w.n}, N={w.N}, J={w.J}, "
-                               f"alpha={w.alpha}, M={w.M}, Legendre gPC p={w.gpc_degree} (n_t={w.n_train})",
+        "config": {"workload": f"{w.name}: {MODEL_NAMES[w.model]} {w.n if w.model != 1 else f'{w.n}x{w.n}'}, "
+                               f"N={w.N}, J={w.J}, alpha={w.alpha}, M={w.M}, "
+                               f"{'Hermite' if w.model == 3 else 'Legendre'} gPC p={w.gpc_degree} (n_t={w.n_train})",
                    "samples": w.M, "grid": w.n, "slices": w.N, "fine_steps": w.J},
         "replication": {"criterion": f"max over slices of the mean (over samples) max-norm error <= {w.err_tol:g}",
-                        "paper": {"kle_pcgc": 10, "parareal_random": 18, "diag_cgc_random": 18}, **runs},
+                        "paper": PAPER_COUNTS.get(w.model), **runs},
         "iterations": k_kle,
         "accuracy": {"mean_error_max_over_slices": mean_err, "max_sample_error": float(per_sample.max()),
                      "n_samples_below_threshold": int((per_sample <= w.err_tol).sum())},

@@ -117,7 +117,11 @@ void klecgc_mlp_free(klecgc_mlp* h);
  * steps, max iterations of one solve; [4..7] the same for the shifted solves of step (b)
  * (2D only; passes unused); [8] shader-clock cycles of the 2D resident fine kernel summed
  * over work-groups, [9] of which inside its float32 Krylov loops; [10] fine implicit steps
- * and [11] shifted solves that ended above their residual target; [12..15] reserved (0). */
+ * and [11] shifted solves that ended above their residual target; [12..15] reserved (0).
+ * After a model_* call on a nonlinear model: [0] Newton steps of all backward-Euler steps
+ * (summed over systems), [2] those backward-Euler steps, [4] Newton steps of the coarse grid
+ * corrections summed over samples, [7] the most one correction of one sample took, [10] the
+ * backward-Euler steps whose Newton iteration reached newton_max_iter. */
 int klecgc_last_stats(const klecgc_ctx* ctx, int64_t* out16);
 /* Device time of the last call on ctx, measured with HIP events on the context stream
  * around each kernel launch (instrumentation): ms8[c] milliseconds and count8[c] launches
@@ -359,7 +363,16 @@ int parareal_solve_batch(klecgc_ctx* ctx, const klecgc_problem* base, const klec
  *     consistent mass matrix times the nodal interpolant of f (boundary nodes included).
  *     Unknown of interior node (i, j) (0-based) is j*n + i.  One backward-Euler step of size
  *     tau ending at t: (M + tau (a K + B)) w' = M w + tau F(t).  n <= 31.
- *   KC_MODEL_BURGERS and KC_MODEL_ALLEN_CAHN (Sections 5.2, 5.3; see model_cgc_solve).
+ *   KC_MODEL_BURGERS (Section 5.2): u_t + u u_x = (c[m]/50) u_xx on (0,1), u = 0 at both ends,
+ *     n interior nodes (h = 1/(n+1)), central second differences, first-order upwinding of
+ *     u u_x by the sign of u_i; u(0) = sin(pi x).
+ *   KC_MODEL_ALLEN_CAHN (Section 5.3): u_t - c[m] u_xx + u^3 - u = 0 on (-1,1), u(-1) = -1,
+ *     u(1) = 1, n interior nodes (h = 2/(n+1)), central differences; u(0) = 0.53 x +
+ *     0.47 sin(-1.5 pi x).  2 <= n <= 512 for both nonlinear models.
+ *   The nonlinear models take each backward-Euler step w - tau f(w) = v by Newton's method
+ *   from w = v with the exact (tridiagonal) Jacobian until the newton_tol test holds or
+ *   newton_max_iter steps have run (the last iterate is kept; klecgc_last_stats counts such
+ *   steps); the linear systems are solved by parallel cyclic reduction.
  * States are [M][N][Nx] float64 (Nx = n^2 for the 2D model, n in 1D).  The coarse problem
  * of Algorithm 2 couples U_0 = alpha U_N; with the mass matrix its all-at-once system is
  * (C_alpha (x) M + dT I (x) L) u = r (Section 3.2 with M in front of the time derivative). */
@@ -374,13 +387,15 @@ typedef struct {
   double  tol;             /* parareal stop on the increment (as parareal_solve); 0 runs max_iter */
   int32_t max_iter;        /* iteration cap, 1 <= max_iter <= 1000 */
   double  beta;            /* KC_MODEL_ADE_P1: advection scale (b = beta (x2, x1)) */
-  double  newton_tol;      /* nonlinear models: Newton stop, |increment|_inf <= newton_tol |u|_inf;
-                              0 selects 1e-13 */
+  double  newton_tol;      /* nonlinear models: Newton stop, |increment|_inf <= newton_tol
+                              max(|u|_inf, 1), for the backward-Euler steps and the coarse grid
+                              correction alike; 0 selects 1e-13 */
   int32_t newton_max_iter; /* nonlinear models: Newton cap per solve; 0 selects 50 */
 } klecgc_model;
 /* model_fine_propagate: end[m][s] = F(start[m][s]) over slice s (J backward-Euler steps of
- * dt = T/(N J), the time-dependent load of slice s).  start_dev, end_dev [M][N][Nx] (may
- * not alias).  KC_ENONFINITE if a sample's step matrix has a zero or non-finite pivot. */
+ * dt = T/(N J); for the advection-diffusion model with the time-dependent load of slice s).
+ * start_dev, end_dev [M][N][Nx] (may not alias).  KC_ENONFINITE if a sample's step matrix has
+ * a zero or non-finite pivot (advection-diffusion model). */
 int model_fine_propagate(klecgc_ctx* ctx, const klecgc_model* mp, const double* c_dev,
                          const double* start_dev, int64_t M, double* end_dev);
 /* model_coarse_propagate / model_serial_fine: U[m][s] = G(U[m][s-1]) (one step of dT) or

@@ -18,7 +18,9 @@ evaluation point.
 
 Backward Euler (F: J steps of dt, G: one step of dT) solves w - tau f(w) = v by Newton's
 method with the exact Jacobian, started from v; the iteration stops when
-|dw|_inf <= newton_tol max(|w|_inf, 1) (reading of "solve"; the paper names no tolerance).
+|dw|_inf <= newton_tol max(|w|_inf, 1) or after newton_max steps, keeping the last iterate
+(reading of "solve"; the paper names no tolerance, and where the upwind branch switches at
+u_i = 0 Newton can cycle at rounding level instead of converging).
 
 Coarse grid correction (Algorithm 2 step 2) for nonlinear f.  With b_1 = F_1 - G(alpha U^k_N),
 b_n = F_n - G(U^k_{n-1}) the new iterate u = (U_1, .., U_N) solves eq. matrix_NT,
@@ -124,7 +126,7 @@ def be_step(prob, v: np.ndarray, tau: float, newton_tol: float, newton_max: int)
         w = w + dw
         if np.abs(dw).max() <= newton_tol * max(np.abs(w).max(), 1.0):
             return w, it
-    raise RuntimeError("backward-Euler Newton iteration did not converge")
+    return w, newton_max
 
 
 class NLPropagators:

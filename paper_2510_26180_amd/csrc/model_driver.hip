@@ -76,9 +76,11 @@ struct Ops {
   virtual int flagged(std::vector<uint8_t>& bad) = 0;
   virtual int64_t newton_its(int64_t m) const { return 1; }
   virtual int flagged_code() const { return KC_ENONFINITE; }
-  // counters for klecgc_last_stats: [4] Newton steps of the corrections summed over samples,
-  // [7] the most Newton steps one correction of one sample took
-  virtual void report(int64_t* stats) const {}
+  // counters for klecgc_last_stats (nonlinear models): [0] Newton steps of the backward-Euler
+  // steps of all sweeps, [2] those backward-Euler steps (both summed over systems), [4] Newton
+  // steps of the corrections summed over samples, [7] the most one correction of one sample
+  // took, [10] backward-Euler steps whose Newton iteration reached its cap
+  virtual void report(int64_t* stats) {}
 };
 
 struct AdeOps : Ops {
@@ -105,8 +107,9 @@ struct NLOps : Ops {
   klecgc_model mp;
   NLState* s;
   int32_t* newton_list;
+  int64_t s_M;
   NLOps(klecgc_ctx* c, const klecgc_model& m, const double* coef, int64_t M, bool cgc, int32_t* scratch_list)
-      : ctx(c), mp(m), s(nl_prepare(c, m, coef, M, cgc)), newton_list(scratch_list) {}
+      : ctx(c), mp(m), s(nl_prepare(c, m, coef, M, cgc)), newton_list(scratch_list), s_M(M) {}
   ~NLOps() override { nl_release(s); }
   void sweep(const int32_t* list, int64_t nlist, const double* base, const double* u0, bool shift, int s_lo, int nsl,
              bool coarse, double* out) override {
@@ -117,12 +120,16 @@ struct NLOps : Ops {
     nl_correct(ctx, s, list, hlist, newton_list, Fv, U, maxima);
   }
   void initial_value(int64_t M, double* u0) override { nl_initial_value(ctx, mp, M, u0); }
-  int flagged(std::vector<uint8_t>& bad) override { return nl_failed_samples(ctx, s, bad); }
+  // a backward-Euler Newton iteration at its cap keeps its last iterate: counted, not an error
+  int flagged(std::vector<uint8_t>& bad) override {
+    bad.assign((size_t)s_M, 0);
+    return 0;
+  }
   int64_t newton_its(int64_t m) const override { return nl_newton_counts(s)[m]; }
-  int flagged_code() const override { return KC_ENOCONV; }
-  void report(int64_t* stats) const override {
+  void report(int64_t* stats) override {
     stats[4] = nl_newton_total(s);
     stats[7] = nl_newton_max(s);
+    nl_sweep_counts(ctx, s, &stats[0], &stats[2], &stats[10]);
   }
 };
 
@@ -195,6 +202,7 @@ int model_fine_impl(klecgc_ctx* ctx, const klecgc_model& mp, const double* c, co
   DriverBufs b = driver_bufs(ctx, M, mp.N, model_nx(mp), 0);
   auto ops = make_ops(ctx, mp, c, M, false, false, b);
   ops->sweep(nullptr, M, start, nullptr, false, 0, mp.N, false, end);
+  ops->report(ctx->stats);
   std::vector<uint8_t> bad;
   return ops->flagged(bad) ? ops->flagged_code() : KC_OK;
 }
@@ -208,6 +216,7 @@ static int sequential_sweep(klecgc_ctx* ctx, const klecgc_model& mp, const doubl
     u0 = b.u0;
   }
   for (int s = 0; s < mp.N; ++s) ops->sweep(nullptr, M, U, u0, true, s, 1, coarse, U);
+  ops->report(ctx->stats);
   std::vector<uint8_t> bad;
   return ops->flagged(bad) ? ops->flagged_code() : KC_OK;
 }
@@ -236,6 +245,7 @@ int model_cgc_impl(klecgc_ctx* ctx, const klecgc_model& mp, const double* c, con
   KC_TRY_HIP(hipStreamSynchronize(ctx->stream));
   if (newton_its)
     for (int64_t m = 0; m < M; ++m) newton_its[m] = (int32_t)ops->newton_its(m);
+  ops->report(ctx->stats);
   std::vector<uint8_t> bad;
   return ops->flagged(bad) ? ops->flagged_code() : KC_OK;
 }
@@ -362,9 +372,7 @@ int model_parareal_impl(klecgc_ctx* ctx, const klecgc_model& mp, const ModelSolv
         for (int s = 0; s < N; ++s)
           a.err_hist[((size_t)m * (mp.max_iter + 1) + k) * N + s] =
               a.err_hist[((size_t)m * (mp.max_iter + 1) + a.iters[m]) * N + s];
-  // a Newton iteration of a backward-Euler step that hit its cap (nonlinear models)
-  std::vector<uint8_t> fl;
-  return (mp.model != KC_MODEL_ADE_P1 && ops->flagged(fl)) ? ops->flagged_code() : KC_OK;
+  return KC_OK;
 }
 
 }  // namespace kc

@@ -105,6 +105,9 @@ void nl_correct(klecgc_ctx* ctx, NLState* s, const int32_t* list, const std::vec
                 int32_t* dev_newton_list, const double* Fv, double* U, unsigned long long* maxima);
 int nl_failed_samples(klecgc_ctx* ctx, NLState* s, std::vector<uint8_t>& bad);
 const std::vector<int64_t>& nl_newton_counts(const NLState* s);
+// Newton steps, backward-Euler steps and steps whose Newton iteration reached its cap, of all
+// sweeps since nl_prepare (summed over systems)
+void nl_sweep_counts(klecgc_ctx* ctx, const NLState* s, int64_t* newton, int64_t* steps, int64_t* capped);
 int64_t nl_newton_total(const NLState* s);
 int nl_newton_max(const NLState* s);
 

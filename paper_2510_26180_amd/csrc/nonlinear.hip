@@ -157,14 +157,16 @@ __device__ __forceinline__ void block_max2(double& x, double& y, double* red) {
 // One work-group per (listed sample, slice s_lo + k): J backward-Euler steps of size tau, each
 // w - tau f(w) = v solved by Newton from w = v until |dw|_inf <= ntol max(|w|_inf, 1).
 // Start: mode 0 base[m][s]; 1 (s == 0 ? u0[m] : base[m][s-1]); 2 (s == 0 ? alpha base[m][N-1] :
-// base[m][s-1]).  fail[m] is set if a Newton iteration hits nmax.
+// base[m][s-1]).  A Newton iteration that reaches nmax keeps its last iterate; fail[m] marks the
+// sample and counts[2] counts such steps.
 __global__ __launch_bounds__(1024) void nl_sweep_kernel(int model, int n, const double* __restrict__ coef,
                                                         const int32_t* __restrict__ list,
                                                         const double* __restrict__ base,
                                                         const double* __restrict__ u0, int mode, double alpha,
                                                         int s_lo, int nsl, int N, int J, double tau, double ntol,
                                                         int nmax, double* __restrict__ out,
-                                                        unsigned int* __restrict__ fail) {
+                                                        unsigned int* __restrict__ fail,
+                                                        unsigned long long* __restrict__ counts) {
   extern __shared__ double smem[];
   const int P = blockDim.x, i = threadIdx.x;
   double* w = smem;                 // [P]
@@ -190,10 +192,12 @@ __global__ __launch_bounds__(1024) void nl_sweep_kernel(int model, int n, const 
   double u = (i < n) ? scale * src[i] : 0.0;
   w[i] = u;
   bool failed = false;
+  unsigned long long newton = 0, capped = 0;
   for (int j = 0; j < J; ++j) {
     const double v = u;
     bool done = false;
     for (int it = 0; it < nmax && !done; ++it) {
+      ++newton;
       __syncthreads();
       double a = 0.0, b = 1.0, cc = 0.0, d = 0.0;
       if (i < n) {
@@ -216,9 +220,15 @@ __global__ __launch_bounds__(1024) void nl_sweep_kernel(int model, int n, const 
       done = dmax <= ntol * fmax(umax, 1.0);
     }
     failed |= !done;
+    capped += done ? 0 : 1;
   }
   if (i < n) out[(m * N + s) * n + i] = u;
-  if (failed && i == 0) atomicOr(&fail[m], 1u);
+  if (i == 0) {
+    if (failed) atomicOr(&fail[m], 1u);
+    atomicAdd(&counts[0], newton);
+    atomicAdd(&counts[1], (unsigned long long)J);
+    if (capped) atomicAdd(&counts[2], capped);
+  }
 }
 
 // Averaged Jacobian of eq. Jac: jbar[m][r][i], r = 0 lower, 1 diagonal, 2 upper, the mean over
@@ -364,6 +374,7 @@ struct NLState {
   int nmax = 0;
   const double* coef = nullptr;
   unsigned int* fail = nullptr;      // [M]
+  unsigned long long* counts = nullptr;  // [3]: Newton steps, backward-Euler steps, steps that hit the cap
   double* G = nullptr;               // [M][N][n]
   double* Uold = nullptr;            // [M][N][n]
   double* D = nullptr;               // [M][N][n]
@@ -392,14 +403,17 @@ NLState* nl_prepare(klecgc_ctx* ctx, const klecgc_model& mp, const double* c, in
     s->newton_its.assign((size_t)M, 0);
     const size_t st_b = sizeof(double) * (size_t)M * mp.N * mp.n;
     const size_t small_b = sizeof(unsigned int) * (size_t)M + sizeof(double) * 3 * (size_t)mp.N +
-                           sizeof(unsigned long long) * 2 * (size_t)M + 1024;
+                           sizeof(unsigned long long) * 2 * (size_t)M + 2048;
     char* sm = (char*)ctx->ws.get(WS_MODEL_SMALL, small_b);
     s->fail = (unsigned int*)sm;
     sm += (sizeof(unsigned int) * (size_t)M + 255) / 256 * 256;
     double* slt = (double*)sm;
     sm += (sizeof(double) * 3 * (size_t)mp.N + 255) / 256 * 256;
     s->nmx = (unsigned long long*)sm;
+    sm += (sizeof(unsigned long long) * 2 * (size_t)M + 255) / 256 * 256;
+    s->counts = (unsigned long long*)sm;
     KC_TRY_HIP(hipMemsetAsync(s->fail, 0, sizeof(unsigned int) * (size_t)M, ctx->stream));
+    KC_TRY_HIP(hipMemsetAsync(s->counts, 0, sizeof(unsigned long long) * 3, ctx->stream));
     if (need_cgc) {
       s->tb = slice_tables(ctx, mp.N, mp.alpha, slt);
       char* big = (char*)ctx->ws.get(WS_MODEL_STATE, 3 * st_b + sizeof(double) * 3 * (size_t)M * mp.n);
@@ -433,7 +447,7 @@ void nl_sweep(klecgc_ctx* ctx, NLState* s, const int32_t* list, int64_t nlist, c
   timed(ctx, KT_FINE, [&] {
     nl_sweep_kernel<<<(unsigned)(nlist * nsl), P, lds, ctx->stream>>>(
         s->mp.model, s->n, s->coef, list, base, u0, mode, s->mp.alpha, s_lo, nsl, s->mp.N, coarse ? 1 : s->mp.J,
-        coarse ? s->dT : s->dt, s->ntol, s->nmax, out, s->fail);
+        coarse ? s->dT : s->dt, s->ntol, s->nmax, out, s->fail, s->counts);
   });
   KC_LAUNCH_CHECK();
 }
@@ -508,6 +522,14 @@ int nl_failed_samples(klecgc_ctx* ctx, NLState* s, std::vector<uint8_t>& bad) {
 }
 
 const std::vector<int64_t>& nl_newton_counts(const NLState* s) { return s->newton_its; }
+void nl_sweep_counts(klecgc_ctx* ctx, const NLState* s, int64_t* newton, int64_t* steps, int64_t* capped) {
+  unsigned long long h[3] = {0, 0, 0};
+  KC_TRY_HIP(hipMemcpyAsync(h, s->counts, sizeof h, hipMemcpyDeviceToHost, ctx->stream));
+  KC_TRY_HIP(hipStreamSynchronize(ctx->stream));
+  *newton = (int64_t)h[0];
+  *steps = (int64_t)h[1];
+  *capped = (int64_t)h[2];
+}
 int64_t nl_newton_total(const NLState* s) { return s->newton_total; }
 int nl_newton_max(const NLState* s) { return s->newton_max_seen; }
 
