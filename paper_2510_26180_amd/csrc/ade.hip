@@ -27,9 +27,14 @@ namespace kc {
 
 namespace {
 
-constexpr int kTab = 24;      // per-node table: M[7], K[7], B[7], l0, l1, (pad)
+constexpr int kTab = 32;      // per-node table: M[7], K[7], B[7], l0, l1, M[7] with the couplings to
+                              // boundary nodes zeroed, (pad)
 constexpr int kMaxW = 32;     // largest half-bandwidth (n <= 31)
 constexpr int kStage = 32;    // factor rows staged per LDS chunk in the shifted solves
+// slices per wavefront in the fine sweep: each wavefront stages its sample's factor twice per
+// step and makes six passes over its lane states, so dealing a sample's slices to several
+// wavefronts multiplies that traffic (8 slices per wavefront measured 2.8x slower than 64)
+constexpr int kSweepLanes = 64;
 
 // stencil slot s -> neighbour offset (di, dj): 0 centre, 1 (-1,0), 2 (+1,0), 3 (0,-1),
 // 4 (0,+1), 5 (+1,+1), 6 (-1,-1) (the P1 couplings on this mesh)
@@ -137,7 +142,11 @@ __global__ void ade_tables_kernel(int n, double beta, double* __restrict__ tab) 
   }
   t[21] = l0;
   t[22] = l1;
-  t[23] = 0.0;
+  for (int s = 0; s < 7; ++s) {
+    const int ii = gi + slot_di(s), jj = gj + slot_dj(s);
+    t[23 + s] = (ii >= 1 && ii <= n && jj >= 1 && jj <= n) ? Mv[s] : 0.0;
+  }
+  t[30] = t[31] = 0.0;
 }
 
 __global__ void ade_u0_kernel(int n, int64_t M, double* __restrict__ u0) {
@@ -228,78 +237,170 @@ __global__ __launch_bounds__(64) void ade_factor_kernel(const double* __restrict
 // One wavefront per listed sample, lane l <-> slice s_lo + l (l < nsl).  J backward-Euler steps
 // of size tau; step j of slice s ends at t = s dT + (j+1) tau:
 //   (M + tau L) w' = M w + tau exp(-t) (l0 + a l1)
-// by the sample's band LU.  work: [nlist][2][Nx][64] (w, then the forward-substituted y).
+// by the sample's band LU.  work: [nlist][2][Nx + 2(n+1)][64]: w between n+1 zero ghost rows on
+// either side, then the right-hand side / forward-substituted y.  Each step: (1) the right-hand
+// sides of all rows, branch-free (the ghost rows and the interior-masked mass couplings stand in
+// for the boundary), so the loads of consecutive rows overlap; (2) forward and (3) back
+// substitution in blocks of W rows: the factor rows of
+// the next block are loaded (coalesced over the lanes) while the current block computes from
+// LDS, and the next block's right-hand sides are loaded into registers the same way, so a row
+// waits only on LDS and its own recurrence.
 template <int W>
 __global__ __launch_bounds__(64) void ade_sweep_kernel(const double* __restrict__ tab, int n,
                                                        const double* __restrict__ coef,
                                                        const double* __restrict__ fac,
                                                        const int32_t* __restrict__ list, const double* __restrict__ base,
                                                        const double* __restrict__ u0, int shift, int s_lo, int nsl,
-                                                       int N, int J, double tau, double dT,
+                                                       int lanes, int N, int J, double tau, double dT,
                                                        double* __restrict__ work, double* __restrict__ out) {
   constexpr int BW = 2 * W + 1;
-  const int li = blockIdx.x;
+  constexpr int BLK = W * BW;              // factor entries of one block of W rows
+  constexpr int SR = (BLK + 63) / 64;      // staged entries per lane
+  __shared__ double stg[2][BLK];
+  // the sample's slices are dealt to ceil(nsl / lanes) wavefronts, `lanes` slices each
+  const int waves = (nsl + lanes - 1) / lanes;
+  const int li = blockIdx.x / waves;
+  const int part = blockIdx.x % waves;
   const int64_t m = list ? list[li] : li;
   const int lane = threadIdx.x;
-  const bool on = lane < nsl;
-  const int s = s_lo + lane;
+  const bool on = lane < lanes && part * lanes + lane < nsl;
+  const int s = s_lo + part * lanes + lane;
   const int Nx = n * n;
+  const int G = n + 1;                       // ghost rows on either side of w
   const double* F = fac + (size_t)m * Nx * BW;
-  double* w = work + (size_t)li * 2 * Nx * 64 + lane;
-  double* y = w + (size_t)Nx * 64;
+  double* wg = work + (size_t)blockIdx.x * 2 * (Nx + 2 * G) * 64 + lane;
+  double* w = wg + (size_t)G * 64;
+  double* y = wg + (size_t)(Nx + 2 * G) * 64;
   const double a = coef[m];
   const double* src = nullptr;
   if (on)
     src = shift ? (s == 0 ? u0 + m * Nx : base + (m * N + s - 1) * Nx) : base + (m * N + s) * Nx;
+  for (int p = 0; p < G; ++p) {
+    wg[(size_t)p * 64] = 0.0;
+    w[(size_t)(Nx + p) * 64] = 0.0;
+  }
+#pragma unroll 4
   for (int p = 0; p < Nx; ++p) w[(size_t)p * 64] = on ? src[p] : 0.0;
   const double t0 = (double)s * dT;
-  double win[W];
+  const int64_t off[7] = {0, -64, 64, -(int64_t)n * 64, (int64_t)n * 64, (int64_t)(n + 1) * 64,
+                          -(int64_t)(n + 1) * 64};
+  // factor rows [rlo, rlo + W) of the sample (rows outside [0, Nx) read as 0)
+  auto stage_load = [&](int rlo, double (&reg)[SR]) {
+#pragma unroll
+    for (int q = 0; q < SR; ++q) {
+      const int e = lane + 64 * q;
+      const int row = rlo + e / BW;
+      reg[q] = (e < BLK && row >= 0 && row < Nx) ? F[(int64_t)rlo * BW + e] : 0.0;
+    }
+  };
+  auto stage_store = [&](double* buf, const double (&reg)[SR]) {
+#pragma unroll
+    for (int q = 0; q < SR; ++q) {
+      const int e = lane + 64 * q;
+      if (e < BLK) buf[e] = reg[q];
+    }
+  };
+  double win[W], rc[W], rn[W], sreg[SR];
 #pragma unroll
   for (int r = 0; r < W; ++r) win[r] = 0.0;
+  const int nblk = (Nx + W - 1) / W;
   for (int j = 0; j < J; ++j) {
     const double et = tau * exp(-(t0 + (double)(j + 1) * tau));
-    // forward substitution with the right-hand side M w + tau F(t), row by row
-    for (int p0 = 0; p0 < Nx; p0 += W) {
+    // (1) right-hand sides M w + tau F(t) into y
+#pragma unroll 8
+    for (int p = 0; p < Nx; ++p) {
+      const double* t = tab + (size_t)p * kTab;
+      const double* wp = w + (size_t)p * 64;
+      double acc = t[23] * wp[off[0]];
+#pragma unroll
+      for (int q = 1; q < 7; ++q) acc += t[23 + q] * wp[off[q]];
+      y[(size_t)p * 64] = acc + et * (t[21] + a * t[22]);
+    }
+    // (2) forward substitution, blocks of rows [bW, bW + W)
+#pragma unroll
+    for (int r = 0; r < W; ++r) win[r] = 0.0;
+    stage_load(0, sreg);
+#pragma unroll
+    for (int r = 0; r < W; ++r) rc[r] = r < Nx ? y[(size_t)r * 64] : 0.0;
+    __syncthreads();
+    stage_store(stg[0], sreg);
+    __syncthreads();
+    for (int b = 0; b < nblk; ++b) {
+      const int p0 = b * W;
+      const bool more = b + 1 < nblk;
+      if (more) {
+        stage_load(p0 + W, sreg);
+#pragma unroll
+        for (int r = 0; r < W; ++r) rn[r] = (p0 + W + r < Nx) ? y[(size_t)(p0 + W + r) * 64] : 0.0;
+      }
+      const double* S = stg[b & 1];
 #pragma unroll
       for (int r = 0; r < W; ++r) {
         const int p = p0 + r;
         if (p < Nx) {
-          const int i = p % n, jj = p / n;
-          const double* t = tab + (size_t)p * kTab;
-          const double* wp = w + (size_t)p * 64;
-          double acc = t[0] * wp[0];
-          if (i > 0) acc += t[1] * wp[-64];
-          if (i < n - 1) acc += t[2] * wp[64];
-          if (jj > 0) acc += t[3] * wp[-(int64_t)n * 64];
-          if (jj < n - 1) acc += t[4] * wp[(int64_t)n * 64];
-          if (i < n - 1 && jj < n - 1) acc += t[5] * wp[(int64_t)(n + 1) * 64];
-          if (i > 0 && jj > 0) acc += t[6] * wp[-(int64_t)(n + 1) * 64];
-          acc += et * (t[21] + a * t[22]);
-          const double* Lr = F + (size_t)p * BW;
+          // band entries of columns below 0 are zero, and so is the window before row 0
+          double acc = rc[r], acc2 = 0.0;
 #pragma unroll
-          for (int k = 1; k <= W; ++k)
-            if (p - k >= 0) acc -= Lr[W - k] * win[(r - k + W) % W];
+          for (int k = 1; k <= W; ++k) {
+            if (k & 1)
+              acc -= S[r * BW + W - k] * win[(r - k + W) % W];
+            else
+              acc2 -= S[r * BW + W - k] * win[(r - k + W) % W];
+          }
+          acc += acc2;
           win[r] = acc;
           y[(size_t)p * 64] = acc;
         }
       }
+      if (more) {
+        stage_store(stg[(b + 1) & 1], sreg);
+#pragma unroll
+        for (int r = 0; r < W; ++r) rc[r] = rn[r];
+      }
+      __syncthreads();
     }
-    // back substitution
-    for (int p0 = Nx - 1; p0 >= 0; p0 -= W) {
+    // (3) back substitution, blocks of rows (p0 - W, p0], p0 = Nx - 1 - bW
+#pragma unroll
+    for (int r = 0; r < W; ++r) win[r] = 0.0;
+    stage_load(Nx - W, sreg);
+#pragma unroll
+    for (int r = 0; r < W; ++r) rc[r] = (Nx - 1 - r >= 0) ? y[(size_t)(Nx - 1 - r) * 64] : 0.0;
+    stage_store(stg[0], sreg);
+    __syncthreads();
+    for (int b = 0; b < nblk; ++b) {
+      const int p0 = Nx - 1 - b * W;
+      const bool more = b + 1 < nblk;
+      if (more) {
+        stage_load(p0 - 2 * W + 1, sreg);
+#pragma unroll
+        for (int r = 0; r < W; ++r) rn[r] = (p0 - W - r >= 0) ? y[(size_t)(p0 - W - r) * 64] : 0.0;
+      }
+      const double* S = stg[b & 1];     // row p0 - r at staging row W - 1 - r
 #pragma unroll
       for (int r = 0; r < W; ++r) {
         const int p = p0 - r;
         if (p >= 0) {
-          const double* Ur = F + (size_t)p * BW;
-          double acc = y[(size_t)p * 64];
+          const double* Ur = S + (W - 1 - r) * BW;
+          // band entries of columns past Nx - 1 are zero, and so is the window before row Nx - 1
+          double acc = rc[r], acc2 = 0.0;
 #pragma unroll
-          for (int k = 1; k <= W; ++k)
-            if (p + k < Nx) acc -= Ur[W + k] * win[(r - k + W) % W];
-          acc *= Ur[W];
+          for (int k = 1; k <= W; ++k) {
+            if (k & 1)
+              acc -= Ur[W + k] * win[(r - k + W) % W];
+            else
+              acc2 -= Ur[W + k] * win[(r - k + W) % W];
+          }
+          acc = (acc + acc2) * Ur[W];
           win[r] = acc;
           w[(size_t)p * 64] = acc;
         }
       }
+      if (more) {
+        stage_store(stg[(b + 1) & 1], sreg);
+#pragma unroll
+        for (int r = 0; r < W; ++r) rc[r] = rn[r];
+      }
+      __syncthreads();
     }
   }
   if (on) {
@@ -404,8 +505,11 @@ template <int W>
 void launch_sweep_w(hipStream_t st, const double* tab, int n, const double* coef, const double* fac,
                     const int32_t* list, int64_t nlist, const AdeSweep& sw, int N, int J, double tau, double dT,
                     double* work) {
-  ade_sweep_kernel<W><<<(unsigned)nlist, 64, 0, st>>>(tab, n, coef, fac, list, sw.base, sw.u0, sw.shift ? 1 : 0,
-                                                      sw.s_lo, sw.nsl, N, J, tau, dT, work, sw.out);
+  const int lanes = kSweepLanes;
+  const int waves = (sw.nsl + lanes - 1) / lanes;
+  ade_sweep_kernel<W><<<(unsigned)(nlist * waves), 64, 0, st>>>(tab, n, coef, fac, list, sw.base, sw.u0,
+                                                                sw.shift ? 1 : 0, sw.s_lo, sw.nsl, lanes, N, J,
+                                                                tau, dT, work, sw.out);
 }
 
 }  // namespace
@@ -484,7 +588,9 @@ AdeState* ade_prepare(klecgc_ctx* ctx, const klecgc_model& mp, const double* c, 
       s->D = (double*)ctx->ws.get(WS_MODEL_STATE, sizeof(double) * (size_t)M * mp.N * s->Nx);
       s->spec = (cplx*)ctx->ws.get(WS_MODEL_SPEC, sizeof(cplx) * (size_t)M * s->K * s->Nx);
     }
-    s->work = (double*)ctx->ws.get(WS_MODEL_WORK, sizeof(double) * (size_t)M * 2 * s->Nx * 64);
+    const int waves = (mp.N + kSweepLanes - 1) / kSweepLanes;   // wavefronts per sample of the widest sweep
+    s->work = (double*)ctx->ws.get(WS_MODEL_WORK,
+                                   sizeof(double) * (size_t)M * waves * 2 * (s->Nx + 2 * (s->n + 1)) * 64);
   } catch (...) {
     delete s;
     throw;
