@@ -15,6 +15,7 @@
 // context and stream, and scattered back.
 #include <algorithm>
 #include <chrono>
+#include <condition_variable>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -562,12 +563,26 @@ static int run_classes_threads(klecgc_ctx* ctx, std::vector<ParaClass*>& cls, bo
   std::vector<int> rcs(C, KC_OK), iters(C, 0);
   std::vector<std::exception_ptr> errs(C);
   std::mutex capture_mu;   // one capture at a time
+  // Every class sizes its workspace in its first iteration, and growing a workspace frees a
+  // buffer, which synchronises the device; that is not allowed while another thread's stream is
+  // being captured.  So no class captures before every class has finished its first iteration.
+  std::mutex bar_mu;
+  std::condition_variable bar_cv;
+  int bar_left = C;
+  auto arrive = [&](bool wait) {
+    std::unique_lock<std::mutex> lk(bar_mu);
+    if (--bar_left == 0)
+      bar_cv.notify_all();
+    else if (wait)
+      bar_cv.wait(lk, [&] { return bar_left == 0; });
+  };
   auto work = [&](int i) {
     ParaClass& pc = *cls[i];
     klecgc_ctx* c = pc.c;
     hipStream_t s = c->stream;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    bool arrived = false;
     try {
       KC_TRY_HIP(hipSetDevice(ctx->device));
       KC_TRY_HIP(hipStreamWaitEvent(s, fork, 0));
@@ -581,6 +596,10 @@ static int run_classes_threads(klecgc_ctx* ctx, std::vector<ParaClass*>& cls, bo
       int left = (int)pc.M, k = 0;
       double last_line = 0.0;
       while (k < pc.p.max_iter && left > 0) {
+        if (k == 1 && !arrived) {
+          arrived = true;
+          arrive(true);
+        }
         if (capture && k == 1) {
           // replays accumulate the solver counters into status blocks cleared here
           status_reset(c, status_block(c, WS_STATUS));
@@ -624,6 +643,7 @@ static int run_classes_threads(klecgc_ctx* ctx, std::vector<ParaClass*>& cls, bo
     } catch (...) {
       errs[i] = std::current_exception();
     }
+    if (!arrived) arrive(false);
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
   };
