@@ -551,6 +551,8 @@ def main():
     ap.add_argument("--epochs", type=int, default=0, help="override the MLP epochs (0 = spec)")
     ap.add_argument("--batch", type=int, default=0, help="override the MLP mini-batch (0 = spec)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the built-in kernel choices")
+    ap.add_argument("--cgc-rtol", type=float, default=0.0,
+                    help="relative residual target of the shifted solves inside parareal_solve (0 = library default)")
     ap.add_argument("--grids", default="", help="ragged batch: comma-separated grid sizes (default 64,128,256)")
     ap.add_argument("--compare-eager", action="store_true", help="ragged batch: also run without the HIP graph")
     ap.add_argument("--no-cpu-baseline", action="store_true",
@@ -596,7 +598,7 @@ def main():
         w = w.replace(n_train=args.n_train)
     dev = torch.device("cuda:0")
     ctx = K.Context(0)
-    prob = K.ProblemSpec.from_workload(w)
+    prob = K.ProblemSpec.from_workload(w, cgc_rtol=args.cgc_rtol)
     log(f"workload {w.name}: dim={w.dim} n={w.n} N={w.N} J={w.J} M={w.M} alpha={w.alpha} n_train={w.n_train}")
 
     # ---- inputs resident in HBM

@@ -72,11 +72,23 @@ __device__ __forceinline__ void f_row(const NLP& P, double c, double um, double 
   }
 }
 
+// 1/b from the hardware reciprocal estimate and two Newton-Raphson steps (e = 1 - b r,
+// r += r e); the estimate is good to ~5e-8, so two steps reach the last bit (correctly rounded
+// on a million random operands over [1e-3, 1e3] on gfx950).  Several times cheaper than the
+// IEEE division sequence.
+__device__ __forceinline__ double rcp64(double b) {
+  double r = __builtin_amdgcn_rcp(b);
+  double e = fma(-b, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-b, r, 1.0);
+  return fma(r, e, r);
+}
+
 __device__ __forceinline__ cplx cmul(cplx a, cplx b) { return cplx{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
 __device__ __forceinline__ cplx cadd(cplx a, cplx b) { return cplx{a.re + b.re, a.im + b.im}; }
 __device__ __forceinline__ cplx cdiv(cplx a, cplx b) {
-  const double d = b.re * b.re + b.im * b.im;
-  return cplx{(a.re * b.re + a.im * b.im) / d, (a.im * b.re - a.re * b.im) / d};
+  const double d = rcp64(b.re * b.re + b.im * b.im);
+  return cplx{(a.re * b.re + a.im * b.im) * d, (a.im * b.re - a.re * b.im) * d};
 }
 __device__ __forceinline__ cplx cneg(cplx a) { return cplx{-a.re, -a.im}; }
 
@@ -86,7 +98,7 @@ struct RealOps {
   static __device__ __forceinline__ T one() { return 1.0; }
   static __device__ __forceinline__ T mul(T a, T b) { return a * b; }
   static __device__ __forceinline__ T add(T a, T b) { return a + b; }
-  static __device__ __forceinline__ T div(T a, T b) { return a / b; }
+  static __device__ __forceinline__ T div(T a, T b) { return a * rcp64(b); }
   static __device__ __forceinline__ T neg(T a) { return -a; }
 };
 struct CplxOps {
