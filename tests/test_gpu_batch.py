@@ -100,17 +100,47 @@ def test_ragged_1d_matches_uniform_and_oracle(ctx, graph):
         assert rel(got, prop.serial_fine(P, np.zeros(wm.Nx), wm.N)) <= 1e-8
 
 
+def _check_against_oracle(w, ns, Ns, xi, U, so, its, picks, init_name, exact_iterate):
+    """Ragged samples against the oracle: the Algorithm 2 iterate (FP64 paths) and the serial
+    fine solution (all paths)."""
+    for m in picks:
+        wm = w.replace(n=int(ns[m]), N=int(Ns[m]))
+        a0 = oracle_faces(wm, xi[m:m + 1])[0]
+        P = prop.Propagators(2, wm.n, a0, wm.T, wm.N, wm.J, wm.forcing)
+        u0 = np.zeros(wm.Nx)
+        U0 = np.zeros((wm.N, wm.Nx)) if init_name == "zero" else prop.coarse_sweep(P, u0, wm.N)
+        got = U[so[m]:so[m] + wm.N * wm.Nx].reshape(wm.N, wm.Nx)
+        assert rel(got, prop.serial_fine(P, u0, wm.N)) <= 1e-8, (m, wm.n, wm.N)
+        if exact_iterate:
+            res = opar.parareal_diag(P, wm.alpha, u0, U0, wm.tol, wm.max_iter)
+            if abs(res.deltas[-1] - wm.tol) > 0.01 * wm.tol:
+                assert its[m] == res.iters, (m, its[m], res.iters)
+            assert rel(got, res.iterates[-1]) <= 1e-10
+
+
+def _one_per_class(ns, Ns, limit):
+    seen, picks = set(), []
+    for m in range(len(ns)):
+        key = (int(ns[m]), int(Ns[m]))
+        if key not in seen:
+            seen.add(key)
+            picks.append(m)
+    return picks[:limit]
+
+
 @pytest.mark.parametrize("graph", [True, False])
-def test_ragged_2d_f64_matches_uniform(ctx, graph):
+def test_ragged_2d_f64_matches_uniform_and_oracle(ctx, graph):
     w = W.small_2d(alpha=1e-2, J=4, d=6)
     log(f"ragged 2D f64 graph={graph}")
-    _case(ctx, w, (9, 16, 20), (4, 8), 12, 202, graph)
+    ns, Ns, xi, U, so, its, lat = _case(ctx, w, (9, 16, 20), (4, 8), 12, 202, graph)
+    _check_against_oracle(w, ns, Ns, xi, U, so, its, _one_per_class(ns, Ns, 4), "zero", True)
 
 
-def test_ragged_2d_f32_refined_matches_uniform(ctx):
+def test_ragged_2d_f32_refined_matches_uniform_and_oracle(ctx):
     w = W.small_2d(alpha=1e-2, J=4, d=6, precision="f32_refined")
     log("ragged 2D f32-refined (resident and multigrid fine and shifted kernels)")
-    _case(ctx, w, (12, 33, 65, 130), (4, 8), 10, 303, True, init_name="coarse")
+    ns, Ns, xi, U, so, its, lat = _case(ctx, w, (12, 33, 65, 130), (4, 8), 10, 303, True, init_name="coarse")
+    _check_against_oracle(w, ns, Ns, xi, U, so, its, _one_per_class(ns, Ns, 8), "coarse", False)
 
 
 def test_ragged_latency_ordered_within_class(ctx):
