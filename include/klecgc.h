@@ -343,8 +343,16 @@ typedef struct {
   int64_t state_off;  /* element offset of the sample's N * n^dim states in U_dev */
 } klecgc_task;
 /* flags: KC_BATCH_GRAPH as above; KC_BATCH_PROGRESS prints one line per iteration to stderr
- * (iteration index, samples still active, elapsed seconds) so a long call is never silent */
-enum { KC_BATCH_GRAPH = 1, KC_BATCH_PROGRESS = 2 };
+ * (iteration index, samples still active, elapsed seconds) so a long call is never silent;
+ * KC_BATCH_PERSISTENT runs the classes from one host thread, and the fine sweeps of all
+ * classes with n <= 128 (2D, KC_PREC_F32_REFINED) of an iteration as ONE persistent launch:
+ * its work-groups take (class, sample, slice) tasks from device counters (eight ranges, one
+ * per XCD, then from each other's) and skip the samples already retired; each task is solved
+ * by the red-black resident kernel (so a class gives the results of the uniform driver with
+ * fine variant KC_FINE_RB128, bit for bit), and the iterations after the first are replayed
+ * from one graph holding that launch and every class's correction branch.  Other classes
+ * run their own fine sweeps in their branches. */
+enum { KC_BATCH_GRAPH = 1, KC_BATCH_PROGRESS = 2, KC_BATCH_PERSISTENT = 4 };
 int parareal_solve_batch(klecgc_ctx* ctx, const klecgc_problem* base, const klecgc_task* tasks,
                          int64_t M, const double* a_dev, int32_t init, double* U_dev, int32_t flags,
                          int32_t* iters_host, int32_t* status_host, double* latency_ms_host,

@@ -55,7 +55,7 @@ class Task(ctypes.Structure):
                 ("state_off", ctypes.c_int64)]
 
 
-KC_BATCH_GRAPH, KC_BATCH_PROGRESS = 1, 2
+KC_BATCH_GRAPH, KC_BATCH_PROGRESS, KC_BATCH_PERSISTENT = 1, 2, 4
 KC_FINE_STREAM64, KC_FINE_RES16, KC_FINE_RES32, KC_FINE_RES64, KC_FINE_RES128, KC_FINE_MG, KC_FINE_RB128 = 0, 1, 2, 3, 4, 5, 6
 KC_CGC_STREAM64, KC_CGC_RES16, KC_CGC_RES32, KC_CGC_RES64, KC_CGC_STREAM32, KC_CGC_MG32 = 0, 1, 2, 3, 4, 5
 

@@ -330,7 +330,7 @@ class Context:
                 np.frombuffer(hist, dtype=np.float64).reshape(M, mp.max_iter).copy(), errs)
 
     def parareal_solve_batch(self, base: ProblemSpec, tasks, a, U, init: int = L.KC_INIT_ZERO, graph: bool = True,
-                             allow_noconv=False, progress: bool = False):
+                             allow_noconv=False, progress: bool = False, persistent: bool = False):
         """tasks: sequence of (n, N, face_off, state_off); a, U: flat float64 device buffers."""
         M = len(tasks)
         arr = (L.Task * M)(*[L.Task(int(n), int(N), int(fo), int(so)) for n, N, fo, so in tasks])
@@ -341,7 +341,8 @@ class Context:
         pc = base.c()
         rc = self.lib.parareal_solve_batch(self.h, ctypes.byref(pc), arr, M, _ptr(a), init, _ptr(U),
                                            (L.KC_BATCH_GRAPH if graph else 0) |
-                                           (L.KC_BATCH_PROGRESS if progress else 0), iters, status, lat,
+                                           (L.KC_BATCH_PROGRESS if progress else 0) |
+                                           (L.KC_BATCH_PERSISTENT if persistent else 0), iters, status, lat,
                                            ctypes.byref(total))
         self._check(rc, allow=(-5,) if allow_noconv else ())
         return (np.frombuffer(iters, dtype=np.int32).copy(), np.frombuffer(status, dtype=np.int32).copy(),

@@ -605,7 +605,7 @@ int parareal_solve_batch(klecgc_ctx* ctx, const klecgc_problem* base, const klec
   return guarded(ctx, [&] {
     KC_REQUIRE(base && tasks && a_dev && U_dev && iters_host && status_host, KC_EINVAL, "null argument");
     KC_REQUIRE(M >= 1, KC_EINVAL, "M must be >= 1");
-    KC_REQUIRE((flags & ~(KC_BATCH_GRAPH | KC_BATCH_PROGRESS)) == 0, KC_EINVAL, "unknown flags");
+    KC_REQUIRE((flags & ~(KC_BATCH_GRAPH | KC_BATCH_PROGRESS | KC_BATCH_PERSISTENT)) == 0, KC_EINVAL, "unknown flags");
     return parareal_batch_impl(ctx, *base, tasks, M, a_dev, init, U_dev, flags, iters_host, status_host,
                                latency_ms_host, total_ms_host);
   });

@@ -248,6 +248,7 @@ struct ParaClass {
   ClassState st;
   int index = 1;            // slot in the device counter array (0 = all classes)
   bool fine_ready = false;  // the F buffer already holds iteration 0's fine sweep
+  bool fine_external = false;  // its fine sweep runs in the driver's persistent launch
 };
 
 static void enqueue_iteration(ParaClass& pc, int k, int* counts, int& rc) {
@@ -260,7 +261,7 @@ static void enqueue_iteration(ParaClass& pc, int k, int* counts, int& rc) {
   double* Fv = (double*)c->ws.get(WS_FINE, sizeof(double) * pc.M * S);
   double* D = (double*)c->ws.get(WS_DEFECT, sizeof(double) * pc.M * S);
   double* spec = (double*)c->ws.get(WS_SPEC, sizeof(double) * 2 * pc.M * K * Nx);
-  if (!(k == 0 && pc.fine_ready)) {
+  if (!(k == 0 && pc.fine_ready) && !pc.fine_external) {
     FineArgs fa{pc.a, pc.U, pc.u0, true, k > 0 ? 1 : 0, pc.st.active, Fv, pc.M};
     const int r = fine_propagate_impl(c, p, fa);
     if (r != KC_OK) rc = r;
@@ -278,6 +279,7 @@ static void enqueue_iteration(ParaClass& pc, int k, int* counts, int& rc) {
 
 // an iteration of the class is a fixed sequence of launches (no host decisions inside)
 static bool iteration_capturable(const ParaClass& pc) {
+  if (pc.fine_external) return true;
   if (pc.p.dim == 1 || pc.p.precision != KC_PREC_F32_REFINED) return true;
   return fine_variant_for(pc.p.n, tuning_for(pc.c, pc.p.n).fine_variant) != KC_FINE_MG;
 }
@@ -294,8 +296,11 @@ struct DriverOut {
 // Runs the parareal iteration over the classes.  `main` is the stream that orders the
 // whole run (the caller's); with use_graph the classes' iterations after the first are
 // replayed from one captured graph.
+// With `persistent`, the fine sweeps of every class that qualifies (persistent_eligible) run
+// as one persistent launch per iteration on the ordering stream, ahead of the classes'
+// branches.
 static int run_classes(klecgc_ctx* ctx, std::vector<ParaClass*>& cls, bool use_graph, bool want_hist,
-                       DriverOut& out, bool progress = false) {
+                       DriverOut& out, bool progress = false, bool persistent = false) {
   const auto t_start = std::chrono::steady_clock::now();
   auto report = [&](int k, int active) {
     if (!progress && !progress_enabled()) return;
@@ -357,6 +362,32 @@ static int run_classes(klecgc_ctx* ctx, std::vector<ParaClass*>& cls, bool use_g
     pc.index = i + 1;
     pc.st.alloc(pc.M, pc.p.max_iter, want_hist);
   }
+  int rc_fine = KC_OK;   // a persistent launch left a system above its target
+  PersistPlan plan;
+  bool use_plan = false;
+  if (persistent) {
+    std::vector<PersistSpec> specs;
+    for (auto* pc : cls) {
+      if (!persistent_eligible(pc->p)) continue;
+      const int64_t S = (int64_t)pc->p.N * n_unknowns(pc->p);
+      double* Fv = (double*)pc->c->ws.get(WS_FINE, sizeof(double) * pc->M * S);
+      specs.push_back(PersistSpec{pc->p, pc->a, pc->U, pc->u0, pc->st.active, Fv, pc->M,
+                                  tuning_for(pc->c, pc->p.n).fine_pcg_rtol});
+      pc->fine_external = true;
+    }
+    if (!specs.empty()) {
+      plan = persistent_prepare(ctx, specs);
+      use_plan = true;
+    }
+  }
+  // the persistent fine launch of an iteration (iteration index k: slice 0 only at k = 0)
+  auto persist_eager = [&](int k) {
+    if (!use_plan) return;
+    const DevStatus ds = status_block(ctx);
+    status_reset(ctx, ds);
+    persistent_launch(ctx, order, plan, k > 0 ? 1 : 0);
+    if (status_collect(ctx, ds, 0)) rc_fine = KC_ENOCONV;
+  };
   fork_all();
   for (auto* pc : cls) {
     class_init_kernel<<<blocks_of(pc->M), 256, 0, pc->c->stream>>>(pc->M, pc->st.active, pc->st.its, pc->st.status,
@@ -385,6 +416,7 @@ static int run_classes(klecgc_ctx* ctx, std::vector<ParaClass*>& cls, bool use_g
   }
   // eager iterations (all of them without a graph; the first one with a graph)
   while (k < max_iter) {
+    persist_eager(k);
     fork_all();
     for (int i = 0; i < C; ++i)
       if (hc[i + 1] > 0) enqueue_iteration(*cls[i], k, counts, rc);
@@ -402,6 +434,10 @@ static int run_classes(klecgc_ctx* ctx, std::vector<ParaClass*>& cls, bool use_g
         status_reset(cls[i]->c, status_block(cls[i]->c, WS_STATUS));
         status_reset(cls[i]->c, status_block(cls[i]->c, WS_STATUS_CGC));
       }
+    if (use_plan) {
+      status_reset(ctx, status_block(ctx));
+      KC_TRY_HIP(hipStreamSynchronize(main));
+    }
     for (auto* pc : cls)
       if (pc->c->stream != main) KC_TRY_HIP(hipStreamSynchronize(pc->c->stream));
   }
@@ -430,7 +466,9 @@ static int run_classes(klecgc_ctx* ctx, std::vector<ParaClass*>& cls, bool use_g
     order = cs.s;
     KC_TRY_HIP(hipStreamBeginCapture(order, hipStreamCaptureModeRelaxed));
     for (int i = 0; i < C; ++i) cls[i]->c->capturing = in_graph[i] != 0;
+    ctx->capturing = use_plan;
     try {
+      if (use_plan) persistent_launch(ctx, order, plan, 1);
       KC_TRY_HIP(hipEventRecord(fork, order));
       for (int i = 0; i < C; ++i)
         if (in_graph[i]) {
@@ -443,12 +481,14 @@ static int run_classes(klecgc_ctx* ctx, std::vector<ParaClass*>& cls, bool use_g
         }
     } catch (...) {
       for (auto* pc : cls) pc->c->capturing = false;
+      ctx->capturing = false;
       hipGraph_t g = nullptr;
       (void)hipStreamEndCapture(order, &g);
       if (g) (void)hipGraphDestroy(g);
       throw;
     }
     for (auto* pc : cls) pc->c->capturing = false;
+    ctx->capturing = false;
     KC_TRY_HIP(hipStreamEndCapture(order, &graph));
     hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     if (ie != hipSuccess) {
@@ -485,6 +525,8 @@ static int run_classes(klecgc_ctx* ctx, std::vector<ParaClass*>& cls, bool use_g
     order = main;
   }
   out.iterations = k;
+  if (replay && use_plan && status_collect(ctx, status_block(ctx), 0)) rc_fine = KC_ENOCONV;
+  if (rc == KC_OK) rc = rc_fine;
   if (replay)
     for (int i = 0; i < C; ++i) {   // eager classes collected their counters call by call
       if (!in_graph[i]) continue;
@@ -1061,8 +1103,20 @@ int parareal_batch_impl(klecgc_ctx* ctx, const klecgc_problem& base, const klecg
     return KC_OK;
   };
   DriverOut out;
-  int r = run_classes_threads(ctx, cls, (flags & KC_BATCH_GRAPH) != 0, (flags & KC_BATCH_PROGRESS) != 0, init_class,
-                              out);
+  int r;
+  if (flags & KC_BATCH_PERSISTENT) {
+    // one thread, one graph: each iteration is one persistent fine launch over the classes
+    // that qualify, then every class's branch (its own fine sweep otherwise, the correction)
+    for (auto* pc : cls) {
+      const int ri = init_class(*pc);
+      if (ri != KC_OK) rc = ri;
+    }
+    for (auto* pc : cls) KC_TRY_HIP(hipStreamSynchronize(pc->c->stream));
+    r = run_classes(ctx, cls, (flags & KC_BATCH_GRAPH) != 0, false, out, (flags & KC_BATCH_PROGRESS) != 0, true);
+  } else {
+    r = run_classes_threads(ctx, cls, (flags & KC_BATCH_GRAPH) != 0, (flags & KC_BATCH_PROGRESS) != 0, init_class,
+                            out);
+  }
   if (r != KC_OK) rc = r;
   // scatter the iterates back
   for (int i = 0; i < C; ++i) {

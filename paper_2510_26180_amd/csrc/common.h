@@ -74,6 +74,7 @@ enum WsSlot {
   WS_MODEL_SPEC,    // model problems: slice spectra
   WS_MODEL_SMALL,   // model problems: tables, lists, maxima, initial values
   WS_MODEL_AUX,     // model problems: second state buffer (Algorithm 1, Newton)
+  WS_PERSIST,       // persistent fine launch: class descriptors, task counters, tables
   WS_COUNT
 };
 
@@ -209,6 +210,33 @@ struct FineArgs {
   int64_t M;
 };
 int fine_propagate_impl(klecgc_ctx* ctx, const klecgc_problem& p, const FineArgs& fa);
+// The fine sweeps of several parareal classes in one persistent launch (fine.hip).  A class
+// qualifies if it is 2D, float32-refined and n <= 128 (it is then solved by the red-black
+// resident kernel whatever its tuning says).
+struct PersistSpec {
+  klecgc_problem p;
+  const double* a;          // [M][Fc]
+  const double* U;          // iterate [M][N][Nx]: slice s starts from U[m][s-1]
+  const double* u0;         // slice 0's start (nullable: zero)
+  const uint8_t* active;    // [M] nullable
+  double* out;              // F(U) [M][N][Nx]
+  int64_t M;
+  float pcg_rtol;
+};
+struct PersistPlan {
+  void* cls = nullptr;                 // device descriptors
+  int ncls = 0;
+  int64_t ntasks = 0;                  // (sample, slice) tasks of all classes
+  int nmax = 0;
+  int grid = 0;
+  double* incbuf = nullptr;
+  unsigned long long* queue = nullptr;
+};
+bool persistent_eligible(const klecgc_problem& p);
+// builds every class's tables and the descriptors in ctx's workspace (outside capture)
+PersistPlan persistent_prepare(klecgc_ctx* ctx, const std::vector<PersistSpec>& cls);
+// one launch on stream st over every task (capturable); counters into ctx's status block
+void persistent_launch(klecgc_ctx* ctx, hipStream_t st, const PersistPlan& plan, int skip_first);
 // multigrid-preconditioned fine propagation streamed pass by pass (fine_mg.hip); dinv and the
 // scaled float32 couplings sf of every sample are built by the caller
 int fine_mg_streamed(klecgc_ctx* ctx, const klecgc_problem& p, const FineArgs& fa, double tau, int J, int N,

@@ -597,15 +597,38 @@ __device__ __forceinline__ RbPassOut rb_pass(lds_float* xs_l, float fis, const f
 // outside the grid), halo rows, reduction slots.
 // RB: the float32 solve runs CG on the red-black reduced system (CPL == 2), else Jacobi-PCG
 // on the full system.
-template <int NW, int CPL, int RPW, bool RB = false>
-__global__ __launch_bounds__(64 * NW) void fine2d_resident_kernel(
+// A work-group's solver counters over the systems it has solved.
+struct ResTally {
+  unsigned long long its = 0, passes = 0, max_it = 0, missed = 0, steps = 0;
+  long long cg_cycles = 0;
+  bool fail = false;
+};
+
+// Thread 0 adds a work-group's counters to the status block (flag, cnt).
+__device__ __forceinline__ void report_tally(const ResTally& tl, long long t_start, int* flag,
+                                             unsigned long long* cnt) {
+  if (threadIdx.x != 0) return;
+  if (tl.fail) atomicOr(flag, 1);
+  atomicAdd(&cnt[0], tl.its);
+  atomicAdd(&cnt[1], tl.passes);
+  atomicAdd(&cnt[2], tl.steps);
+  atomicMax(&cnt[3], tl.max_it);
+  atomicAdd(&cnt[5], tl.missed);
+  atomicAdd(&cnt[8], (unsigned long long)(clock64() - t_start));
+  atomicAdd(&cnt[9], (unsigned long long)tl.cg_cycles);
+}
+
+// J implicit steps of one (sample m, slice) system by the whole work-group: the sample's
+// faces a, scaled faces sf, D^{-1/2} (float64 dinv, float32 dinvf) at their [M] bases, the
+// start row src (nullptr: zero), the result row w, and two Nx rows of scratch (inc, incp)
+// for the current and the previous step's increment.
+template <int NW, int CPL, int RPW, bool RB>
+__device__ __forceinline__ void resident_system(
     const double* __restrict__ a, const float* __restrict__ sf, const double* __restrict__ dinv,
-    const float* __restrict__ dinvf,
-    int n, double c, double tauf, int J, double tol, float pcg_rtol, int maxit, StartRef sr,
-    double* __restrict__ out, double* __restrict__ incbuf, int64_t M, int N, int skip_first, const uint8_t* __restrict__ active, int* __restrict__ flag,
-    unsigned long long* __restrict__ cnt) {
+    const float* __restrict__ dinvf, int n, double c, double tauf, int J, double tol, float pcg_rtol,
+    int maxit, const double* __restrict__ src, double* __restrict__ w, double* __restrict__ inc,
+    double* __restrict__ incp, int64_t m, ResTally& tally) {
   using RS = Resident<NW, CPL, RPW>;
-  const long long t_start = clock64();
   long long t_cg = 0;
   extern __shared__ float xs[];                       // [n*n + 2]
   __shared__ float hr_top[NW * RS::ROWW], hp_top[NW * RS::ROWW];
@@ -617,13 +640,6 @@ __global__ __launch_bounds__(64 * NW) void fine2d_resident_kernel(
   unsigned long long tot_it = 0, tot_pass = 0, max_it = 0, missed = 0;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  // the slices of a sample share its coefficients (and scaled forms): XCD-major order
-  // keeps them under one L2
-  const int64_t sys = xcd_major(blockIdx.x, gridDim.x);
-  const int64_t m = sys / N;
-  const int s = (int)(sys % N);
-  if (active && !active[m]) return;
-  if (skip_first && s == 0) return;
   const int64_t Nx = (int64_t)n * n;
   Grid2 g{n, (int64_t)n * (n + 1)};
   const int64_t Fc = 2 * g.nx;
@@ -631,9 +647,6 @@ __global__ __launch_bounds__(64 * NW) void fine2d_resident_kernel(
   const float* sfm = sf + m * Fc;
   const double* dv = dinv + m * Nx;
   const float* dvf = dinvf + m * Nx;   // the same, float32: scaling of float32 quantities
-  double* w = out + sys * Nx;
-  double* inc = incbuf + sys * Nx;   // increment w_{j+1} - w_j of the current step
-  double* incp = incbuf + ((int64_t)gridDim.x + sys) * Nx;   // the previous step's increment
   const int j0 = wave * RPW;
   const int i0 = lane * CPL;
 
@@ -651,7 +664,6 @@ __global__ __launch_bounds__(64 * NW) void fine2d_resident_kernel(
     }
   }
 
-  const double* src = sr.row(m, s, N, Nx);
   double dmx[1] = {0.0};
   const bool mxd[1] = {true};
   for (int64_t p = threadIdx.x; p < Nx; p += blockDim.x) {
@@ -1061,16 +1073,38 @@ __global__ __launch_bounds__(64 * NW) void fine2d_resident_kernel(
     }
     __syncthreads();   // the next residual sweep reads neighbours' w and inc
   }
-  if (threadIdx.x == 0) {
-    if (fail) atomicOr(flag, 1);
-    atomicAdd(&cnt[0], tot_it);
-    atomicAdd(&cnt[1], tot_pass);
-    atomicAdd(&cnt[2], (unsigned long long)J);
-    atomicMax(&cnt[3], max_it);
-    atomicAdd(&cnt[5], missed);
-    atomicAdd(&cnt[8], (unsigned long long)(clock64() - t_start));
-    atomicAdd(&cnt[9], (unsigned long long)t_cg);
-  }
+  tally.its += tot_it;
+  tally.passes += tot_pass;
+  tally.steps += (unsigned long long)J;
+  tally.max_it = max_it > tally.max_it ? max_it : tally.max_it;
+  tally.missed += missed;
+  tally.cg_cycles += t_cg;
+  tally.fail = tally.fail || fail;
+}
+
+// One work-group per (sample, slice) system of an [M][N] batch.
+template <int NW, int CPL, int RPW, bool RB = false>
+__global__ __launch_bounds__(64 * NW) void fine2d_resident_kernel(
+    const double* __restrict__ a, const float* __restrict__ sf, const double* __restrict__ dinv,
+    const float* __restrict__ dinvf,
+    int n, double c, double tauf, int J, double tol, float pcg_rtol, int maxit, StartRef sr,
+    double* __restrict__ out, double* __restrict__ incbuf, int64_t M, int N, int skip_first, const uint8_t* __restrict__ active, int* __restrict__ flag,
+    unsigned long long* __restrict__ cnt) {
+  const long long t_start = clock64();
+  // the slices of a sample share its coefficients (and scaled forms): XCD-major order
+  // keeps them under one L2
+  const int64_t sys = xcd_major(blockIdx.x, gridDim.x);
+  const int64_t m = sys / N;
+  const int s = (int)(sys % N);
+  if (active && !active[m]) return;
+  if (skip_first && s == 0) return;
+  const int64_t Nx = (int64_t)n * n;
+  ResTally tl;
+  // increments of the current and the previous step in [2][nsys][Nx]
+  resident_system<NW, CPL, RPW, RB>(a, sf, dinv, dinvf, n, c, tauf, J, tol, pcg_rtol, maxit,
+                                    sr.row(m, s, N, Nx), out + sys * Nx, incbuf + sys * Nx,
+                                    incbuf + ((int64_t)gridDim.x + sys) * Nx, m, tl);
+  report_tally(tl, t_start, flag, cnt);
 }
 
 template <int NW, int CPL, int RPW, bool RB = false>
@@ -1083,6 +1117,84 @@ void launch_resident(hipStream_t st, int64_t nsys, const double* a, const float*
       a, sf, dinv, dinvf, n, c, tauf, J, tol, pcg_rtol, maxit, sr, out, incbuf, M, N, skip_first, active,
       flag, cnt);
   KC_LAUNCH_CHECK();
+}
+
+// One class of a ragged batch as the persistent fine launch reads it (device copy).
+struct PersistClass {
+  const double* a;          // [M][Fc] faces
+  const float* sf;          // [M][Fc] scaled float32 couplings
+  const double* dinv;       // [M][Nx] D^{-1/2}
+  const float* dinvf;       // [M][Nx] its float32 copy
+  const double* U;          // starts in the parareal layout (slice s from U[m][s-1])
+  const double* u0;         // slice 0's start (nullable: zero)
+  const uint8_t* active;    // [M] nullable
+  double* out;              // [M][N][Nx]
+  double c, tauf, tol;
+  int64_t first;            // index of the class's first task
+  int n, N, J, maxit;
+  float pcg_rtol;
+};
+
+// The fine sweeps of several classes (grids up to 128 x 128, any N and J) in one launch:
+// every work-group takes (class, sample, slice) tasks from device counters until none is
+// left, and solves each as fine2d_resident_kernel solves its system (same code, so the same
+// result bit for bit).  Tasks are numbered class by class, sample-major, and dealt to the
+// XCDs in eight contiguous ranges, one counter each: a work-group takes from its own XCD's
+// range first (the slices of a sample share their coefficients under one L2), then from the
+// others.  Every work-group leaves once all eight counters have passed their range, so the
+// launch ends whatever the timing.  Retired samples' tasks are skipped.  incbuf: two rows of
+// nx_max per work-group; queue: 8 counters, zero at launch.
+template <int NW, int CPL, int RPW, bool RB>
+__global__ __launch_bounds__(64 * NW) void fine2d_persistent_kernel(
+    const PersistClass* __restrict__ cls, int ncls, int64_t ntasks, int skip_first,
+    double* __restrict__ incbuf, int64_t nx_max, unsigned long long* __restrict__ queue,
+    int* __restrict__ flag, unsigned long long* __restrict__ cnt) {
+  const long long t_start = clock64();
+  __shared__ long long task_s;
+  ResTally tl;
+  double* inc = incbuf + 2 * (int64_t)blockIdx.x * nx_max;
+  double* incp = inc + nx_max;
+  const int home = (int)(blockIdx.x % kXcds);
+  int tried = 0;   // thread 0: ranges found empty
+  for (;;) {
+    if (threadIdx.x == 0) {
+      long long t = -1;
+      while (tried < kXcds) {
+        const int x = (home + tried) % kXcds;
+        const int64_t lo = ntasks * x / kXcds, hi = ntasks * (x + 1) / kXcds;
+        const unsigned long long k = atomicAdd(&queue[x], 1ull);
+        if ((int64_t)k < hi - lo) {
+          t = lo + (int64_t)k;
+          break;
+        }
+        ++tried;
+      }
+      task_s = t;
+    }
+    __syncthreads();
+    const long long tv = task_s;
+    __syncthreads();   // read by all before thread 0 writes the next task
+    const long long t = ((long long)(unsigned)__builtin_amdgcn_readfirstlane((int)(tv >> 32)) << 32) |
+                        (unsigned)__builtin_amdgcn_readfirstlane((int)tv);
+    if (t < 0) break;
+    int k = 0;
+    while (k + 1 < ncls && t >= cls[k + 1].first) ++k;
+    const PersistClass& C = cls[k];
+    const int64_t local = t - C.first;
+    const int64_t m = local / C.N;
+    const int s = (int)(local % C.N);
+    if (C.active && !C.active[m]) continue;
+    if (skip_first && s == 0) continue;
+    const int64_t Nx = (int64_t)C.n * C.n;
+    const StartRef sr{C.U, C.u0, true};
+    resident_system<NW, CPL, RPW, RB>(C.a, C.sf, C.dinv, C.dinvf, C.n, C.c, C.tauf, C.J, C.tol, C.pcg_rtol,
+                                      C.maxit, sr.row(m, s, C.N, Nx), C.out + local * Nx, inc, incp, m, tl);
+  }
+  report_tally(tl, t_start, flag, cnt);
+}
+
+__global__ void queue_reset_kernel(unsigned long long* q) {
+  if (threadIdx.x < kXcds) q[threadIdx.x] = 0ull;
 }
 
 }  // namespace
@@ -1206,6 +1318,92 @@ int fine_variant_for(int n, int requested) {
   if (n <= 64) return KC_FINE_RES64;
   if (n <= 128) return KC_FINE_RB128;
   return KC_FINE_MG;
+}
+
+bool persistent_eligible(const klecgc_problem& p) {
+  return p.dim == 2 && p.precision == KC_PREC_F32_REFINED && p.n <= 128;
+}
+
+PersistPlan persistent_prepare(klecgc_ctx* ctx, const std::vector<PersistSpec>& specs) {
+  PersistPlan pl;
+  hipStream_t st = ctx->stream;
+  auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+  size_t bytes = al(sizeof(PersistClass) * specs.size()) + al(sizeof(unsigned long long) * kXcds);
+  for (const PersistSpec& sp : specs) {
+    KC_REQUIRE(persistent_eligible(sp.p), KC_EINVAL, "persistent fine launch: 2D float32-refined classes, n <= 128");
+    const int64_t Nx = (int64_t)sp.p.n * sp.p.n, Fc = 2LL * sp.p.n * (sp.p.n + 1);
+    bytes += al(sizeof(double) * sp.M * Nx) + al(sizeof(float) * sp.M * Nx) + al(sizeof(float) * sp.M * Fc);
+  }
+  char* base = (char*)ctx->ws.get(WS_PERSIST, bytes);
+  char* q = base;
+  pl.cls = q;
+  q += al(sizeof(PersistClass) * specs.size());
+  pl.queue = (unsigned long long*)q;
+  q += al(sizeof(unsigned long long) * kXcds);
+  std::vector<PersistClass> h(specs.size());
+  int64_t first = 0;
+  for (size_t i = 0; i < specs.size(); ++i) {
+    const PersistSpec& sp = specs[i];
+    const int n = sp.p.n;
+    const int64_t Nx = (int64_t)n * n, Fc = 2LL * n * (n + 1);
+    double* dinv = (double*)q;
+    q += al(sizeof(double) * sp.M * Nx);
+    float* dinvf = (float*)q;
+    q += al(sizeof(float) * sp.M * Nx);
+    float* sf = (float*)q;
+    q += al(sizeof(float) * sp.M * Fc);
+    // the same step, tables and stopping rule as propagate_impl
+    const double tau = sp.p.T / sp.p.N / sp.p.J;
+    const double hh = 1.0 / (n + 1);
+    const double c = tau / (hh * hh);
+    build_tables_2d(st, sp.a, n, c, sp.M, dinv, dinvf, sf);
+    PersistClass& d = h[i];
+    d.a = sp.a;
+    d.sf = sf;
+    d.dinv = dinv;
+    d.dinvf = dinvf;
+    d.U = sp.U;
+    d.u0 = sp.u0;
+    d.active = sp.active;
+    d.out = sp.out;
+    d.c = c;
+    d.tauf = tau * sp.p.forcing;
+    d.tol = sp.p.inner_rtol > 0 ? sp.p.inner_rtol : 1e-13;
+    d.first = first;
+    d.n = n;
+    d.N = sp.p.N;
+    d.J = sp.p.J;
+    d.maxit = sp.p.inner_max_iter > 0 ? sp.p.inner_max_iter : 4000;
+    d.pcg_rtol = sp.pcg_rtol;
+    first += sp.M * sp.p.N;
+    pl.nmax = std::max(pl.nmax, n);
+  }
+  KC_TRY_HIP(hipMemcpyAsync(pl.cls, h.data(), sizeof(PersistClass) * h.size(), hipMemcpyHostToDevice, st));
+  KC_TRY_HIP(hipStreamSynchronize(st));   // h is a host temporary
+  pl.ncls = (int)specs.size();
+  pl.ntasks = first;
+  pl.grid = std::max(ctx->num_cus, kXcds);
+  pl.incbuf = (double*)ctx->ws.get(WS_FINE_INC, 2 * sizeof(double) * (size_t)pl.grid * pl.nmax * pl.nmax);
+  return pl;
+}
+
+void persistent_launch(klecgc_ctx* ctx, hipStream_t st, const PersistPlan& pl, int skip_first) {
+  if (pl.ntasks == 0) return;
+  DevStatus ds = status_block(ctx);
+  queue_reset_kernel<<<1, 64, 0, st>>>(pl.queue);
+  KC_LAUNCH_CHECK();
+  const size_t lds = sizeof(float) * ((size_t)pl.nmax * pl.nmax + 2);
+  auto go = [&] {
+    fine2d_persistent_kernel<KC_RES128_NW, 2, 128 / KC_RES128_NW, true>
+        <<<dim3((unsigned)pl.grid), dim3(64 * KC_RES128_NW), lds, st>>>(
+            (const PersistClass*)pl.cls, pl.ncls, pl.ntasks, skip_first, pl.incbuf, (int64_t)pl.nmax * pl.nmax,
+            pl.queue, ds.flag, ds.cnt);
+    KC_LAUNCH_CHECK();
+  };
+  if (st == ctx->stream)
+    timed(ctx, KT_FINE, go);
+  else
+    go();
 }
 
 int fine_propagate_impl(klecgc_ctx* ctx, const klecgc_problem& p, const FineArgs& fa) {

@@ -3,8 +3,9 @@ slice count, grouped into classes that run on their own streams, with the iterat
 after the first replayed from a captured HIP graph and the convergence test on the device.
 
 Every sample must reproduce, bit for bit, what parareal_solve returns for its class run
-alone (same kernels on the same data), with and without the graph; a few samples are
-also checked against the oracle's Algorithm 2 iterate and serial fine solution.
+alone (same kernels on the same data), with and without the graph, and with the fine sweeps
+of the classes up to 128 x 128 run as one persistent launch; a few samples are also checked
+against the oracle's Algorithm 2 iterate and serial fine solution.
 """
 import numpy as np
 import pytest
@@ -49,18 +50,42 @@ def _ragged(w, grids, slices, M, seed):
     return ns, Ns, xi, a, fo, so, s_off
 
 
-def _case(ctx, w, grids, slices, M, seed, graph, init_name="zero"):
+def _case(ctx, w, grids, slices, M, seed, graph, init_name="zero", persistent=False):
     import paper_2510_26180_amd as K
+    import paper_2510_26180_amd._lib as L
     ns, Ns, xi, a, fo, so, s_len = _ragged(w, grids, slices, M, seed)
     base = K.ProblemSpec.from_workload(w)
     tasks = [(int(ns[m]), int(Ns[m]), int(fo[m]), int(so[m])) for m in range(M)]
     a_d = dev(a)
     U_d = torch.full((s_len,), 7.0, dtype=torch.float64, device="cuda")
     init = {"zero": K.KC_INIT_ZERO, "coarse": K.KC_INIT_COARSE}[init_name]
-    its, st, lat, total, rc = ctx.parareal_solve_batch(base, tasks, a_d, U_d, init=init, graph=graph)
-    log(f"  batch M={M} graph={graph}: iterations {its.min()}..{its.max()}, total {total:.1f} ms, "
-        f"latency p50 {np.percentile(lat, 50):.1f} p99 {np.percentile(lat, 99):.1f} ms")
-    U = host(U_d)
+    # the persistent launch solves every 2D float32-refined class with n <= 128 on the
+    # red-black resident kernel: the uniform driver below is asked for the same kernel
+    rb = sorted({int(n) for n in ns if persistent and w.dim == 2 and w.precision == "f32_refined" and n <= 128})
+    for n in rb:
+        ctx.set_tuning(n, fine_variant=L.KC_FINE_RB128)
+    try:
+        its, st, lat, total, rc = ctx.parareal_solve_batch(base, tasks, a_d, U_d, init=init, graph=graph,
+                                                           persistent=persistent)
+        log(f"  batch M={M} graph={graph} persistent={persistent}: iterations {its.min()}..{its.max()}, "
+            f"total {total:.1f} ms, latency p50 {np.percentile(lat, 50):.1f} p99 {np.percentile(lat, 99):.1f} ms")
+        U = host(U_d)
+        _compare_uniform(ctx, w, ns, Ns, a, fo, so, U, its, st, init, M)
+    finally:
+        for n in rb:
+            ctx.set_tuning(n)
+    # the gaps between samples are untouched
+    mask = np.ones(s_len, bool)
+    for m in range(M):
+        mask[so[m]:so[m] + Ns[m] * ns[m] ** w.dim] = False
+    assert np.all(U[mask] == 7.0)
+    assert (st == K.KC_SAMPLE_CONVERGED).all()
+    assert np.all(lat > 0) and np.all(lat <= total * (1 + 1e-6))
+    return ns, Ns, xi, U, so, its, lat
+
+
+def _compare_uniform(ctx, w, ns, Ns, a, fo, so, U, its, st, init, M):
+    import paper_2510_26180_amd as K
     # per class: the uniform driver on the same samples
     for (n, N) in sorted(set(zip(ns.tolist(), Ns.tolist()))):
         idx = [m for m in range(M) if ns[m] == n and Ns[m] == N]
@@ -74,14 +99,6 @@ def _case(ctx, w, grids, slices, M, seed, graph, init_name="zero"):
             assert its[m] == itc[j] and st[m] == stc[j], (n, N, m)
             got = U[so[m]:so[m] + N * wc.Nx].reshape(N, wc.Nx)
             assert np.array_equal(got, Uh[j]), (n, N, m)
-    # the gaps between samples are untouched
-    mask = np.ones(s_len, bool)
-    for m in range(M):
-        mask[so[m]:so[m] + Ns[m] * ns[m] ** w.dim] = False
-    assert np.all(U[mask] == 7.0)
-    assert (st == K.KC_SAMPLE_CONVERGED).all()
-    assert np.all(lat > 0) and np.all(lat <= total * (1 + 1e-6))
-    return ns, Ns, xi, U, so, its, lat
 
 
 @pytest.mark.parametrize("graph", [True, False])
@@ -141,6 +158,18 @@ def test_ragged_2d_f32_refined_matches_uniform_and_oracle(ctx):
     log("ragged 2D f32-refined (resident and multigrid fine and shifted kernels)")
     ns, Ns, xi, U, so, its, lat = _case(ctx, w, (12, 33, 65, 130), (4, 8), 10, 303, True, init_name="coarse")
     _check_against_oracle(w, ns, Ns, xi, U, so, its, _one_per_class(ns, Ns, 8), "coarse", False)
+
+
+@pytest.mark.parametrize("graph", [True, False])
+def test_ragged_persistent_matches_uniform_and_oracle(ctx, graph):
+    # one persistent fine launch per iteration over the classes with n <= 128 (several grid
+    # sizes, even and odd, and slice counts); the 130 x 130 class runs its own multigrid fine
+    # sweep in its branch beside it
+    w = W.small_2d(alpha=1e-2, J=4, d=6, precision="f32_refined")
+    log(f"ragged 2D f32-refined, persistent fine launch, graph={graph}")
+    ns, Ns, xi, U, so, its, lat = _case(ctx, w, (12, 33, 64, 72, 130), (4, 8), 14, 505, graph, init_name="coarse",
+                                        persistent=True)
+    _check_against_oracle(w, ns, Ns, xi, U, so, its, _one_per_class(ns, Ns, 4), "coarse", False)
 
 
 def test_ragged_latency_ordered_within_class(ctx):
