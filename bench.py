@@ -239,30 +239,46 @@ def run_ragged(args):
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
     tasks = [(int(ns[m]), int(Ns[m]), int(fo[m]), int(so[m])) for m in range(M)]
-    runs = {}
-    for graph in ([True, False] if args.compare_eager else [True]):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        its, st, lat, total, rc = ctx.parareal_solve_batch(base, tasks, a_d, U, init=K.KC_INIT_COARSE, graph=graph,
-                                                           allow_noconv=True, progress=True)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        runs[graph] = dict(its=its, st=st, lat=lat, total=total, wall=wall, rc=rc)
-        log(f"graph={graph}: {wall:.2f} s, iterations mean {its.mean():.2f} max {its.max()}, "
-            f"latency p50 {np.percentile(lat, 50) / 1e3:.2f} s p99 {np.percentile(lat, 99) / 1e3:.2f} s")
-    # accuracy: GPU serial fine per class
-    err = np.zeros(M)
+    # accuracy reference: the GPU serial fine solution of every class, computed once
     t0 = time.perf_counter()
+    refs = {}
     for (n, N), idx in classes.items():
         pc = K.ProblemSpec.from_workload(bw.replace(n=n, N=N))
         ac = torch.stack([a_d[fo[m]:fo[m] + fc[m]] for m in idx])
-        ref = torch.empty((len(idx), N, n * n), dtype=torch.float64, device=dev)
-        ctx.serial_fine_propagate(pc, ac, None, ref)
-        for j, m in enumerate(idx):
-            got = U[so[m]:so[m] + sz[m]].view(N, n * n)
-            err[m] = float((got - ref[j]).abs().max() / ref[j].abs().max())
+        refs[(n, N)] = torch.empty((len(idx), N, n * n), dtype=torch.float64, device=dev)
+        ctx.serial_fine_propagate(pc, ac, None, refs[(n, N)])
+    torch.cuda.synchronize()
     t_ref = time.perf_counter() - t0
-    r = runs[True]
+
+    def errors():
+        e = np.zeros(M)
+        for (n, N), idx in classes.items():
+            for j, m in enumerate(idx):
+                got = U[so[m]:so[m] + sz[m]].view(N, n * n)
+                ref = refs[(n, N)][j]
+                e[m] = float((got - ref).abs().max() / ref.abs().max())
+        return e
+
+    # the per-class graph driver (the default), its eager form, and the persistent fine launch
+    modes = [("graph", dict(graph=True))]
+    if args.compare_eager:
+        modes.append(("eager", dict(graph=False)))
+    if args.compare_persistent:
+        modes.append(("persistent", dict(graph=True, persistent=True)))
+    runs = {}
+    for name, kw in modes:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        its, st, lat, total, rc = ctx.parareal_solve_batch(base, tasks, a_d, U, init=K.KC_INIT_COARSE,
+                                                           allow_noconv=True, progress=True, **kw)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        runs[name] = dict(its=its, st=st, lat=lat, total=total, wall=wall, rc=rc, err=errors(),
+                          fine_ms=ctx.last_times()["fine"][0])
+        log(f"{name}: {wall:.2f} s, iterations mean {its.mean():.2f} max {its.max()}, "
+            f"latency p50 {np.percentile(lat, 50) / 1e3:.2f} s p99 {np.percentile(lat, 99) / 1e3:.2f} s")
+    err = runs["graph"]["err"]
+    r = runs["graph"]
     n_ok = int((err <= 1e-8).sum())
     cls_stats = {f"{n}x{n},N={N}": {"samples": len(idx), "iters_mean": float(r["its"][idx].mean()),
                                     "latency_p50_ms": float(np.percentile(r["lat"][idx], 50))}
@@ -281,11 +297,19 @@ def run_ragged(args):
         "accuracy": {"n_within_1e-8": n_ok, "max_rel_err_vs_serial_fine": float(err.max())},
         "classes": cls_stats, "setup_s": t_setup, "serial_fine_reference_s": t_ref,
     }
-    if False in runs:
-        e = runs[False]
-        line["eager"] = {"ms": 1e3 * e["wall"], "latency_p50_ms": float(np.percentile(e["lat"], 50)),
-                         "latency_p99_ms": float(np.percentile(e["lat"], 99)),
-                         "same_iterations": bool((e["its"] == r["its"]).all())}
+    for name in ("eager", "persistent"):
+        if name not in runs:
+            continue
+        e = runs[name]
+        line[name] = {"ms": 1e3 * e["wall"], "solves_per_s": int((e["err"] <= 1e-8).sum()) / e["wall"],
+                      "latency_p50_ms": float(np.percentile(e["lat"], 50)),
+                      "latency_p99_ms": float(np.percentile(e["lat"], 99)),
+                      "fine_kernel_ms": e["fine_ms"], "n_within_1e-8": int((e["err"] <= 1e-8).sum()),
+                      "max_rel_err_vs_serial_fine": float(e["err"].max()),
+                      "same_iterations": bool((e["its"] == r["its"]).all()),
+                      "classes": {f"{n}x{n},N={N}": {"iters_mean": float(e["its"][idx].mean()),
+                                                     "latency_p50_ms": float(np.percentile(e["lat"][idx], 50))}
+                                  for (n, N), idx in sorted(classes.items())}}
     print(json.dumps(line), flush=True)
     ctx.close()
 
@@ -553,6 +577,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="keep the built-in kernel choices")
     ap.add_argument("--cgc-rtol", type=float, default=0.0,
                     help="relative residual target of the shifted solves inside parareal_solve (0 = library default)")
+    ap.add_argument("--compare-persistent", action="store_true",
+                    help="ragged batch: also run the persistent fine launch (KC_BATCH_PERSISTENT)")
     ap.add_argument("--grids", default="", help="ragged batch: comma-separated grid sizes (default 64,128,256)")
     ap.add_argument("--compare-eager", action="store_true", help="ragged batch: also run without the HIP graph")
     ap.add_argument("--no-cpu-baseline", action="store_true",
