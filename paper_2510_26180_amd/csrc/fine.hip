@@ -490,6 +490,7 @@ __device__ __forceinline__ RbPassOut rb_pass(lds_float* xs_l, float fis, const f
   int lane = threadIdx.x & 63;
   int wave = threadIdx.x >> 6;
   asm volatile("" : "+v"(lane), "+v"(wave));
+  wave = __builtin_amdgcn_readfirstlane(wave);   // uniform: halo branches on the scalar unit
   const int j0 = wave * RPW, i0 = lane * 2;
   // negated scaled couplings (0 on boundary faces and outside the grid)
   float EW[RPW][2], NS[RPW][2];
@@ -639,7 +640,8 @@ __device__ __forceinline__ void resident_system(
   __shared__ double dslots[4 * NW];
   unsigned long long tot_it = 0, tot_pass = 0, max_it = 0, missed = 0;
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  // uniform across the wave: its rows' indices, tests and offsets go to the scalar unit
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int64_t Nx = (int64_t)n * n;
   Grid2 g{n, (int64_t)n * (n + 1)};
   const int64_t Fc = 2 * g.nx;
