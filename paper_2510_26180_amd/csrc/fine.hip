@@ -254,6 +254,54 @@ __device__ __forceinline__ double dppd(double v) {
 }
 
 __device__ __forceinline__ double2 ld2(const double* p) { return *reinterpret_cast<const double2*>(p); }
+
+// float64 DPP move restricted to the rows in ROWMASK (other rows, and lanes without a source,
+// read 0.0)
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dppd_rows(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROWMASK, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWMASK, 0xf, true);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Maximum within each 16-lane row, left in the row's lane 15 (row shifts by 1, 2, 4, 8 with
+// 0.0 shifted in: the values are non-negative, and a NaN anywhere stays NaN).
+__device__ __forceinline__ double row_max_dpp(double x) {
+  x = nanmax(x, dppd_rows<0x111, 0xf>(x));
+  x = nanmax(x, dppd_rows<0x112, 0xf>(x));
+  x = nanmax(x, dppd_rows<0x114, 0xf>(x));
+  x = nanmax(x, dppd_rows<0x118, 0xf>(x));
+  return x;
+}
+
+// Maxima over the work-group of K non-negative float64 values per thread (NaN if any is NaN),
+// returned uniform in every lane.  Within a wave by DPP (rows, then two row broadcasts into
+// lane 63), one slot per wave, a barrier, then lanes 0..NW-1 reduce the slots within row 0
+// and lane 15's result is read back as a scalar.  slots: K * NW doubles; the closing barrier
+// lets the next call reuse them.
+template <int NW, int K>
+__device__ __forceinline__ void block_max_nn(double (&v)[K], double* slots, int lane, int wave) {
+  static_assert(NW <= 16, "one slot per lane of row 0");
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    double x = row_max_dpp(v[k]);
+    x = nanmax(x, dppd_rows<0x142, 0xa>(x));   // row_bcast:15 into rows 1 and 3
+    x = nanmax(x, dppd_rows<0x143, 0xc>(x));   // row_bcast:31 into rows 2 and 3
+    if (lane == 63) slots[k * NW + wave] = x;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const double x = row_max_dpp(lane < NW ? slots[k * NW + lane] : 0.0);
+    const long long b = __builtin_bit_cast(long long, x);
+    const int lo = __builtin_amdgcn_readlane((int)b, 15);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 15);
+    v[k] = __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+  }
+  __syncthreads();
+}
+
 __device__ __forceinline__ void st2(double* p, double x, double y) {
   *reinterpret_cast<double2*>(p) = make_double2(x, y);
 }
@@ -667,14 +715,13 @@ __device__ __forceinline__ void resident_system(
   }
 
   double dmx[1] = {0.0};
-  const bool mxd[1] = {true};
   for (int64_t p = threadIdx.x; p < Nx; p += blockDim.x) {
     w[p] = src ? src[p] : 0.0;
     inc[p] = 0.0;
     incp[p] = 0.0;
     dmx[0] = nanmax(dmx[0], 1.0 / (dv[p] * dv[p]));
   }
-  block_reduce<1>(dmx, mxd, dslots);   // also orders the copy before the first stencil
+  block_max_nn<NW, 1>(dmx, dslots, lane, wave);   // also orders the copy before the first stencil
   const double dmax = dmx[0];
 
   float X[RPW][CPL], R[RPW][CPL], P[RPW][CPL], Q[RPW][CPL];
@@ -703,7 +750,6 @@ __device__ __forceinline__ void resident_system(
     constexpr int MODE = decltype(mode)::value;
     constexpr bool FUSED = MODE != kSweepPlain;
     acc[0] = acc[1] = acc[2] = 0.0;
-    const bool mx[3] = {true, true, true};
     if (pairs) {
       // A lane's two columns (i0, i0 + 1) together: 16-byte loads of w, inc, D^{-1/2} and
       // the y-faces use every byte of the cache lines a wave touches (two 8-byte loads
@@ -833,7 +879,7 @@ __device__ __forceinline__ void resident_system(
         Ic = Il;
         FSc = FN;
       }
-      block_reduce<3>(acc, mx, dslots);
+      block_max_nn<NW, 3>(acc, dslots, lane, wave);
       return;
     }
     if constexpr (!FUSED) {   // odd n: updates run in their own passes
@@ -879,7 +925,7 @@ __device__ __forceinline__ void resident_system(
         if (okk[u]) xs[pp[u]] = rhs[u];
     }
     }
-    block_reduce<3>(acc, mx, dslots);
+    block_max_nn<NW, 3>(acc, dslots, lane, wave);
   };
 
   for (int step = 0; step < J; ++step) {
