@@ -416,12 +416,15 @@ __device__ __forceinline__ void block_sum_fk(float (&v)[K], float* slots, int la
     for (int k = 0; k < K; ++k) slots[k * NW + wave] = v[k];
   }
   __syncthreads();
+  // the NW wave sums by the same row butterfly in lanes 0..NW-1, read back as a scalar
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    float acc = slots[k * NW];
-#pragma unroll
-    for (int w = 1; w < NW; ++w) acc += slots[k * NW + w];
-    v[k] = acc;
+    float x = lane < NW ? slots[k * NW + lane] : 0.f;
+    x += dppf_c<0xB1>(x);
+    x += dppf_c<0x4E>(x);
+    x += dppf_c<0x141>(x);
+    x += dppf_c<0x140>(x);
+    v[k] = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), 0));
   }
 }
 
