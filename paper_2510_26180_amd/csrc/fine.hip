@@ -759,6 +759,7 @@ __device__ __forceinline__ void resident_system(
       const bool lane_ok = i0 < n;
       const int ic = lane_ok ? i0 : 0;   // clamped: every load in bounds
       const double2 zero2 = make_double2(0.0, 0.0);
+      double bad = 0.0;
       // rows are walked upwards with a window of three rows of w and inc (south, current,
       // north) and the south y-faces carried over, so each row loads only its north row
       // FUSED: the update of the pair at q (in the grid); Iold: the increment it held
@@ -869,9 +870,11 @@ __device__ __forceinline__ void resident_system(
         *reinterpret_cast<float2*>(xs + (ok ? j * n + i0 : n * n)) =
             make_float2((float)(D.x * rv0), (float)(D.y * rv1));
         if (ok) {
-          acc[0] = nanmax(acc[0], nanmax(fabs(rv0), fabs(rv1)));
-          acc[1] = nanmax(acc[1], nanmax(fabs(W.x + I.x), fabs(W.y + I.y)));
-          acc[2] = nanmax(acc[2], nanmax(D.x * fabs(rv0), D.y * fabs(rv1)));
+          // a non-finite residual turns bad into NaN (v_max_f64 would drop it)
+          bad = fma(rv0, 0.0, fma(rv1, 0.0, bad));
+          acc[0] = fmax(acc[0], fmax(fabs(rv0), fabs(rv1)));
+          acc[1] = fmax(acc[1], fmax(fabs(W.x + I.x), fabs(W.y + I.y)));
+          acc[2] = fmax(acc[2], fmax(D.x * fabs(rv0), D.y * fabs(rv1)));
         }
         Ws = W;
         Is = I;
@@ -879,6 +882,7 @@ __device__ __forceinline__ void resident_system(
         Ic = Il;
         FSc = FN;
       }
+      if (bad != bad) acc[0] = bad;
       block_max_nn<NW, 3>(acc, dslots, lane, wave);
       return;
     }
