@@ -31,7 +31,7 @@ namespace kc {
 namespace {
 
 constexpr int kT = 256;            // threads of a streamed pass (4 waves)
-constexpr int kOnChipMax = 32;     // levels of at most this many nodes per side run in LDS
+constexpr int kOnChipMax = 64;     // levels of at most this many nodes per side run in LDS
 constexpr int kRing = 1024;        // counters of the host-visible decisions
 
 // --------------------------------------------------------------- host-side level table
