@@ -15,7 +15,6 @@
 // context and stream, and scattered back.
 #include <algorithm>
 #include <chrono>
-#include <condition_variable>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -607,16 +606,17 @@ static int run_classes_threads(klecgc_ctx* ctx, std::vector<ParaClass*>& cls, bo
   std::mutex capture_mu;   // one capture at a time
   // Every class sizes its workspace in its first iteration, and growing a workspace frees a
   // buffer, which synchronises the device; that is not allowed while another thread's stream is
-  // being captured.  So no class captures before every class has finished its first iteration.
+  // being captured.  So no class captures before every class has finished its first iteration;
+  // until then a class that could capture keeps iterating eagerly instead of waiting.
   std::mutex bar_mu;
-  std::condition_variable bar_cv;
   int bar_left = C;
-  auto arrive = [&](bool wait) {
-    std::unique_lock<std::mutex> lk(bar_mu);
-    if (--bar_left == 0)
-      bar_cv.notify_all();
-    else if (wait)
-      bar_cv.wait(lk, [&] { return bar_left == 0; });
+  auto arrive = [&]() {
+    std::lock_guard<std::mutex> lk(bar_mu);
+    --bar_left;
+  };
+  auto all_sized = [&]() {
+    std::lock_guard<std::mutex> lk(bar_mu);
+    return bar_left == 0;
   };
   auto work = [&](int i) {
     ParaClass& pc = *cls[i];
@@ -640,9 +640,9 @@ static int run_classes_threads(klecgc_ctx* ctx, std::vector<ParaClass*>& cls, bo
       while (k < pc.p.max_iter && left > 0) {
         if (k == 1 && !arrived) {
           arrived = true;
-          arrive(true);
+          arrive();
         }
-        if (capture && k == 1) {
+        if (capture && k >= 1 && !exec && all_sized()) {
           // replays accumulate the solver counters into status blocks cleared here
           status_reset(c, status_block(c, WS_STATUS));
           status_reset(c, status_block(c, WS_STATUS_CGC));
@@ -685,7 +685,7 @@ static int run_classes_threads(klecgc_ctx* ctx, std::vector<ParaClass*>& cls, bo
     } catch (...) {
       errs[i] = std::current_exception();
     }
-    if (!arrived) arrive(false);
+    if (!arrived) arrive();
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
   };
