@@ -13,7 +13,7 @@
 // Galerkin coarse operators, red-black Gauss-Seidel smoothing, coarse correction scaled by
 // kMgScale), with the same sweep order.  The coarse operators depend only on the sample and
 // are built once per call and shared by the sample's slices; level 0 reads the sample's
-// scaled float32 couplings directly (its diagonal is 1).  Levels of at most 32 x 32 nodes
+// scaled float32 couplings directly (its diagonal is 1).  Levels of at most 64 x 64 nodes
 // run in one work-group per system with the level data in LDS.  Two fusions keep the
 // level-0 passes to four per V-cycle at one sweep: the first sweep's red half (x = b / d
 // from x = 0) is folded into its black half, and the prolongation x += s P e into the
@@ -233,6 +233,42 @@ __global__ __launch_bounds__(kT) void k_first_sweep(Lv lv, Chunk c) {
   });
 }
 
+// The same first sweep on a level of even side with 8-byte aligned vectors: each lane takes
+// a red and a black node of its row (columns 2k, 2k + 1), reads the pair's b and d as one
+// float2 and writes both x as one; the black node's value is formed in the order above, so
+// both kernels give the same bits.
+__global__ __launch_bounds__(kT) void k_first_sweep_pairs(Lv lv, Chunk c) {
+  int64_t sample, ls;
+  if (!pick(c, kInCg, sample, ls)) return;
+  const LvS v = view(lv, sample, ls);
+  const int m = v.m;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int j0 = blockIdx.x * lv.rb, j1 = min(m, j0 + lv.rb);
+  for (int j = j0 + w; j < j1; j += 4) {
+    const int row = j * m, odd = j & 1;   // red at column 2k + odd, black at 2k + 1 - odd
+    for (int i = 2 * lane; i < m; i += 128) {
+      const int p = row + i;
+      const float2 b2 = *reinterpret_cast<const float2*>(v.b + p);
+      const float2 d2 = v.l0 ? make_float2(1.f, 1.f) : *reinterpret_cast<const float2*>(v.dg + p);
+      const int ib = i + 1 - odd, pb = row + ib;
+      const float bb = odd ? b2.x : b2.y, db = odd ? d2.x : d2.y;
+      const float br = odd ? b2.y : b2.x, dr = odd ? d2.y : d2.x;
+      float acc = bb;
+      if (odd) {   // west neighbour outside the pair, east one the pair's red node
+        if (ib > 0) acc = fmaf(v.cW(ib, j), v.b[pb - 1] / v.d(pb - 1), acc);
+        acc = fmaf(v.cW(ib + 1, j), br / dr, acc);
+      } else {
+        acc = fmaf(v.cW(ib, j), br / dr, acc);
+        if (ib < m - 1) acc = fmaf(v.cW(ib + 1, j), v.b[pb + 1] / v.d(pb + 1), acc);
+      }
+      if (j > 0) acc = fmaf(v.cS(ib, j), v.b[pb - m] / v.d(pb - m), acc);
+      if (j < m - 1) acc = fmaf(v.cS(ib, j + 1), v.b[pb + m] / v.d(pb + m), acc);
+      const float xr = br / dr, xb = acc / db;
+      *reinterpret_cast<float2*>(v.x + p) = odd ? make_float2(xb, xr) : make_float2(xr, xb);
+    }
+  }
+}
+
 // half sweep of colour col: x_p += (b_p - (L x)_p) / d_p.  The prolongation x += s P e (e the
 // coarse level's x) is folded into the first post-smoothing sweep: its black half (emode 1)
 // reads every value as x + s e(parent), the other colour unchanged in memory; its red half
@@ -291,6 +327,71 @@ __global__ __launch_bounds__(kT) void k_restrict(Lv lv, Lv cv, Chunk c) {
       }
     bc[P] = sum;
   });
+}
+
+// The same restriction from a level of even side with 8-byte aligned vectors: the 2x2 block
+// and the rows above and below it are read as float2 (the columns beside it as single
+// floats), and the block is summed in the order above, so both kernels give the same bits.
+__global__ __launch_bounds__(kT) void k_restrict_pairs(Lv lv, Lv cv, Chunk c) {
+  int64_t sample, ls;
+  if (!pick(c, kInCg, sample, ls)) return;
+  const LvS v = view(lv, sample, ls);
+  float* bc = const_cast<float*>(cv.b) + ls * cv.vstride;
+  const int m = v.m;
+  auto ld2 = [](const float* q) { return *reinterpret_cast<const float2*>(q); };
+  band_nodes(cv.m, cv.rb, [&](int P, int I, int J) {
+    const int i0 = 2 * I, j0 = 2 * J;
+    const int p0 = j0 * m + i0, p1 = p0 + m;
+    const bool hw = i0 > 0, he = i0 + 2 < m, hs = j0 > 0, hn = j0 + 2 < m;
+    const float2 zero = make_float2(0.f, 0.f);
+    const float2 x0 = ld2(v.x + p0), x1 = ld2(v.x + p1);
+    const float2 xs = hs ? ld2(v.x + p0 - m) : zero, xn = hn ? ld2(v.x + p1 + m) : zero;
+    const float xw0 = hw ? v.x[p0 - 1] : 0.f, xw1 = hw ? v.x[p1 - 1] : 0.f;
+    const float xe0 = he ? v.x[p0 + 2] : 0.f, xe1 = he ? v.x[p1 + 2] : 0.f;
+    const float2 b0 = ld2(v.b + p0), b1 = ld2(v.b + p1);
+    const float2 d0 = v.l0 ? make_float2(1.f, 1.f) : ld2(v.dg + p0);
+    const float2 d1 = v.l0 ? make_float2(1.f, 1.f) : ld2(v.dg + p1);
+    // couplings: west / middle / east of each block row, south / middle / north of each column
+    const float ww0 = hw ? v.cW(i0, j0) : 0.f, wm0 = v.cW(i0 + 1, j0), we0 = he ? v.cW(i0 + 2, j0) : 0.f;
+    const float ww1 = hw ? v.cW(i0, j0 + 1) : 0.f, wm1 = v.cW(i0 + 1, j0 + 1),
+                we1 = he ? v.cW(i0 + 2, j0 + 1) : 0.f;
+    const float2 ss = hs ? ld2(v.cs + j0 * m + i0) : zero, sm = ld2(v.cs + (j0 + 1) * m + i0),
+                 sn = hn ? ld2(v.cs + (j0 + 2) * m + i0) : zero;
+    float sum = 0.f, acc;
+    acc = d0.x * x0.x;   // (i0, j0)
+    if (hw) acc = fmaf(-ww0, xw0, acc);
+    acc = fmaf(-wm0, x0.y, acc);
+    if (hs) acc = fmaf(-ss.x, xs.x, acc);
+    acc = fmaf(-sm.x, x1.x, acc);
+    sum += b0.x - acc;
+    acc = d0.y * x0.y;   // (i0 + 1, j0)
+    acc = fmaf(-wm0, x0.x, acc);
+    if (he) acc = fmaf(-we0, xe0, acc);
+    if (hs) acc = fmaf(-ss.y, xs.y, acc);
+    acc = fmaf(-sm.y, x1.y, acc);
+    sum += b0.y - acc;
+    acc = d1.x * x1.x;   // (i0, j0 + 1)
+    if (hw) acc = fmaf(-ww1, xw1, acc);
+    acc = fmaf(-wm1, x1.y, acc);
+    acc = fmaf(-sm.x, x0.x, acc);
+    if (hn) acc = fmaf(-sn.x, xn.x, acc);
+    sum += b1.x - acc;
+    acc = d1.y * x1.y;   // (i0 + 1, j0 + 1)
+    acc = fmaf(-wm1, x1.x, acc);
+    if (he) acc = fmaf(-we1, xe1, acc);
+    acc = fmaf(-sm.y, x0.y, acc);
+    if (hn) acc = fmaf(-sn.y, xn.y, acc);
+    sum += b1.y - acc;
+    bc[P] = sum;
+  });
+}
+
+// the paired kernels' condition: even side, every vector and coupling array 8-byte aligned
+// with even strides
+bool pairs_ok(const Lv& v) {
+  const auto al = [](const void* q) { return (reinterpret_cast<uintptr_t>(q) & 7) == 0; };
+  return v.m % 2 == 0 && v.vstride % 2 == 0 && v.cstride % 2 == 0 && al(v.x) && al(v.b) && al(v.cs) &&
+         (v.l0 || al(v.dg));
 }
 
 // The levels lc..L-1 of one system in LDS: b of level lc in, x of level lc out, with the
@@ -895,6 +996,8 @@ int fine_mg_streamed(klecgc_ctx* ctx, const klecgc_problem& p, const FineArgs& f
         lv[l].b = l == 0 ? R : f32 + y.b_off[l];
       }
     }
+    bool pairs[kMgMaxLevels] = {};
+    for (int l = 0; l < y.L; ++l) pairs[l] = l <= y.lc && pairs_ok(lv[l]);
     const dim3 g0((unsigned)nb0, (unsigned)S);
     k_init_sys<<<grid1(S), 256, 0, st>>>(sysst, S, s0, N, fa.skip_first, fa.active, M);
     KC_LAUNCH_CHECK();
@@ -905,7 +1008,10 @@ int fine_mg_streamed(klecgc_ctx* ctx, const klecgc_problem& p, const FineArgs& f
       const int last_streamed = y.lc < y.L ? y.lc - 1 : y.L - 1;
       for (int l = 0; l <= last_streamed; ++l) {
         const dim3 gl((unsigned)y.nb[l], (unsigned)S);
-        k_first_sweep<<<gl, kT, 0, st>>>(lv[l], ch);
+        if (pairs[l])
+          k_first_sweep_pairs<<<gl, kT, 0, st>>>(lv[l], ch);
+        else
+          k_first_sweep<<<gl, kT, 0, st>>>(lv[l], ch);
         KC_LAUNCH_CHECK();
         for (int s = 1; s < sw; ++s) {
           k_half<<<gl, kT, 0, st>>>(lv[l], ch, 0, nullptr, 0, 0, 0, nullptr, 0, 0);
@@ -913,7 +1019,11 @@ int fine_mg_streamed(klecgc_ctx* ctx, const klecgc_problem& p, const FineArgs& f
         }
         KC_LAUNCH_CHECK();
         if (l + 1 < y.L) {
-          k_restrict<<<dim3((unsigned)y.nb[l + 1], (unsigned)S), kT, 0, st>>>(lv[l], lv[l + 1], ch);
+          const dim3 gr((unsigned)y.nb[l + 1], (unsigned)S);
+          if (pairs[l])
+            k_restrict_pairs<<<gr, kT, 0, st>>>(lv[l], lv[l + 1], ch);
+          else
+            k_restrict<<<gr, kT, 0, st>>>(lv[l], lv[l + 1], ch);
           KC_LAUNCH_CHECK();
         } else {   // level 0 is the coarsest (n <= 2): the transposed sweeps, r.z on the last
           for (int s = 0; s < sw; ++s) {

@@ -38,7 +38,7 @@ def spec_of(w, **kw):
                                             (13, "res128", 1e-6), (13, "stream64", 1e-6), (20, "res32", 3e-6),
                                             (40, "res64", 1e-5), (40, "res128", 3e-7), (100, "res128", 1e-5),
                                             (1, "mg", 1e-5), (13, "mg", 1e-6), (40, "mg", 1e-5), (100, "mg", 3e-6),
-                                            (150, "mg", 1e-5), (150, "stream64", 1e-6),
+                                            (150, "mg", 1e-5), (132, "mg", 3e-6), (150, "stream64", 1e-6),
                                             # red-black reduced system: odd and even n, padding
                                             # rows and lanes, one node, the full 128 tile
                                             (1, "rb128", 1e-6), (13, "rb128", 1e-6), (40, "rb128", 3e-7),
