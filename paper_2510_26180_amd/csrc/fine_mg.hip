@@ -32,6 +32,7 @@ namespace {
 
 constexpr int kT = 256;            // threads of a streamed pass (4 waves)
 constexpr int kOnChipMax = 64;     // levels of at most this many nodes per side run in LDS
+constexpr int kOnChipT = 1024;     // threads of the on-chip work-group (one per CU, LDS-bound)
 constexpr int kRing = 1024;        // counters of the host-visible decisions
 
 // --------------------------------------------------------------- host-side level table
@@ -401,6 +402,7 @@ struct OnChip {
   int lc, L, sweeps;
   int m[kMgMaxLevels];
   int64_t coef_off[kMgMaxLevels];
+  int lds_off[kMgMaxLevels];   // floats: cw, cs, d, x, b of level l, m^2 each, from here
 };
 
 __device__ __forceinline__ void lds_half(int m, const float* cw, const float* cs, const float* dg, const float* b,
@@ -422,45 +424,44 @@ __device__ __forceinline__ void lds_half(int m, const float* cw, const float* cs
   __syncthreads();
 }
 
-__global__ __launch_bounds__(kT) void k_onchip(OnChip oc, const float* __restrict__ coef, int64_t cps,
+__global__ __launch_bounds__(kOnChipT) void k_onchip(OnChip oc, const float* __restrict__ coef, int64_t cps,
                                                const float* __restrict__ bin, float* __restrict__ xout,
                                                int64_t vstride, Chunk c) {
   int64_t sample, ls;
   if (!pick(c, kInCg, sample, ls)) return;
   extern __shared__ float lds[];
-  float *CW[kMgMaxLevels], *CS[kMgMaxLevels], *DG[kMgMaxLevels], *XL[kMgMaxLevels], *BL[kMgMaxLevels];
+  // the level arrays, found from the per-level offsets (wave-uniform, no per-thread table)
+  auto arr = [&](int l, int k) { return lds + oc.lds_off[l] + k * oc.m[l] * oc.m[l]; };
+  auto CW = [&](int l) { return arr(l, 0); };
+  auto CS = [&](int l) { return arr(l, 1); };
+  auto DG = [&](int l) { return arr(l, 2); };
+  auto XL = [&](int l) { return arr(l, 3); };
+  auto BL = [&](int l) { return arr(l, 4); };
   {
-    float* q = lds;
     for (int l = oc.lc; l < oc.L; ++l) {
       const int mm = oc.m[l] * oc.m[l];
-      CW[l] = q;
-      CS[l] = q + mm;
-      DG[l] = q + 2 * mm;
-      XL[l] = q + 3 * mm;
-      BL[l] = q + 4 * mm;
-      q += 5 * mm;
       const float* src = coef + sample * cps + oc.coef_off[l];
       for (int p = threadIdx.x; p < mm; p += blockDim.x) {
-        CW[l][p] = src[p];
-        CS[l][p] = src[mm + p];
-        DG[l][p] = src[2 * mm + p];
+        CW(l)[p] = src[p];
+        CS(l)[p] = src[mm + p];
+        DG(l)[p] = src[2 * mm + p];
       }
     }
     const int m0 = oc.m[oc.lc];
-    for (int p = threadIdx.x; p < m0 * m0; p += blockDim.x) BL[oc.lc][p] = bin[ls * vstride + p];
+    for (int p = threadIdx.x; p < m0 * m0; p += blockDim.x) BL(oc.lc)[p] = bin[ls * vstride + p];
   }
   __syncthreads();
   for (int l = oc.lc; l < oc.L; ++l) {
     const int m = oc.m[l];
     for (int p = threadIdx.x; p < m * m; p += blockDim.x) {
       const int j = p / m, i = p - j * m;
-      XL[l][p] = ((i + j) & 1) == 0 ? BL[l][p] / DG[l][p] : 0.f;
+      XL(l)[p] = ((i + j) & 1) == 0 ? BL(l)[p] / DG(l)[p] : 0.f;
     }
     __syncthreads();
-    lds_half(m, CW[l], CS[l], DG[l], BL[l], XL[l], 1);
+    lds_half(m, CW(l), CS(l), DG(l), BL(l), XL(l), 1);
     for (int s = 1; s < oc.sweeps; ++s) {
-      lds_half(m, CW[l], CS[l], DG[l], BL[l], XL[l], 0);
-      lds_half(m, CW[l], CS[l], DG[l], BL[l], XL[l], 1);
+      lds_half(m, CW(l), CS(l), DG(l), BL(l), XL(l), 0);
+      lds_half(m, CW(l), CS(l), DG(l), BL(l), XL(l), 1);
     }
     if (l + 1 < oc.L) {
       const int mc = oc.m[l + 1];
@@ -472,21 +473,21 @@ __global__ __launch_bounds__(kT) void k_onchip(OnChip oc, const float* __restric
             const int i = 2 * I + di, j = 2 * J + dj;
             if (i < m && j < m) {
               const int p = j * m + i;
-              float acc = DG[l][p] * XL[l][p];
-              if (i > 0) acc = fmaf(-CW[l][p], XL[l][p - 1], acc);
-              if (i < m - 1) acc = fmaf(-CW[l][p + 1], XL[l][p + 1], acc);
-              if (j > 0) acc = fmaf(-CS[l][p], XL[l][p - m], acc);
-              if (j < m - 1) acc = fmaf(-CS[l][p + m], XL[l][p + m], acc);
-              sum += BL[l][p] - acc;
+              float acc = DG(l)[p] * XL(l)[p];
+              if (i > 0) acc = fmaf(-CW(l)[p], XL(l)[p - 1], acc);
+              if (i < m - 1) acc = fmaf(-CW(l)[p + 1], XL(l)[p + 1], acc);
+              if (j > 0) acc = fmaf(-CS(l)[p], XL(l)[p - m], acc);
+              if (j < m - 1) acc = fmaf(-CS(l)[p + m], XL(l)[p + m], acc);
+              sum += BL(l)[p] - acc;
             }
           }
-        BL[l + 1][P] = sum;
+        BL(l + 1)[P] = sum;
       }
       __syncthreads();
     } else {
       for (int s = 0; s < oc.sweeps; ++s) {
-        lds_half(m, CW[l], CS[l], DG[l], BL[l], XL[l], 1);
-        lds_half(m, CW[l], CS[l], DG[l], BL[l], XL[l], 0);
+        lds_half(m, CW(l), CS(l), DG(l), BL(l), XL(l), 1);
+        lds_half(m, CW(l), CS(l), DG(l), BL(l), XL(l), 0);
       }
     }
   }
@@ -494,16 +495,16 @@ __global__ __launch_bounds__(kT) void k_onchip(OnChip oc, const float* __restric
     const int m = oc.m[l], mc = oc.m[l + 1];
     for (int p = threadIdx.x; p < m * m; p += blockDim.x) {
       const int j = p / m, i = p - j * m;
-      XL[l][p] = fmaf(kMgScale, XL[l + 1][(j >> 1) * mc + (i >> 1)], XL[l][p]);
+      XL(l)[p] = fmaf(kMgScale, XL(l + 1)[(j >> 1) * mc + (i >> 1)], XL(l)[p]);
     }
     __syncthreads();
     for (int s = 0; s < oc.sweeps; ++s) {
-      lds_half(m, CW[l], CS[l], DG[l], BL[l], XL[l], 1);
-      lds_half(m, CW[l], CS[l], DG[l], BL[l], XL[l], 0);
+      lds_half(m, CW(l), CS(l), DG(l), BL(l), XL(l), 1);
+      lds_half(m, CW(l), CS(l), DG(l), BL(l), XL(l), 0);
     }
   }
   const int m0 = oc.m[oc.lc];
-  for (int p = threadIdx.x; p < m0 * m0; p += blockDim.x) xout[ls * vstride + p] = XL[oc.lc][p];
+  for (int p = threadIdx.x; p < m0 * m0; p += blockDim.x) xout[ls * vstride + p] = XL(oc.lc)[p];
 }
 
 // Galerkin coarse operator of level l from level l - 1 (level 0 from the scaled couplings
@@ -968,9 +969,11 @@ int fine_mg_streamed(klecgc_ctx* ctx, const klecgc_problem& p, const FineArgs& f
   oc.lc = y.lc;
   oc.L = y.L;
   oc.sweeps = y.sweeps;
-  for (int l = 0; l < y.L; ++l) {
+  for (int l = 0, off = 0; l < y.L; ++l) {
     oc.m[l] = y.m[l];
     oc.coef_off[l] = y.coef_off[l];
+    oc.lds_off[l] = off;
+    if (l >= y.lc) off += 5 * y.m[l] * y.m[l];
   }
 
   double last_line = 0.0;
@@ -1036,7 +1039,7 @@ int fine_mg_streamed(klecgc_ctx* ctx, const klecgc_problem& p, const FineArgs& f
         }
       }
       if (y.lc < y.L) {
-        k_onchip<<<dim3(1, (unsigned)S), kT, y.lds_bytes, st>>>(oc, coef, y.coef_per_sample, lv[y.lc].b, lv[y.lc].x,
+        k_onchip<<<dim3(1, (unsigned)S), kOnChipT, y.lds_bytes, st>>>(oc, coef, y.coef_per_sample, lv[y.lc].b, lv[y.lc].x,
                                                                 vs, ch);
         KC_LAUNCH_CHECK();
       }
