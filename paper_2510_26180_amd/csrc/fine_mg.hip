@@ -556,6 +556,53 @@ __global__ __launch_bounds__(kT) void k_matvec(Lv l0, const float* __restrict__ 
   band_partials<1>(d1, mx, part + (ls * nb + blockIdx.x) * 4);
 }
 
+// The same product on a level of even side with 8-byte aligned vectors: each lane takes two
+// neighbouring nodes of its row (columns 2k, 2k + 1), reading P's rows as float2 and writing
+// both Q values as one; each node is formed in the order of apply_at.
+__global__ __launch_bounds__(kT) void k_matvec_pairs(Lv l0, const float* __restrict__ P, float* __restrict__ Q,
+                                                     int64_t vs, Chunk c, double* __restrict__ part, int nb) {
+  int64_t sample, ls;
+  if (!pick(c, kInCg, sample, ls)) return;
+  const LvS v = view(l0, sample, ls);
+  const float* p_ = P + ls * vs;
+  float* q_ = Q + ls * vs;
+  const int m = v.m;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int j0 = blockIdx.x * l0.rb, j1 = min(m, j0 + l0.rb);
+  auto ld2 = [](const float* q) { return *reinterpret_cast<const float2*>(q); };
+  const float2 zero = make_float2(0.f, 0.f);
+  double acc = 0.0;
+  for (int j = j0 + w; j < j1; j += 4) {
+    const int row = j * m;
+    const bool hs = j > 0, hn = j < m - 1;
+    for (int i = 2 * lane; i < m; i += 128) {
+      const int p = row + i;
+      const bool hw = i > 0, he = i + 2 < m;
+      const float2 x = ld2(p_ + p);
+      const float2 xs = hs ? ld2(p_ + p - m) : zero, xn = hn ? ld2(p_ + p + m) : zero;
+      const float xw = hw ? p_[p - 1] : 0.f, xe = he ? p_[p + 2] : 0.f;
+      const float2 d2 = v.l0 ? make_float2(1.f, 1.f) : ld2(v.dg + p);
+      const float cw0 = hw ? v.cW(i, j) : 0.f, cw1 = v.cW(i + 1, j), cw2 = he ? v.cW(i + 2, j) : 0.f;
+      const float2 cs0 = hs ? ld2(v.cs + row + i) : zero, cs1 = hn ? ld2(v.cs + row + m + i) : zero;
+      float a0 = d2.x * x.x;
+      if (hw) a0 = fmaf(-cw0, xw, a0);
+      a0 = fmaf(-cw1, x.y, a0);
+      if (hs) a0 = fmaf(-cs0.x, xs.x, a0);
+      if (hn) a0 = fmaf(-cs1.x, xn.x, a0);
+      float a1 = d2.y * x.y;
+      a1 = fmaf(-cw1, x.x, a1);
+      if (he) a1 = fmaf(-cw2, xe, a1);
+      if (hs) a1 = fmaf(-cs0.y, xs.y, a1);
+      if (hn) a1 = fmaf(-cs1.y, xn.y, a1);
+      *reinterpret_cast<float2*>(q_ + p) = make_float2(a0, a1);
+      acc += (double)(x.x * a0);
+      acc += (double)(x.y * a1);
+    }
+  }
+  double d1[1] = {acc};
+  const bool mx[1] = {false};
+  band_partials<1>(d1, mx, part + (ls * nb + blockIdx.x) * 4);
+}
 __global__ __launch_bounds__(kT) void k_xr(int m, int rb, float* __restrict__ X, float* __restrict__ R,
                                            const float* __restrict__ P, const float* __restrict__ Q, int64_t vs,
                                            Chunk c, double* __restrict__ part, int nb) {
@@ -1001,6 +1048,8 @@ int fine_mg_streamed(klecgc_ctx* ctx, const klecgc_problem& p, const FineArgs& f
     }
     bool pairs[kMgMaxLevels] = {};
     for (int l = 0; l < y.L; ++l) pairs[l] = l <= y.lc && pairs_ok(lv[l]);
+    const bool mv_pairs = pairs[0] && (reinterpret_cast<uintptr_t>(P) & 7) == 0 &&
+                          (reinterpret_cast<uintptr_t>(Q) & 7) == 0;
     const dim3 g0((unsigned)nb0, (unsigned)S);
     k_init_sys<<<grid1(S), 256, 0, st>>>(sysst, S, s0, N, fa.skip_first, fa.active, M);
     KC_LAUNCH_CHECK();
@@ -1078,7 +1127,10 @@ int fine_mg_streamed(klecgc_ctx* ctx, const klecgc_problem& p, const FineArgs& f
           vcycle();
           k_decide<<<(unsigned)S, 64, 0, st>>>(ch, part, nb0, first ? PH_RZ : PH_BETA, k0);
           k_pupd<<<g0, kT, 0, st>>>(n, y.rb[0], P, lv[0].x, vs, ch, first ? 1 : 0);
-          k_matvec<<<g0, kT, 0, st>>>(lv[0], P, Q, vs, ch, part, nb0);
+          if (mv_pairs)
+            k_matvec_pairs<<<g0, kT, 0, st>>>(lv[0], P, Q, vs, ch, part, nb0);
+          else
+            k_matvec<<<g0, kT, 0, st>>>(lv[0], P, Q, vs, ch, part, nb0);
           k_decide<<<(unsigned)S, 64, 0, st>>>(ch, part, nb0, PH_ALPHA, k0);
           k_xr<<<g0, kT, 0, st>>>(n, y.rb[0], X, R, P, Q, vs, ch, part, nb0);
           KC_LAUNCH_CHECK();
