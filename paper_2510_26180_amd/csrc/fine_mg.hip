@@ -636,6 +636,27 @@ __global__ __launch_bounds__(kT) void k_pupd(int m, int rb, float* __restrict__ 
   band_nodes(m, rb, [&](int p, int, int) { p_[p] = first ? z[p] : fmaf(be, p_[p], z[p]); });
 }
 
+// The same update as float4 over the band's rows taken as one range (side a multiple of 4,
+// 16-byte aligned vectors and stride): elementwise, so both kernels give the same bits.
+__global__ __launch_bounds__(kT) void k_pupd4(int m, int rb, float* __restrict__ P, const float* __restrict__ Z,
+                                              int64_t vs, Chunk c, int first) {
+  int64_t sample, ls;
+  if (!pick(c, kInCg, sample, ls)) return;
+  const float be = first ? 0.f : c.st[ls].be;
+  float4* p4 = reinterpret_cast<float4*>(P + ls * vs);
+  const float4* z4 = reinterpret_cast<const float4*>(Z + ls * vs);
+  const int a = blockIdx.x * rb * (m / 4), b = min(m, (int)(blockIdx.x + 1) * rb) * (m / 4);
+  for (int q = a + threadIdx.x; q < b; q += kT) {
+    const float4 z = z4[q];
+    if (first) {
+      p4[q] = z;
+    } else {
+      const float4 pv = p4[q];
+      p4[q] = make_float4(fmaf(be, pv.x, z.x), fmaf(be, pv.y, z.y), fmaf(be, pv.z, z.z), fmaf(be, pv.w, z.w));
+    }
+  }
+}
+
 // ---- float64 refinement passes
 struct F64 {
   const double* a;     // faces [M][Fc]
@@ -1050,6 +1071,8 @@ int fine_mg_streamed(klecgc_ctx* ctx, const klecgc_problem& p, const FineArgs& f
     for (int l = 0; l < y.L; ++l) pairs[l] = l <= y.lc && pairs_ok(lv[l]);
     const bool mv_pairs = pairs[0] && (reinterpret_cast<uintptr_t>(P) & 7) == 0 &&
                           (reinterpret_cast<uintptr_t>(Q) & 7) == 0;
+    const bool pupd4 = n % 4 == 0 && vs % 4 == 0 && (reinterpret_cast<uintptr_t>(P) & 15) == 0 &&
+                       (reinterpret_cast<uintptr_t>(lv[0].x) & 15) == 0;
     const dim3 g0((unsigned)nb0, (unsigned)S);
     k_init_sys<<<grid1(S), 256, 0, st>>>(sysst, S, s0, N, fa.skip_first, fa.active, M);
     KC_LAUNCH_CHECK();
@@ -1126,7 +1149,10 @@ int fine_mg_streamed(klecgc_ctx* ctx, const klecgc_problem& p, const FineArgs& f
         while (incg > 0) {
           vcycle();
           k_decide<<<(unsigned)S, 64, 0, st>>>(ch, part, nb0, first ? PH_RZ : PH_BETA, k0);
-          k_pupd<<<g0, kT, 0, st>>>(n, y.rb[0], P, lv[0].x, vs, ch, first ? 1 : 0);
+          if (pupd4)
+            k_pupd4<<<g0, kT, 0, st>>>(n, y.rb[0], P, lv[0].x, vs, ch, first ? 1 : 0);
+          else
+            k_pupd<<<g0, kT, 0, st>>>(n, y.rb[0], P, lv[0].x, vs, ch, first ? 1 : 0);
           if (mv_pairs)
             k_matvec_pairs<<<g0, kT, 0, st>>>(lv[0], P, Q, vs, ch, part, nb0);
           else
