@@ -14,10 +14,12 @@
 // kMgScale), with the same sweep order.  The coarse operators depend only on the sample and
 // are built once per call and shared by the sample's slices; level 0 reads the sample's
 // scaled float32 couplings directly (its diagonal is 1).  Levels of at most 64 x 64 nodes
-// run in one work-group per system with the level data in LDS.  Two fusions keep the
-// level-0 passes to four per V-cycle at one sweep: the first sweep's red half (x = b / d
-// from x = 0) is folded into its black half, and the prolongation x += s P e into the
-// first post-smoothing half sweeps, each half adding s P e to the values it reads.
+// run in one 1024-thread work-group per system with the level data in LDS.  Two fusions
+// keep the level-0 passes to four per V-cycle at one sweep: the first sweep's red half
+// (x = b / d from x = 0) is folded into its black half, and the prolongation x += s P e into
+// the first post-smoothing half sweeps, each half adding s P e to the values it reads.
+// On levels of even side the first sweep, the restriction and the level-0 product take
+// node pairs per lane (float2 accesses), the direction update four nodes (float4).
 #include <algorithm>
 #include <string>
 
