@@ -97,3 +97,24 @@ def test_subset_draw_is_seeded_and_distinct():
     s = W.draw_subset(256, 16, 2009)
     assert len(set(s.tolist())) == 16 and np.all(np.diff(s) > 0) and s.max() < 256
     assert np.array_equal(s, W.draw_subset(256, 16, 2009))
+
+
+def test_profile_summaries_run_committed_files_only():
+    # every summary under profiles/ is short text whose commands run files of the repository
+    import re
+    import subprocess
+    tracked = set(subprocess.run(["git", "ls-files"], cwd=ROOT, capture_output=True, text=True,
+                                 check=True).stdout.split())
+    pdir = os.path.join(ROOT, "profiles")
+    names = sorted(os.listdir(pdir))
+    assert names
+    for name in names:
+        path = os.path.join(pdir, name)
+        assert name.endswith((".md", ".txt", ".json")), name
+        assert os.path.getsize(path) < 64 * 1024, name
+        text = open(path).read()
+        assert "_work/" not in text and "gpurun" not in text, name
+        if name.endswith(".md"):
+            assert "rocprofv3" in text or "python" in text, name
+            for script in re.findall(r"python3?\s+(?:-u\s+)?([\w/.-]+\.py)", text):
+                assert script in tracked, (name, script)
